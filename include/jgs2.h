@@ -1,0 +1,180 @@
+/*
+ * libjgs2 -- C ABI of the MI355X (gfx950) JGS2 per-iteration solver.
+ *
+ * Method: Lan et al., "JGS2: Near Second-order Converging Jacobi/Gauss-Seidel
+ * for GPU Elastodynamics" (arXiv 2506.06494).  Each implicit-Euler step
+ * minimises the incremental potential E = I + Psi (Sec. 3, Eq. variation) by
+ * parallel per-vertex 3x3 Newton sweeps (Sec. 7.1), optionally corrected by
+ * the precomputed co-rotated, cubature-sampled subspace of Secs. 4-6
+ * (Eqs. tilde_phi, reduced_local, reduced_h_g, cubature, u).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an int32 status (JGS2_OK or a negative code);
+ *     no exception crosses the ABI.  jgs2_last_error() describes the last
+ *     failure of a handle.
+ *   - Host arrays are read or written during the call only and never
+ *     retained.  Arrays of vertices are row-major (nV x 3), arrays of tets are
+ *     row-major (nT x 4) of vertex ids.
+ *   - The library owns all device memory it allocates and frees it in
+ *     jgs2_destroy().  Work is ordered on the handle's HIP stream (the null
+ *     stream unless jgs2_set_stream() was called); calls that return host
+ *     data synchronise that stream.
+ *   - A handle is not thread-safe: use one handle per host thread / stream.
+ */
+#ifndef JGS2_H
+#define JGS2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define JGS2_OK            0
+#define JGS2_E_INVALID    -1  /* bad argument, size, order of calls, non-finite input */
+#define JGS2_E_OOM        -2  /* device allocation failed */
+#define JGS2_E_HIP        -3  /* a HIP runtime call failed */
+#define JGS2_E_NOT_READY  -4  /* mesh, material, correction or state missing */
+#define JGS2_E_DIVERGED   -5  /* residual grew past 1e8 x its start value */
+#define JGS2_E_INFEASIBLE -6  /* a vertex is on or behind a contact plane */
+#define JGS2_E_NONFINITE  -7  /* NaN/Inf appeared in the residual */
+
+/* Local system of a vertex sub-problem (Sec. 7.1: one sub-problem per vertex,
+ * N_i = 3).
+ *   JGS2_PLAIN    A_i = H_ii (assembled diagonal block), b_i = g_i: the plain
+ *                 per-vertex Newton relaxation without overshoot correction.
+ *   JGS2_CUBATURE A_i, b_i from the co-rotated subspace Phi_{i,a} =
+ *                 R_a Ubar_{i,a} R_i^T (Eq. tilde_phi): incident elements and
+ *                 one-ring gradients exactly, remote elements by the
+ *                 cubature samples of Eq. cubature (reading R3, see the
+ *                 design notes).                                            */
+#define JGS2_PLAIN     0
+#define JGS2_CUBATURE  3
+
+/* Parallel order (Sec. 7.1): Jacobi (all vertices from one iterate) or
+ * coloured Gauss-Seidel (greedy colours in ascending order; gradients and
+ * rotations refreshed before each colour). */
+#define JGS2_JACOBI    0
+#define JGS2_GS        1
+
+#define JGS2_MAX_PLANES 8
+
+typedef struct jgs2_solver jgs2_solver;
+
+typedef struct jgs2_params {
+    double  dt;                 /* time step h [s] */
+    double  gravity[3];         /* f_ext / m [m/s^2] */
+    int32_t variant;            /* JGS2_PLAIN or JGS2_CUBATURE */
+    int32_t order;              /* JGS2_JACOBI or JGS2_GS */
+    double  omega;              /* step scale: x_i += omega dx_i (1 = none) */
+    double  rel_tol;            /* stop when |g| / |g(x0)| <= rel_tol */
+    int32_t max_sweeps;         /* sweep cap per step */
+    int32_t check_every;        /* sweeps between residual reads (>= 1) */
+    double  d_hat;              /* IPC barrier activation distance (Eq. barrier) */
+    double  kappa;              /* barrier stiffness (not given in the paper) */
+    int32_t n_planes;           /* static planes n . x >= c, 0..JGS2_MAX_PLANES */
+    int32_t line_search;        /* 1: feasibility clamp + energy backtracking */
+    double  planes[JGS2_MAX_PLANES][4];  /* (n_x, n_y, n_z, c), n unit length */
+} jgs2_params;
+
+typedef struct jgs2_step_stats {
+    int32_t sweeps;             /* sweeps performed this step */
+    int32_t status;             /* JGS2_OK, JGS2_E_DIVERGED, ... */
+    double  r0;                 /* |g(x0)| over free DOFs */
+    double  r_final;            /* |g(x)| / r0 at the end of the step */
+    double  seconds;            /* device time of the step (HIP events) */
+    int32_t ls_halvings;        /* energy backtracking halvings this step */
+    int32_t reserved;
+} jgs2_step_stats;
+
+/* Fills *p with defaults: dt 1/120, gravity (0,-9.8,0), JGS2_PLAIN,
+ * JGS2_JACOBI, omega 1, rel_tol 1e-5, max_sweeps 20000, check_every 8,
+ * d_hat 1e-3, kappa 1e4, no planes, no line search. */
+void jgs2_default_params(jgs2_params* p);
+
+/* Creates a handle.  Fails with JGS2_E_INVALID on a bad parameter set and
+ * JGS2_E_HIP when no gfx950 device is current. */
+int32_t jgs2_create(const jgs2_params* p, jgs2_solver** out);
+void    jgs2_destroy(jgs2_solver* s);
+const char* jgs2_last_error(const jgs2_solver* s);
+
+/* Replaces the parameters; the mesh, material and correction stay. */
+int32_t jgs2_set_params(jgs2_solver* s, const jgs2_params* p);
+/* Orders all later work on the HIP stream `stream` (a hipStream_t). */
+int32_t jgs2_set_stream(jgs2_solver* s, void* stream);
+
+/* Mesh: nV rest positions X (nV x 3, metres), nT tets (nT x 4) with positive
+ * orientation, pinned[nV] (1 = held at its rest position).  Builds vertex
+ * adjacency, the greedy colouring and the device layout.  Invalidates
+ * material, correction and state. */
+int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X,
+                         int32_t nT, const int32_t* tets, const uint8_t* pinned);
+
+/* Per-tet Young's modulus E [Pa], Poisson ratio nu and density rho
+ * [kg/m^3] (stable Neo-Hookean, Sec. 7 / Table 1 caption).  Lumped masses
+ * follow.  Invalidates the correction. */
+int32_t jgs2_set_material(jgs2_solver* s, const double* E, const double* nu,
+                          const double* rho);
+
+/* Precompute of the overshoot correction on the GPU (Secs. 5-6): rest
+ * Hessian, its banded Cholesky factor, training poses (smallest
+ * eigenvectors), U-bar by Eq. u, greedy NNLS cubature with `samples` samples
+ * per vertex drawn from `n_cand` candidates per round (counter-based
+ * SplitMix64 keyed by `seed`).  Needed by JGS2_CUBATURE only. */
+int32_t jgs2_precompute(jgs2_solver* s, int32_t samples, int32_t n_cand, uint64_t seed);
+
+/* Correction tables in free-vertex order (free vertices ascending by id).
+ * For free vertex f with one-ring list ring(f) = its free neighbours in
+ * ascending id order (length given by jgs2_get_ring_sizes):
+ *   U_ring : for f, k < |ring(f)|: rows Ubar_{f,ring(f)[k]} (3x3 row-major),
+ *            packed consecutively over f and k (total sum |ring(f)|).
+ *   samples: nVf x S element ids (-1 = unused slot).
+ *   weights: nVf x S cubature weights (>= 0).
+ *   U_samp : nVf x S x 4 x 3x3: Ubar rows at each sample's 4 corners
+ *            (zero rows at pinned corners).
+ *   fit    : nVf relative NNLS residuals (export only; may be NULL).
+ * import copies these into the device layout (a cache or an external
+ * precompute); export reads back what jgs2_precompute produced. */
+int32_t jgs2_import_correction(jgs2_solver* s, int32_t S, const double* U_ring,
+                               const int32_t* samples, const double* weights,
+                               const double* U_samp);
+int32_t jgs2_export_correction(jgs2_solver* s, int32_t S, double* U_ring,
+                               int32_t* samples, double* weights, double* U_samp,
+                               double* fit);
+/* Number of free vertices, one-ring sizes per free vertex (nVf entries) and
+ * the training-pose eigenvalues of the last precompute (up to 17 entries;
+ * *n_poses receives the pose count n_T). */
+int32_t jgs2_get_ring_sizes(jgs2_solver* s, int32_t* nVf, int32_t* sizes);
+int32_t jgs2_get_poses(jgs2_solver* s, int32_t* n_poses, double* eigenvalues);
+
+/* State: positions x and velocities v (nV x 3) copied from / to the host. */
+int32_t jgs2_set_state(jgs2_solver* s, const double* x, const double* v);
+int32_t jgs2_get_state(jgs2_solver* s, double* x, double* v);
+
+/* One implicit-Euler step (Sec. 3): z = xhat + h vhat + h^2 g, x0 = xhat,
+ * sweeps until |g|/|g(x0)| <= rel_tol or max_sweeps, then v = (x - xhat)/h.
+ * On JGS2_E_DIVERGED / NONFINITE / INFEASIBLE the state is left at the
+ * start of the step. */
+int32_t jgs2_step(jgs2_solver* s, jgs2_step_stats* stats);
+/* The same step in pieces: begin (z, x0, r0), n sweeps (relative residual
+ * of the resulting iterate in *rel_res, may be NULL), end (velocity). */
+int32_t jgs2_begin_step(jgs2_solver* s);
+int32_t jgs2_iterate(jgs2_solver* s, int32_t n_sweeps, double* rel_res);
+int32_t jgs2_end_step(jgs2_solver* s);
+
+/* |g| over free DOFs at the current iterate, and |g| / r0. */
+int32_t jgs2_residual(jgs2_solver* s, double* abs_res, double* rel_res);
+/* Incremental potential E at the current iterate (FP64 sum of FP32 terms). */
+int32_t jgs2_energy(jgs2_solver* s, double* e);
+/* Assembled gradient g (nV x 3, zero at pinned vertices) and per-vertex
+ * rotations R (nV x 3x3 row-major, identity at pinned vertices) at the
+ * current iterate: the outputs of the first sweep phase. */
+int32_t jgs2_get_phase1(jgs2_solver* s, double* g, double* R);
+/* Greedy colour per vertex (-1 for pinned) and the colour count. */
+int32_t jgs2_get_coloring(jgs2_solver* s, int32_t* color, int32_t* n_colors);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JGS2_H */

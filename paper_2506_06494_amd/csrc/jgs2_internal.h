@@ -1,0 +1,122 @@
+// Internal declarations shared by the libjgs2 translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/jgs2.h"
+
+namespace jgs2 {
+
+constexpr int LPV = 32;          // lanes per vertex sub-problem
+constexpr int VPB = 8;           // vertices per 256-thread block
+constexpr int BLOCK = LPV * VPB;
+constexpr int KMAX = 32;         // max free one-ring size held in LDS
+constexpr int SMAX = 8;          // max cubature samples per vertex
+constexpr int SREC = 41;         // floats per sample: w, 4 gcoef, 4 x 9 U-bar
+constexpr uint8_t SLOT_SELF = 0xFE;
+constexpr uint8_t SLOT_NONE = 0xFF;
+
+// Tet record: 5 x float4 = ids(bitcast) | Dm^-1 (9) | vol | V mu | V lam | rho V / (4 h^2)
+constexpr int TET_F4 = 5;
+
+struct SweepArgs {
+    int nV, nVf, maxi, K, S;
+    const int* free_ids;    // [nVf]
+    const int* list;        // optional subset of free indices (colour), or nullptr
+    int n_list;
+    const float4* tet;      // [nT * TET_F4]
+    const int* inc;         // [nVf * maxi] packed (tet << 2 | corner), -1 pad
+    const uint32_t* incslot;// [nVf * maxi] one-ring slot byte per corner
+    const int* inc_n;       // [nVf]
+    const int* ring;        // [nVf * K] vertex ids
+    const int* ring_n;      // [nVf]
+    const float* Uring;     // [(nVf * 9 + comp) * K + k]
+    const int* samp_e;      // [nVf * S]
+    const float* samp;      // [(nVf * SREC + field) * S + s]
+    const float* X;         // [3 * nV] rest positions
+    const float* u;         // [3 * nV] current displacement
+    float* unext;           // [3 * nV]
+    const float* zu;        // [3 * nV] inertial target displacement
+    const float* mh2;       // [nV] m_a / h^2
+    float* g;               // [3 * nV]
+    float* R;               // [9 * nV]
+    double* partial;        // [gridDim] per-block partial sums of |g|^2
+    float omega;
+    int in_place;           // write the update into u (coloured GS, plain variant)
+    // planes
+    int n_planes;
+    float planes[JGS2_MAX_PLANES][4];
+    float d_hat, kappa;
+};
+
+}  // namespace jgs2
+
+struct jgs2_solver {
+    jgs2_params p;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int device = 0;
+
+    // mesh (host)
+    int nV = 0, nT = 0, nVf = 0, maxi = 0, K = 0;
+    std::vector<double> X;
+    std::vector<int> tets;
+    std::vector<uint8_t> pinned;
+    std::vector<int> free_ids, free_index;
+    std::vector<int> inc, inc_n, ring, ring_n;
+    std::vector<uint32_t> incslot;
+    std::vector<int> color, col_perm, col_off;  // colour per vertex, free idx sorted by colour
+    int n_colors = 0;
+    std::vector<int> valence;
+    std::vector<double> vol, Dm_inv;  // per tet (FP64 host copies)
+    std::vector<double> E, nu, rho;
+    std::vector<double> mass;
+
+    bool have_mesh = false, have_material = false, have_corr = false, have_state = false;
+    bool in_step = false, phase1_valid = false;
+    int S = 0;
+    std::vector<double> fit;          // per free vertex NNLS residual
+    std::vector<double> pose_eigs;    // training-pose eigenvalues
+    int n_poses = 0;
+    double r0 = 0.0;
+    int sweeps_in_step = 0;
+
+    // device
+    float4* d_tet = nullptr;
+    float *d_X = nullptr, *d_u = nullptr, *d_unext = nullptr, *d_uhat = nullptr, *d_vhat = nullptr;
+    float *d_zu = nullptr, *d_mh2 = nullptr, *d_g = nullptr, *d_R = nullptr;
+    int *d_free = nullptr, *d_inc = nullptr, *d_inc_n = nullptr, *d_ring = nullptr, *d_ring_n = nullptr;
+    uint32_t* d_incslot = nullptr;
+    int* d_colperm = nullptr;
+    float* d_Uring = nullptr;
+    int* d_samp_e = nullptr;
+    float* d_samp = nullptr;
+    double* d_partial = nullptr;
+    double* d_red = nullptr;
+    int n_partial = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    int fail(int code, const std::string& msg) {
+        err = msg;
+        return code;
+    }
+};
+
+namespace jgs2 {
+int hip_check(jgs2_solver* s, hipError_t e, const char* what);
+void free_device(jgs2_solver* s);
+void build_sweep_args(jgs2_solver* s, SweepArgs& a);
+// kernels launched from the host driver (sweep.hip)
+void launch_phase1(jgs2_solver* s, const SweepArgs& a, bool want_R);
+void launch_phase2_cubature(jgs2_solver* s, const SweepArgs& a);
+void launch_plain(jgs2_solver* s, const SweepArgs& a);
+void launch_commit(jgs2_solver* s, const SweepArgs& a);
+void launch_reduce(jgs2_solver* s, int n);
+void launch_predict(jgs2_solver* s, float h, const float* grav);
+void launch_velocity(jgs2_solver* s, float h);
+void launch_energy(jgs2_solver* s, const SweepArgs& a, int nT);
+int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed);
+}  // namespace jgs2

@@ -1,0 +1,228 @@
+// Small dense math for the JGS2 kernels (device and host), templated on the
+// scalar type: float in the sweeps, double in the precompute.
+//
+// Material: stable Neo-Hookean (Sec. 7 / Table 1 caption); the energy used
+// is Psi = mu/2 (|F|^2 - 3) - mu (J - 1) + lam/2 (J - 1)^2 with
+// mu = mu_L, lam = lam_L + mu_L, which linearises to linear elasticity with
+// the given (E, nu).  Quantities named v* are pre-multiplied by the tet
+// volume.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#define JGS2_HD __host__ __device__ __forceinline__
+
+namespace jgs2 {
+
+template <typename T> struct M3 { T a[9]; };  // row-major 3x3
+
+template <typename T> JGS2_HD T det3(const T* F) {
+    return F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+           F[2] * (F[3] * F[7] - F[4] * F[6]);
+}
+
+// cof(F): column k is the cross product of the other two columns of F
+// (cyclically), so cof(F) = det(F) F^-T.
+template <typename T> JGS2_HD void cof3(const T* F, T* C) {
+    C[0] = F[4] * F[8] - F[7] * F[5];
+    C[3] = F[7] * F[2] - F[1] * F[8];
+    C[6] = F[1] * F[5] - F[4] * F[2];
+    C[1] = F[5] * F[6] - F[8] * F[3];
+    C[4] = F[8] * F[0] - F[2] * F[6];
+    C[7] = F[2] * F[3] - F[5] * F[0];
+    C[2] = F[3] * F[7] - F[6] * F[4];
+    C[5] = F[6] * F[1] - F[0] * F[7];
+    C[8] = F[0] * F[4] - F[3] * F[1];
+}
+
+// Directional derivative of cof at F along D.
+template <typename T> JGS2_HD void dcof3(const T* F, const T* D, T* C) {
+    C[0] = D[4] * F[8] + F[4] * D[8] - D[7] * F[5] - F[7] * D[5];
+    C[3] = D[7] * F[2] + F[7] * D[2] - D[1] * F[8] - F[1] * D[8];
+    C[6] = D[1] * F[5] + F[1] * D[5] - D[4] * F[2] - F[4] * D[2];
+    C[1] = D[5] * F[6] + F[5] * D[6] - D[8] * F[3] - F[8] * D[3];
+    C[4] = D[8] * F[0] + F[8] * D[0] - D[2] * F[6] - F[2] * D[6];
+    C[7] = D[2] * F[3] + F[2] * D[3] - D[5] * F[0] - F[5] * D[0];
+    C[2] = D[3] * F[7] + F[3] * D[7] - D[6] * F[4] - F[6] * D[4];
+    C[5] = D[6] * F[1] + F[6] * D[1] - D[0] * F[7] - F[0] * D[7];
+    C[8] = D[0] * F[4] + F[0] * D[4] - D[3] * F[1] - F[3] * D[1];
+}
+
+// Volume-scaled first Piola-Kirchhoff stress V P(F).
+template <typename T> JGS2_HD void snh_stress(const T* F, const T* C, T J, T vmu, T vlam, T* P) {
+    const T k = vlam * (J - T(1)) - vmu;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) P[i] = vmu * F[i] + k * C[i];
+}
+
+// Volume-scaled stress differential V dP[D].
+template <typename T> JGS2_HD void snh_dstress(const T* F, const T* C, T J, T vmu, T vlam,
+                                               const T* D, T* dP) {
+    T CD = T(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) CD += C[i] * D[i];
+    T dC[9];
+    dcof3(F, D, dC);
+    const T k = vlam * (J - T(1)) - vmu;
+    const T l = vlam * CD;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dP[i] = vmu * D[i] + l * C[i] + k * dC[i];
+}
+
+template <typename T> JGS2_HD T snh_psi(const T* F, T J, T vmu, T vlam) {
+    T I2 = T(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) I2 += F[i] * F[i];
+    return T(0.5) * vmu * (I2 - T(3)) - vmu * (J - T(1)) + T(0.5) * vlam * (J - T(1)) * (J - T(1));
+}
+
+// IPC log barrier B(d) = -(d - dh)^2 log(d / dh) on 0 < d < dh (Eq. barrier)
+// and its first two derivatives.
+template <typename T> JGS2_HD T barrier(T d, T dh) {
+    if (d >= dh) return T(0);
+    return -(d - dh) * (d - dh) * log(d / dh);
+}
+template <typename T> JGS2_HD T barrier_d1(T d, T dh) {
+    if (d >= dh) return T(0);
+    return -T(2) * (d - dh) * log(d / dh) - (d - dh) * (d - dh) / d;
+}
+template <typename T> JGS2_HD T barrier_d2(T d, T dh) {
+    if (d >= dh) return T(0);
+    const T r = (d - dh) / d;
+    return -T(2) * log(d / dh) - T(4) * r + r * r;
+}
+
+// Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations.
+// A (row-major, symmetric) is overwritten; w receives the eigenvalues and
+// V (row-major) the eigenvectors as columns.
+template <typename T> JGS2_HD void sym_eig3(T* A, T* w, T* V) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) V[i] = (i % 4 == 0) ? T(1) : T(0);
+    for (int sweep = 0; sweep < 8; ++sweep) {
+        const T off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+        const T dia = A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
+        if (off <= dia * T(1e-30) || off == T(0)) break;
+#pragma unroll
+        for (int pq = 0; pq < 3; ++pq) {
+            const int p = pq == 2 ? 1 : 0;
+            const int q = pq == 0 ? 1 : 2;
+            const T apq = A[3 * p + q];
+            if (apq == T(0)) continue;
+            const T theta = (A[3 * q + q] - A[3 * p + p]) / (T(2) * apq);
+            const T t = (theta >= T(0) ? T(1) : T(-1)) / (fabs(theta) + sqrt(theta * theta + T(1)));
+            const T c = T(1) / sqrt(t * t + T(1));
+            const T s = t * c;
+            // A <- G^T A G with G the (p,q) rotation
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const T akp = A[3 * k + p], akq = A[3 * k + q];
+                A[3 * k + p] = c * akp - s * akq;
+                A[3 * k + q] = s * akp + c * akq;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const T apk = A[3 * p + k], aqk = A[3 * q + k];
+                A[3 * p + k] = c * apk - s * aqk;
+                A[3 * q + k] = s * apk + c * aqk;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const T vkp = V[3 * k + p], vkq = V[3 * k + q];
+                V[3 * k + p] = c * vkp - s * vkq;
+                V[3 * k + q] = s * vkp + c * vkq;
+            }
+        }
+    }
+    w[0] = A[0]; w[1] = A[4]; w[2] = A[8];
+}
+
+// Closest rotation to F (the rotation of the polar decomposition when
+// det F > 0; otherwise U diag(1,1,det(U V^T)) V^T of the SVD):
+// with the eigenvectors v_k of F^T F, let a, b index the two largest
+// eigenvalues and m the smallest; u_k = F v_k / sigma_k; then
+// R = u_a v_a^T + u_b v_b^T + det[v_a v_b v_m] (u_a x u_b) v_m^T.
+template <typename T> JGS2_HD void closest_rotation(const T* F, T* R) {
+    T C[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
+    T w[3], V[9];
+    sym_eig3(C, w, V);
+    int m = 0;
+    if (w[1] < w[m]) m = 1;
+    if (w[2] < w[m]) m = 2;
+    const int a = (m + 1) % 3, b = (m + 2) % 3;
+    T va[3] = {V[a], V[3 + a], V[6 + a]};
+    T vb[3] = {V[b], V[3 + b], V[6 + b]};
+    T vm[3] = {V[m], V[3 + m], V[6 + m]};
+    const T sa = sqrt(w[a] > T(0) ? w[a] : T(0));
+    const T sb = sqrt(w[b] > T(0) ? w[b] : T(0));
+    if (!(sa > T(0)) || !(sb > T(0))) {  // rank <= 1: no unique rotation
+#pragma unroll
+        for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? T(1) : T(0);
+        return;
+    }
+    T ua[3], ub[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        ua[i] = (F[3 * i] * va[0] + F[3 * i + 1] * va[1] + F[3 * i + 2] * va[2]) / sa;
+        ub[i] = (F[3 * i] * vb[0] + F[3 * i + 1] * vb[1] + F[3 * i + 2] * vb[2]) / sb;
+    }
+    T um[3] = {ua[1] * ub[2] - ua[2] * ub[1], ua[2] * ub[0] - ua[0] * ub[2], ua[0] * ub[1] - ua[1] * ub[0]};
+    const T dv = va[0] * (vb[1] * vm[2] - vb[2] * vm[1]) - va[1] * (vb[0] * vm[2] - vb[2] * vm[0]) +
+                 va[2] * (vb[0] * vm[1] - vb[1] * vm[0]);
+    const T sgn = dv >= T(0) ? T(1) : T(-1);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            R[3 * i + j] = ua[i] * va[j] + ub[i] * vb[j] + sgn * um[i] * vm[j];
+}
+
+// LDL^T pivots of a symmetric 3x3 (lower triangle used).
+template <typename T> JGS2_HD void ldl_pivots(const T* A, T* d, T* l10, T* l20, T* l21) {
+    d[0] = A[0];
+    *l10 = d[0] != T(0) ? A[3] / d[0] : T(0);
+    *l20 = d[0] != T(0) ? A[6] / d[0] : T(0);
+    d[1] = A[4] - (*l10) * (*l10) * d[0];
+    *l21 = d[1] != T(0) ? (A[7] - (*l20) * (*l10) * d[0]) / d[1] : T(0);
+    d[2] = A[8] - (*l20) * (*l20) * d[0] - (*l21) * (*l21) * d[1];
+}
+
+// dx = -A^-1 b for a symmetric 3x3 A.  If A is not safely positive definite
+// (an LDL^T pivot <= 1e-6 |tr A|), A is shifted by (|d_min| + 1e-6 |tr A|) I,
+// the shift doubling until it is.
+template <typename T> JGS2_HD void local_solve(const T* A_in, const T* b, T* dx) {
+    T A[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) A[i] = A_in[i];
+    const T tr = fabs(A[0] + A[4] + A[8]);
+    T d[3], l10, l20, l21;
+    ldl_pivots(A, d, &l10, &l20, &l21);
+    T dmin = fmin(d[0], fmin(d[1], d[2]));
+    if (!(dmin > T(1e-6) * tr)) {
+        T shift = fabs(dmin) + T(1e-6) * tr;
+        for (int it = 0; it < 60; ++it) {
+            T As[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) As[i] = A[i];
+            As[0] += shift; As[4] += shift; As[8] += shift;
+            ldl_pivots(As, d, &l10, &l20, &l21);
+            dmin = fmin(d[0], fmin(d[1], d[2]));
+            if (dmin > T(1e-6) * tr) break;
+            shift *= T(2);
+        }
+    }
+    // forward: L y = b ; diagonal ; back: L^T x = y
+    T y0 = b[0];
+    T y1 = b[1] - l10 * y0;
+    T y2 = b[2] - l20 * y0 - l21 * y1;
+    y0 /= d[0]; y1 /= d[1]; y2 /= d[2];
+    T x2 = y2;
+    T x1 = y1 - l21 * x2;
+    T x0 = y0 - l10 * x1 - l20 * x2;
+    dx[0] = -x0; dx[1] = -x1; dx[2] = -x2;
+}
+
+}  // namespace jgs2

@@ -1,0 +1,724 @@
+// Host side of libjgs2: handle, mesh/material upload, device layout, the
+// time-step driver and the C ABI declared in include/jgs2.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "jgs2_internal.h"
+
+using jgs2::KMAX;
+using jgs2::SMAX;
+using jgs2::SREC;
+
+namespace jgs2 {
+
+int hip_check(jgs2_solver* s, hipError_t e, const char* what) {
+    if (e == hipSuccess) return JGS2_OK;
+    if (s) s->err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? JGS2_E_OOM : JGS2_E_HIP;
+}
+
+template <typename T> static void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void free_device(jgs2_solver* s) {
+    dfree(s->d_tet); dfree(s->d_X); dfree(s->d_u); dfree(s->d_unext); dfree(s->d_uhat); dfree(s->d_vhat);
+    dfree(s->d_zu); dfree(s->d_mh2); dfree(s->d_g); dfree(s->d_R); dfree(s->d_free); dfree(s->d_inc);
+    dfree(s->d_inc_n); dfree(s->d_ring); dfree(s->d_ring_n); dfree(s->d_incslot); dfree(s->d_colperm);
+    dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
+}
+
+void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
+    std::memset(&a, 0, sizeof(a));
+    a.nV = s->nV; a.nVf = s->nVf; a.maxi = s->maxi; a.K = s->K; a.S = s->have_corr ? s->S : 0;
+    a.free_ids = s->d_free; a.list = nullptr; a.n_list = 0;
+    a.tet = s->d_tet; a.inc = s->d_inc; a.incslot = s->d_incslot; a.inc_n = s->d_inc_n;
+    a.ring = s->d_ring; a.ring_n = s->d_ring_n; a.Uring = s->d_Uring; a.samp_e = s->d_samp_e; a.samp = s->d_samp;
+    a.X = s->d_X; a.u = s->d_u; a.unext = s->d_unext; a.zu = s->d_zu; a.mh2 = s->d_mh2; a.g = s->d_g; a.R = s->d_R;
+    a.partial = s->d_partial; a.omega = (float)s->p.omega; a.in_place = 0;
+    a.n_planes = s->p.n_planes;
+    for (int i = 0; i < s->p.n_planes; ++i)
+        for (int k = 0; k < 4; ++k) a.planes[i][k] = (float)s->p.planes[i][k];
+    a.d_hat = (float)s->p.d_hat; a.kappa = (float)s->p.kappa;
+}
+
+}  // namespace jgs2
+
+using namespace jgs2;
+
+#define HIPCHK(expr)                                               \
+    do {                                                           \
+        int _r = jgs2::hip_check(s, (expr), #expr);                \
+        if (_r != JGS2_OK) return _r;                              \
+    } while (0)
+
+template <typename T> static int dalloc(jgs2_solver* s, T*& p, size_t n) {
+    dfree(p);
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void**)&p, n * sizeof(T));
+    if (e != hipSuccess) {
+        p = nullptr;
+        return jgs2::hip_check(s, e, "hipMalloc");
+    }
+    return JGS2_OK;
+}
+
+template <typename T> static int upload(jgs2_solver* s, T* d, const T* h, size_t n) {
+    return jgs2::hip_check(s, hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, s->stream), "upload");
+}
+
+static int validate_params(const jgs2_params* p, std::string& why) {
+    if (!p) { why = "params is NULL"; return JGS2_E_INVALID; }
+    if (!(p->dt > 0) || !std::isfinite(p->dt)) { why = "dt must be positive"; return JGS2_E_INVALID; }
+    if (p->variant != JGS2_PLAIN && p->variant != JGS2_CUBATURE) { why = "unknown variant"; return JGS2_E_INVALID; }
+    if (p->order != JGS2_JACOBI && p->order != JGS2_GS) { why = "unknown order"; return JGS2_E_INVALID; }
+    if (!(p->omega > 0) || !std::isfinite(p->omega)) { why = "omega must be positive"; return JGS2_E_INVALID; }
+    if (p->max_sweeps < 0 || p->check_every < 1) { why = "bad sweep limits"; return JGS2_E_INVALID; }
+    if (p->n_planes < 0 || p->n_planes > JGS2_MAX_PLANES) { why = "bad plane count"; return JGS2_E_INVALID; }
+    if (p->n_planes > 0 && !(p->d_hat > 0 && p->kappa >= 0)) { why = "bad barrier parameters"; return JGS2_E_INVALID; }
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(p->gravity[i])) { why = "gravity must be finite"; return JGS2_E_INVALID; }
+    return JGS2_OK;
+}
+
+static float bits_as_float(int i) {
+    float f;
+    std::memcpy(&f, &i, sizeof(f));
+    return f;
+}
+
+// Per-tet device record and per-vertex m/h^2 from the current material and dt.
+static int upload_material_records(jgs2_solver* s) {
+    const double h = s->p.dt;
+    std::vector<float4> rec((size_t)s->nT * TET_F4);
+    for (int t = 0; t < s->nT; ++t) {
+        const double E = s->E[t], nu = s->nu[t];
+        const double mu_l = E / (2.0 * (1.0 + nu));
+        const double lam_l = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        const double mu = mu_l, lam = lam_l + mu_l;
+        const double V = s->vol[t];
+        const double* D = &s->Dm_inv[9 * (size_t)t];
+        float4* r = &rec[(size_t)t * TET_F4];
+        r[0] = make_float4(bits_as_float(s->tets[4 * t]), bits_as_float(s->tets[4 * t + 1]),
+                           bits_as_float(s->tets[4 * t + 2]), bits_as_float(s->tets[4 * t + 3]));
+        r[1] = make_float4((float)D[0], (float)D[1], (float)D[2], (float)D[3]);
+        r[2] = make_float4((float)D[4], (float)D[5], (float)D[6], (float)D[7]);
+        r[3] = make_float4((float)D[8], (float)V, (float)(V * mu), (float)(V * lam));
+        r[4] = make_float4((float)(s->rho[t] * V / (4.0 * h * h)), 0.f, 0.f, 0.f);
+    }
+    std::vector<float> mh2(s->nV, 0.0f);
+    for (int v = 0; v < s->nV; ++v)
+        if (!s->pinned[v]) mh2[v] = (float)(s->mass[v] / (h * h));
+    int r;
+    if ((r = upload(s, s->d_tet, rec.data(), rec.size())) != JGS2_OK) return r;
+    if ((r = upload(s, s->d_mh2, mh2.data(), mh2.size())) != JGS2_OK) return r;
+    return jgs2::hip_check(s, hipStreamSynchronize(s->stream), "upload material");
+}
+
+extern "C" {
+
+void jgs2_default_params(jgs2_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->dt = 1.0 / 120.0;
+    p->gravity[1] = -9.8;
+    p->variant = JGS2_PLAIN;
+    p->order = JGS2_JACOBI;
+    p->omega = 1.0;
+    p->rel_tol = 1e-5;
+    p->max_sweeps = 20000;
+    p->check_every = 8;
+    p->d_hat = 1e-3;
+    p->kappa = 1e4;
+}
+
+int32_t jgs2_create(const jgs2_params* p, jgs2_solver** out) {
+    if (!out) return JGS2_E_INVALID;
+    *out = nullptr;
+    std::string why;
+    int r = validate_params(p, why);
+    if (r != JGS2_OK) return r;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return JGS2_E_HIP;
+    jgs2_solver* s = new jgs2_solver();
+    s->p = *p;
+    (void)hipGetDevice(&s->device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, s->device) != hipSuccess) { delete s; return JGS2_E_HIP; }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) { delete s; return JGS2_E_HIP; }
+    if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess) { delete s; return JGS2_E_HIP; }
+    *out = s;
+    return JGS2_OK;
+}
+
+void jgs2_destroy(jgs2_solver* s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    free_device(s);
+    if (s->ev0) (void)hipEventDestroy(s->ev0);
+    if (s->ev1) (void)hipEventDestroy(s->ev1);
+    delete s;
+}
+
+const char* jgs2_last_error(const jgs2_solver* s) { return s ? s->err.c_str() : "null handle"; }
+
+int32_t jgs2_set_params(jgs2_solver* s, const jgs2_params* p) {
+    if (!s) return JGS2_E_INVALID;
+    std::string why;
+    int r = validate_params(p, why);
+    if (r != JGS2_OK) return s->fail(r, why);
+    if (s->in_step && (p->dt != s->p.dt || std::memcmp(p->gravity, s->p.gravity, sizeof(p->gravity)) != 0))
+        return s->fail(JGS2_E_INVALID, "dt and gravity cannot change inside a step");
+    const bool dt_changed = p->dt != s->p.dt;
+    s->p = *p;
+    if (dt_changed && s->have_material) {
+        if ((r = upload_material_records(s)) != JGS2_OK) return r;
+    }
+    return JGS2_OK;
+}
+
+int32_t jgs2_set_stream(jgs2_solver* s, void* stream) {
+    if (!s) return JGS2_E_INVALID;
+    s->stream = (hipStream_t)stream;
+    return JGS2_OK;
+}
+
+int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT, const int32_t* tets,
+                         const uint8_t* pinned) {
+    if (!s) return JGS2_E_INVALID;
+    if (nV <= 0 || nT <= 0 || !X || !tets || !pinned) return s->fail(JGS2_E_INVALID, "empty or NULL mesh");
+    for (int64_t i = 0; i < 3LL * nV; ++i)
+        if (!std::isfinite(X[i])) return s->fail(JGS2_E_INVALID, "non-finite rest position");
+    for (int64_t i = 0; i < 4LL * nT; ++i)
+        if (tets[i] < 0 || tets[i] >= nV) return s->fail(JGS2_E_INVALID, "tet vertex id out of range");
+    free_device(s);
+    s->have_mesh = s->have_material = s->have_corr = s->have_state = s->in_step = false;
+    s->nV = nV; s->nT = nT;
+    s->X.assign(X, X + 3 * (size_t)nV);
+    s->tets.assign(tets, tets + 4 * (size_t)nT);
+    s->pinned.assign(pinned, pinned + nV);
+    // rest-shape geometry
+    s->vol.resize(nT);
+    s->Dm_inv.resize(9 * (size_t)nT);
+    for (int t = 0; t < nT; ++t) {
+        const int* c = &tets[4 * t];
+        double Dm[9];
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) Dm[3 * i + k] = X[3 * c[k + 1] + i] - X[3 * c[0] + i];
+        const double det = Dm[0] * (Dm[4] * Dm[8] - Dm[5] * Dm[7]) - Dm[1] * (Dm[3] * Dm[8] - Dm[5] * Dm[6]) +
+                           Dm[2] * (Dm[3] * Dm[7] - Dm[4] * Dm[6]);
+        if (!(det > 0)) return s->fail(JGS2_E_INVALID, "tet with non-positive orientation");
+        s->vol[t] = det / 6.0;
+        double* I = &s->Dm_inv[9 * (size_t)t];
+        I[0] = (Dm[4] * Dm[8] - Dm[5] * Dm[7]) / det; I[1] = (Dm[2] * Dm[7] - Dm[1] * Dm[8]) / det;
+        I[2] = (Dm[1] * Dm[5] - Dm[2] * Dm[4]) / det; I[3] = (Dm[5] * Dm[6] - Dm[3] * Dm[8]) / det;
+        I[4] = (Dm[0] * Dm[8] - Dm[2] * Dm[6]) / det; I[5] = (Dm[2] * Dm[3] - Dm[0] * Dm[5]) / det;
+        I[6] = (Dm[3] * Dm[7] - Dm[4] * Dm[6]) / det; I[7] = (Dm[1] * Dm[6] - Dm[0] * Dm[7]) / det;
+        I[8] = (Dm[0] * Dm[4] - Dm[1] * Dm[3]) / det;
+    }
+    // free numbering
+    s->free_ids.clear();
+    s->free_index.assign(nV, -1);
+    for (int v = 0; v < nV; ++v)
+        if (!pinned[v]) { s->free_index[v] = (int)s->free_ids.size(); s->free_ids.push_back(v); }
+    s->nVf = (int)s->free_ids.size();
+    // incidence (ascending tet id) and valence
+    std::vector<int> cnt(nV, 0);
+    for (int64_t i = 0; i < 4LL * nT; ++i) cnt[tets[i]]++;
+    s->valence = cnt;
+    std::vector<int64_t> off(nV + 1, 0);
+    for (int v = 0; v < nV; ++v) off[v + 1] = off[v] + cnt[v];
+    std::vector<int> incall(off[nV]);
+    std::vector<int64_t> pos(off.begin(), off.end() - 1);
+    for (int t = 0; t < nT; ++t)
+        for (int c = 0; c < 4; ++c) incall[pos[tets[4 * t + c]]++] = (t << 2) | c;
+    // free one-ring, ascending
+    std::vector<std::vector<int>> ringv(s->nVf);
+    s->maxi = 0; s->K = 0;
+    for (int f = 0; f < s->nVf; ++f) {
+        const int v = s->free_ids[f];
+        auto& r = ringv[f];
+        for (int64_t k = off[v]; k < off[v + 1]; ++k) {
+            const int t = incall[k] >> 2;
+            for (int c = 0; c < 4; ++c) {
+                const int a = tets[4 * t + c];
+                if (a != v && !pinned[a]) r.push_back(a);
+            }
+        }
+        std::sort(r.begin(), r.end());
+        r.erase(std::unique(r.begin(), r.end()), r.end());
+        s->maxi = std::max<int>(s->maxi, (int)(off[v + 1] - off[v]));
+        s->K = std::max<int>(s->K, (int)r.size());
+    }
+    if (s->K > KMAX) return s->fail(JGS2_E_INVALID, "one-ring larger than 32 free vertices");
+    if (s->maxi == 0) s->maxi = 1;
+    if (s->K == 0) s->K = 1;
+    const size_t nf = s->nVf;
+    s->inc.assign(nf * s->maxi, -1);
+    s->incslot.assign(nf * s->maxi, 0xFFFFFFFFu);
+    s->inc_n.assign(nf, 0);
+    s->ring.assign(nf * s->K, -1);
+    s->ring_n.assign(nf, 0);
+    for (int f = 0; f < s->nVf; ++f) {
+        const int v = s->free_ids[f];
+        const auto& r = ringv[f];
+        s->ring_n[f] = (int)r.size();
+        for (size_t k = 0; k < r.size(); ++k) s->ring[(size_t)f * s->K + k] = r[k];
+        int j = 0;
+        for (int64_t k = off[v]; k < off[v + 1]; ++k, ++j) {
+            const int pk = incall[k];
+            const int t = pk >> 2;
+            s->inc[(size_t)f * s->maxi + j] = pk;
+            uint32_t sl = 0;
+            for (int c = 0; c < 4; ++c) {
+                const int a = tets[4 * t + c];
+                uint32_t b;
+                if (a == v) b = SLOT_SELF;
+                else if (pinned[a]) b = SLOT_NONE;
+                else b = (uint32_t)(std::lower_bound(r.begin(), r.end(), a) - r.begin());
+                sl |= b << (8 * c);
+            }
+            s->incslot[(size_t)f * s->maxi + j] = sl;
+        }
+        s->inc_n[f] = j;
+    }
+    // greedy colouring of free vertices in id order
+    s->color.assign(nV, -1);
+    s->n_colors = 0;
+    for (int f = 0; f < s->nVf; ++f) {
+        std::vector<char> used(64, 0);
+        for (int a : ringv[f]) {
+            const int c = s->color[a];
+            if (c >= 0) { if (c >= (int)used.size()) used.resize(c + 1, 0); used[c] = 1; }
+        }
+        int c = 0;
+        while (c < (int)used.size() && used[c]) ++c;
+        s->color[s->free_ids[f]] = c;
+        s->n_colors = std::max(s->n_colors, c + 1);
+    }
+    s->col_off.assign(s->n_colors + 1, 0);
+    for (int f = 0; f < s->nVf; ++f) s->col_off[s->color[s->free_ids[f]] + 1]++;
+    for (int c = 0; c < s->n_colors; ++c) s->col_off[c + 1] += s->col_off[c];
+    s->col_perm.assign(nf, 0);
+    {
+        std::vector<int> p(s->col_off.begin(), s->col_off.end() - 1);
+        for (int f = 0; f < s->nVf; ++f) s->col_perm[p[s->color[s->free_ids[f]]]++] = f;
+    }
+    // device layout
+    int r;
+    const size_t V3 = 3 * (size_t)nV;
+    if ((r = dalloc(s, s->d_X, V3)) || (r = dalloc(s, s->d_u, V3)) || (r = dalloc(s, s->d_unext, V3)) ||
+        (r = dalloc(s, s->d_uhat, V3)) || (r = dalloc(s, s->d_vhat, V3)) || (r = dalloc(s, s->d_zu, V3)) ||
+        (r = dalloc(s, s->d_g, V3)) || (r = dalloc(s, s->d_R, 9 * (size_t)nV)) || (r = dalloc(s, s->d_mh2, (size_t)nV)) ||
+        (r = dalloc(s, s->d_free, nf)) || (r = dalloc(s, s->d_inc, nf * s->maxi)) ||
+        (r = dalloc(s, s->d_incslot, nf * s->maxi)) || (r = dalloc(s, s->d_inc_n, nf)) ||
+        (r = dalloc(s, s->d_ring, nf * s->K)) || (r = dalloc(s, s->d_ring_n, nf)) ||
+        (r = dalloc(s, s->d_colperm, nf)) || (r = dalloc(s, s->d_tet, (size_t)nT * TET_F4)))
+        return r;
+    s->n_partial = std::max<int>((s->nVf + VPB - 1) / VPB, (std::max(nT, s->nVf) + 255) / 256) + 1;
+    if ((r = dalloc(s, s->d_partial, (size_t)s->n_partial)) || (r = dalloc(s, s->d_red, 4))) return r;
+    std::vector<float> Xs(V3), Rid(9 * (size_t)nV, 0.0f);
+    for (int v = 0; v < nV; ++v)
+        for (int i = 0; i < 3; ++i) Xs[i * (size_t)nV + v] = (float)X[3 * (size_t)v + i];
+    for (int v = 0; v < nV; ++v) Rid[0 * (size_t)nV + v] = Rid[4 * (size_t)nV + v] = Rid[8 * (size_t)nV + v] = 1.0f;
+    if ((r = upload(s, s->d_X, Xs.data(), V3)) || (r = upload(s, s->d_R, Rid.data(), 9 * (size_t)nV)) ||
+        (r = upload(s, s->d_free, s->free_ids.data(), nf)) || (r = upload(s, s->d_inc, s->inc.data(), nf * s->maxi)) ||
+        (r = upload(s, s->d_incslot, s->incslot.data(), nf * s->maxi)) || (r = upload(s, s->d_inc_n, s->inc_n.data(), nf)) ||
+        (r = upload(s, s->d_ring, s->ring.data(), nf * s->K)) || (r = upload(s, s->d_ring_n, s->ring_n.data(), nf)) ||
+        (r = upload(s, s->d_colperm, s->col_perm.data(), nf)))
+        return r;
+    for (float* d : {s->d_u, s->d_unext, s->d_uhat, s->d_vhat, s->d_zu, s->d_g})
+        HIPCHK(hipMemsetAsync(d, 0, V3 * sizeof(float), s->stream));
+    HIPCHK(hipMemsetAsync(s->d_mh2, 0, (size_t)nV * sizeof(float), s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->have_mesh = true;
+    return JGS2_OK;
+}
+
+int32_t jgs2_set_material(jgs2_solver* s, const double* E, const double* nu, const double* rho) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_mesh) return s->fail(JGS2_E_NOT_READY, "no mesh");
+    if (!E || !nu || !rho) return s->fail(JGS2_E_INVALID, "NULL material array");
+    for (int t = 0; t < s->nT; ++t)
+        if (!(E[t] >= 0) || !(nu[t] > -1 && nu[t] < 0.5) || !(rho[t] > 0) || !std::isfinite(E[t]))
+            return s->fail(JGS2_E_INVALID, "material out of range");
+    s->E.assign(E, E + s->nT);
+    s->nu.assign(nu, nu + s->nT);
+    s->rho.assign(rho, rho + s->nT);
+    s->mass.assign(s->nV, 0.0);
+    for (int t = 0; t < s->nT; ++t)
+        for (int c = 0; c < 4; ++c) s->mass[s->tets[4 * t + c]] += rho[t] * s->vol[t] / 4.0;
+    int r = upload_material_records(s);
+    if (r != JGS2_OK) return r;
+    s->have_material = true;
+    s->have_corr = false;
+    return JGS2_OK;
+}
+
+int32_t jgs2_get_ring_sizes(jgs2_solver* s, int32_t* nVf, int32_t* sizes) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_mesh) return s->fail(JGS2_E_NOT_READY, "no mesh");
+    if (nVf) *nVf = s->nVf;
+    if (sizes) std::copy(s->ring_n.begin(), s->ring_n.end(), sizes);
+    return JGS2_OK;
+}
+
+int32_t jgs2_get_poses(jgs2_solver* s, int32_t* n_poses, double* eigenvalues) {
+    if (!s) return JGS2_E_INVALID;
+    if (n_poses) *n_poses = s->n_poses;
+    if (eigenvalues) std::copy(s->pose_eigs.begin(), s->pose_eigs.end(), eigenvalues);
+    return JGS2_OK;
+}
+
+int32_t jgs2_import_correction(jgs2_solver* s, int32_t S, const double* U_ring, const int32_t* samples,
+                               const double* weights, const double* U_samp) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_mesh || !s->have_material) return s->fail(JGS2_E_NOT_READY, "no mesh or material");
+    if (S < 0 || S > SMAX) return s->fail(JGS2_E_INVALID, "samples per vertex must be in [0, 8]");
+    if (!U_ring || (S > 0 && (!samples || !weights || !U_samp))) return s->fail(JGS2_E_INVALID, "NULL table");
+    const size_t nf = s->nVf, K = s->K;
+    std::vector<float> Ur(nf * 9 * K, 0.0f);
+    size_t row = 0;
+    for (size_t f = 0; f < nf; ++f)
+        for (int k = 0; k < s->ring_n[f]; ++k, ++row)
+            for (int q = 0; q < 9; ++q) {
+                const double val = U_ring[row * 9 + q];
+                if (!std::isfinite(val)) return s->fail(JGS2_E_INVALID, "non-finite U-bar row");
+                Ur[(f * 9 + q) * K + k] = (float)val;
+            }
+    const int Sd = S > 0 ? S : 1;
+    std::vector<int> se(nf * Sd, -1);
+    std::vector<float> sr(nf * SREC * Sd, 0.0f);
+    for (size_t f = 0; f < nf && S > 0; ++f) {
+        const int v = s->free_ids[f];
+        const int* rb = &s->ring[f * K];
+        const int rn = s->ring_n[f];
+        for (int j = 0; j < S; ++j) {
+            const int e = samples[f * S + j];
+            if (e < -1 || e >= s->nT) return s->fail(JGS2_E_INVALID, "sample element out of range");
+            if (e < 0) continue;
+            const double w = weights[f * S + j];
+            if (!(w >= 0) || !std::isfinite(w)) return s->fail(JGS2_E_INVALID, "bad cubature weight");
+            se[f * S + j] = e;
+            float* rec = &sr[f * SREC * S];
+            rec[j] = (float)w;
+            for (int c = 0; c < 4; ++c) {
+                const int a = s->tets[4 * e + c];
+                if (a == v) return s->fail(JGS2_E_INVALID, "sample element contains its own vertex");
+                const bool in_ring = std::binary_search(rb, rb + rn, a);
+                const double gc = (!s->pinned[a] && !in_ring) ? w / s->valence[a] : 0.0;
+                rec[(1 + c) * S + j] = (float)gc;
+                for (int q = 0; q < 9; ++q)
+                    rec[(5 + 9 * c + q) * S + j] = (float)U_samp[((f * S + j) * 4 + c) * 9 + q];
+            }
+        }
+    }
+    int r;
+    if ((r = dalloc(s, s->d_Uring, Ur.size())) || (r = dalloc(s, s->d_samp_e, se.size())) ||
+        (r = dalloc(s, s->d_samp, sr.size())))
+        return r;
+    if ((r = upload(s, s->d_Uring, Ur.data(), Ur.size())) || (r = upload(s, s->d_samp_e, se.data(), se.size())) ||
+        (r = upload(s, s->d_samp, sr.data(), sr.size())))
+        return r;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->S = S;
+    s->have_corr = true;
+    return JGS2_OK;
+}
+
+int32_t jgs2_export_correction(jgs2_solver* s, int32_t S, double* U_ring, int32_t* samples, double* weights,
+                               double* U_samp, double* fit) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_corr) return s->fail(JGS2_E_NOT_READY, "no correction");
+    if (S != s->S) return s->fail(JGS2_E_INVALID, "sample count differs from the stored correction");
+    const size_t nf = s->nVf, K = s->K;
+    const int Sd = S > 0 ? S : 1;
+    std::vector<float> Ur(nf * 9 * K), sr(nf * SREC * Sd);
+    std::vector<int> se(nf * Sd);
+    HIPCHK(hipMemcpyAsync(Ur.data(), s->d_Uring, Ur.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(se.data(), s->d_samp_e, se.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(sr.data(), s->d_samp, sr.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    size_t row = 0;
+    for (size_t f = 0; f < nf; ++f)
+        for (int k = 0; k < s->ring_n[f]; ++k, ++row)
+            for (int q = 0; q < 9; ++q)
+                if (U_ring) U_ring[row * 9 + q] = Ur[(f * 9 + q) * K + k];
+    for (size_t f = 0; f < nf && S > 0; ++f)
+        for (int j = 0; j < S; ++j) {
+            if (samples) samples[f * S + j] = se[f * S + j];
+            const float* rec = &sr[f * SREC * S];
+            if (weights) weights[f * S + j] = rec[j];
+            if (U_samp)
+                for (int c = 0; c < 4; ++c)
+                    for (int q = 0; q < 9; ++q) U_samp[((f * S + j) * 4 + c) * 9 + q] = rec[(5 + 9 * c + q) * S + j];
+        }
+    if (fit) {
+        for (size_t f = 0; f < nf; ++f) fit[f] = f < s->fit.size() ? s->fit[f] : 0.0;
+    }
+    return JGS2_OK;
+}
+
+int32_t jgs2_precompute(jgs2_solver* s, int32_t samples, int32_t n_cand, uint64_t seed) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_mesh || !s->have_material) return s->fail(JGS2_E_NOT_READY, "no mesh or material");
+    if (samples < 1 || samples > SMAX || n_cand < 1 || n_cand > 64)
+        return s->fail(JGS2_E_INVALID, "samples in [1,8] and candidates in [1,64] required");
+    return precompute_device(s, samples, n_cand, seed);
+}
+
+int32_t jgs2_set_state(jgs2_solver* s, const double* x, const double* v) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_mesh) return s->fail(JGS2_E_NOT_READY, "no mesh");
+    if (!x || !v) return s->fail(JGS2_E_INVALID, "NULL state");
+    const size_t nV = s->nV;
+    std::vector<float> u(3 * nV), vv(3 * nV);
+    for (size_t a = 0; a < nV; ++a)
+        for (int i = 0; i < 3; ++i) {
+            const double xi = x[3 * a + i], vi = v[3 * a + i];
+            if (!std::isfinite(xi) || !std::isfinite(vi)) return s->fail(JGS2_E_INVALID, "non-finite state");
+            u[i * nV + a] = (float)(xi - s->X[3 * a + i]);
+            vv[i * nV + a] = s->pinned[a] ? 0.0f : (float)vi;
+        }
+    int r;
+    if ((r = upload(s, s->d_uhat, u.data(), 3 * nV)) || (r = upload(s, s->d_u, u.data(), 3 * nV)) ||
+        (r = upload(s, s->d_unext, u.data(), 3 * nV)) || (r = upload(s, s->d_vhat, vv.data(), 3 * nV)))
+        return r;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->have_state = true;
+    s->in_step = false;
+    s->phase1_valid = false;
+    return JGS2_OK;
+}
+
+int32_t jgs2_get_state(jgs2_solver* s, double* x, double* v) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_state) return s->fail(JGS2_E_NOT_READY, "no state");
+    const size_t nV = s->nV;
+    std::vector<float> u(3 * nV), vv(3 * nV);
+    // inside a step the current iterate is u; otherwise uhat == u
+    HIPCHK(hipMemcpyAsync(u.data(), s->d_u, 3 * nV * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(vv.data(), s->d_vhat, 3 * nV * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (size_t a = 0; a < nV; ++a)
+        for (int i = 0; i < 3; ++i) {
+            if (x) x[3 * a + i] = s->X[3 * a + i] + (double)u[i * nV + a];
+            if (v) v[3 * a + i] = vv[i * nV + a];
+        }
+    return JGS2_OK;
+}
+
+static int read_reduced(jgs2_solver* s, int n_partials, double* out) {
+    launch_reduce(s, n_partials);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, s->d_red, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return JGS2_OK;
+}
+
+static int gradient_norm2(jgs2_solver* s, double* out) {
+    SweepArgs a;
+    build_sweep_args(s, a);
+    launch_phase1(s, a, s->p.variant == JGS2_CUBATURE);
+    s->phase1_valid = true;
+    return read_reduced(s, (s->nVf + VPB - 1) / VPB, out);
+}
+
+static bool ready_to_step(jgs2_solver* s) {
+    if (!s->have_mesh || !s->have_material) { s->err = "no mesh or material"; return false; }
+    if (!s->have_state) { s->err = "no state"; return false; }
+    if (s->p.variant == JGS2_CUBATURE && !s->have_corr) { s->err = "no correction (precompute or import)"; return false; }
+    return true;
+}
+
+int32_t jgs2_begin_step(jgs2_solver* s) {
+    if (!s) return JGS2_E_INVALID;
+    if (!ready_to_step(s)) return JGS2_E_NOT_READY;
+    const float grav[3] = {(float)s->p.gravity[0], (float)s->p.gravity[1], (float)s->p.gravity[2]};
+    // contact feasibility of the start state
+    if (s->p.n_planes > 0) {
+        std::vector<float> u(3 * (size_t)s->nV);
+        HIPCHK(hipMemcpyAsync(u.data(), s->d_uhat, u.size() * 4, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        for (int f = 0; f < s->nVf; ++f) {
+            const int v = s->free_ids[f];
+            for (int p = 0; p < s->p.n_planes; ++p) {
+                double d = -s->p.planes[p][3];
+                for (int i = 0; i < 3; ++i) d += s->p.planes[p][i] * (s->X[3 * (size_t)v + i] + u[i * (size_t)s->nV + v]);
+                if (!(d > 0)) return s->fail(JGS2_E_INFEASIBLE, "a vertex is on or behind a contact plane");
+            }
+        }
+    }
+    launch_predict(s, (float)s->p.dt, grav);
+    double g2 = 0;
+    int r = gradient_norm2(s, &g2);
+    if (r != JGS2_OK) return r;
+    if (!std::isfinite(g2)) return s->fail(JGS2_E_NONFINITE, "non-finite residual at the start of the step");
+    s->r0 = std::sqrt(g2);
+    s->in_step = true;
+    s->sweeps_in_step = 0;
+    return JGS2_OK;
+}
+
+static void swap_u(jgs2_solver* s) {
+    std::swap(s->d_u, s->d_unext);
+    s->phase1_valid = false;
+}
+
+// One sweep in the configured order and variant.
+static int sweep_once(jgs2_solver* s) {
+    SweepArgs a;
+    build_sweep_args(s, a);
+    const bool cub = s->p.variant == JGS2_CUBATURE;
+    if (s->p.order == JGS2_JACOBI) {
+        if (cub) {
+            if (!s->phase1_valid) launch_phase1(s, a, true);
+            launch_phase2_cubature(s, a);
+        } else {
+            launch_plain(s, a);
+        }
+        swap_u(s);
+    } else {
+        for (int c = 0; c < s->n_colors; ++c) {
+            SweepArgs ac = a;
+            ac.list = s->d_colperm + s->col_off[c];
+            ac.n_list = s->col_off[c + 1] - s->col_off[c];
+            if (cub) {
+                SweepArgs all = a;
+                launch_phase1(s, all, true);
+                launch_phase2_cubature(s, ac);
+                launch_commit(s, ac);
+            } else {
+                ac.in_place = 1;
+                launch_plain(s, ac);
+            }
+        }
+        s->phase1_valid = false;
+    }
+    s->sweeps_in_step++;
+    return jgs2::hip_check(s, hipGetLastError(), "sweep launch");
+}
+
+int32_t jgs2_iterate(jgs2_solver* s, int32_t n_sweeps, double* rel_res) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->in_step) return s->fail(JGS2_E_NOT_READY, "iterate outside begin_step/end_step");
+    if (n_sweeps < 0) return s->fail(JGS2_E_INVALID, "negative sweep count");
+    for (int k = 0; k < n_sweeps; ++k) {
+        int r = sweep_once(s);
+        if (r != JGS2_OK) return r;
+    }
+    double g2 = 0;
+    int r = gradient_norm2(s, &g2);
+    if (r != JGS2_OK) return r;
+    const double rel = s->r0 > 0 ? std::sqrt(g2) / s->r0 : 0.0;
+    if (rel_res) *rel_res = rel;
+    if (!std::isfinite(g2)) return s->fail(JGS2_E_NONFINITE, "non-finite residual");
+    if (rel > 1e8) return s->fail(JGS2_E_DIVERGED, "residual exceeded 1e8 x its start value");
+    return JGS2_OK;
+}
+
+int32_t jgs2_end_step(jgs2_solver* s) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->in_step) return s->fail(JGS2_E_NOT_READY, "end_step without begin_step");
+    launch_velocity(s, (float)s->p.dt);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(s->d_unext, s->d_u, 3 * (size_t)s->nV * 4, hipMemcpyDeviceToDevice, s->stream));
+    s->in_step = false;
+    s->phase1_valid = false;
+    return JGS2_OK;
+}
+
+static int abandon_step(jgs2_solver* s) {
+    // restore the iterate to the start of the step
+    (void)hipMemcpyAsync(s->d_u, s->d_uhat, 3 * (size_t)s->nV * 4, hipMemcpyDeviceToDevice, s->stream);
+    (void)hipMemcpyAsync(s->d_unext, s->d_uhat, 3 * (size_t)s->nV * 4, hipMemcpyDeviceToDevice, s->stream);
+    (void)hipStreamSynchronize(s->stream);
+    s->in_step = false;
+    s->phase1_valid = false;
+    return JGS2_OK;
+}
+
+int32_t jgs2_step(jgs2_solver* s, jgs2_step_stats* st) {
+    if (!s) return JGS2_E_INVALID;
+    jgs2_step_stats loc;
+    std::memset(&loc, 0, sizeof(loc));
+    HIPCHK(hipEventRecord(s->ev0, s->stream));
+    int r = jgs2_begin_step(s);
+    if (r != JGS2_OK) { loc.status = r; if (st) *st = loc; return r; }
+    double rel = 1.0;
+    if (s->r0 == 0.0) rel = 0.0;
+    while (rel > s->p.rel_tol && s->sweeps_in_step < s->p.max_sweeps) {
+        const int k = std::min(s->p.check_every, s->p.max_sweeps - s->sweeps_in_step);
+        r = jgs2_iterate(s, k, &rel);
+        if (r != JGS2_OK) {
+            loc.status = r; loc.sweeps = s->sweeps_in_step; loc.r0 = s->r0; loc.r_final = rel;
+            abandon_step(s);
+            if (st) *st = loc;
+            return r;
+        }
+    }
+    r = jgs2_end_step(s);
+    if (r != JGS2_OK) return r;
+    HIPCHK(hipEventRecord(s->ev1, s->stream));
+    HIPCHK(hipEventSynchronize(s->ev1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    loc.sweeps = s->sweeps_in_step; loc.status = JGS2_OK; loc.r0 = s->r0; loc.r_final = rel; loc.seconds = ms * 1e-3;
+    if (st) *st = loc;
+    return JGS2_OK;
+}
+
+int32_t jgs2_residual(jgs2_solver* s, double* abs_res, double* rel_res) {
+    if (!s) return JGS2_E_INVALID;
+    if (!ready_to_step(s)) return JGS2_E_NOT_READY;
+    double g2 = 0;
+    int r = gradient_norm2(s, &g2);
+    if (r != JGS2_OK) return r;
+    if (abs_res) *abs_res = std::sqrt(g2);
+    if (rel_res) *rel_res = s->r0 > 0 ? std::sqrt(g2) / s->r0 : 0.0;
+    return JGS2_OK;
+}
+
+int32_t jgs2_energy(jgs2_solver* s, double* e) {
+    if (!s) return JGS2_E_INVALID;
+    if (!ready_to_step(s)) return JGS2_E_NOT_READY;
+    SweepArgs a;
+    build_sweep_args(s, a);
+    launch_energy(s, a, s->nT);
+    return read_reduced(s, (std::max(s->nT, s->nVf) + 255) / 256, e);
+}
+
+int32_t jgs2_get_phase1(jgs2_solver* s, double* g, double* R) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_mesh || !s->have_material || !s->have_state) return s->fail(JGS2_E_NOT_READY, "no state");
+    SweepArgs a;
+    build_sweep_args(s, a);
+    launch_phase1(s, a, true);
+    s->phase1_valid = s->in_step;
+    HIPCHK(hipGetLastError());
+    const size_t nV = s->nV;
+    std::vector<float> gg(3 * nV), RR(9 * nV);
+    HIPCHK(hipMemcpyAsync(gg.data(), s->d_g, gg.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(RR.data(), s->d_R, RR.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (size_t v = 0; v < nV; ++v) {
+        for (int i = 0; i < 3; ++i)
+            if (g) g[3 * v + i] = s->pinned[v] ? 0.0 : gg[i * nV + v];
+        for (int i = 0; i < 9; ++i)
+            if (R) R[9 * v + i] = s->pinned[v] ? ((i % 4 == 0) ? 1.0 : 0.0) : RR[i * nV + v];
+    }
+    return JGS2_OK;
+}
+
+int32_t jgs2_get_coloring(jgs2_solver* s, int32_t* color, int32_t* n_colors) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_mesh) return s->fail(JGS2_E_NOT_READY, "no mesh");
+    if (color) std::copy(s->color.begin(), s->color.end(), color);
+    if (n_colors) *n_colors = s->n_colors;
+    return JGS2_OK;
+}
+
+}  // extern "C"

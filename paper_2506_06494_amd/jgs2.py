@@ -1,0 +1,268 @@
+"""Thin ctypes binding of libjgs2 (see include/jgs2.h for every contract).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Raises if the library has not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjgs2.so")
+
+OK, E_INVALID, E_OOM, E_HIP, E_NOT_READY, E_DIVERGED, E_INFEASIBLE, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
+PLAIN, CUBATURE = 0, 3
+JACOBI, GS = 0, 1
+MAX_PLANES = 8
+
+STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -4: "NOT_READY", -5: "DIVERGED",
+                -6: "INFEASIBLE", -7: "NONFINITE"}
+
+
+class Params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("gravity", C.c_double * 3), ("variant", C.c_int32), ("order", C.c_int32),
+                ("omega", C.c_double), ("rel_tol", C.c_double), ("max_sweeps", C.c_int32),
+                ("check_every", C.c_int32), ("d_hat", C.c_double), ("kappa", C.c_double),
+                ("n_planes", C.c_int32), ("line_search", C.c_int32), ("planes", (C.c_double * 4) * MAX_PLANES)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("status", C.c_int32), ("r0", C.c_double), ("r_final", C.c_double),
+                ("seconds", C.c_double), ("ls_halvings", C.c_int32), ("reserved", C.c_int32)]
+
+
+EXPORTS = ["jgs2_default_params", "jgs2_create", "jgs2_destroy", "jgs2_last_error", "jgs2_set_params",
+           "jgs2_set_stream", "jgs2_upload_mesh", "jgs2_set_material", "jgs2_precompute",
+           "jgs2_import_correction", "jgs2_export_correction", "jgs2_get_ring_sizes", "jgs2_get_poses",
+           "jgs2_set_state", "jgs2_get_state", "jgs2_step", "jgs2_begin_step", "jgs2_iterate", "jgs2_end_step",
+           "jgs2_residual", "jgs2_energy", "jgs2_get_phase1", "jgs2_get_coloring"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libjgs2 (no GPU needed to load)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_2506_06494_amd.build.build() first")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    d, i32, u8 = P(C.c_double), P(C.c_int32), P(C.c_uint8)
+    sig = {
+        "jgs2_default_params": (None, [P(Params)]),
+        "jgs2_create": (C.c_int32, [P(Params), P(C.c_void_p)]),
+        "jgs2_destroy": (None, [C.c_void_p]),
+        "jgs2_last_error": (C.c_char_p, [C.c_void_p]),
+        "jgs2_set_params": (C.c_int32, [C.c_void_p, P(Params)]),
+        "jgs2_set_stream": (C.c_int32, [C.c_void_p, C.c_void_p]),
+        "jgs2_upload_mesh": (C.c_int32, [C.c_void_p, C.c_int32, d, C.c_int32, i32, u8]),
+        "jgs2_set_material": (C.c_int32, [C.c_void_p, d, d, d]),
+        "jgs2_precompute": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64]),
+        "jgs2_import_correction": (C.c_int32, [C.c_void_p, C.c_int32, d, i32, d, d]),
+        "jgs2_export_correction": (C.c_int32, [C.c_void_p, C.c_int32, d, i32, d, d, d]),
+        "jgs2_get_ring_sizes": (C.c_int32, [C.c_void_p, i32, i32]),
+        "jgs2_get_poses": (C.c_int32, [C.c_void_p, i32, d]),
+        "jgs2_set_state": (C.c_int32, [C.c_void_p, d, d]),
+        "jgs2_get_state": (C.c_int32, [C.c_void_p, d, d]),
+        "jgs2_step": (C.c_int32, [C.c_void_p, P(StepStats)]),
+        "jgs2_begin_step": (C.c_int32, [C.c_void_p]),
+        "jgs2_iterate": (C.c_int32, [C.c_void_p, C.c_int32, d]),
+        "jgs2_end_step": (C.c_int32, [C.c_void_p]),
+        "jgs2_residual": (C.c_int32, [C.c_void_p, d, d]),
+        "jgs2_energy": (C.c_int32, [C.c_void_p, d]),
+        "jgs2_get_phase1": (C.c_int32, [C.c_void_p, d, d]),
+        "jgs2_get_coloring": (C.c_int32, [C.c_void_p, i32, i32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class JGS2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def default_params() -> Params:
+    p = Params()
+    load().jgs2_default_params(C.byref(p))
+    return p
+
+
+def make_params(**kw) -> Params:
+    p = default_params()
+    planes = kw.pop("planes", None)
+    for k, v in kw.items():
+        if k == "gravity":
+            for i in range(3):
+                p.gravity[i] = float(v[i])
+        else:
+            setattr(p, k, v)
+    if planes is not None:
+        planes = np.asarray(planes, dtype=np.float64).reshape(-1, 4)
+        p.n_planes = planes.shape[0]
+        for i in range(planes.shape[0]):
+            for k in range(4):
+                p.planes[i][k] = float(planes[i, k])
+    return p
+
+
+class Solver:
+    """One libjgs2 handle."""
+
+    def __init__(self, params: Params | None = None, **kw):
+        self.lib = load()
+        self.params = params if params is not None else make_params(**kw)
+        h = C.c_void_p()
+        r = self.lib.jgs2_create(C.byref(self.params), C.byref(h))
+        if r != OK:
+            raise JGS2Error(r, "jgs2_create failed (no gfx950 device?)")
+        self.h = h
+        self.nV = self.nT = 0
+
+    def _chk(self, r):
+        if r != OK:
+            raise JGS2Error(r, self.lib.jgs2_last_error(self.h).decode())
+        return r
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.jgs2_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, **kw):
+        for k, v in kw.items():
+            if k == "gravity":
+                for i in range(3):
+                    self.params.gravity[i] = float(v[i])
+            else:
+                setattr(self.params, k, v)
+        self._chk(self.lib.jgs2_set_params(self.h, C.byref(self.params)))
+
+    def set_stream(self, stream_handle: int):
+        self._chk(self.lib.jgs2_set_stream(self.h, C.c_void_p(stream_handle)))
+
+    def upload_mesh(self, X, tets, pinned):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        pinned = np.ascontiguousarray(pinned, dtype=np.uint8)
+        self.nV, self.nT = X.shape[0], tets.shape[0]
+        self._chk(self.lib.jgs2_upload_mesh(self.h, self.nV, _dptr(X), self.nT, _iptr(tets),
+                                            pinned.ctypes.data_as(C.POINTER(C.c_uint8))))
+
+    def set_material(self, E, nu, rho):
+        arr = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (self.nT,))) for a in (E, nu, rho)]
+        self._chk(self.lib.jgs2_set_material(self.h, *[_dptr(a) for a in arr]))
+
+    def precompute(self, samples=4, n_cand=64, seed=0):
+        self._chk(self.lib.jgs2_precompute(self.h, samples, n_cand, C.c_uint64(seed)))
+
+    def ring_sizes(self):
+        n = C.c_int32()
+        self._chk(self.lib.jgs2_get_ring_sizes(self.h, C.byref(n), None))
+        sizes = np.zeros(n.value, dtype=np.int32)
+        self._chk(self.lib.jgs2_get_ring_sizes(self.h, C.byref(n), _iptr(sizes)))
+        return sizes
+
+    def poses(self):
+        n = C.c_int32()
+        ev = np.zeros(32)
+        self._chk(self.lib.jgs2_get_poses(self.h, C.byref(n), _dptr(ev)))
+        return ev[:n.value].copy()
+
+    def import_correction(self, S, U_ring, samples, weights, U_samp):
+        U_ring = np.ascontiguousarray(U_ring, dtype=np.float64)
+        samples = np.ascontiguousarray(samples, dtype=np.int32)
+        weights = np.ascontiguousarray(weights, dtype=np.float64)
+        U_samp = np.ascontiguousarray(U_samp, dtype=np.float64)
+        self._chk(self.lib.jgs2_import_correction(self.h, S, _dptr(U_ring), _iptr(samples), _dptr(weights),
+                                                  _dptr(U_samp)))
+
+    def export_correction(self, S):
+        sizes = self.ring_sizes()
+        nf = sizes.size
+        U_ring = np.zeros((int(sizes.sum()), 3, 3))
+        samples = np.zeros((nf, S), dtype=np.int32)
+        weights = np.zeros((nf, S))
+        U_samp = np.zeros((nf, S, 4, 3, 3))
+        fit = np.zeros(nf)
+        self._chk(self.lib.jgs2_export_correction(self.h, S, _dptr(U_ring), _iptr(samples), _dptr(weights),
+                                                  _dptr(U_samp), _dptr(fit)))
+        return dict(sizes=sizes, U_ring=U_ring, samples=samples, weights=weights, U_samp=U_samp, fit=fit)
+
+    def set_state(self, x, v):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        self._chk(self.lib.jgs2_set_state(self.h, _dptr(x), _dptr(v)))
+
+    def get_state(self):
+        x = np.zeros((self.nV, 3))
+        v = np.zeros((self.nV, 3))
+        self._chk(self.lib.jgs2_get_state(self.h, _dptr(x), _dptr(v)))
+        return x, v
+
+    def step(self, raise_on_error=True):
+        st = StepStats()
+        r = self.lib.jgs2_step(self.h, C.byref(st))
+        if raise_on_error:
+            self._chk(r)
+        return dict(status=r, sweeps=st.sweeps, r0=st.r0, r_final=st.r_final, seconds=st.seconds,
+                    ls_halvings=st.ls_halvings)
+
+    def begin_step(self):
+        self._chk(self.lib.jgs2_begin_step(self.h))
+
+    def iterate(self, n, raise_on_error=True):
+        rel = C.c_double()
+        r = self.lib.jgs2_iterate(self.h, int(n), C.byref(rel))
+        if raise_on_error:
+            self._chk(r)
+        return rel.value
+
+    def end_step(self):
+        self._chk(self.lib.jgs2_end_step(self.h))
+
+    def residual(self):
+        a, r = C.c_double(), C.c_double()
+        self._chk(self.lib.jgs2_residual(self.h, C.byref(a), C.byref(r)))
+        return a.value, r.value
+
+    def energy(self):
+        e = C.c_double()
+        self._chk(self.lib.jgs2_energy(self.h, C.byref(e)))
+        return e.value
+
+    def phase1(self):
+        g = np.zeros((self.nV, 3))
+        R = np.zeros((self.nV, 3, 3))
+        self._chk(self.lib.jgs2_get_phase1(self.h, _dptr(g), _dptr(R)))
+        return g, R
+
+    def coloring(self):
+        c = np.zeros(self.nV, dtype=np.int32)
+        n = C.c_int32()
+        self._chk(self.lib.jgs2_get_coloring(self.h, _iptr(c), C.byref(n)))
+        return c, n.value
