@@ -119,4 +119,5 @@ void launch_predict(jgs2_solver* s, float h, const float* grav);
 void launch_velocity(jgs2_solver* s, float h);
 void launch_energy(jgs2_solver* s, const SweepArgs& a, int nT);
 int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed);
+int alloc_tables(jgs2_solver* s, int S);
 }  // namespace jgs2

@@ -1,10 +1,1106 @@
-// GPU precompute of the overshoot correction (placeholder until the band
-// solver lands).
+// GPU precompute of the overshoot correction (Secs. 5-6 of the paper).
+//
+//   1. Rest Hessian H-bar = M/h^2 + K(X) over free DOFs: per-tet 12x12
+//      blocks in FP64 on the GPU, assembled on the host into a block-band
+//      matrix after a reverse Cuthill-McKee ordering of the free vertices.
+//   2. Banded Cholesky H-bar = L L^T on the GPU, 64x64 FP64 blocks
+//      (right-looking: diagonal factor, inverse of the diagonal block, panel
+//      by GEMM with that inverse, trailing GEMM updates), then the inverses
+//      of all diagonal blocks so that both triangular sweeps are GEMMs.
+//   3. Training poses (Sec. 5): the smallest eigenpairs of H-bar by block
+//      inverse subspace iteration (64 vectors) with Rayleigh-Ritz; since
+//      H-bar Y = X for Y = H-bar^-1 X, the projected matrix needs no
+//      sparse product: with Y = Q R, Q^T H-bar Q = R^-T (Y^T X) R^-1.
+//   4. Eq. u in full coordinates: per vertex three solves W = H-bar^-1 S_i^T,
+//      B = S_i W, U-bar_i = W B^-1, batched 21 vertices (63 right-hand
+//      sides) per workgroup.
+//   5. Per vertex, one wavefront: one-ring rows, training targets, greedy
+//      NNLS cubature over counter-based SplitMix64 candidates, packed FP32
+//      tables.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <queue>
+
 #include "jgs2_internal.h"
+#include "jgs2_math.h"
 
 namespace jgs2 {
-int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
-    (void)S; (void)n_cand; (void)seed;
-    return s->fail(JGS2_E_INVALID, "GPU precompute not available in this build");
+
+constexpr int NB = 64;             // band block size (DOFs)
+constexpr int NB2 = NB * NB;
+constexpr int VPBATCH = 21;        // vertices per 64-column solve batch
+constexpr int PMAX = 64;           // subspace iteration block size
+constexpr int NTMAX = 16;          // max training poses
+constexpr int NCOL = 3 * NTMAX;    // max rows of the NNLS system
+
+// ---------------------------------------------------------------------------
+// FP64 helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void load_block(double* __restrict__ s, const double* __restrict__ g) {
+    for (int i = threadIdx.x; i < NB2; i += blockDim.x) s[i] = g[i];
 }
+
+// 64x64 GEMM on LDS operands with a 4x4 register tile per thread (256 threads):
+// acc += sign * op(A) op(B), op = identity or transpose.
+template <bool TA, bool TB>
+__device__ __forceinline__ void tile_gemm(const double* __restrict__ A, const double* __restrict__ B, double sign,
+                                          double acc[4][4]) {
+    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+    for (int k = 0; k < NB; ++k) {
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = TA ? A[k * NB + 4 * ty + i] : A[(4 * ty + i) * NB + k];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = TB ? B[(4 * tx + j) * NB + k] : B[k * NB + 4 * tx + j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = fma(sign * a[i], b[j], acc[i][j]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 1. element Hessians at rest (F = I), FP64, 12x12 per tet
+// ---------------------------------------------------------------------------
+__global__ void k_rest_elem_hessian(int nT, const double* __restrict__ Dinv, const double* __restrict__ vmu,
+                                    const double* __restrict__ vlam, const double* __restrict__ mi,
+                                    double* __restrict__ He) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nT) return;
+    const double* D = Dinv + 9 * (size_t)t;
+    double gn[4][3];
+    for (int j = 0; j < 3; ++j) {
+        gn[0][j] = -(D[j] + D[3 + j] + D[6 + j]);
+        gn[1][j] = D[j]; gn[2][j] = D[3 + j]; gn[3][j] = D[6 + j];
+    }
+    double F[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, C[9];
+    cof3(F, C);
+    double* H = He + 144 * (size_t)t;
+    for (int b = 0; b < 4; ++b)
+        for (int d = 0; d < 3; ++d) {
+            double dF[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dP[9];
+            for (int j = 0; j < 3; ++j) dF[3 * d + j] = gn[b][j];
+            snh_dstress(F, C, 1.0, vmu[t], vlam[t], dF, dP);
+            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 3; ++i) {
+                    double v = dP[3 * i] * gn[a][0] + dP[3 * i + 1] * gn[a][1] + dP[3 * i + 2] * gn[a][2];
+                    if (a == b && i == d) v += mi[t];
+                    H[(3 * a + i) * 12 + 3 * b + d] = v;
+                }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// 2. banded Cholesky.  Block (I, J), I - J = d in [0, w], lives at
+//    Lb + ((J * (w + 1) + d) * NB2), row-major 64x64.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ Lb, int w, int J, int* __restrict__ flag) {
+    __shared__ double A[NB2];
+    double* g = Lb + (size_t)J * (w + 1) * NB2;
+    load_block(A, g);
+    __syncthreads();
+    for (int k = 0; k < NB; ++k) {
+        const double dkk = A[k * NB + k];
+        if (dkk <= 0.0) {
+            if (threadIdx.x == 0) atomicOr(flag, 1);
+            return;  // uniform across the block: every thread read the same dkk
+        }
+        const double s = sqrt(dkk);
+        __syncthreads();
+        for (int i = threadIdx.x; i < NB; i += blockDim.x) {
+            if (i == k) A[k * NB + k] = s;
+            else if (i > k) A[i * NB + k] /= s;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < NB2; e += blockDim.x) {
+            const int i = e / NB, j = e % NB;
+            if (j > k && i >= j) A[i * NB + j] -= A[i * NB + k] * A[j * NB + k];
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < NB2; e += blockDim.x) {
+        const int i = e / NB, j = e % NB;
+        g[e] = (j <= i) ? A[e] : 0.0;
+    }
+}
+
+// Inverse of the lower-triangular diagonal block J (column per thread).
+__global__ __launch_bounds__(64) void k_trinv_diag(const double* __restrict__ Lb, int w, int J0,
+                                                   double* __restrict__ Linv) {
+    __shared__ double A[NB2];
+    const int J = J0 + blockIdx.x;
+    const double* g = Lb + (size_t)J * (w + 1) * NB2;
+    for (int i = threadIdx.x; i < NB2; i += blockDim.x) A[i] = g[i];
+    __syncthreads();
+    const int c = threadIdx.x;
+    double x[NB];
+    for (int i = 0; i < NB; ++i) {
+        double s = (i == c) ? 1.0 : 0.0;
+        for (int k = 0; k < i; ++k) s -= A[i * NB + k] * x[k];
+        x[i] = s / A[i * NB + i];
+    }
+    double* o = Linv + (size_t)J * NB2;
+    for (int i = 0; i < NB; ++i) o[i * NB + c] = x[i];
+}
+
+// Panel: L(J+d, J) <- A(J+d, J) L(J,J)^-T for d = 1..w (blockIdx.x = d - 1).
+__global__ __launch_bounds__(256) void k_panel(double* __restrict__ Lb, const double* __restrict__ Linv, int w,
+                                               int J, int nB) {
+    const int d = blockIdx.x + 1;
+    if (J + d >= nB) return;
+    __shared__ double A[NB2], Bi[NB2];
+    double* g = Lb + ((size_t)J * (w + 1) + d) * NB2;
+    load_block(A, g);
+    load_block(Bi, Linv + (size_t)J * NB2);
+    __syncthreads();
+    double acc[4][4] = {};
+    tile_gemm<false, true>(A, Bi, 1.0, acc);
+    __syncthreads();
+    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) g[(4 * ty + i) * NB + 4 * tx + j] = acc[i][j];
+}
+
+// Trailing update: block (J+d1, J+d2) -= L(J+d1, J) L(J+d2, J)^T, d2 <= d1.
+__global__ __launch_bounds__(256) void k_update(double* __restrict__ Lb, int w, int J, int nB) {
+    int p = blockIdx.x, d1 = 1;
+    while (p >= d1) { p -= d1; ++d1; }
+    const int d2 = p + 1;
+    if (J + d1 >= nB) return;
+    __shared__ double A1[NB2], A2[NB2];
+    load_block(A1, Lb + ((size_t)J * (w + 1) + d1) * NB2);
+    load_block(A2, Lb + ((size_t)J * (w + 1) + d2) * NB2);
+    __syncthreads();
+    double* C = Lb + ((size_t)(J + d2) * (w + 1) + (d1 - d2)) * NB2;
+    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+    double acc[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] = C[(4 * ty + i) * NB + 4 * tx + j];
+    tile_gemm<false, true>(A1, A2, -1.0, acc);
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) C[(4 * ty + i) * NB + 4 * tx + j] = acc[i][j];
+}
+
+// ---------------------------------------------------------------------------
+// Multi-right-hand-side solve H-bar X = B in place, one workgroup per batch
+// of 64 columns stored row-major [n_pad][64] at X + batch * n_pad * 64.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_band_solve(const double* __restrict__ Lb, const double* __restrict__ Linv,
+                                                    int nB, int w, int n_pad, double* __restrict__ Xall,
+                                                    const int* __restrict__ first_block) {
+    __shared__ double sA[NB2], sB[NB2];
+    double* X = Xall + (size_t)blockIdx.x * n_pad * NB;
+    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+    const int I0 = first_block ? first_block[blockIdx.x] : 0;
+    // forward: Y_I = L_II^-1 (B_I - sum_d L(I, I-d) Y_{I-d})
+    for (int I = I0; I < nB; ++I) {
+        double acc[4][4];
+        double* XI = X + (size_t)I * NB2;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) acc[i][j] = XI[(4 * ty + i) * NB + 4 * tx + j];
+        const int dmax = min(w, I - I0);
+        for (int d = 1; d <= dmax; ++d) {
+            load_block(sA, Lb + ((size_t)(I - d) * (w + 1) + d) * NB2);
+            load_block(sB, X + (size_t)(I - d) * NB2);
+            __syncthreads();
+            tile_gemm<false, false>(sA, sB, -1.0, acc);
+            __syncthreads();
+        }
+        load_block(sA, Linv + (size_t)I * NB2);
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) sB[(4 * ty + i) * NB + 4 * tx + j] = acc[i][j];
+        __syncthreads();
+        double y[4][4] = {};
+        tile_gemm<false, false>(sA, sB, 1.0, y);
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) XI[(4 * ty + i) * NB + 4 * tx + j] = y[i][j];
+        __syncthreads();
+    }
+    // backward: X_I = L_II^-T (Y_I - sum_d L(I+d, I)^T X_{I+d})
+    for (int I = nB - 1; I >= 0; --I) {
+        double acc[4][4];
+        double* XI = X + (size_t)I * NB2;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) acc[i][j] = (I >= I0) ? XI[(4 * ty + i) * NB + 4 * tx + j] : 0.0;
+        const int dmax = min(w, nB - 1 - I);
+        for (int d = 1; d <= dmax; ++d) {
+            load_block(sA, Lb + ((size_t)I * (w + 1) + d) * NB2);
+            load_block(sB, X + (size_t)(I + d) * NB2);
+            __syncthreads();
+            tile_gemm<true, false>(sA, sB, -1.0, acc);
+            __syncthreads();
+        }
+        load_block(sA, Linv + (size_t)I * NB2);
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) sB[(4 * ty + i) * NB + 4 * tx + j] = acc[i][j];
+        __syncthreads();
+        double y[4][4] = {};
+        tile_gemm<true, false>(sA, sB, 1.0, y);
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) XI[(4 * ty + i) * NB + 4 * tx + j] = y[i][j];
+        __syncthreads();
+    }
+}
+
+// Unit right-hand sides: batch b holds vertices at permuted positions
+// p0 + 21 b + j (j < 21), column 3 j + c is e at DOF 3 p + c.
+__global__ void k_unit_rhs(double* __restrict__ Xall, int n_pad, int p0, int n_vert, int nbatch) {
+    const size_t per = (size_t)n_pad * NB;
+    const size_t total = per * nbatch;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int b = (int)(e / per);
+        const size_t r = (e % per) / NB;
+        const int col = (int)(e % NB);
+        const int j = col / 3, c = col % 3;
+        double v = 0.0;
+        if (j < VPBATCH) {
+            const int p = p0 + b * VPBATCH + j;
+            if (p - p0 < n_vert && r == (size_t)(3 * p + c)) v = 1.0;
+        }
+        Xall[e] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Subspace iteration helpers (FP64, column blocks stored [n_pad][64]).
+// out[64x64] = A^T B (one block per output row i; reduction over n).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, const double* __restrict__ B, int n,
+                                              double* __restrict__ out) {
+    const int i = blockIdx.x;  // column of A
+    __shared__ double s[256][PMAX / 4];
+    // each thread accumulates 16 output columns over a strided range of rows
+    const int jg = threadIdx.x % 4;   // column group of 16
+    const int rt = threadIdx.x / 4;   // 64 row lanes
+    double acc[16] = {};
+    for (int r = rt; r < n; r += 64) {
+        const double a = A[(size_t)r * PMAX + i];
+        const double* b = B + (size_t)r * PMAX + 16 * jg;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] += a * b[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) s[threadIdx.x][j] = acc[j];
+    __syncthreads();
+    if (threadIdx.x < PMAX) {
+        const int j = threadIdx.x;
+        double t = 0.0;
+        for (int q = 0; q < 64; ++q) t += s[q * 4 + j / 16][j % 16];
+        out[i * PMAX + j] = t;
+    }
+}
+
+// out = A M (A: [n][64], M: 64x64 row-major)
+__global__ void k_apply64(const double* __restrict__ A, const double* __restrict__ M, int n, double* __restrict__ out) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)n * PMAX) return;
+    const size_t r = e / PMAX;
+    const int j = (int)(e % PMAX);
+    double s = 0.0;
+    for (int k = 0; k < PMAX; ++k) s += A[r * PMAX + k] * M[k * PMAX + j];
+    out[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// 5. per-vertex correction tables and greedy NNLS cubature (one wave each)
+// ---------------------------------------------------------------------------
+struct CubArgs {
+    int nV, nVf, nT, n_pad, nTp, S, n_cand, K, maxi, E_free, p0, n_vert;
+    uint64_t seed;
+    const int* tets;        // [nT * 4]
+    const int* free_ids;    // [nVf]
+    const int* free_index;  // [nV]
+    const int* perm;        // [nVf] permuted position -> free index
+    const int* iperm;       // [nVf] free index -> permuted position
+    const int* valence;     // [nV]
+    const int* ring;        // [nVf * K]
+    const int* ring_n;
+    const int* inc;         // [nVf * maxi]
+    const int* inc_n;
+    const double* W;        // solved columns of this chunk
+    const double* G;        // [nTp][n_pad] poses lambda_t v_t (permuted DOFs)
+    const double* lam;      // [nTp]
+    const int* cid;         // [nTp]
+    float* Uring;           // tables (device layout of the sweep)
+    int* samp_e;
+    float* samp;
+    double* fit;            // [nVf]
+};
+
+__device__ __forceinline__ uint64_t sm_fin(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t sm_step(uint64_t s) { return sm_fin(s + 0x9E3779B97F4A7C15ull); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// NNLS on m <= 9 columns by enumerating supports: the positive unconstrained
+// least-squares solution of minimal residual over all column subsets.
+// G: m x m Gram (row stride 9), c: A^T b, bb: b^T b.  Returns rho^2, w[m].
+__device__ double nnls_enum(int m, const double* G, const double* c, double bb, double* w) {
+    double best = bb;
+    for (int j = 0; j < m; ++j) w[j] = 0.0;
+    const int nsub = 1 << m;
+    for (int mask = 1; mask < nsub; ++mask) {
+        int idx[9], q = 0;
+        for (int j = 0; j < m; ++j)
+            if (mask & (1 << j)) idx[q++] = j;
+        double L[81], y[9];
+        bool ok = true;
+        double gmax = 0.0;
+        for (int a = 0; a < q; ++a) gmax = fmax(gmax, G[idx[a] * 9 + idx[a]]);
+        for (int a = 0; a < q && ok; ++a) {
+            for (int b = 0; b <= a; ++b) {
+                double s = G[idx[a] * 9 + idx[b]];
+                for (int k = 0; k < b; ++k) s -= L[a * 9 + k] * L[b * 9 + k];
+                if (a == b) {
+                    if (!(s > 1e-13 * gmax)) { ok = false; break; }
+                    L[a * 9 + a] = sqrt(s);
+                } else {
+                    L[a * 9 + b] = s / L[b * 9 + b];
+                }
+            }
+        }
+        if (!ok) continue;
+        for (int a = 0; a < q; ++a) {
+            double s = c[idx[a]];
+            for (int k = 0; k < a; ++k) s -= L[a * 9 + k] * y[k];
+            y[a] = s / L[a * 9 + a];
+        }
+        double x[9];
+        bool pos = true;
+        for (int a = q - 1; a >= 0; --a) {
+            double s = y[a];
+            for (int k = a + 1; k < q; ++k) s -= L[k * 9 + a] * x[k];
+            x[a] = s / L[a * 9 + a];
+            if (!(x[a] > 0.0)) pos = false;
+        }
+        if (!pos) continue;
+        double rho = bb;
+        for (int a = 0; a < q; ++a) rho -= x[a] * c[idx[a]];
+        if (rho < best) {
+            best = rho;
+            for (int j = 0; j < m; ++j) w[j] = 0.0;
+            for (int a = 0; a < q; ++a) w[idx[a]] = x[a];
+        }
+    }
+    return best > 0.0 ? best : 0.0;
+}
+
+__global__ __launch_bounds__(64) void k_cubature(CubArgs a) {
+    const int lane = threadIdx.x;
+    const int j = blockIdx.x;                  // vertex within the chunk
+    if (j >= a.n_vert) return;
+    const int p = a.p0 + j;                    // permuted position
+    const int f = a.perm[p];
+    const int v = a.free_ids[f];
+    const int S = a.S;
+    const int nTp = a.nTp;
+    const double* Wb = a.W + (size_t)(j / VPBATCH) * a.n_pad * NB;
+    const int col0 = 3 * (j % VPBATCH);
+
+    __shared__ int sNbar[KMAX + 1];
+    __shared__ double sBinv[9];
+    __shared__ double sTau[NCOL];
+    __shared__ double sScale[NTMAX];
+    __shared__ double sSel[SMAX][NCOL];       // selected columns
+    __shared__ double sCol[64][NCOL];         // candidate columns
+    __shared__ double sGsel[SMAX * SMAX];
+    __shared__ double sCsel[SMAX];
+    __shared__ int sCand[64];
+    __shared__ int sNc;
+    __shared__ int sChosen[SMAX];
+    __shared__ int sDrawn[64];
+
+    const int nr = a.ring_n[f];
+    if (lane < nr) sNbar[lane] = a.ring[(size_t)f * a.K + lane];
+    if (lane == 0) sNbar[nr] = v;
+    // B = S_i W, B^-1 (FP64, all lanes keep a copy)
+    double B[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) B[3 * r + c] = Wb[(size_t)(3 * p + r) * NB + col0 + c];
+    double Binv[9];
+    {
+        const double det = det3(B);
+        double C[9];
+        cof3(B, C);  // cof(B) = det B^-T  ->  B^-1 = cof(B)^T / det
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) Binv[3 * r + c] = C[3 * c + r] / det;
+    }
+    if (lane < 9) sBinv[lane] = Binv[lane];
+    __syncthreads();
+    const int nbar = nr + 1;
+    auto in_nbar = [&](int x) {
+        for (int k = 0; k < nbar; ++k)
+            if (sNbar[k] == x) return true;
+        return false;
+    };
+    // U-bar rows of vertex x (global id): W rows at x times B^-1; zero if pinned
+    auto ubar = [&](int x, double* U) {
+        const int fx = a.free_index[x];
+        if (fx < 0) {
+            for (int q = 0; q < 9; ++q) U[q] = 0.0;
+            return;
+        }
+        const int qx = a.iperm[fx];
+        double Wr[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) Wr[3 * r + c] = Wb[(size_t)(3 * qx + r) * NB + col0 + c];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                U[3 * r + c] = Wr[3 * r] * sBinv[c] + Wr[3 * r + 1] * sBinv[3 + c] + Wr[3 * r + 2] * sBinv[6 + c];
+    };
+    // one-ring rows (ring order ascending)
+    if (lane < nr) {
+        double U[9];
+        ubar(sNbar[lane], U);
+        for (int q = 0; q < 9; ++q) a.Uring[((size_t)f * 9 + q) * a.K + lane] = (float)U[q];
+    }
+    // training targets: tau^(t) = B^-1 v_{t,i} - sum_{x in Nbar(i)} U-bar_{i,x}^T g_x^(t)
+    if (lane < nTp) {
+        const int t = lane;
+        double tau[3];
+        double vi[3];
+        for (int r = 0; r < 3; ++r) vi[r] = a.G[(size_t)t * a.n_pad + 3 * p + r] / a.lam[t];
+        for (int r = 0; r < 3; ++r) tau[r] = sBinv[3 * r] * vi[0] + sBinv[3 * r + 1] * vi[1] + sBinv[3 * r + 2] * vi[2];
+        for (int k = 0; k < nbar; ++k) {
+            const int x = sNbar[k];
+            const int fx = a.free_index[x];
+            if (fx < 0) continue;
+            const int qx = a.iperm[fx];
+            double U[9];
+            if (x == v) {
+                for (int q = 0; q < 9; ++q) U[q] = (q % 4 == 0) ? 1.0 : 0.0;
+            } else {
+                ubar(x, U);
+            }
+            const double* gx = a.G + (size_t)t * a.n_pad + 3 * qx;
+            for (int c = 0; c < 3; ++c) tau[c] -= U[c] * gx[0] + U[3 + c] * gx[1] + U[6 + c] * gx[2];
+        }
+        for (int r = 0; r < 3; ++r) sTau[3 * t + r] = tau[r];
+    }
+    __syncthreads();
+    // per-cluster RMS normalisation
+    if (lane == 0) {
+        double rms[NTMAX];
+        int ncl = 0;
+        for (int t = 0; t < nTp; ++t) ncl = max(ncl, a.cid[t] + 1);
+        double mx = 0.0;
+        for (int c = 0; c < ncl; ++c) {
+            double s = 0.0;
+            int n = 0;
+            for (int t = 0; t < nTp; ++t)
+                if (a.cid[t] == c) { s += sTau[3 * t] * sTau[3 * t] + sTau[3 * t + 1] * sTau[3 * t + 1] + sTau[3 * t + 2] * sTau[3 * t + 2]; ++n; }
+            rms[c] = sqrt(s / n);
+            mx = fmax(mx, rms[c]);
+        }
+        for (int t = 0; t < nTp; ++t) {
+            const double r = rms[a.cid[t]];
+            sScale[t] = (mx > 0.0 && r > 1e-12 * mx) ? 1.0 / r : 0.0;
+        }
+    }
+    __syncthreads();
+    const int nrow = 3 * nTp;
+    double bb = 0.0;
+    for (int r = 0; r < nrow; ++r) {
+        const double b = sTau[r] * sScale[r / 3];
+        bb += b * b;
+    }
+    const double bnorm = sqrt(bb);
+    // eligibility of an element for vertex v
+    auto eligible = [&](int e) {
+        bool has_out = false;
+        for (int c = 0; c < 4; ++c) {
+            const int x = a.tets[4 * (size_t)e + c];
+            if (x == v) return false;
+            if (a.free_index[x] >= 0 && !in_nbar(x)) has_out = true;
+        }
+        return has_out;
+    };
+    // ineligible elements with a free corner all lie around Nbar(i): count each
+    // once, from its smallest free corner inside Nbar(i)
+    int inel = 0;
+    for (int k = 0; k < nbar; ++k) {
+        const int x = sNbar[k];
+        const int fx = a.free_index[x];
+        if (fx < 0) continue;
+        const int ni = a.inc_n[fx];
+        for (int q = lane; q < ni; q += 64) {
+            const int e = a.inc[(size_t)fx * a.maxi + q] >> 2;
+            int first = 0x7FFFFFFF;
+            for (int c = 0; c < 4; ++c) {
+                const int y = a.tets[4 * (size_t)e + c];
+                if (a.free_index[y] >= 0 && in_nbar(y)) first = min(first, y);
+            }
+            if (first == x && !eligible(e)) inel++;
+        }
+    }
+    inel = wave_sum_i(inel);
+    // column of a candidate (scaled, 3 nTp rows)
+    auto column = [&](int e, double* out) {
+        for (int r = 0; r < nrow; ++r) out[r] = 0.0;
+        for (int c = 0; c < 4; ++c) {
+            const int x = a.tets[4 * (size_t)e + c];
+            const int fx = a.free_index[x];
+            if (fx < 0 || in_nbar(x)) continue;
+            const int qx = a.iperm[fx];
+            double U[9];
+            ubar(x, U);
+            const double wgt = 1.0 / a.valence[x];
+            for (int t = 0; t < nTp; ++t) {
+                const double* gx = a.G + (size_t)t * a.n_pad + 3 * qx;
+                for (int cc = 0; cc < 3; ++cc)
+                    out[3 * t + cc] += wgt * (U[cc] * gx[0] + U[3 + cc] * gx[1] + U[6 + cc] * gx[2]);
+            }
+        }
+        for (int r = 0; r < nrow; ++r) out[r] *= sScale[r / 3];
+    };
+    int nsel = 0;
+    const uint64_t key0 = sm_step(sm_step(a.seed) ^ (uint64_t)v);
+    for (int k = 0; k < S; ++k) {
+        // ---- candidates ----
+        const int pool = a.E_free - inel - nsel;
+        if (lane == 0) sNc = 0;
+        __syncthreads();
+        if (pool <= a.n_cand) {
+            for (int e0 = 0; e0 < a.nT; e0 += 64) {
+                const int e = e0 + lane;
+                bool ok = e < a.nT && eligible(e);
+                for (int q = 0; q < nsel && ok; ++q) ok = sChosen[q] != e;
+                const unsigned long long m = __ballot(ok);
+                if (ok) {
+                    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                    if (sNc + rank < 64) sCand[sNc + rank] = e;
+                }
+                __syncthreads();
+                if (lane == 0) sNc = min(64, sNc + __popcll(m));
+                __syncthreads();
+            }
+        } else {
+            const uint64_t key = sm_step(key0 ^ (uint64_t)k);
+            for (int j0 = 0; j0 < a.n_cand * 64; j0 += 64) {
+                const uint64_t u = sm_step(key + (uint64_t)(j0 + lane) * 0x9E3779B97F4A7C15ull);
+                const int e = (int)(((u >> 32) * (uint64_t)a.nT) >> 32);
+                bool ok = eligible(e);
+                for (int q = 0; q < nsel && ok; ++q) ok = sChosen[q] != e;
+                sDrawn[lane] = ok ? e : -1;
+                __syncthreads();
+                if (lane == 0) {
+                    int nc = sNc;
+                    for (int q = 0; q < 64 && nc < a.n_cand; ++q) {
+                        const int d = sDrawn[q];
+                        if (d < 0) continue;
+                        bool dup = false;
+                        for (int r = 0; r < nc; ++r)
+                            if (sCand[r] == d) { dup = true; break; }
+                        if (!dup) sCand[nc++] = d;
+                    }
+                    sNc = nc;
+                }
+                __syncthreads();
+                if (sNc >= a.n_cand) break;
+            }
+        }
+        __syncthreads();
+        const int nc = sNc;
+        if (nc == 0) break;
+        // ---- score every candidate ----
+        double res = INFINITY;
+        int eid = 0x7FFFFFFF;
+        if (lane < nc) {
+            eid = sCand[lane];
+            column(eid, sCol[lane]);
+            const int m = nsel + 1;
+            double G[81], c[9], w[9];
+            for (int q = 0; q < nsel; ++q) {
+                for (int r = 0; r < nsel; ++r) G[q * 9 + r] = sGsel[q * SMAX + r];
+                c[q] = sCsel[q];
+            }
+            double cc = 0.0, gcc = 0.0;
+            for (int r = 0; r < nrow; ++r) {
+                const double x = sCol[lane][r];
+                cc += x * sTau[r] * sScale[r / 3];
+                gcc += x * x;
+            }
+            for (int q = 0; q < nsel; ++q) {
+                double s = 0.0;
+                for (int r = 0; r < nrow; ++r) s += sSel[q][r] * sCol[lane][r];
+                G[q * 9 + nsel] = s;
+                G[nsel * 9 + q] = s;
+            }
+            G[nsel * 9 + nsel] = gcc;
+            c[nsel] = cc;
+            res = sqrt(nnls_enum(m, G, c, bb, w));
+        }
+        // ---- argmin with the tie rule ----
+        double best = res;
+        for (int o = 32; o > 0; o >>= 1) best = fmin(best, __shfl_xor(best, o, 64));
+        const bool tie = lane < nc && res <= best + 1e-9 * best + 1e-15 * bnorm;
+        int pick = tie ? eid : 0x7FFFFFFF;
+        for (int o = 32; o > 0; o >>= 1) pick = min(pick, __shfl_xor(pick, o, 64));
+        __syncthreads();
+        // append the chosen column
+        int src = -1;
+        for (int q = 0; q < nc; ++q)
+            if (sCand[q] == pick) { src = q; break; }
+        if (src < 0) break;  // no finite residual (uniform across the wave)
+        for (int r = lane; r < nrow; r += 64) sSel[nsel][r] = sCol[src][r];
+        if (lane == 0) sChosen[nsel] = pick;
+        __syncthreads();
+        if (lane <= nsel) {
+            double s = 0.0;
+            for (int r = 0; r < nrow; ++r) s += sSel[lane][r] * sSel[nsel][r];
+            sGsel[lane * SMAX + nsel] = s;
+            sGsel[nsel * SMAX + lane] = s;
+        }
+        if (lane == 0) {
+            double s = 0.0;
+            for (int r = 0; r < nrow; ++r) s += sSel[nsel][r] * sTau[r] * sScale[r / 3];
+            sCsel[nsel] = s;
+        }
+        __syncthreads();
+        ++nsel;
+    }
+    // ---- final weights and tables ----
+    double w[9] = {};
+    double rho2 = bb;
+    {
+        double G[81], c[9];
+        for (int q = 0; q < nsel; ++q) {
+            for (int r = 0; r < nsel; ++r) G[q * 9 + r] = sGsel[q * SMAX + r];
+            c[q] = sCsel[q];
+        }
+        if (nsel > 0) rho2 = nnls_enum(nsel, G, c, bb, w);
+    }
+    if (lane == 0) a.fit[f] = bnorm > 0.0 ? sqrt(rho2) / bnorm : 0.0;
+    if (lane < S) {
+        const int s = lane;
+        float* rec = a.samp + (size_t)f * SREC * S;
+        const int e = s < nsel ? sChosen[s] : -1;
+        a.samp_e[(size_t)f * S + s] = e;
+        const double ws = s < nsel ? w[s] : 0.0;
+        rec[s] = (float)ws;
+        for (int c = 0; c < 4; ++c) {
+            double U[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            double gc = 0.0;
+            if (e >= 0) {
+                const int x = a.tets[4 * (size_t)e + c];
+                ubar(x, U);
+                if (a.free_index[x] >= 0 && !in_nbar(x)) gc = ws / a.valence[x];
+            }
+            rec[(1 + c) * S + s] = (float)gc;
+            for (int q = 0; q < 9; ++q) rec[(5 + 9 * c + q) * S + s] = (float)U[q];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host orchestration
+// ---------------------------------------------------------------------------
+#define PCHK(expr)                                                 \
+    do {                                                           \
+        int _r = jgs2::hip_check(s, (expr), #expr);                \
+        if (_r != JGS2_OK) return _r;                              \
+    } while (0)
+
+template <typename T> struct DevBuf {
+    T* p = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() { if (p) (void)hipFree(p); p = nullptr; }
+    int alloc(jgs2_solver* s, size_t n) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        return jgs2::hip_check(s, hipMalloc((void**)&p, (n ? n : 1) * sizeof(T)), "hipMalloc (precompute)");
+    }
+};
+
+// reverse Cuthill-McKee over the free one-ring graph
+static void rcm_order(jgs2_solver* s, std::vector<int>& perm) {
+    const int n = s->nVf;
+    std::vector<int> deg(n), free_nb;
+    for (int f = 0; f < n; ++f) deg[f] = s->ring_n[f];
+    std::vector<char> seen(n, 0);
+    perm.clear();
+    perm.reserve(n);
+    auto nbrs = [&](int f, std::vector<int>& out) {
+        out.clear();
+        for (int k = 0; k < s->ring_n[f]; ++k) out.push_back(s->free_index[s->ring[(size_t)f * s->K + k]]);
+        std::sort(out.begin(), out.end(), [&](int x, int y) { return deg[x] != deg[y] ? deg[x] < deg[y] : x < y; });
+    };
+    auto bfs_last = [&](int root) {
+        std::vector<int> lvl(n, -1), q{root}, nb;
+        lvl[root] = 0;
+        size_t h = 0;
+        int last = root;
+        while (h < q.size()) {
+            const int x = q[h++];
+            last = x;
+            nbrs(x, nb);
+            for (int y : nb)
+                if (lvl[y] < 0) { lvl[y] = lvl[x] + 1; q.push_back(y); }
+        }
+        return last;
+    };
+    std::vector<int> nb;
+    for (int start = 0; start < n; ++start) {
+        if (seen[start]) continue;
+        // pseudo-peripheral root of this component
+        int root = start;
+        for (int it = 0; it < 2; ++it) root = bfs_last(root);
+        std::vector<int> q{root};
+        seen[root] = 1;
+        size_t h = 0;
+        while (h < q.size()) {
+            const int x = q[h++];
+            perm.push_back(x);
+            nbrs(x, nb);
+            for (int y : nb)
+                if (!seen[y]) { seen[y] = 1; q.push_back(y); }
+        }
+    }
+    std::reverse(perm.begin(), perm.end());
+}
+
+// Host symmetric eigen-decomposition (cyclic Jacobi), ascending.
+static void host_sym_eig(int n, std::vector<double> A, std::vector<double>& w, std::vector<double>& V) {
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) (i == j ? dia : off) += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+        if (off <= 1e-30 * dia) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[(size_t)p * n + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                const double th = (A[(size_t)q * n + q] - A[(size_t)p * n + p]) / (2 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1));
+                const double c = 1 / std::sqrt(t * t + 1), sn = t * c;
+                for (int k = 0; k < n; ++k) {
+                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = c * akp - sn * akq;
+                    A[(size_t)k * n + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = c * apk - sn * aqk;
+                    A[(size_t)q * n + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = c * vkp - sn * vkq;
+                    V[(size_t)k * n + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    std::vector<int> o(n);
+    for (int i = 0; i < n; ++i) o[i] = i;
+    std::sort(o.begin(), o.end(), [&](int x, int y) { return A[(size_t)x * n + x] < A[(size_t)y * n + y]; });
+    w.resize(n);
+    std::vector<double> V2((size_t)n * n);
+    for (int j = 0; j < n; ++j) {
+        w[j] = A[(size_t)o[j] * n + o[j]];
+        for (int k = 0; k < n; ++k) V2[(size_t)k * n + j] = V[(size_t)k * n + o[j]];
+    }
+    V.swap(V2);
+}
+
+// Cholesky of a 64x64 SPD (host), returns lower factor in place; false if not PD.
+static bool host_chol(std::vector<double>& A, int n) {
+    for (int j = 0; j < n; ++j) {
+        double d = A[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+        if (!(d > 0)) return false;
+        d = std::sqrt(d);
+        A[(size_t)j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double v = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) v -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+            A[(size_t)i * n + j] = v / d;
+        }
+        for (int k = j + 1; k < n; ++k) A[(size_t)j * n + k] = 0.0;
+    }
+    return true;
+}
+
+int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
+    const int nVf = s->nVf, nT = s->nT, nV = s->nV;
+    if (3 * nVf < 2 * PMAX) return s->fail(JGS2_E_INVALID, "precompute needs at least 43 free vertices");
+    hipStream_t st = s->stream;
+    // --- ordering ---
+    std::vector<int> perm, iperm(nVf);
+    rcm_order(s, perm);
+    for (int p = 0; p < nVf; ++p) iperm[perm[p]] = p;
+    const int n = 3 * nVf;
+    const int nB = (n + NB - 1) / NB;
+    const int n_pad = nB * NB;
+    // --- element Hessians at rest on the GPU ---
+    std::vector<double> vmu(nT), vlam(nT), mi(nT);
+    const double h = s->p.dt;
+    for (int t = 0; t < nT; ++t) {
+        const double E = s->E[t], nu = s->nu[t];
+        const double mu_l = E / (2 * (1 + nu)), lam_l = E * nu / ((1 + nu) * (1 - 2 * nu));
+        vmu[t] = s->vol[t] * mu_l;
+        vlam[t] = s->vol[t] * (lam_l + mu_l);
+        mi[t] = s->rho[t] * s->vol[t] / (4 * h * h);
+    }
+    std::vector<double> He((size_t)nT * 144);
+    {
+        DevBuf<double> dD, dmu, dla, dmi, dHe;
+        int r;
+        if ((r = dD.alloc(s, 9 * (size_t)nT)) || (r = dmu.alloc(s, nT)) || (r = dla.alloc(s, nT)) ||
+            (r = dmi.alloc(s, nT)) || (r = dHe.alloc(s, 144 * (size_t)nT)))
+            return r;
+        PCHK(hipMemcpyAsync(dD.p, s->Dm_inv.data(), 9 * (size_t)nT * 8, hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(dmu.p, vmu.data(), nT * 8, hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(dla.p, vlam.data(), nT * 8, hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(dmi.p, mi.data(), nT * 8, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_rest_elem_hessian, dim3((nT + 127) / 128), dim3(128), 0, st, nT, dD.p, dmu.p, dla.p,
+                           dmi.p, dHe.p);
+        PCHK(hipGetLastError());
+        PCHK(hipMemcpyAsync(He.data(), dHe.p, He.size() * 8, hipMemcpyDeviceToHost, st));
+        PCHK(hipStreamSynchronize(st));
+    }
+    // --- band width and assembly (lower triangle, permuted DOFs) ---
+    auto dof = [&](int vtx, int c) { return 3 * iperm[s->free_index[vtx]] + c; };
+    int w = 0;
+    for (int t = 0; t < nT; ++t)
+        for (int ca = 0; ca < 4; ++ca)
+            for (int cb = 0; cb < 4; ++cb) {
+                const int a = s->tets[4 * t + ca], b = s->tets[4 * t + cb];
+                if (s->pinned[a] || s->pinned[b]) continue;
+                const int ra = dof(a, 2) / NB, rb = dof(b, 0) / NB;
+                w = std::max(w, ra - rb);
+            }
+    const size_t band_doubles = (size_t)nB * (w + 1) * NB2;
+    std::vector<double> Lh(band_doubles, 0.0);
+    for (int t = 0; t < nT; ++t)
+        for (int ca = 0; ca < 4; ++ca)
+            for (int cb = 0; cb < 4; ++cb) {
+                const int a = s->tets[4 * t + ca], b = s->tets[4 * t + cb];
+                if (s->pinned[a] || s->pinned[b]) continue;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) {
+                        const int r = dof(a, i), c = dof(b, j);
+                        if (r < c) continue;
+                        const int I = r / NB, J = c / NB;
+                        Lh[((size_t)J * (w + 1) + (I - J)) * NB2 + (size_t)(r - I * NB) * NB + (c - J * NB)] +=
+                            He[144 * (size_t)t + (3 * ca + i) * 12 + 3 * cb + j];
+                    }
+            }
+    for (int r = n; r < n_pad; ++r) {  // padded DOFs: identity
+        const int I = r / NB;
+        Lh[((size_t)I * (w + 1)) * NB2 + (size_t)(r - I * NB) * NB + (r - I * NB)] = 1.0;
+    }
+    He.clear();
+    He.shrink_to_fit();
+    DevBuf<double> dL, dLinv;
+    DevBuf<int> dflag;
+    int r;
+    if ((r = dL.alloc(s, band_doubles)) || (r = dLinv.alloc(s, (size_t)nB * NB2)) || (r = dflag.alloc(s, 1))) return r;
+    PCHK(hipMemcpyAsync(dL.p, Lh.data(), band_doubles * 8, hipMemcpyHostToDevice, st));
+    PCHK(hipMemsetAsync(dflag.p, 0, sizeof(int), st));
+    Lh.clear();
+    Lh.shrink_to_fit();
+    // --- factorisation ---
+    const int nupd = w * (w + 1) / 2;
+    for (int J = 0; J < nB; ++J) {
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, dL.p, w, J, dflag.p);
+        hipLaunchKernelGGL(k_trinv_diag, dim3(1), dim3(64), 0, st, dL.p, w, J, dLinv.p);
+        if (w > 0) {
+            hipLaunchKernelGGL(k_panel, dim3(w), dim3(256), 0, st, dL.p, dLinv.p, w, J, nB);
+            hipLaunchKernelGGL(k_update, dim3(nupd), dim3(256), 0, st, dL.p, w, J, nB);
+        }
+    }
+    PCHK(hipGetLastError());
+    int flag = 0;
+    PCHK(hipMemcpyAsync(&flag, dflag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    PCHK(hipStreamSynchronize(st));
+    if (flag) return s->fail(JGS2_E_INVALID, "rest Hessian is not positive definite");
+    // --- training poses: block inverse subspace iteration ---
+    const int nwant = std::min(NTMAX + 1, n - 1);
+    std::vector<double> lam_all;
+    DevBuf<double> dX, dY, dM, dT;
+    if ((r = dX.alloc(s, (size_t)n_pad * PMAX)) || (r = dY.alloc(s, (size_t)n_pad * PMAX)) ||
+        (r = dM.alloc(s, PMAX * PMAX)) || (r = dT.alloc(s, (size_t)n_pad * PMAX)))
+        return r;
+    {
+        std::vector<double> X0((size_t)n_pad * PMAX, 0.0);
+        uint64_t z = seed ^ 0x5EEDF00DULL;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < PMAX; ++j) {
+                z += 0x9E3779B97F4A7C15ull;
+                uint64_t q = z;
+                q = (q ^ (q >> 30)) * 0xBF58476D1CE4E5B9ull;
+                q = (q ^ (q >> 27)) * 0x94D049BB133111EBull;
+                q ^= q >> 31;
+                X0[(size_t)i * PMAX + j] = (double)(q >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+            }
+        PCHK(hipMemcpyAsync(dX.p, X0.data(), X0.size() * 8, hipMemcpyHostToDevice, st));
+    }
+    const int ngrid = (int)(((size_t)n_pad * PMAX + 255) / 256);
+    std::vector<double> YY(PMAX * PMAX), YX(PMAX * PMAX), theta;
+    bool converged = false;
+    for (int it = 0; it < 400 && !converged; ++it) {
+        PCHK(hipMemcpyAsync(dY.p, dX.p, (size_t)n_pad * PMAX * 8, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_band_solve, dim3(1), dim3(256), 0, st, dL.p, dLinv.p, nB, w, n_pad, dY.p, (const int*)nullptr);
+        hipLaunchKernelGGL(k_gram, dim3(PMAX), dim3(256), 0, st, dY.p, dY.p, n, dM.p);
+        PCHK(hipMemcpyAsync(YY.data(), dM.p, PMAX * PMAX * 8, hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(k_gram, dim3(PMAX), dim3(256), 0, st, dY.p, dX.p, n, dM.p);
+        PCHK(hipMemcpyAsync(YX.data(), dM.p, PMAX * PMAX * 8, hipMemcpyDeviceToHost, st));
+        PCHK(hipStreamSynchronize(st));
+        // Y = Q R (Cholesky QR); T = R^-T (Y^T X) R^-1 = Q^T H Q
+        std::vector<double> Rl = YY;  // lower factor Rl Rl^T = Y^T Y, R = Rl^T
+        if (!host_chol(Rl, PMAX)) return s->fail(JGS2_E_INVALID, "subspace iteration lost rank");
+        std::vector<double> Rinv(PMAX * PMAX, 0.0);  // inverse of upper R = Rl^T
+        for (int c = 0; c < PMAX; ++c) {             // solve Rl x = e_c -> column c of Rl^-1
+            std::vector<double> x(PMAX, 0.0);
+            for (int i = 0; i < PMAX; ++i) {
+                double v = (i == c) ? 1.0 : 0.0;
+                for (int k = 0; k < i; ++k) v -= Rl[(size_t)i * PMAX + k] * x[k];
+                x[i] = v / Rl[(size_t)i * PMAX + i];
+            }
+            for (int i = 0; i < PMAX; ++i) Rinv[(size_t)c * PMAX + i] = x[i];  // (Rl^-1)^T = R^-1
+        }
+        std::vector<double> T(PMAX * PMAX, 0.0), tmp(PMAX * PMAX, 0.0);
+        for (int i = 0; i < PMAX; ++i)  // tmp = (Y^T X) R^-1
+            for (int j = 0; j < PMAX; ++j) {
+                double v = 0.0;
+                for (int k = 0; k < PMAX; ++k) v += YX[(size_t)i * PMAX + k] * Rinv[(size_t)k * PMAX + j];
+                tmp[(size_t)i * PMAX + j] = v;
+            }
+        for (int i = 0; i < PMAX; ++i)  // T = R^-T tmp
+            for (int j = 0; j < PMAX; ++j) {
+                double v = 0.0;
+                for (int k = 0; k < PMAX; ++k) v += Rinv[(size_t)k * PMAX + i] * tmp[(size_t)k * PMAX + j];
+                T[(size_t)i * PMAX + j] = v;
+            }
+        for (int i = 0; i < PMAX; ++i)
+            for (int j = 0; j < i; ++j) {
+                const double m = 0.5 * (T[(size_t)i * PMAX + j] + T[(size_t)j * PMAX + i]);
+                T[(size_t)i * PMAX + j] = T[(size_t)j * PMAX + i] = m;
+            }
+        std::vector<double> Vr;
+        host_sym_eig(PMAX, T, theta, Vr);
+        // new basis Z = Y R^-1 V (orthonormal Ritz vectors), and H Z = X R^-1 V
+        std::vector<double> M(PMAX * PMAX);
+        for (int i = 0; i < PMAX; ++i)
+            for (int j = 0; j < PMAX; ++j) {
+                double v = 0.0;
+                for (int k = 0; k < PMAX; ++k) v += Rinv[(size_t)i * PMAX + k] * Vr[(size_t)k * PMAX + j];
+                M[(size_t)i * PMAX + j] = v;
+            }
+        PCHK(hipMemcpyAsync(dM.p, M.data(), PMAX * PMAX * 8, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_apply64, dim3(ngrid), dim3(256), 0, st, dX.p, dM.p, n_pad, dT.p);  // H Z
+        hipLaunchKernelGGL(k_apply64, dim3(ngrid), dim3(256), 0, st, dY.p, dM.p, n_pad, dX.p);  // Z
+        // residuals |H z - theta z| for the wanted pairs
+        hipLaunchKernelGGL(k_gram, dim3(PMAX), dim3(256), 0, st, dT.p, dT.p, n, dM.p);
+        std::vector<double> HH(PMAX * PMAX), ZH(PMAX * PMAX);
+        PCHK(hipMemcpyAsync(HH.data(), dM.p, PMAX * PMAX * 8, hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(k_gram, dim3(PMAX), dim3(256), 0, st, dX.p, dT.p, n, dM.p);
+        PCHK(hipMemcpyAsync(ZH.data(), dM.p, PMAX * PMAX * 8, hipMemcpyDeviceToHost, st));
+        PCHK(hipStreamSynchronize(st));
+        double worst = 0.0;
+        for (int k = 0; k < nwant; ++k) {
+            // |Hz|^2 - 2 theta z.Hz + theta^2 (|z| = 1)
+            const double r2 = HH[(size_t)k * PMAX + k] - 2 * theta[k] * ZH[(size_t)k * PMAX + k] + theta[k] * theta[k];
+            worst = std::max(worst, std::sqrt(std::max(r2, 0.0)) / theta[k]);
+        }
+        converged = worst < 1e-10;
+    }
+    if (!converged) return s->fail(JGS2_E_INVALID, "training-pose eigen-solve did not converge");
+    // gap cut and clusters (same rule as the reading of Sec. 5)
+    int nTp = std::min(NTMAX, nwant);
+    for (int m = 8; m <= std::min(NTMAX, nwant - 1); ++m)
+        if (theta[m] / theta[m - 1] > 1.0 + 1e-3) { nTp = m; break; }
+    std::vector<int> cid(nTp, 0);
+    for (int t = 1; t < nTp; ++t) cid[t] = cid[t - 1] + (theta[t] / theta[t - 1] > 1.0 + 1e-3 ? 1 : 0);
+    s->n_poses = nTp;
+    s->pose_eigs.assign(theta.begin(), theta.begin() + std::min(nwant, (int)theta.size()));
+    // G[t][dof] = lambda_t z_t (transpose of the first nTp columns of Z)
+    DevBuf<double> dG, dlam;
+    DevBuf<int> dcid;
+    if ((r = dG.alloc(s, (size_t)nTp * n_pad)) || (r = dlam.alloc(s, nTp)) || (r = dcid.alloc(s, nTp))) return r;
+    {
+        std::vector<double> Z((size_t)n_pad * PMAX), G((size_t)nTp * n_pad);
+        PCHK(hipMemcpyAsync(Z.data(), dX.p, Z.size() * 8, hipMemcpyDeviceToHost, st));
+        PCHK(hipStreamSynchronize(st));
+        for (int t = 0; t < nTp; ++t)
+            for (int i = 0; i < n_pad; ++i) G[(size_t)t * n_pad + i] = theta[t] * Z[(size_t)i * PMAX + t];
+        PCHK(hipMemcpyAsync(dG.p, G.data(), G.size() * 8, hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(dlam.p, theta.data(), nTp * 8, hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(dcid.p, cid.data(), nTp * 4, hipMemcpyHostToDevice, st));
+    }
+    dX.release(); dY.release(); dT.release();
+    // --- tables ---
+    int nfree_el = 0;
+    for (int t = 0; t < nT; ++t) {
+        bool any = false;
+        for (int c = 0; c < 4; ++c) any = any || !s->pinned[s->tets[4 * t + c]];
+        nfree_el += any;
+    }
+    const size_t nf = nVf, K = s->K;
+    if ((r = alloc_tables(s, S))) return r;
+    DevBuf<int> dtets, dfidx, dperm, diperm, dval;
+    DevBuf<double> dfit;
+    if ((r = dtets.alloc(s, 4 * (size_t)nT)) || (r = dfidx.alloc(s, nV)) || (r = dperm.alloc(s, nVf)) ||
+        (r = diperm.alloc(s, nVf)) || (r = dval.alloc(s, nV)) || (r = dfit.alloc(s, nVf)))
+        return r;
+    PCHK(hipMemcpyAsync(dtets.p, s->tets.data(), 4 * (size_t)nT * 4, hipMemcpyHostToDevice, st));
+    PCHK(hipMemcpyAsync(dfidx.p, s->free_index.data(), nV * 4, hipMemcpyHostToDevice, st));
+    PCHK(hipMemcpyAsync(dperm.p, perm.data(), nVf * 4, hipMemcpyHostToDevice, st));
+    PCHK(hipMemcpyAsync(diperm.p, iperm.data(), nVf * 4, hipMemcpyHostToDevice, st));
+    PCHK(hipMemcpyAsync(dval.p, s->valence.data(), nV * 4, hipMemcpyHostToDevice, st));
+    // chunks of vertices in permuted order; W for a chunk is nbatch x [n_pad][64]
+    const size_t budget = (size_t)24 << 30;  // bytes of solved columns per chunk
+    int chunk_batches = (int)std::max<size_t>(1, budget / ((size_t)n_pad * NB * 8));
+    chunk_batches = std::min(chunk_batches, (nVf + VPBATCH - 1) / VPBATCH);
+    DevBuf<double> dW;
+    DevBuf<int> dfirst;
+    if ((r = dW.alloc(s, (size_t)chunk_batches * n_pad * NB)) || (r = dfirst.alloc(s, chunk_batches))) return r;
+    CubArgs ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.nV = nV; ca.nVf = nVf; ca.nT = nT; ca.n_pad = n_pad; ca.nTp = nTp; ca.S = S; ca.n_cand = n_cand;
+    ca.K = s->K; ca.maxi = s->maxi; ca.E_free = nfree_el; ca.seed = seed;
+    ca.tets = dtets.p; ca.free_ids = s->d_free; ca.free_index = dfidx.p; ca.perm = dperm.p; ca.iperm = diperm.p;
+    ca.valence = dval.p; ca.ring = s->d_ring; ca.ring_n = s->d_ring_n; ca.inc = s->d_inc; ca.inc_n = s->d_inc_n;
+    ca.W = dW.p; ca.G = dG.p; ca.lam = dlam.p; ca.cid = dcid.p;
+    ca.Uring = s->d_Uring; ca.samp_e = s->d_samp_e; ca.samp = s->d_samp; ca.fit = dfit.p;
+    for (int p0 = 0; p0 < nVf; p0 += chunk_batches * VPBATCH) {
+        const int nvert = std::min(chunk_batches * VPBATCH, nVf - p0);
+        const int nbatch = (nvert + VPBATCH - 1) / VPBATCH;
+        std::vector<int> first(nbatch);
+        for (int b = 0; b < nbatch; ++b) first[b] = (3 * (p0 + b * VPBATCH)) / NB;
+        PCHK(hipMemcpyAsync(dfirst.p, first.data(), nbatch * 4, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_unit_rhs, dim3(4096), dim3(256), 0, st, dW.p, n_pad, p0, nvert, nbatch);
+        hipLaunchKernelGGL(k_band_solve, dim3(nbatch), dim3(256), 0, st, dL.p, dLinv.p, nB, w, n_pad, dW.p, dfirst.p);
+        ca.p0 = p0;
+        ca.n_vert = nvert;
+        hipLaunchKernelGGL(k_cubature, dim3(nvert), dim3(64), 0, st, ca);
+        PCHK(hipGetLastError());
+        PCHK(hipStreamSynchronize(st));
+    }
+    s->fit.resize(nVf);
+    PCHK(hipMemcpyAsync(s->fit.data(), dfit.p, nVf * 8, hipMemcpyDeviceToHost, st));
+    PCHK(hipStreamSynchronize(st));
+    s->S = S;
+    s->have_corr = true;
+    (void)nf; (void)K;
+    return JGS2_OK;
+}
+
 }  // namespace jgs2

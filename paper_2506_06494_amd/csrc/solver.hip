@@ -49,6 +49,28 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
 
 using namespace jgs2;
 
+namespace jgs2 {
+// Device correction tables for S samples per free vertex (zero-filled).
+int alloc_tables(jgs2_solver* s, int S) {
+    const size_t nf = s->nVf, K = s->K;
+    const size_t Sd = S > 0 ? S : 1;
+    for (void** p : {(void**)&s->d_Uring, (void**)&s->d_samp_e, (void**)&s->d_samp}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    int r;
+    if ((r = hip_check(s, hipMalloc((void**)&s->d_Uring, nf * 9 * K * sizeof(float)), "hipMalloc tables")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_samp_e, nf * Sd * sizeof(int)), "hipMalloc tables")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_samp, nf * SREC * Sd * sizeof(float)), "hipMalloc tables")))
+        return r;
+    if ((r = hip_check(s, hipMemsetAsync(s->d_Uring, 0, nf * 9 * K * sizeof(float), s->stream), "memset")) ||
+        (r = hip_check(s, hipMemsetAsync(s->d_samp_e, 0xFF, nf * Sd * sizeof(int), s->stream), "memset")) ||
+        (r = hip_check(s, hipMemsetAsync(s->d_samp, 0, nf * SREC * Sd * sizeof(float), s->stream), "memset")))
+        return r;
+    return JGS2_OK;
+}
+}  // namespace jgs2
+
 #define HIPCHK(expr)                                               \
     do {                                                           \
         int _r = jgs2::hip_check(s, (expr), #expr);                \
@@ -417,9 +439,7 @@ int32_t jgs2_import_correction(jgs2_solver* s, int32_t S, const double* U_ring, 
         }
     }
     int r;
-    if ((r = dalloc(s, s->d_Uring, Ur.size())) || (r = dalloc(s, s->d_samp_e, se.size())) ||
-        (r = dalloc(s, s->d_samp, sr.size())))
-        return r;
+    if ((r = alloc_tables(s, S))) return r;
     if ((r = upload(s, s->d_Uring, Ur.data(), Ur.size())) || (r = upload(s, s->d_samp_e, se.data(), se.size())) ||
         (r = upload(s, s->d_samp, sr.data(), sr.size())))
         return r;
