@@ -174,6 +174,24 @@ int32_t jgs2_get_phase1(jgs2_solver* s, double* g, double* R);
 /* Greedy colour per vertex (-1 for pinned) and the colour count. */
 int32_t jgs2_get_coloring(jgs2_solver* s, int32_t* color, int32_t* n_colors);
 
+/* Per-kernel device timing with HIP events on the handle's stream.  While
+ * profiling is on, every launch of a library kernel is bracketed by an event
+ * pair; jgs2_kernel_times() returns, per kernel id below, the accumulated
+ * milliseconds and launch counts since profiling was (re)enabled.  ms and
+ * launches point to JGS2_NKERNELS entries each.  Profiling adds a small gap
+ * between launches, not to the kernels themselves. */
+#define JGS2_K_PHASE1    0   /* gradient, rotations, |g|^2 partials */
+#define JGS2_K_PHASE2    1   /* cubature-corrected local solves */
+#define JGS2_K_PLAIN     2   /* plain per-vertex Newton, fused */
+#define JGS2_K_COMMIT    3
+#define JGS2_K_REDUCE    4
+#define JGS2_K_PREDICT   5
+#define JGS2_K_VELOCITY  6
+#define JGS2_K_ENERGY    7
+#define JGS2_NKERNELS    8
+int32_t jgs2_set_profiling(jgs2_solver* s, int32_t on);
+int32_t jgs2_kernel_times(jgs2_solver* s, double* ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -98,6 +98,13 @@ struct jgs2_solver {
     double* d_red = nullptr;
     int n_partial = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // per-kernel event timing
+    bool prof = false;
+    double kt_ms[JGS2_NKERNELS] = {};
+    int64_t kt_n[JGS2_NKERNELS] = {};
+    struct Pending { int k; hipEvent_t a, b; };
+    std::vector<Pending> kt_pending;
+    std::vector<hipEvent_t> ev_pool;
 
     int fail(int code, const std::string& msg) {
         err = msg;
@@ -120,4 +127,5 @@ void launch_velocity(jgs2_solver* s, float h);
 void launch_energy(jgs2_solver* s, const SweepArgs& a, int nT);
 int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed);
 int alloc_tables(jgs2_solver* s, int S);
+void prof_collect(jgs2_solver* s);
 }  // namespace jgs2

@@ -68,6 +68,52 @@ template <typename T> JGS2_HD void snh_dstress(const T* F, const T* C, T J, T vm
     for (int i = 0; i < 9; ++i) dP[i] = vmu * D[i] + l * C[i] + k * dC[i];
 }
 
+// The same quantities from the displacement gradient H = F - I without the
+// O(mu) cancellation of F - cof F at small strain (needed in FP32):
+//   cof(I + H) = I + tr(H) I - H^T + cof(H)
+//   J - 1      = tr(H) + tr(cof H) + det(H)
+//   V P        = V mu (H + H^T - tr(H) I - cof H) + V lam (J - 1) cof(F)
+//   V Psi      = V mu/2 |H|^2 - V mu (tr(cof H) + det H) + V lam/2 (J - 1)^2
+template <typename T> struct Kin {
+    T F[9], C[9];  // F = I + H and cof F
+    T Jm1;         // J - 1
+};
+
+template <typename T> JGS2_HD void kinematics(const T* H, Kin<T>& k, T* cofH) {
+    cof3(H, cofH);
+    const T trH = H[0] + H[4] + H[8];
+    const T i2 = cofH[0] + cofH[4] + cofH[8];
+    k.Jm1 = trH + i2 + det3(H);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const T d = (i == j) ? T(1) : T(0);
+            k.F[3 * i + j] = d + H[3 * i + j];
+            k.C[3 * i + j] = d + d * trH - H[3 * j + i] + cofH[3 * i + j];
+        }
+}
+
+template <typename T> JGS2_HD void snh_stress_H(const T* H, const Kin<T>& k, const T* cofH, T vmu, T vlam, T* P) {
+    const T trH = H[0] + H[4] + H[8];
+    const T l = vlam * k.Jm1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const T d = (i == j) ? trH : T(0);
+            P[3 * i + j] = vmu * (H[3 * i + j] + H[3 * j + i] - d - cofH[3 * i + j]) + l * k.C[3 * i + j];
+        }
+}
+
+template <typename T> JGS2_HD T snh_psi_H(const T* H, const Kin<T>& k, const T* cofH, T vmu, T vlam) {
+    T H2 = T(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) H2 += H[i] * H[i];
+    const T i2 = cofH[0] + cofH[4] + cofH[8];
+    return T(0.5) * vmu * H2 - vmu * (i2 + det3(H)) + T(0.5) * vlam * k.Jm1 * k.Jm1;
+}
+
 template <typename T> JGS2_HD T snh_psi(const T* F, T J, T vmu, T vlam) {
     T I2 = T(0);
 #pragma unroll

@@ -18,7 +18,10 @@
 //      NNLS cubature over counter-based SplitMix64 candidates, packed FP32
 //      tables.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <queue>
 
@@ -291,6 +294,18 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, cons
     }
 }
 
+// mode 0: out = A M, 1: out -= A M, 2: out += A M
+__global__ void k_apply64m(const double* __restrict__ A, const double* __restrict__ M, int n, double* __restrict__ out,
+                           int mode) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)n * PMAX) return;
+    const size_t r = e / PMAX;
+    const int j = (int)(e % PMAX);
+    double s = 0.0;
+    for (int k = 0; k < PMAX; ++k) s += A[r * PMAX + k] * M[k * PMAX + j];
+    out[e] = mode == 0 ? s : (mode == 1 ? out[e] - s : out[e] + s);
+}
+
 // out = A M (A: [n][64], M: 64x64 row-major)
 __global__ void k_apply64(const double* __restrict__ A, const double* __restrict__ M, int n, double* __restrict__ out) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -300,6 +315,26 @@ __global__ void k_apply64(const double* __restrict__ A, const double* __restrict
     double s = 0.0;
     for (int k = 0; k < PMAX; ++k) s += A[r * PMAX + k] * M[k * PMAX + j];
     out[e] = s;
+}
+
+// Column norms of HZ - theta Z for the first `nw` columns (one block each).
+__global__ __launch_bounds__(256) void k_ritz_resid(const double* __restrict__ HZ, const double* __restrict__ Z,
+                                                    const double* __restrict__ theta, int n, double* __restrict__ out) {
+    const int k = blockIdx.x;
+    __shared__ double s[256];
+    double acc = 0.0;
+    const double th = theta[k];
+    for (int r = threadIdx.x; r < n; r += 256) {
+        const double d = HZ[(size_t)r * PMAX + k] - th * Z[(size_t)r * PMAX + k];
+        acc += d * d;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = sqrt(s[0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -837,7 +872,18 @@ static bool host_chol(std::vector<double>& A, int n) {
     return true;
 }
 
+// Stage log on stderr when JGS2_VERBOSE is set (precompute of large meshes
+// takes seconds to minutes).
+static void stage(const char* what, std::chrono::steady_clock::time_point t0) {
+    static const bool on = std::getenv("JGS2_VERBOSE") != nullptr;
+    if (!on) return;
+    const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    std::fprintf(stderr, "[jgs2] precompute %-28s %8.2f s\n", what, s);
+    std::fflush(stderr);
+}
+
 int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
+    const auto t_start = std::chrono::steady_clock::now();
     const int nVf = s->nVf, nT = s->nT, nV = s->nV;
     if (3 * nVf < 2 * PMAX) return s->fail(JGS2_E_INVALID, "precompute needs at least 43 free vertices");
     hipStream_t st = s->stream;
@@ -875,6 +921,7 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
         PCHK(hipMemcpyAsync(He.data(), dHe.p, He.size() * 8, hipMemcpyDeviceToHost, st));
         PCHK(hipStreamSynchronize(st));
     }
+    stage("element Hessians", t_start);
     // --- band width and assembly (lower triangle, permuted DOFs) ---
     auto dof = [&](int vtx, int c) { return 3 * iperm[s->free_index[vtx]] + c; };
     int w = 0;
@@ -916,6 +963,7 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
     PCHK(hipMemsetAsync(dflag.p, 0, sizeof(int), st));
     Lh.clear();
     Lh.shrink_to_fit();
+    stage("band assembly", t_start);
     // --- factorisation ---
     const int nupd = w * (w + 1) / 2;
     for (int J = 0; J < nB; ++J) {
@@ -931,15 +979,60 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
     PCHK(hipMemcpyAsync(&flag, dflag.p, sizeof(int), hipMemcpyDeviceToHost, st));
     PCHK(hipStreamSynchronize(st));
     if (flag) return s->fail(JGS2_E_INVALID, "rest Hessian is not positive definite");
-    // --- training poses: block inverse subspace iteration ---
+    stage("band Cholesky", t_start);
+    // --- training poses: restarted block Krylov Rayleigh-Ritz on H-bar^-1 ---
+    // Basis Q = [Q_0 .. Q_{m-1}] of span{X, H^-1 X, ..., H^-(m-1) X} (block
+    // Gram-Schmidt, two passes), W_j = H^-1 Q_j, projected T = Q^T H^-1 Q with
+    // blocks Q_i^T W_j; the largest Ritz values mu of H^-1 give lambda = 1/mu.
     const int nwant = std::min(NTMAX + 1, n - 1);
-    std::vector<double> lam_all;
-    DevBuf<double> dX, dY, dM, dT;
-    if ((r = dX.alloc(s, (size_t)n_pad * PMAX)) || (r = dY.alloc(s, (size_t)n_pad * PMAX)) ||
-        (r = dM.alloc(s, PMAX * PMAX)) || (r = dT.alloc(s, (size_t)n_pad * PMAX)))
+    const int MB = 4;                  // Krylov blocks per restart
+    const int MD = MB * PMAX;          // projected dimension
+    const size_t blk = (size_t)n_pad * PMAX;
+    DevBuf<double> dQ, dKW, dV, dM, dZ, dHZ;
+    if ((r = dQ.alloc(s, (size_t)MB * blk)) || (r = dKW.alloc(s, (size_t)MB * blk)) || (r = dV.alloc(s, blk)) ||
+        (r = dM.alloc(s, PMAX * PMAX + 2 * PMAX)) || (r = dZ.alloc(s, blk)) || (r = dHZ.alloc(s, blk)))
         return r;
+    const int ngrid = (int)((blk + 255) / 256);
+    std::vector<double> theta;        // eigenvalues of H-bar (ascending), from Ritz values
+    auto gram = [&](const double* A, const double* B, std::vector<double>& out) -> int {
+        hipLaunchKernelGGL(k_gram, dim3(PMAX), dim3(256), 0, st, A, B, n, dM.p);
+        out.resize(PMAX * PMAX);
+        PCHK(hipMemcpyAsync(out.data(), dM.p, PMAX * PMAX * 8, hipMemcpyDeviceToHost, st));
+        PCHK(hipStreamSynchronize(st));
+        return JGS2_OK;
+    };
+    auto apply = [&](const double* A, const std::vector<double>& Mh, double* out, int mode) -> int {
+        // mode 0: out = A M ; mode 1: out -= A M ; mode 2: out += A M
+        PCHK(hipMemcpyAsync(dM.p, Mh.data(), PMAX * PMAX * 8, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_apply64m, dim3(ngrid), dim3(256), 0, st, A, dM.p, n_pad, out, mode);
+        return jgs2::hip_check(s, hipGetLastError(), "apply");
+    };
+    // orthonormalise the block at V in place (Cholesky QR) -> writes Q block
+    auto orth_into = [&](double* V, double* Qout) -> int {
+        std::vector<double> G;
+        int rr;
+        for (int pass = 0; pass < 2; ++pass) {
+            if ((rr = gram(V, V, G))) return rr;
+            std::vector<double> Rl = G;
+            if (!host_chol(Rl, PMAX)) return s->fail(JGS2_E_INVALID, "Krylov block lost rank");
+            std::vector<double> Rinv(PMAX * PMAX, 0.0);
+            for (int c = 0; c < PMAX; ++c) {
+                std::vector<double> x(PMAX, 0.0);
+                for (int i = 0; i < PMAX; ++i) {
+                    double v = (i == c) ? 1.0 : 0.0;
+                    for (int k = 0; k < i; ++k) v -= Rl[(size_t)i * PMAX + k] * x[k];
+                    x[i] = v / Rl[(size_t)i * PMAX + i];
+                }
+                for (int i = 0; i < PMAX; ++i) Rinv[(size_t)c * PMAX + i] = x[i];
+            }
+            double* dst = pass == 1 ? Qout : dHZ.p;
+            if ((rr = apply(V, Rinv, dst, 0))) return rr;
+            if (pass == 0) PCHK(hipMemcpyAsync(V, dHZ.p, blk * 8, hipMemcpyDeviceToDevice, st));
+        }
+        return JGS2_OK;
+    };
     {
-        std::vector<double> X0((size_t)n_pad * PMAX, 0.0);
+        std::vector<double> X0(blk, 0.0);
         uint64_t z = seed ^ 0x5EEDF00DULL;
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < PMAX; ++j) {
@@ -950,79 +1043,77 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
                 q ^= q >> 31;
                 X0[(size_t)i * PMAX + j] = (double)(q >> 11) * (1.0 / 9007199254740992.0) - 0.5;
             }
-        PCHK(hipMemcpyAsync(dX.p, X0.data(), X0.size() * 8, hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(dV.p, X0.data(), blk * 8, hipMemcpyHostToDevice, st));
+        if ((r = orth_into(dV.p, dQ.p))) return r;
     }
-    const int ngrid = (int)(((size_t)n_pad * PMAX + 255) / 256);
-    std::vector<double> YY(PMAX * PMAX), YX(PMAX * PMAX), theta;
     bool converged = false;
-    for (int it = 0; it < 400 && !converged; ++it) {
-        PCHK(hipMemcpyAsync(dY.p, dX.p, (size_t)n_pad * PMAX * 8, hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL(k_band_solve, dim3(1), dim3(256), 0, st, dL.p, dLinv.p, nB, w, n_pad, dY.p, (const int*)nullptr);
-        hipLaunchKernelGGL(k_gram, dim3(PMAX), dim3(256), 0, st, dY.p, dY.p, n, dM.p);
-        PCHK(hipMemcpyAsync(YY.data(), dM.p, PMAX * PMAX * 8, hipMemcpyDeviceToHost, st));
-        hipLaunchKernelGGL(k_gram, dim3(PMAX), dim3(256), 0, st, dY.p, dX.p, n, dM.p);
-        PCHK(hipMemcpyAsync(YX.data(), dM.p, PMAX * PMAX * 8, hipMemcpyDeviceToHost, st));
-        PCHK(hipStreamSynchronize(st));
-        // Y = Q R (Cholesky QR); T = R^-T (Y^T X) R^-1 = Q^T H Q
-        std::vector<double> Rl = YY;  // lower factor Rl Rl^T = Y^T Y, R = Rl^T
-        if (!host_chol(Rl, PMAX)) return s->fail(JGS2_E_INVALID, "subspace iteration lost rank");
-        std::vector<double> Rinv(PMAX * PMAX, 0.0);  // inverse of upper R = Rl^T
-        for (int c = 0; c < PMAX; ++c) {             // solve Rl x = e_c -> column c of Rl^-1
-            std::vector<double> x(PMAX, 0.0);
-            for (int i = 0; i < PMAX; ++i) {
-                double v = (i == c) ? 1.0 : 0.0;
-                for (int k = 0; k < i; ++k) v -= Rl[(size_t)i * PMAX + k] * x[k];
-                x[i] = v / Rl[(size_t)i * PMAX + i];
+    for (int restart = 0; restart < 40 && !converged; ++restart) {
+        for (int j = 0; j < MB; ++j) {
+            double* Qj = dQ.p + (size_t)j * blk;
+            double* Wj = dKW.p + (size_t)j * blk;
+            PCHK(hipMemcpyAsync(Wj, Qj, blk * 8, hipMemcpyDeviceToDevice, st));
+            hipLaunchKernelGGL(k_band_solve, dim3(1), dim3(256), 0, st, dL.p, dLinv.p, nB, w, n_pad, Wj,
+                               (const int*)nullptr);
+            PCHK(hipGetLastError());
+            if (j + 1 < MB) {
+                PCHK(hipMemcpyAsync(dV.p, Wj, blk * 8, hipMemcpyDeviceToDevice, st));
+                for (int pass = 0; pass < 2; ++pass)
+                    for (int i = 0; i <= j; ++i) {
+                        std::vector<double> C;
+                        if ((r = gram(dQ.p + (size_t)i * blk, dV.p, C))) return r;
+                        if ((r = apply(dQ.p + (size_t)i * blk, C, dV.p, 1))) return r;
+                    }
+                if ((r = orth_into(dV.p, dQ.p + (size_t)(j + 1) * blk))) return r;
             }
-            for (int i = 0; i < PMAX; ++i) Rinv[(size_t)c * PMAX + i] = x[i];  // (Rl^-1)^T = R^-1
         }
-        std::vector<double> T(PMAX * PMAX, 0.0), tmp(PMAX * PMAX, 0.0);
-        for (int i = 0; i < PMAX; ++i)  // tmp = (Y^T X) R^-1
-            for (int j = 0; j < PMAX; ++j) {
-                double v = 0.0;
-                for (int k = 0; k < PMAX; ++k) v += YX[(size_t)i * PMAX + k] * Rinv[(size_t)k * PMAX + j];
-                tmp[(size_t)i * PMAX + j] = v;
+        // projected matrix
+        std::vector<double> T((size_t)MD * MD);
+        for (int i = 0; i < MB; ++i)
+            for (int j = 0; j < MB; ++j) {
+                std::vector<double> C;
+                if ((r = gram(dQ.p + (size_t)i * blk, dKW.p + (size_t)j * blk, C))) return r;
+                for (int a = 0; a < PMAX; ++a)
+                    for (int b = 0; b < PMAX; ++b) T[(size_t)(i * PMAX + a) * MD + j * PMAX + b] = C[(size_t)a * PMAX + b];
             }
-        for (int i = 0; i < PMAX; ++i)  // T = R^-T tmp
-            for (int j = 0; j < PMAX; ++j) {
-                double v = 0.0;
-                for (int k = 0; k < PMAX; ++k) v += Rinv[(size_t)k * PMAX + i] * tmp[(size_t)k * PMAX + j];
-                T[(size_t)i * PMAX + j] = v;
-            }
-        for (int i = 0; i < PMAX; ++i)
+        for (int i = 0; i < MD; ++i)
             for (int j = 0; j < i; ++j) {
-                const double m = 0.5 * (T[(size_t)i * PMAX + j] + T[(size_t)j * PMAX + i]);
-                T[(size_t)i * PMAX + j] = T[(size_t)j * PMAX + i] = m;
+                const double m = 0.5 * (T[(size_t)i * MD + j] + T[(size_t)j * MD + i]);
+                T[(size_t)i * MD + j] = T[(size_t)j * MD + i] = m;
             }
-        std::vector<double> Vr;
-        host_sym_eig(PMAX, T, theta, Vr);
-        // new basis Z = Y R^-1 V (orthonormal Ritz vectors), and H Z = X R^-1 V
-        std::vector<double> M(PMAX * PMAX);
-        for (int i = 0; i < PMAX; ++i)
-            for (int j = 0; j < PMAX; ++j) {
-                double v = 0.0;
-                for (int k = 0; k < PMAX; ++k) v += Rinv[(size_t)i * PMAX + k] * Vr[(size_t)k * PMAX + j];
-                M[(size_t)i * PMAX + j] = v;
-            }
-        PCHK(hipMemcpyAsync(dM.p, M.data(), PMAX * PMAX * 8, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_apply64, dim3(ngrid), dim3(256), 0, st, dX.p, dM.p, n_pad, dT.p);  // H Z
-        hipLaunchKernelGGL(k_apply64, dim3(ngrid), dim3(256), 0, st, dY.p, dM.p, n_pad, dX.p);  // Z
-        // residuals |H z - theta z| for the wanted pairs
-        hipLaunchKernelGGL(k_gram, dim3(PMAX), dim3(256), 0, st, dT.p, dT.p, n, dM.p);
-        std::vector<double> HH(PMAX * PMAX), ZH(PMAX * PMAX);
-        PCHK(hipMemcpyAsync(HH.data(), dM.p, PMAX * PMAX * 8, hipMemcpyDeviceToHost, st));
-        hipLaunchKernelGGL(k_gram, dim3(PMAX), dim3(256), 0, st, dX.p, dT.p, n, dM.p);
-        PCHK(hipMemcpyAsync(ZH.data(), dM.p, PMAX * PMAX * 8, hipMemcpyDeviceToHost, st));
+        std::vector<double> mu, Y;
+        host_sym_eig(MD, T, mu, Y);            // ascending mu; take the largest PMAX
+        // Ritz vectors Z = Q Y_top, H^-1 Z = W Y_top (columns in descending mu)
+        std::vector<double> mu_top(PMAX);
+        PCHK(hipMemsetAsync(dZ.p, 0, blk * 8, st));
+        PCHK(hipMemsetAsync(dHZ.p, 0, blk * 8, st));
+        for (int i = 0; i < MB; ++i) {
+            std::vector<double> Yi(PMAX * PMAX);
+            for (int a = 0; a < PMAX; ++a)
+                for (int c = 0; c < PMAX; ++c) Yi[(size_t)a * PMAX + c] = Y[(size_t)(i * PMAX + a) * MD + (MD - 1 - c)];
+            if ((r = apply(dQ.p + (size_t)i * blk, Yi, dZ.p, 2))) return r;
+            if ((r = apply(dKW.p + (size_t)i * blk, Yi, dHZ.p, 2))) return r;
+        }
+        for (int c = 0; c < PMAX; ++c) mu_top[c] = mu[MD - 1 - c];
+        PCHK(hipMemcpyAsync(dM.p + PMAX * PMAX, mu_top.data(), PMAX * 8, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_ritz_resid, dim3(nwant), dim3(256), 0, st, dHZ.p, dZ.p, dM.p + PMAX * PMAX, n,
+                           dM.p + PMAX * PMAX + PMAX);
+        std::vector<double> rn(nwant);
+        PCHK(hipMemcpyAsync(rn.data(), dM.p + PMAX * PMAX + PMAX, nwant * 8, hipMemcpyDeviceToHost, st));
         PCHK(hipStreamSynchronize(st));
         double worst = 0.0;
-        for (int k = 0; k < nwant; ++k) {
-            // |Hz|^2 - 2 theta z.Hz + theta^2 (|z| = 1)
-            const double r2 = HH[(size_t)k * PMAX + k] - 2 * theta[k] * ZH[(size_t)k * PMAX + k] + theta[k] * theta[k];
-            worst = std::max(worst, std::sqrt(std::max(r2, 0.0)) / theta[k]);
-        }
+        for (int k = 0; k < nwant; ++k) worst = std::max(worst, rn[k] / mu_top[k]);
+        theta.resize(PMAX);
+        for (int c = 0; c < PMAX; ++c) theta[c] = 1.0 / mu_top[c];
         converged = worst < 1e-10;
+        stage(converged ? "eigen restart (converged)" : "eigen restart", t_start);
+        if (!converged) {  // restart from the current Ritz block
+            PCHK(hipMemcpyAsync(dV.p, dZ.p, blk * 8, hipMemcpyDeviceToDevice, st));
+            if ((r = orth_into(dV.p, dQ.p))) return r;
+        }
     }
     if (!converged) return s->fail(JGS2_E_INVALID, "training-pose eigen-solve did not converge");
+    // Ritz vectors of the converged pairs are the columns of dZ
+    DevBuf<double>& dX = dZ;
     // gap cut and clusters (same rule as the reading of Sec. 5)
     int nTp = std::min(NTMAX, nwant);
     for (int m = 8; m <= std::min(NTMAX, nwant - 1); ++m)
@@ -1045,7 +1136,7 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
         PCHK(hipMemcpyAsync(dlam.p, theta.data(), nTp * 8, hipMemcpyHostToDevice, st));
         PCHK(hipMemcpyAsync(dcid.p, cid.data(), nTp * 4, hipMemcpyHostToDevice, st));
     }
-    dX.release(); dY.release(); dT.release();
+    dQ.release(); dKW.release(); dV.release(); dHZ.release();
     // --- tables ---
     int nfree_el = 0;
     for (int t = 0; t < nT; ++t) {
@@ -1093,6 +1184,7 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
         hipLaunchKernelGGL(k_cubature, dim3(nvert), dim3(64), 0, st, ca);
         PCHK(hipGetLastError());
         PCHK(hipStreamSynchronize(st));
+        stage("vertex chunk", t_start);
     }
     s->fit.resize(nVf);
     PCHK(hipMemcpyAsync(s->fit.data(), dfit.p, nVf * 8, hipMemcpyDeviceToHost, st));

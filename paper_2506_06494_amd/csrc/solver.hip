@@ -50,6 +50,47 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
 using namespace jgs2;
 
 namespace jgs2 {
+static hipEvent_t pool_event(jgs2_solver* s) {
+    if (!s->ev_pool.empty()) {
+        hipEvent_t e = s->ev_pool.back();
+        s->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// Accumulates finished event pairs (call after the stream is synchronised).
+void prof_collect(jgs2_solver* s) {
+    for (auto& p : s->kt_pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            s->kt_ms[p.k] += ms;
+            s->kt_n[p.k] += 1;
+        }
+        s->ev_pool.push_back(p.a);
+        s->ev_pool.push_back(p.b);
+    }
+    s->kt_pending.clear();
+}
+}  // namespace jgs2
+
+// Runs `call` (a kernel launch) bracketed by an event pair when profiling.
+#define TIMED(s, kid, call)                                                  \
+    do {                                                                     \
+        if ((s)->prof) {                                                     \
+            jgs2_solver::Pending _p{(kid), jgs2::pool_event(s), jgs2::pool_event(s)}; \
+            (void)hipEventRecord(_p.a, (s)->stream);                         \
+            call;                                                            \
+            (void)hipEventRecord(_p.b, (s)->stream);                         \
+            (s)->kt_pending.push_back(_p);                                   \
+        } else {                                                             \
+            call;                                                            \
+        }                                                                    \
+    } while (0)
+
+namespace jgs2 {
 // Device correction tables for S samples per free vertex (zero-filled).
 int alloc_tables(jgs2_solver* s, int S) {
     const size_t nf = s->nVf, K = s->K;
@@ -180,6 +221,8 @@ void jgs2_destroy(jgs2_solver* s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
     free_device(s);
+    prof_collect(s);
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
     delete s;
@@ -532,17 +575,18 @@ int32_t jgs2_get_state(jgs2_solver* s, double* x, double* v) {
 }
 
 static int read_reduced(jgs2_solver* s, int n_partials, double* out) {
-    launch_reduce(s, n_partials);
+    TIMED(s, JGS2_K_REDUCE, launch_reduce(s, n_partials));
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(out, s->d_red, sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    prof_collect(s);
     return JGS2_OK;
 }
 
 static int gradient_norm2(jgs2_solver* s, double* out) {
     SweepArgs a;
     build_sweep_args(s, a);
-    launch_phase1(s, a, s->p.variant == JGS2_CUBATURE);
+    TIMED(s, JGS2_K_PHASE1, launch_phase1(s, a, s->p.variant == JGS2_CUBATURE));
     s->phase1_valid = true;
     return read_reduced(s, (s->nVf + VPB - 1) / VPB, out);
 }
@@ -572,7 +616,7 @@ int32_t jgs2_begin_step(jgs2_solver* s) {
             }
         }
     }
-    launch_predict(s, (float)s->p.dt, grav);
+    TIMED(s, JGS2_K_PREDICT, launch_predict(s, (float)s->p.dt, grav));
     double g2 = 0;
     int r = gradient_norm2(s, &g2);
     if (r != JGS2_OK) return r;
@@ -595,10 +639,10 @@ static int sweep_once(jgs2_solver* s) {
     const bool cub = s->p.variant == JGS2_CUBATURE;
     if (s->p.order == JGS2_JACOBI) {
         if (cub) {
-            if (!s->phase1_valid) launch_phase1(s, a, true);
-            launch_phase2_cubature(s, a);
+            if (!s->phase1_valid) TIMED(s, JGS2_K_PHASE1, launch_phase1(s, a, true));
+            TIMED(s, JGS2_K_PHASE2, launch_phase2_cubature(s, a));
         } else {
-            launch_plain(s, a);
+            TIMED(s, JGS2_K_PLAIN, launch_plain(s, a));
         }
         swap_u(s);
     } else {
@@ -608,12 +652,12 @@ static int sweep_once(jgs2_solver* s) {
             ac.n_list = s->col_off[c + 1] - s->col_off[c];
             if (cub) {
                 SweepArgs all = a;
-                launch_phase1(s, all, true);
-                launch_phase2_cubature(s, ac);
-                launch_commit(s, ac);
+                TIMED(s, JGS2_K_PHASE1, launch_phase1(s, all, true));
+                TIMED(s, JGS2_K_PHASE2, launch_phase2_cubature(s, ac));
+                TIMED(s, JGS2_K_COMMIT, launch_commit(s, ac));
             } else {
                 ac.in_place = 1;
-                launch_plain(s, ac);
+                TIMED(s, JGS2_K_PLAIN, launch_plain(s, ac));
             }
         }
         s->phase1_valid = false;
@@ -643,7 +687,7 @@ int32_t jgs2_iterate(jgs2_solver* s, int32_t n_sweeps, double* rel_res) {
 int32_t jgs2_end_step(jgs2_solver* s) {
     if (!s) return JGS2_E_INVALID;
     if (!s->in_step) return s->fail(JGS2_E_NOT_READY, "end_step without begin_step");
-    launch_velocity(s, (float)s->p.dt);
+    TIMED(s, JGS2_K_VELOCITY, launch_velocity(s, (float)s->p.dt));
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(s->d_unext, s->d_u, 3 * (size_t)s->nV * 4, hipMemcpyDeviceToDevice, s->stream));
     s->in_step = false;
@@ -707,7 +751,7 @@ int32_t jgs2_energy(jgs2_solver* s, double* e) {
     if (!ready_to_step(s)) return JGS2_E_NOT_READY;
     SweepArgs a;
     build_sweep_args(s, a);
-    launch_energy(s, a, s->nT);
+    TIMED(s, JGS2_K_ENERGY, launch_energy(s, a, s->nT));
     return read_reduced(s, (std::max(s->nT, s->nVf) + 255) / 256, e);
 }
 
@@ -729,6 +773,26 @@ int32_t jgs2_get_phase1(jgs2_solver* s, double* g, double* R) {
             if (g) g[3 * v + i] = s->pinned[v] ? 0.0 : gg[i * nV + v];
         for (int i = 0; i < 9; ++i)
             if (R) R[9 * v + i] = s->pinned[v] ? ((i % 4 == 0) ? 1.0 : 0.0) : RR[i * nV + v];
+    }
+    return JGS2_OK;
+}
+
+int32_t jgs2_set_profiling(jgs2_solver* s, int32_t on) {
+    if (!s) return JGS2_E_INVALID;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    prof_collect(s);
+    s->prof = on != 0;
+    for (int k = 0; k < JGS2_NKERNELS; ++k) { s->kt_ms[k] = 0.0; s->kt_n[k] = 0; }
+    return JGS2_OK;
+}
+
+int32_t jgs2_kernel_times(jgs2_solver* s, double* ms, int64_t* launches) {
+    if (!s) return JGS2_E_INVALID;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    prof_collect(s);
+    for (int k = 0; k < JGS2_NKERNELS; ++k) {
+        if (ms) ms[k] = s->kt_ms[k];
+        if (launches) launches[k] = s->kt_n[k];
     }
     return JGS2_OK;
 }

@@ -10,7 +10,8 @@
 //
 // All arrays of vertices are SoA [component][vertex] in FP32; positions are
 // stored as displacements u = x - X from the rest shape, so that
-// F = I + sum_a u_a (grad N_a)^T keeps full FP32 precision in F - I.
+// H = F - I = sum_a u_a (grad N_a)^T keeps full FP32 precision, and the
+// stress is evaluated from H without cancelling O(mu) terms.
 #include "jgs2_internal.h"
 #include "jgs2_math.h"
 
@@ -55,8 +56,8 @@ __device__ __forceinline__ void gradN(const float* D, int c, float* gn) {
     }
 }
 
-// F = I + [u1-u0, u2-u0, u3-u0] Dm^-1
-__device__ __forceinline__ void defgrad(const float* __restrict__ u, int nV, const Tet& T, float* F) {
+// H = F - I = [u1-u0, u2-u0, u3-u0] Dm^-1 (displacement gradient)
+__device__ __forceinline__ void dispgrad(const float* __restrict__ u, int nV, const Tet& T, float* F) {
     float du[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -68,14 +69,14 @@ __device__ __forceinline__ void defgrad(const float* __restrict__ u, int nV, con
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            F[3 * i + j] = (i == j ? 1.0f : 0.0f) + du[0][i] * T.D[j] + du[1][i] * T.D[3 + j] + du[2][i] * T.D[6 + j];
+            F[3 * i + j] = du[0][i] * T.D[j] + du[1][i] * T.D[3 + j] + du[2][i] * T.D[6 + j];
 }
 
 // Adds w * (U_e^T H_e U_e) for the 12x3 basis U_e whose 3x3 row blocks are
 // Phi[b] (b = tet corner): three stress differentials dP[dF_d] with
 // dF_d = sum_b Phi_b[:, d] (grad N_b)^T, contracted with dF_e, plus the
 // element's inertia share mi * sum_b Phi_b^T Phi_b.
-__device__ __forceinline__ void galerkin_hessian(const Tet& T, const float* F, const float* C, float J,
+__device__ __forceinline__ void galerkin_hessian(const Tet& T, const Kin<float>& K,
                                                  const float (*Phi)[9], float w, float* A6) {
     float gn[4][3];
 #pragma unroll
@@ -93,7 +94,7 @@ __device__ __forceinline__ void galerkin_hessian(const Tet& T, const float* F, c
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         float dP[9];
-        snh_dstress(F, C, J, T.vmu, T.vlam, dF[d], dP);
+        snh_dstress(K.F, K.C, 1.0f + K.Jm1, T.vmu, T.vlam, dF[d], dP);
 #pragma unroll
         for (int e = d; e < 3; ++e) {
             float s = 0.0f, m = 0.0f;
@@ -157,16 +158,16 @@ __global__ __launch_bounds__(BLOCK) void k_phase1(SweepArgs a, int want_R) {
             const int t = pk >> 2, c = pk & 3;
             Tet T;
             load_tet(a.tet, t, T);
-            float F[9], C[9], P[9], gn[3];
-            defgrad(a.u, a.nV, T, F);
-            cof3(F, C);
-            const float J = F[0] * C[0] + F[3] * C[3] + F[6] * C[6];
-            snh_stress(F, C, J, T.vmu, T.vlam, P);
+            float H[9], cH[9], P[9], gn[3];
+            Kin<float> K;
+            dispgrad(a.u, a.nV, T, H);
+            kinematics(H, K, cH);
+            snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
             gradN(T.D, c, gn);
 #pragma unroll
             for (int i = 0; i < 3; ++i) g[i] += P[3 * i] * gn[0] + P[3 * i + 1] * gn[1] + P[3 * i + 2] * gn[2];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) Fs[i] += T.vol * F[i];
+            for (int i = 0; i < 9; ++i) Fs[i] += T.vol * K.F[i];
         }
     }
 #pragma unroll
@@ -253,10 +254,10 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
         const uint32_t sl = a.incslot[(size_t)f * a.maxi + j];
         Tet T;
         load_tet(a.tet, pk >> 2, T);
-        float F[9], C[9];
-        defgrad(a.u, a.nV, T, F);
-        cof3(F, C);
-        const float J = F[0] * C[0] + F[3] * C[3] + F[6] * C[6];
+        float H[9], cH[9];
+        Kin<float> K;
+        dispgrad(a.u, a.nV, T, H);
+        kinematics(H, K, cH);
         float Phi[4][9];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
                 for (int q = 0; q < 9; ++q) Phi[c][q] = sPhi[vloc][s][q];
             }
         }
-        galerkin_hessian(T, F, C, J, Phi, 1.0f, A6);
+        galerkin_hessian(T, K, Phi, 1.0f, A6);
     }
 
     // cubature samples on the last S lanes
@@ -284,10 +285,10 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
             const float w = rec[s];
             Tet T;
             load_tet(a.tet, e, T);
-            float F[9], C[9];
-            defgrad(a.u, a.nV, T, F);
-            cof3(F, C);
-            const float J = F[0] * C[0] + F[3] * C[3] + F[6] * C[6];
+            float H[9], cH[9];
+            Kin<float> K;
+            dispgrad(a.u, a.nV, T, H);
+            kinematics(H, K, cH);
             float Phi[4][9];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
                         b[jj] += gc * (Phi[c][jj] * g0 + Phi[c][3 + jj] * g1 + Phi[c][6 + jj] * g2);
                 }
             }
-            galerkin_hessian(T, F, C, J, Phi, w, A6);
+            galerkin_hessian(T, K, Phi, w, A6);
         }
     }
 
@@ -358,11 +359,11 @@ __global__ __launch_bounds__(BLOCK) void k_plain(SweepArgs a) {
             const int c = pk & 3;
             Tet T;
             load_tet(a.tet, pk >> 2, T);
-            float F[9], C[9], P[9], gn[3];
-            defgrad(a.u, a.nV, T, F);
-            cof3(F, C);
-            const float J = F[0] * C[0] + F[3] * C[3] + F[6] * C[6];
-            snh_stress(F, C, J, T.vmu, T.vlam, P);
+            float H[9], cH[9], P[9], gn[3];
+            Kin<float> K;
+            dispgrad(a.u, a.nV, T, H);
+            kinematics(H, K, cH);
+            snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
             gradN(T.D, c, gn);
 #pragma unroll
             for (int i = 0; i < 3; ++i) g[i] += P[3 * i] * gn[0] + P[3 * i + 1] * gn[1] + P[3 * i + 2] * gn[2];
@@ -374,7 +375,7 @@ __global__ __launch_bounds__(BLOCK) void k_plain(SweepArgs a) {
                 for (int i = 0; i < 3; ++i)
 #pragma unroll
                     for (int jj = 0; jj < 3; ++jj) dF[3 * i + jj] = (i == d) ? gn[jj] : 0.0f;
-                snh_dstress(F, C, J, T.vmu, T.vlam, dF, dP);
+                snh_dstress(K.F, K.C, 1.0f + K.Jm1, T.vmu, T.vlam, dF, dP);
 #pragma unroll
                 for (int e = d; e < 3; ++e)
                     A6[k++] += dP[3 * e] * gn[0] + dP[3 * e + 1] * gn[1] + dP[3 * e + 2] * gn[2];
@@ -469,11 +470,11 @@ __global__ __launch_bounds__(256) void k_energy(SweepArgs a, int nT) {
     if (i < nT) {
         Tet T;
         load_tet(a.tet, i, T);
-        float F[9], C[9];
-        defgrad(a.u, a.nV, T, F);
-        cof3(F, C);
-        const float J = F[0] * C[0] + F[3] * C[3] + F[6] * C[6];
-        e += (double)snh_psi(F, J, T.vmu, T.vlam);
+        float H[9], cH[9];
+        Kin<float> K;
+        dispgrad(a.u, a.nV, T, H);
+        kinematics(H, K, cH);
+        e += (double)snh_psi_H(H, K, cH, T.vmu, T.vlam);
     }
     if (i < a.nVf) {
         const int v = a.free_ids[i];

@@ -38,7 +38,10 @@ EXPORTS = ["jgs2_default_params", "jgs2_create", "jgs2_destroy", "jgs2_last_erro
            "jgs2_set_stream", "jgs2_upload_mesh", "jgs2_set_material", "jgs2_precompute",
            "jgs2_import_correction", "jgs2_export_correction", "jgs2_get_ring_sizes", "jgs2_get_poses",
            "jgs2_set_state", "jgs2_get_state", "jgs2_step", "jgs2_begin_step", "jgs2_iterate", "jgs2_end_step",
-           "jgs2_residual", "jgs2_energy", "jgs2_get_phase1", "jgs2_get_coloring"]
+           "jgs2_residual", "jgs2_energy", "jgs2_get_phase1", "jgs2_get_coloring", "jgs2_set_profiling",
+           "jgs2_kernel_times"]
+
+KERNELS = ["phase1", "phase2", "plain", "commit", "reduce", "predict", "velocity", "energy"]
 
 _lib = None
 
@@ -77,6 +80,8 @@ def load(path: str = LIB_PATH):
         "jgs2_energy": (C.c_int32, [C.c_void_p, d]),
         "jgs2_get_phase1": (C.c_int32, [C.c_void_p, d, d]),
         "jgs2_get_coloring": (C.c_int32, [C.c_void_p, i32, i32]),
+        "jgs2_set_profiling": (C.c_int32, [C.c_void_p, C.c_int32]),
+        "jgs2_kernel_times": (C.c_int32, [C.c_void_p, d, P(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -260,6 +265,16 @@ class Solver:
         R = np.zeros((self.nV, 3, 3))
         self._chk(self.lib.jgs2_get_phase1(self.h, _dptr(g), _dptr(R)))
         return g, R
+
+    def set_profiling(self, on=True):
+        self._chk(self.lib.jgs2_set_profiling(self.h, 1 if on else 0))
+
+    def kernel_times(self):
+        """{kernel name: (total ms, launches)} since profiling was enabled."""
+        ms = np.zeros(len(KERNELS))
+        n = np.zeros(len(KERNELS), dtype=np.int64)
+        self._chk(self.lib.jgs2_kernel_times(self.h, _dptr(ms), n.ctypes.data_as(C.POINTER(C.c_int64))))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
 
     def coloring(self):
         c = np.zeros(self.nV, dtype=np.int32)
