@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="4x4x16 beam instead (quick check)")
     ap.add_argument("--modes", default="jgs2_jacobi,jgs2_gs,plain_jacobi,plain_jacobi_w0.8,plain_gs")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (5x) to calibrate HBM byte counters")
     return ap.parse_args()
 
 
@@ -44,8 +46,23 @@ def sync():
         pass
 
 
+def calibrate_copy():
+    """A plain copy kernel of known size: 1 GiB read + 1 GiB written per copy."""
+    import torch
+    n = 1 << 28  # float32 elements = 1 GiB
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 5}))
+
+
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
               file=sys.stderr)

@@ -36,13 +36,12 @@ struct SweepArgs {
     const float* Uring;     // [(nVf * 9 + comp) * K + k]
     const int* samp_e;      // [nVf * S]
     const float* samp;      // [(nVf * SREC + field) * S + s]
-    const float* X;         // [3 * nV] rest positions
-    const float* u;         // [3 * nV] current displacement
-    float* unext;           // [3 * nV]
-    const float* zu;        // [3 * nV] inertial target displacement
-    const float* mh2;       // [nV] m_a / h^2
-    float* g;               // [3 * nV]
-    float* R;               // [9 * nV]
+    const float4* X;        // [nV] rest positions (w unused)
+    const float4* u;        // [nV] current displacement x - X (w unused)
+    float4* unext;          // [nV]
+    const float4* zu;       // [nV] inertial target displacement, w = m_a / h^2 (0 if pinned)
+    float4* g;              // [nV] assembled gradient (w unused)
+    float4* R;              // [nV] per-vertex rotation as a unit quaternion (x, y, z, w)
     double* partial;        // [gridDim] per-block partial sums of |g|^2
     float omega;
     int in_place;           // write the update into u (coloured GS, plain variant)
@@ -86,8 +85,9 @@ struct jgs2_solver {
 
     // device
     float4* d_tet = nullptr;
-    float *d_X = nullptr, *d_u = nullptr, *d_unext = nullptr, *d_uhat = nullptr, *d_vhat = nullptr;
-    float *d_zu = nullptr, *d_mh2 = nullptr, *d_g = nullptr, *d_R = nullptr;
+    float4 *d_X = nullptr, *d_u = nullptr, *d_unext = nullptr, *d_uhat = nullptr, *d_vhat = nullptr;
+    float4 *d_zu = nullptr, *d_g = nullptr, *d_R = nullptr;
+    float* d_mh2 = nullptr;
     int *d_free = nullptr, *d_inc = nullptr, *d_inc_n = nullptr, *d_ring = nullptr, *d_ring_n = nullptr;
     uint32_t* d_incslot = nullptr;
     int* d_colperm = nullptr;
@@ -128,4 +128,5 @@ void launch_energy(jgs2_solver* s, const SweepArgs& a, int nT);
 int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed);
 int alloc_tables(jgs2_solver* s, int S);
 void prof_collect(jgs2_solver* s);
+hipEvent_t pool_event(jgs2_solver* s);
 }  // namespace jgs2

@@ -195,15 +195,21 @@ template <typename T> JGS2_HD void closest_rotation(const T* F, T* R) {
             C[3 * i + j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
     T w[3], V[9];
     sym_eig3(C, w, V);
-    int m = 0;
-    if (w[1] < w[m]) m = 1;
-    if (w[2] < w[m]) m = 2;
-    const int a = (m + 1) % 3, b = (m + 2) % 3;
-    T va[3] = {V[a], V[3 + a], V[6 + a]};
-    T vb[3] = {V[b], V[3 + b], V[6 + b]};
-    T vm[3] = {V[m], V[3 + m], V[6 + m]};
-    const T sa = sqrt(w[a] > T(0) ? w[a] : T(0));
-    const T sb = sqrt(w[b] > T(0) ? w[b] : T(0));
+    // m = index of the smallest eigenvalue, (a, b) = the other two (static selects)
+    const bool m0 = (w[0] <= w[1]) && (w[0] <= w[2]);
+    const bool m1 = !m0 && (w[1] <= w[2]);
+    T va[3], vb[3], vm[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const T c0 = V[3 * i], c1 = V[3 * i + 1], c2 = V[3 * i + 2];
+        vm[i] = m0 ? c0 : (m1 ? c1 : c2);
+        va[i] = m0 ? c1 : (m1 ? c2 : c0);
+        vb[i] = m0 ? c2 : (m1 ? c0 : c1);
+    }
+    const T wa = m0 ? w[1] : (m1 ? w[2] : w[0]);
+    const T wb = m0 ? w[2] : (m1 ? w[0] : w[1]);
+    const T sa = sqrt(wa > T(0) ? wa : T(0));
+    const T sb = sqrt(wb > T(0) ? wb : T(0));
     if (!(sa > T(0)) || !(sb > T(0))) {  // rank <= 1: no unique rotation
 #pragma unroll
         for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? T(1) : T(0);
@@ -224,6 +230,92 @@ template <typename T> JGS2_HD void closest_rotation(const T* F, T* R) {
 #pragma unroll
         for (int j = 0; j < 3; ++j)
             R[3 * i + j] = ua[i] * va[j] + ub[i] * vb[j] + sgn * um[i] * vm[j];
+}
+
+// Rotation of the polar decomposition F = R S for det F > 0 by Higham's
+// scaled Newton iteration X <- (zeta X + X^-T / zeta) / 2 with
+// zeta = sqrt(|X^-1|_F / |X|_F), then one unscaled step once the update is
+// below 1e-4 |X|.  Falls back to the eigen route (closest_rotation, which
+// also covers det F <= 0).
+template <typename T> JGS2_HD void polar_rotation(const T* F, T* R) {
+    T X[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) X[i] = F[i];
+    if (!(det3(X) > T(0))) {
+        closest_rotation(F, R);
+        return;
+    }
+    bool done = false;
+    for (int it = 0; it < 24 && !done; ++it) {
+        T C[9];
+        cof3(X, C);
+        const T det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
+        T nX = T(0), nC = T(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) { nX += X[i] * X[i]; nC += C[i] * C[i]; }
+        nX = sqrt(nX);
+        nC = sqrt(nC);
+        T zeta = sqrt((nC / det) / nX);
+        T diff = T(0);
+        for (int pass = 0; pass < 2; ++pass) {
+            const T a = T(0.5) * zeta, b = T(0.5) / (zeta * det);
+            T Xn[9];
+            diff = T(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                Xn[i] = a * X[i] + b * C[i];
+                diff += (Xn[i] - X[i]) * (Xn[i] - X[i]);
+            }
+            if (pass == 0) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) X[i] = Xn[i];
+                if (diff > T(1e-8) * nX * nX) break;  // keep iterating with scaling
+                // converged to ~1e-4: one unscaled polishing step
+                cof3(X, C);
+                const T d2 = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
+                zeta = T(1);
+                const T a2 = T(0.5), b2 = T(0.5) / d2;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) X[i] = a2 * X[i] + b2 * C[i];
+                done = true;
+                break;
+            }
+        }
+    }
+    if (!done) {
+        closest_rotation(F, R);
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = X[i];
+}
+
+// Unit quaternion (x, y, z, w) of a rotation matrix (Shepperd's branches)
+// and back.
+template <typename T> JGS2_HD void quat_from_rot(const T* R, T* q) {
+    const T tr = R[0] + R[4] + R[8];
+    T x, y, z, w;
+    if (tr > T(0)) {
+        const T s = sqrt(tr + T(1)) * T(2);
+        w = T(0.25) * s; x = (R[7] - R[5]) / s; y = (R[2] - R[6]) / s; z = (R[3] - R[1]) / s;
+    } else if (R[0] > R[4] && R[0] > R[8]) {
+        const T s = sqrt(T(1) + R[0] - R[4] - R[8]) * T(2);
+        w = (R[7] - R[5]) / s; x = T(0.25) * s; y = (R[1] + R[3]) / s; z = (R[2] + R[6]) / s;
+    } else if (R[4] > R[8]) {
+        const T s = sqrt(T(1) + R[4] - R[0] - R[8]) * T(2);
+        w = (R[2] - R[6]) / s; x = (R[1] + R[3]) / s; y = T(0.25) * s; z = (R[5] + R[7]) / s;
+    } else {
+        const T s = sqrt(T(1) + R[8] - R[0] - R[4]) * T(2);
+        w = (R[3] - R[1]) / s; x = (R[2] + R[6]) / s; y = (R[5] + R[7]) / s; z = T(0.25) * s;
+    }
+    const T n = T(1) / sqrt(x * x + y * y + z * z + w * w);
+    q[0] = x * n; q[1] = y * n; q[2] = z * n; q[3] = w * n;
+}
+
+template <typename T> JGS2_HD void rot_from_quat(T x, T y, T z, T w, T* R) {
+    R[0] = T(1) - T(2) * (y * y + z * z); R[1] = T(2) * (x * y - z * w); R[2] = T(2) * (x * z + y * w);
+    R[3] = T(2) * (x * y + z * w); R[4] = T(1) - T(2) * (x * x + z * z); R[5] = T(2) * (y * z - x * w);
+    R[6] = T(2) * (x * z - y * w); R[7] = T(2) * (y * z + x * w); R[8] = T(1) - T(2) * (x * x + y * y);
 }
 
 // LDL^T pivots of a symmetric 3x3 (lower triangle used).

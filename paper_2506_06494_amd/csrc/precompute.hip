@@ -40,8 +40,31 @@ constexpr int NCOL = 3 * NTMAX;    // max rows of the NNLS system
 // ---------------------------------------------------------------------------
 // FP64 helpers
 // ---------------------------------------------------------------------------
+// Global -> LDS copy of one 64x64 block by a 256-thread block: all eight
+// 16-byte loads are issued before any store so their latencies overlap.
 __device__ __forceinline__ void load_block(double* __restrict__ s, const double* __restrict__ g) {
-    for (int i = threadIdx.x; i < NB2; i += blockDim.x) s[i] = g[i];
+    const double2* g2 = reinterpret_cast<const double2*>(g);
+    double2* s2 = reinterpret_cast<double2*>(s);
+    double2 r[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = g2[threadIdx.x + 256 * k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s2[threadIdx.x + 256 * k] = r[k];
+}
+
+__device__ __forceinline__ void load_two_blocks(double* __restrict__ s1, const double* __restrict__ g1,
+                                                double* __restrict__ s2, const double* __restrict__ g2) {
+    const double2* a = reinterpret_cast<const double2*>(g1);
+    const double2* b = reinterpret_cast<const double2*>(g2);
+    double2 ra[8], rb[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ra[k] = a[threadIdx.x + 256 * k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) rb[k] = b[threadIdx.x + 256 * k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) reinterpret_cast<double2*>(s1)[threadIdx.x + 256 * k] = ra[k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) reinterpret_cast<double2*>(s2)[threadIdx.x + 256 * k] = rb[k];
 }
 
 // 64x64 GEMM on LDS operands with a 4x4 register tile per thread (256 threads):
@@ -154,8 +177,7 @@ __global__ __launch_bounds__(256) void k_panel(double* __restrict__ Lb, const do
     if (J + d >= nB) return;
     __shared__ double A[NB2], Bi[NB2];
     double* g = Lb + ((size_t)J * (w + 1) + d) * NB2;
-    load_block(A, g);
-    load_block(Bi, Linv + (size_t)J * NB2);
+    load_two_blocks(A, g, Bi, Linv + (size_t)J * NB2);
     __syncthreads();
     double acc[4][4] = {};
     tile_gemm<false, true>(A, Bi, 1.0, acc);
@@ -172,8 +194,7 @@ __global__ __launch_bounds__(256) void k_update(double* __restrict__ Lb, int w, 
     const int d2 = p + 1;
     if (J + d1 >= nB) return;
     __shared__ double A1[NB2], A2[NB2];
-    load_block(A1, Lb + ((size_t)J * (w + 1) + d1) * NB2);
-    load_block(A2, Lb + ((size_t)J * (w + 1) + d2) * NB2);
+    load_two_blocks(A1, Lb + ((size_t)J * (w + 1) + d1) * NB2, A2, Lb + ((size_t)J * (w + 1) + d2) * NB2);
     __syncthreads();
     double* C = Lb + ((size_t)(J + d2) * (w + 1) + (d1 - d2)) * NB2;
     const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
@@ -204,8 +225,7 @@ __global__ __launch_bounds__(256) void k_band_solve(const double* __restrict__ L
             for (int j = 0; j < 4; ++j) acc[i][j] = XI[(4 * ty + i) * NB + 4 * tx + j];
         const int dmax = min(w, I - I0);
         for (int d = 1; d <= dmax; ++d) {
-            load_block(sA, Lb + ((size_t)(I - d) * (w + 1) + d) * NB2);
-            load_block(sB, X + (size_t)(I - d) * NB2);
+            load_two_blocks(sA, Lb + ((size_t)(I - d) * (w + 1) + d) * NB2, sB, X + (size_t)(I - d) * NB2);
             __syncthreads();
             tile_gemm<false, false>(sA, sB, -1.0, acc);
             __syncthreads();
@@ -228,8 +248,7 @@ __global__ __launch_bounds__(256) void k_band_solve(const double* __restrict__ L
             for (int j = 0; j < 4; ++j) acc[i][j] = (I >= I0) ? XI[(4 * ty + i) * NB + 4 * tx + j] : 0.0;
         const int dmax = min(w, nB - 1 - I);
         for (int d = 1; d <= dmax; ++d) {
-            load_block(sA, Lb + ((size_t)I * (w + 1) + d) * NB2);
-            load_block(sB, X + (size_t)(I + d) * NB2);
+            load_two_blocks(sA, Lb + ((size_t)I * (w + 1) + d) * NB2, sB, X + (size_t)(I + d) * NB2);
             __syncthreads();
             tile_gemm<true, false>(sA, sB, -1.0, acc);
             __syncthreads();

@@ -6,6 +6,7 @@
 #include <numeric>
 
 #include "jgs2_internal.h"
+#include "jgs2_math.h"
 
 using jgs2::KMAX;
 using jgs2::SMAX;
@@ -37,7 +38,7 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
     a.free_ids = s->d_free; a.list = nullptr; a.n_list = 0;
     a.tet = s->d_tet; a.inc = s->d_inc; a.incslot = s->d_incslot; a.inc_n = s->d_inc_n;
     a.ring = s->d_ring; a.ring_n = s->d_ring_n; a.Uring = s->d_Uring; a.samp_e = s->d_samp_e; a.samp = s->d_samp;
-    a.X = s->d_X; a.u = s->d_u; a.unext = s->d_unext; a.zu = s->d_zu; a.mh2 = s->d_mh2; a.g = s->d_g; a.R = s->d_R;
+    a.X = s->d_X; a.u = s->d_u; a.unext = s->d_unext; a.zu = s->d_zu; a.g = s->d_g; a.R = s->d_R;
     a.partial = s->d_partial; a.omega = (float)s->p.omega; a.in_place = 0;
     a.n_planes = s->p.n_planes;
     for (int i = 0; i < s->p.n_planes; ++i)
@@ -50,7 +51,7 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
 using namespace jgs2;
 
 namespace jgs2 {
-static hipEvent_t pool_event(jgs2_solver* s) {
+hipEvent_t pool_event(jgs2_solver* s) {
     if (!s->ev_pool.empty()) {
         hipEvent_t e = s->ev_pool.back();
         s->ev_pool.pop_back();
@@ -75,20 +76,6 @@ void prof_collect(jgs2_solver* s) {
     s->kt_pending.clear();
 }
 }  // namespace jgs2
-
-// Runs `call` (a kernel launch) bracketed by an event pair when profiling.
-#define TIMED(s, kid, call)                                                  \
-    do {                                                                     \
-        if ((s)->prof) {                                                     \
-            jgs2_solver::Pending _p{(kid), jgs2::pool_event(s), jgs2::pool_event(s)}; \
-            (void)hipEventRecord(_p.a, (s)->stream);                         \
-            call;                                                            \
-            (void)hipEventRecord(_p.b, (s)->stream);                         \
-            (s)->kt_pending.push_back(_p);                                   \
-        } else {                                                             \
-            call;                                                            \
-        }                                                                    \
-    } while (0)
 
 namespace jgs2 {
 // Device correction tables for S samples per free vertex (zero-filled).
@@ -374,10 +361,10 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
     }
     // device layout
     int r;
-    const size_t V3 = 3 * (size_t)nV;
-    if ((r = dalloc(s, s->d_X, V3)) || (r = dalloc(s, s->d_u, V3)) || (r = dalloc(s, s->d_unext, V3)) ||
-        (r = dalloc(s, s->d_uhat, V3)) || (r = dalloc(s, s->d_vhat, V3)) || (r = dalloc(s, s->d_zu, V3)) ||
-        (r = dalloc(s, s->d_g, V3)) || (r = dalloc(s, s->d_R, 9 * (size_t)nV)) || (r = dalloc(s, s->d_mh2, (size_t)nV)) ||
+    const size_t V4 = (size_t)nV;
+    if ((r = dalloc(s, s->d_X, V4)) || (r = dalloc(s, s->d_u, V4)) || (r = dalloc(s, s->d_unext, V4)) ||
+        (r = dalloc(s, s->d_uhat, V4)) || (r = dalloc(s, s->d_vhat, V4)) || (r = dalloc(s, s->d_zu, V4)) ||
+        (r = dalloc(s, s->d_g, V4)) || (r = dalloc(s, s->d_R, V4)) || (r = dalloc(s, s->d_mh2, (size_t)nV)) ||
         (r = dalloc(s, s->d_free, nf)) || (r = dalloc(s, s->d_inc, nf * s->maxi)) ||
         (r = dalloc(s, s->d_incslot, nf * s->maxi)) || (r = dalloc(s, s->d_inc_n, nf)) ||
         (r = dalloc(s, s->d_ring, nf * s->K)) || (r = dalloc(s, s->d_ring_n, nf)) ||
@@ -385,18 +372,17 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
         return r;
     s->n_partial = std::max<int>((s->nVf + VPB - 1) / VPB, (std::max(nT, s->nVf) + 255) / 256) + 1;
     if ((r = dalloc(s, s->d_partial, (size_t)s->n_partial)) || (r = dalloc(s, s->d_red, 4))) return r;
-    std::vector<float> Xs(V3), Rid(9 * (size_t)nV, 0.0f);
+    std::vector<float4> Xs(V4), Rid(V4, make_float4(0.f, 0.f, 0.f, 1.f));
     for (int v = 0; v < nV; ++v)
-        for (int i = 0; i < 3; ++i) Xs[i * (size_t)nV + v] = (float)X[3 * (size_t)v + i];
-    for (int v = 0; v < nV; ++v) Rid[0 * (size_t)nV + v] = Rid[4 * (size_t)nV + v] = Rid[8 * (size_t)nV + v] = 1.0f;
-    if ((r = upload(s, s->d_X, Xs.data(), V3)) || (r = upload(s, s->d_R, Rid.data(), 9 * (size_t)nV)) ||
+        Xs[v] = make_float4((float)X[3 * (size_t)v], (float)X[3 * (size_t)v + 1], (float)X[3 * (size_t)v + 2], 0.f);
+    if ((r = upload(s, s->d_X, Xs.data(), V4)) || (r = upload(s, s->d_R, Rid.data(), V4)) ||
         (r = upload(s, s->d_free, s->free_ids.data(), nf)) || (r = upload(s, s->d_inc, s->inc.data(), nf * s->maxi)) ||
         (r = upload(s, s->d_incslot, s->incslot.data(), nf * s->maxi)) || (r = upload(s, s->d_inc_n, s->inc_n.data(), nf)) ||
         (r = upload(s, s->d_ring, s->ring.data(), nf * s->K)) || (r = upload(s, s->d_ring_n, s->ring_n.data(), nf)) ||
         (r = upload(s, s->d_colperm, s->col_perm.data(), nf)))
         return r;
-    for (float* d : {s->d_u, s->d_unext, s->d_uhat, s->d_vhat, s->d_zu, s->d_g})
-        HIPCHK(hipMemsetAsync(d, 0, V3 * sizeof(float), s->stream));
+    for (float4* d : {s->d_u, s->d_unext, s->d_uhat, s->d_vhat, s->d_zu, s->d_g})
+        HIPCHK(hipMemsetAsync(d, 0, V4 * sizeof(float4), s->stream));
     HIPCHK(hipMemsetAsync(s->d_mh2, 0, (size_t)nV * sizeof(float), s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     s->have_mesh = true;
@@ -538,17 +524,21 @@ int32_t jgs2_set_state(jgs2_solver* s, const double* x, const double* v) {
     if (!s->have_mesh) return s->fail(JGS2_E_NOT_READY, "no mesh");
     if (!x || !v) return s->fail(JGS2_E_INVALID, "NULL state");
     const size_t nV = s->nV;
-    std::vector<float> u(3 * nV), vv(3 * nV);
-    for (size_t a = 0; a < nV; ++a)
+    std::vector<float4> u(nV), vv(nV);
+    for (size_t a = 0; a < nV; ++a) {
+        float uu[3], vl[3];
         for (int i = 0; i < 3; ++i) {
             const double xi = x[3 * a + i], vi = v[3 * a + i];
             if (!std::isfinite(xi) || !std::isfinite(vi)) return s->fail(JGS2_E_INVALID, "non-finite state");
-            u[i * nV + a] = (float)(xi - s->X[3 * a + i]);
-            vv[i * nV + a] = s->pinned[a] ? 0.0f : (float)vi;
+            uu[i] = (float)(xi - s->X[3 * a + i]);
+            vl[i] = s->pinned[a] ? 0.0f : (float)vi;
         }
+        u[a] = make_float4(uu[0], uu[1], uu[2], 0.f);
+        vv[a] = make_float4(vl[0], vl[1], vl[2], 0.f);
+    }
     int r;
-    if ((r = upload(s, s->d_uhat, u.data(), 3 * nV)) || (r = upload(s, s->d_u, u.data(), 3 * nV)) ||
-        (r = upload(s, s->d_unext, u.data(), 3 * nV)) || (r = upload(s, s->d_vhat, vv.data(), 3 * nV)))
+    if ((r = upload(s, s->d_uhat, u.data(), nV)) || (r = upload(s, s->d_u, u.data(), nV)) ||
+        (r = upload(s, s->d_unext, u.data(), nV)) || (r = upload(s, s->d_vhat, vv.data(), nV)))
         return r;
     HIPCHK(hipStreamSynchronize(s->stream));
     s->have_state = true;
@@ -561,21 +551,23 @@ int32_t jgs2_get_state(jgs2_solver* s, double* x, double* v) {
     if (!s) return JGS2_E_INVALID;
     if (!s->have_state) return s->fail(JGS2_E_NOT_READY, "no state");
     const size_t nV = s->nV;
-    std::vector<float> u(3 * nV), vv(3 * nV);
+    std::vector<float4> u(nV), vv(nV);
     // inside a step the current iterate is u; otherwise uhat == u
-    HIPCHK(hipMemcpyAsync(u.data(), s->d_u, 3 * nV * 4, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipMemcpyAsync(vv.data(), s->d_vhat, 3 * nV * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(u.data(), s->d_u, nV * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(vv.data(), s->d_vhat, nV * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
-    for (size_t a = 0; a < nV; ++a)
+    for (size_t a = 0; a < nV; ++a) {
+        const float uu[3] = {u[a].x, u[a].y, u[a].z}, vl[3] = {vv[a].x, vv[a].y, vv[a].z};
         for (int i = 0; i < 3; ++i) {
-            if (x) x[3 * a + i] = s->X[3 * a + i] + (double)u[i * nV + a];
-            if (v) v[3 * a + i] = vv[i * nV + a];
+            if (x) x[3 * a + i] = s->X[3 * a + i] + (double)uu[i];
+            if (v) v[3 * a + i] = vl[i];
         }
+    }
     return JGS2_OK;
 }
 
 static int read_reduced(jgs2_solver* s, int n_partials, double* out) {
-    TIMED(s, JGS2_K_REDUCE, launch_reduce(s, n_partials));
+    launch_reduce(s, n_partials);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(out, s->d_red, sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -586,7 +578,7 @@ static int read_reduced(jgs2_solver* s, int n_partials, double* out) {
 static int gradient_norm2(jgs2_solver* s, double* out) {
     SweepArgs a;
     build_sweep_args(s, a);
-    TIMED(s, JGS2_K_PHASE1, launch_phase1(s, a, s->p.variant == JGS2_CUBATURE));
+    launch_phase1(s, a, s->p.variant == JGS2_CUBATURE);
     s->phase1_valid = true;
     return read_reduced(s, (s->nVf + VPB - 1) / VPB, out);
 }
@@ -604,19 +596,20 @@ int32_t jgs2_begin_step(jgs2_solver* s) {
     const float grav[3] = {(float)s->p.gravity[0], (float)s->p.gravity[1], (float)s->p.gravity[2]};
     // contact feasibility of the start state
     if (s->p.n_planes > 0) {
-        std::vector<float> u(3 * (size_t)s->nV);
-        HIPCHK(hipMemcpyAsync(u.data(), s->d_uhat, u.size() * 4, hipMemcpyDeviceToHost, s->stream));
+        std::vector<float4> u((size_t)s->nV);
+        HIPCHK(hipMemcpyAsync(u.data(), s->d_uhat, u.size() * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
         for (int f = 0; f < s->nVf; ++f) {
             const int v = s->free_ids[f];
+            const float uu[3] = {u[v].x, u[v].y, u[v].z};
             for (int p = 0; p < s->p.n_planes; ++p) {
                 double d = -s->p.planes[p][3];
-                for (int i = 0; i < 3; ++i) d += s->p.planes[p][i] * (s->X[3 * (size_t)v + i] + u[i * (size_t)s->nV + v]);
+                for (int i = 0; i < 3; ++i) d += s->p.planes[p][i] * (s->X[3 * (size_t)v + i] + uu[i]);
                 if (!(d > 0)) return s->fail(JGS2_E_INFEASIBLE, "a vertex is on or behind a contact plane");
             }
         }
     }
-    TIMED(s, JGS2_K_PREDICT, launch_predict(s, (float)s->p.dt, grav));
+    launch_predict(s, (float)s->p.dt, grav);
     double g2 = 0;
     int r = gradient_norm2(s, &g2);
     if (r != JGS2_OK) return r;
@@ -639,10 +632,10 @@ static int sweep_once(jgs2_solver* s) {
     const bool cub = s->p.variant == JGS2_CUBATURE;
     if (s->p.order == JGS2_JACOBI) {
         if (cub) {
-            if (!s->phase1_valid) TIMED(s, JGS2_K_PHASE1, launch_phase1(s, a, true));
-            TIMED(s, JGS2_K_PHASE2, launch_phase2_cubature(s, a));
+            if (!s->phase1_valid) launch_phase1(s, a, true);
+            launch_phase2_cubature(s, a);
         } else {
-            TIMED(s, JGS2_K_PLAIN, launch_plain(s, a));
+            launch_plain(s, a);
         }
         swap_u(s);
     } else {
@@ -652,12 +645,12 @@ static int sweep_once(jgs2_solver* s) {
             ac.n_list = s->col_off[c + 1] - s->col_off[c];
             if (cub) {
                 SweepArgs all = a;
-                TIMED(s, JGS2_K_PHASE1, launch_phase1(s, all, true));
-                TIMED(s, JGS2_K_PHASE2, launch_phase2_cubature(s, ac));
-                TIMED(s, JGS2_K_COMMIT, launch_commit(s, ac));
+                launch_phase1(s, all, true);
+                launch_phase2_cubature(s, ac);
+                launch_commit(s, ac);
             } else {
                 ac.in_place = 1;
-                TIMED(s, JGS2_K_PLAIN, launch_plain(s, ac));
+                launch_plain(s, ac);
             }
         }
         s->phase1_valid = false;
@@ -687,9 +680,9 @@ int32_t jgs2_iterate(jgs2_solver* s, int32_t n_sweeps, double* rel_res) {
 int32_t jgs2_end_step(jgs2_solver* s) {
     if (!s) return JGS2_E_INVALID;
     if (!s->in_step) return s->fail(JGS2_E_NOT_READY, "end_step without begin_step");
-    TIMED(s, JGS2_K_VELOCITY, launch_velocity(s, (float)s->p.dt));
+    launch_velocity(s, (float)s->p.dt);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(s->d_unext, s->d_u, 3 * (size_t)s->nV * 4, hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_unext, s->d_u, (size_t)s->nV * sizeof(float4), hipMemcpyDeviceToDevice, s->stream));
     s->in_step = false;
     s->phase1_valid = false;
     return JGS2_OK;
@@ -697,8 +690,8 @@ int32_t jgs2_end_step(jgs2_solver* s) {
 
 static int abandon_step(jgs2_solver* s) {
     // restore the iterate to the start of the step
-    (void)hipMemcpyAsync(s->d_u, s->d_uhat, 3 * (size_t)s->nV * 4, hipMemcpyDeviceToDevice, s->stream);
-    (void)hipMemcpyAsync(s->d_unext, s->d_uhat, 3 * (size_t)s->nV * 4, hipMemcpyDeviceToDevice, s->stream);
+    (void)hipMemcpyAsync(s->d_u, s->d_uhat, (size_t)s->nV * sizeof(float4), hipMemcpyDeviceToDevice, s->stream);
+    (void)hipMemcpyAsync(s->d_unext, s->d_uhat, (size_t)s->nV * sizeof(float4), hipMemcpyDeviceToDevice, s->stream);
     (void)hipStreamSynchronize(s->stream);
     s->in_step = false;
     s->phase1_valid = false;
@@ -751,7 +744,7 @@ int32_t jgs2_energy(jgs2_solver* s, double* e) {
     if (!ready_to_step(s)) return JGS2_E_NOT_READY;
     SweepArgs a;
     build_sweep_args(s, a);
-    TIMED(s, JGS2_K_ENERGY, launch_energy(s, a, s->nT));
+    launch_energy(s, a, s->nT);
     return read_reduced(s, (std::max(s->nT, s->nVf) + 255) / 256, e);
 }
 
@@ -764,15 +757,19 @@ int32_t jgs2_get_phase1(jgs2_solver* s, double* g, double* R) {
     s->phase1_valid = s->in_step;
     HIPCHK(hipGetLastError());
     const size_t nV = s->nV;
-    std::vector<float> gg(3 * nV), RR(9 * nV);
-    HIPCHK(hipMemcpyAsync(gg.data(), s->d_g, gg.size() * 4, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipMemcpyAsync(RR.data(), s->d_R, RR.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    std::vector<float4> gg(nV), qq(nV);
+    HIPCHK(hipMemcpyAsync(gg.data(), s->d_g, nV * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(qq.data(), s->d_R, nV * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     for (size_t v = 0; v < nV; ++v) {
+        const double gv[3] = {gg[v].x, gg[v].y, gg[v].z};
         for (int i = 0; i < 3; ++i)
-            if (g) g[3 * v + i] = s->pinned[v] ? 0.0 : gg[i * nV + v];
-        for (int i = 0; i < 9; ++i)
-            if (R) R[9 * v + i] = s->pinned[v] ? ((i % 4 == 0) ? 1.0 : 0.0) : RR[i * nV + v];
+            if (g) g[3 * v + i] = s->pinned[v] ? 0.0 : gv[i];
+        if (R) {
+            double Rm[9];
+            jgs2::rot_from_quat<double>(qq[v].x, qq[v].y, qq[v].z, qq[v].w, Rm);
+            for (int i = 0; i < 9; ++i) R[9 * v + i] = s->pinned[v] ? ((i % 4 == 0) ? 1.0 : 0.0) : Rm[i];
+        }
     }
     return JGS2_OK;
 }

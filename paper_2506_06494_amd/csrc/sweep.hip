@@ -8,14 +8,31 @@
 // (blocks are dealt round-robin to the 8 XCDs) works on one contiguous
 // range of vertices, keeping a slab's tets and neighbours in that XCD's L2.
 //
-// All arrays of vertices are SoA [component][vertex] in FP32; positions are
-// stored as displacements u = x - X from the rest shape, so that
-// H = F - I = sum_a u_a (grad N_a)^T keeps full FP32 precision, and the
-// stress is evaluated from H without cancelling O(mu) terms.
+// Vertex data are float4 records (one 16-byte load per gathered corner):
+// displacement u = x - X from the rest shape (so H = F - I keeps full FP32
+// precision and the stress is evaluated from H without cancelling O(mu)
+// terms), inertial target with m/h^2 in w, gradient, and the per-vertex
+// rotation as a unit quaternion.
+#include <hip/hip_ext.h>
+
 #include "jgs2_internal.h"
 #include "jgs2_math.h"
 
 namespace jgs2 {
+
+// Launches a kernel; while profiling, the dispatch itself stamps a start and
+// an end event (hipExtLaunchKernelGGL), so the recorded duration is the
+// kernel's own execution time.
+template <typename Kern, typename... Args>
+static void launch(jgs2_solver* s, int kid, Kern kernel, dim3 grid, dim3 block, Args... args) {
+    if (s->prof) {
+        hipEvent_t e0 = pool_event(s), e1 = pool_event(s);
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s->stream, e0, e1, 0, args...);
+        s->kt_pending.push_back(jgs2_solver::Pending{kid, e0, e1});
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, s->stream, args...);
+    }
+}
 
 __device__ __forceinline__ int xcd_remap(int i, int nb) {
     const int x = i & 7, j = i >> 3;
@@ -46,30 +63,32 @@ __device__ __forceinline__ void load_tet(const float4* __restrict__ tet, int t, 
 }
 
 // grad N of corner c: rows of Dm^-1 for corners 1..3, minus their sum for 0.
+// (Static selects: indexing D with a runtime corner would move the record
+// to scratch memory.)
 __device__ __forceinline__ void gradN(const float* D, int c, float* gn) {
-    if (c == 0) {
-        gn[0] = -(D[0] + D[3] + D[6]);
-        gn[1] = -(D[1] + D[4] + D[7]);
-        gn[2] = -(D[2] + D[5] + D[8]);
-    } else {
-        gn[0] = D[3 * (c - 1)]; gn[1] = D[3 * (c - 1) + 1]; gn[2] = D[3 * (c - 1) + 2];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const float r0 = D[j], r1 = D[3 + j], r2 = D[6 + j];
+        gn[j] = c == 0 ? -(r0 + r1 + r2) : (c == 1 ? r0 : (c == 2 ? r1 : r2));
     }
 }
 
 // H = F - I = [u1-u0, u2-u0, u3-u0] Dm^-1 (displacement gradient)
-__device__ __forceinline__ void dispgrad(const float* __restrict__ u, int nV, const Tet& T, float* F) {
-    float du[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const float u0 = u[i * nV + T.id[0]];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) du[k][i] = u[i * nV + T.id[k + 1]] - u0;
-    }
+__device__ __forceinline__ void dispgrad(const float4* __restrict__ u, const Tet& T, float* H) {
+    const float4 u0 = u[T.id[0]], u1 = u[T.id[1]], u2 = u[T.id[2]], u3 = u[T.id[3]];
+    const float du[3][3] = {{u1.x - u0.x, u1.y - u0.y, u1.z - u0.z},
+                            {u2.x - u0.x, u2.y - u0.y, u2.z - u0.z},
+                            {u3.x - u0.x, u3.y - u0.y, u3.z - u0.z}};
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            F[3 * i + j] = du[0][i] * T.D[j] + du[1][i] * T.D[3 + j] + du[2][i] * T.D[6 + j];
+            H[3 * i + j] = du[0][i] * T.D[j] + du[1][i] * T.D[3 + j] + du[2][i] * T.D[6 + j];
+}
+
+__device__ __forceinline__ void load_rot(const float4* __restrict__ R, int v, float* M) {
+    const float4 q = R[v];
+    rot_from_quat(q.x, q.y, q.z, q.w, M);
 }
 
 // Adds w * (U_e^T H_e U_e) for the 12x3 basis U_e whose 3x3 row blocks are
@@ -108,18 +127,24 @@ __device__ __forceinline__ void galerkin_hessian(const Tet& T, const Kin<float>&
     }
 }
 
-__device__ __forceinline__ void barrier_terms(const SweepArgs& a, int v, float* g, float* H6) {
-    const float x0 = a.X[v] + a.u[v], x1 = a.X[a.nV + v] + a.u[a.nV + v], x2 = a.X[2 * a.nV + v] + a.u[2 * a.nV + v];
-    for (int p = 0; p < a.n_planes; ++p) {
-        const float* pl = a.planes[p];
-        const float d = pl[0] * x0 + pl[1] * x1 + pl[2] * x2 - pl[3];
+// IPC plane barriers of vertex v at displacement uv: gradient into g and,
+// if H6 is given, the Hessian kappa B'' n n^T into H6.
+__device__ __forceinline__ void barrier_terms(const SweepArgs& a, int v, float4 uv, float* g, float* H6) {
+    if (a.n_planes == 0) return;
+    const float4 X = a.X[v];
+    const float x0 = X.x + uv.x, x1 = X.y + uv.y, x2 = X.z + uv.z;
+#pragma unroll
+    for (int p = 0; p < JGS2_MAX_PLANES; ++p) {
+        if (p >= a.n_planes) break;
+        const float n0 = a.planes[p][0], n1 = a.planes[p][1], n2 = a.planes[p][2];
+        const float d = n0 * x0 + n1 * x1 + n2 * x2 - a.planes[p][3];
         if (d < a.d_hat && d > 0.0f) {
             const float b1 = a.kappa * barrier_d1(d, a.d_hat);
-            g[0] += b1 * pl[0]; g[1] += b1 * pl[1]; g[2] += b1 * pl[2];
+            g[0] += b1 * n0; g[1] += b1 * n1; g[2] += b1 * n2;
             if (H6) {
                 const float b2 = a.kappa * barrier_d2(d, a.d_hat);
-                H6[0] += b2 * pl[0] * pl[0]; H6[1] += b2 * pl[0] * pl[1]; H6[2] += b2 * pl[0] * pl[2];
-                H6[3] += b2 * pl[1] * pl[1]; H6[4] += b2 * pl[1] * pl[2]; H6[5] += b2 * pl[2] * pl[2];
+                H6[0] += b2 * n0 * n0; H6[1] += b2 * n0 * n1; H6[2] += b2 * n0 * n2;
+                H6[3] += b2 * n1 * n1; H6[4] += b2 * n1 * n2; H6[5] += b2 * n2 * n2;
             }
         }
     }
@@ -140,7 +165,7 @@ __device__ __forceinline__ void block_partial(double val, bool lane0, double* pa
 // ---------------------------------------------------------------------------
 // Phase 1: assembled gradient g_a (elastic + inertia + barrier), the
 // volume-weighted mean deformation gradient of the incident tets and its
-// closest rotation R_a; per-block partial sums of |g|^2 (FP64).
+// polar rotation R_a; per-block partial sums of |g|^2 (FP64).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_phase1(SweepArgs a, int want_R) {
     const int lane = threadIdx.x % LPV;
@@ -160,7 +185,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase1(SweepArgs a, int want_R) {
             load_tet(a.tet, t, T);
             float H[9], cH[9], P[9], gn[3];
             Kin<float> K;
-            dispgrad(a.u, a.nV, T, H);
+            dispgrad(a.u, T, H);
             kinematics(H, K, cH);
             snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
             gradN(T.D, c, gn);
@@ -179,18 +204,24 @@ __global__ __launch_bounds__(BLOCK) void k_phase1(SweepArgs a, int want_R) {
     double gsq = 0.0;
     if (active && lane == 0) {
         const int v = a.free_ids[f];
-        const float m = a.mh2[v];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) g[i] += m * (a.u[i * a.nV + v] - a.zu[i * a.nV + v]);
-        barrier_terms(a, v, g, nullptr);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) a.g[i * a.nV + v] = g[i];
+        const float4 uv = a.u[v], zv = a.zu[v];
+        g[0] += zv.w * (uv.x - zv.x);
+        g[1] += zv.w * (uv.y - zv.y);
+        g[2] += zv.w * (uv.z - zv.z);
+        barrier_terms(a, v, uv, g, nullptr);
+        a.g[v] = make_float4(g[0], g[1], g[2], 0.0f);
         gsq = (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
         if (want_R) {
-            float R[9];
-            closest_rotation(Fs, R);
+            float mx = 0.0f;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) a.R[i * a.nV + v] = R[i];
+            for (int i = 0; i < 9; ++i) mx = fmaxf(mx, fabsf(Fs[i]));
+            const float inv = mx > 0.0f ? 1.0f / mx : 1.0f;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Fs[i] *= inv;
+            float R[9], q[4];
+            polar_rotation(Fs, R);
+            quat_from_rot(R, q);
+            a.R[v] = make_float4(q[0], q[1], q[2], q[3]);
         }
     }
     block_partial(gsq, active && lane == 0, a.partial);
@@ -204,6 +235,20 @@ __global__ __launch_bounds__(BLOCK) void k_phase1(SweepArgs a, int want_R) {
 // with Phi_{i,a} = R_a Ubar_{i,a} R_i^T (Eq. tilde_phi); then
 // x_i <- x_i - omega A_i^-1 b_i (Eq. reduced_local).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void corotate(const float* U, const float* Ri, const float* Ra, float* Phi) {
+    float T9[9];  // U R_i^T
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            T9[3 * i + j] = U[3 * i] * Ri[3 * j] + U[3 * i + 1] * Ri[3 * j + 1] + U[3 * i + 2] * Ri[3 * j + 2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            Phi[3 * i + j] = Ra[3 * i] * T9[j] + Ra[3 * i + 1] * T9[3 + j] + Ra[3 * i + 2] * T9[6 + j];
+}
+
 __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
     __shared__ float sPhi[VPB][KMAX][9];
     const int lane = threadIdx.x % LPV;
@@ -215,35 +260,23 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
     const int f = active ? (a.list ? a.list[idx] : idx) : 0;
     const int v = a.free_ids[f];
     float Ri[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) Ri[i] = active ? a.R[i * a.nV + v] : 0.0f;
+    load_rot(a.R, v, Ri);
     float A6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, b[3] = {0.f, 0.f, 0.f};
 
     // one-ring rows: Phi_{i,a} into LDS, gradient projection
     const int nr = active ? a.ring_n[f] : 0;
     for (int k = lane; k < nr; k += LPV) {
         const int av = a.ring[(size_t)f * a.K + k];
-        float U[9], Ra[9], T9[9], Phi[9];
+        float U[9], Ra[9], Phi[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) U[q] = a.Uring[((size_t)f * 9 + q) * a.K + k];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) Ra[q] = a.R[q * a.nV + av];
-        // T9 = U R_i^T ; Phi = R_a T9
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                T9[3 * i + j] = U[3 * i] * Ri[3 * j] + U[3 * i + 1] * Ri[3 * j + 1] + U[3 * i + 2] * Ri[3 * j + 2];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                Phi[3 * i + j] = Ra[3 * i] * T9[j] + Ra[3 * i + 1] * T9[3 + j] + Ra[3 * i + 2] * T9[6 + j];
+        load_rot(a.R, av, Ra);
+        corotate(U, Ri, Ra, Phi);
 #pragma unroll
         for (int q = 0; q < 9; ++q) sPhi[vloc][k][q] = Phi[q];
-        const float g0 = a.g[av], g1 = a.g[a.nV + av], g2 = a.g[2 * a.nV + av];
+        const float4 ga = a.g[av];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) b[j] += Phi[j] * g0 + Phi[3 + j] * g1 + Phi[6 + j] * g2;
+        for (int j = 0; j < 3; ++j) b[j] += Phi[j] * ga.x + Phi[3 + j] * ga.y + Phi[6 + j] * ga.z;
     }
     __syncthreads();
 
@@ -256,7 +289,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
         load_tet(a.tet, pk >> 2, T);
         float H[9], cH[9];
         Kin<float> K;
-        dispgrad(a.u, a.nV, T, H);
+        dispgrad(a.u, T, H);
         kinematics(H, K, cH);
         float Phi[4][9];
 #pragma unroll
@@ -287,33 +320,23 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
             load_tet(a.tet, e, T);
             float H[9], cH[9];
             Kin<float> K;
-            dispgrad(a.u, a.nV, T, H);
+            dispgrad(a.u, T, H);
             kinematics(H, K, cH);
             float Phi[4][9];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int av = T.id[c];
-                float U[9], Ra[9], T9[9];
+                float U[9], Ra[9];
 #pragma unroll
                 for (int q = 0; q < 9; ++q) U[q] = rec[(5 + 9 * c + q) * a.S + s];
-#pragma unroll
-                for (int q = 0; q < 9; ++q) Ra[q] = a.R[q * a.nV + av];
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int jj = 0; jj < 3; ++jj)
-                        T9[3 * i + jj] = U[3 * i] * Ri[3 * jj] + U[3 * i + 1] * Ri[3 * jj + 1] + U[3 * i + 2] * Ri[3 * jj + 2];
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int jj = 0; jj < 3; ++jj)
-                        Phi[c][3 * i + jj] = Ra[3 * i] * T9[jj] + Ra[3 * i + 1] * T9[3 + jj] + Ra[3 * i + 2] * T9[6 + jj];
+                load_rot(a.R, av, Ra);
+                corotate(U, Ri, Ra, Phi[c]);
                 const float gc = rec[(1 + c) * a.S + s];
                 if (gc != 0.0f) {
-                    const float g0 = a.g[av], g1 = a.g[a.nV + av], g2 = a.g[2 * a.nV + av];
+                    const float4 ga = a.g[av];
 #pragma unroll
                     for (int jj = 0; jj < 3; ++jj)
-                        b[jj] += gc * (Phi[c][jj] * g0 + Phi[c][3 + jj] * g1 + Phi[c][6 + jj] * g2);
+                        b[jj] += gc * (Phi[c][jj] * ga.x + Phi[c][3 + jj] * ga.y + Phi[c][6 + jj] * ga.z);
                 }
             }
             galerkin_hessian(T, K, Phi, w, A6);
@@ -325,16 +348,15 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) b[i] = lane_sum(b[i]);
     if (active && lane == 0) {
+        const float4 uv = a.u[v];
         float gv[3] = {0.f, 0.f, 0.f};
-        barrier_terms(a, v, gv, A6);  // barrier Hessian of vertex i only (gv unused: g holds it)
+        barrier_terms(a, v, uv, gv, A6);  // barrier Hessian of vertex i only (g already holds its gradient)
         float A[9] = {A6[0], A6[1], A6[2], A6[1], A6[3], A6[4], A6[2], A6[4], A6[5]};
-        float bb[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) bb[i] = b[i] + a.g[i * a.nV + v];
+        const float4 gi = a.g[v];
+        const float bb[3] = {b[0] + gi.x, b[1] + gi.y, b[2] + gi.z};
         float dx[3];
         local_solve(A, bb, dx);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) a.unext[i * a.nV + v] = a.u[i * a.nV + v] + a.omega * dx[i];
+        a.unext[v] = make_float4(uv.x + a.omega * dx[0], uv.y + a.omega * dx[1], uv.z + a.omega * dx[2], 0.0f);
     }
 }
 
@@ -361,7 +383,7 @@ __global__ __launch_bounds__(BLOCK) void k_plain(SweepArgs a) {
             load_tet(a.tet, pk >> 2, T);
             float H[9], cH[9], P[9], gn[3];
             Kin<float> K;
-            dispgrad(a.u, a.nV, T, H);
+            dispgrad(a.u, T, H);
             kinematics(H, K, cH);
             snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
             gradN(T.D, c, gn);
@@ -389,21 +411,19 @@ __global__ __launch_bounds__(BLOCK) void k_plain(SweepArgs a) {
     double gsq = 0.0;
     if (active && lane == 0) {
         const int v = a.free_ids[f];
-        const float m = a.mh2[v];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) g[i] += m * (a.u[i * a.nV + v] - a.zu[i * a.nV + v]);
+        const float4 uv = a.u[v], zv = a.zu[v];
+        const float m = zv.w;
+        g[0] += m * (uv.x - zv.x);
+        g[1] += m * (uv.y - zv.y);
+        g[2] += m * (uv.z - zv.z);
         A6[0] += m; A6[3] += m; A6[5] += m;
-        barrier_terms(a, v, g, A6);
+        barrier_terms(a, v, uv, g, A6);
         gsq = (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
         float A[9] = {A6[0], A6[1], A6[2], A6[1], A6[3], A6[4], A6[2], A6[4], A6[5]};
         float dx[3];
         local_solve(A, g, dx);
-        float* out = a.in_place ? const_cast<float*>(a.u) : a.unext;
-        float un[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) un[i] = a.u[i * a.nV + v] + a.omega * dx[i];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) out[i * a.nV + v] = un[i];
+        float4* out = a.in_place ? const_cast<float4*>(a.u) : a.unext;
+        out[v] = make_float4(uv.x + a.omega * dx[0], uv.y + a.omega * dx[1], uv.z + a.omega * dx[2], 0.0f);
     }
     block_partial(gsq, active && lane == 0, a.partial);
 }
@@ -413,8 +433,7 @@ __global__ void k_commit(SweepArgs a) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.n_list) return;
     const int v = a.free_ids[a.list[idx]];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) const_cast<float*>(a.u)[i * a.nV + v] = a.unext[i * a.nV + v];
+    const_cast<float4*>(a.u)[v] = a.unext[v];
 }
 
 // Fixed-order sum of n per-block partials into out[0] (one block).
@@ -431,34 +450,34 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ in, i
     if (threadIdx.x == 0) out[0] = s[0];
 }
 
-// z = xhat + h vhat + h^2 g on free vertices (displacement form), x0 = xhat.
-__global__ void k_predict(int nV, const float* __restrict__ uhat, const float* __restrict__ vhat,
+// z = xhat + h vhat + h^2 g on free vertices (displacement form; w = m/h^2),
+// x0 = xhat.
+__global__ void k_predict(int nV, const float4* __restrict__ uhat, const float4* __restrict__ vhat,
                           const float* __restrict__ mh2, float h, float g0, float g1, float g2,
-                          float* __restrict__ u, float* __restrict__ unext, float* __restrict__ zu) {
+                          float4* __restrict__ u, float4* __restrict__ unext, float4* __restrict__ zu) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nV) return;
-    const float gg[3] = {g0, g1, g2};
-    const bool free = mh2[v] > 0.0f;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const float x = uhat[i * nV + v];
-        u[i * nV + v] = x;
-        unext[i * nV + v] = x;
-        zu[i * nV + v] = free ? x + h * vhat[i * nV + v] + h * h * gg[i] : x;
+    const float4 x = uhat[v];
+    u[v] = x;
+    unext[v] = x;
+    const float m = mh2[v];
+    if (m > 0.0f) {
+        const float4 vv = vhat[v];
+        const float h2 = h * h;
+        zu[v] = make_float4(x.x + h * vv.x + h2 * g0, x.y + h * vv.y + h2 * g1, x.z + h * vv.z + h2 * g2, m);
+    } else {
+        zu[v] = make_float4(x.x, x.y, x.z, 0.0f);
     }
 }
 
 // v = (x - xhat) / h ; xhat <- x
-__global__ void k_velocity(int nV, const float* __restrict__ u, float* __restrict__ uhat,
-                           float* __restrict__ vhat, float inv_h) {
+__global__ void k_velocity(int nV, const float4* __restrict__ u, float4* __restrict__ uhat,
+                           float4* __restrict__ vhat, float inv_h) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nV) return;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const float x = u[i * nV + v];
-        vhat[i * nV + v] = (x - uhat[i * nV + v]) * inv_h;
-        uhat[i * nV + v] = x;
-    }
+    const float4 x = u[v], x0 = uhat[v];
+    vhat[v] = make_float4((x.x - x0.x) * inv_h, (x.y - x0.y) * inv_h, (x.z - x0.z) * inv_h, 0.0f);
+    uhat[v] = x;
 }
 
 // Incremental potential: per-tet V Psi(F) + per-free-vertex inertia and
@@ -472,21 +491,19 @@ __global__ __launch_bounds__(256) void k_energy(SweepArgs a, int nT) {
         load_tet(a.tet, i, T);
         float H[9], cH[9];
         Kin<float> K;
-        dispgrad(a.u, a.nV, T, H);
+        dispgrad(a.u, T, H);
         kinematics(H, K, cH);
         e += (double)snh_psi_H(H, K, cH, T.vmu, T.vlam);
     }
     if (i < a.nVf) {
         const int v = a.free_ids[i];
-        double in = 0.0;
-        for (int k = 0; k < 3; ++k) {
-            const double d = (double)a.u[k * a.nV + v] - (double)a.zu[k * a.nV + v];
-            in += d * d;
-        }
-        e += 0.5 * (double)a.mh2[v] * in;
-        const double x[3] = {(double)a.X[v] + a.u[v], (double)a.X[a.nV + v] + a.u[a.nV + v],
-                             (double)a.X[2 * a.nV + v] + a.u[2 * a.nV + v]};
-        for (int p = 0; p < a.n_planes; ++p) {
+        const float4 uv = a.u[v], zv = a.zu[v];
+        const double d0 = (double)uv.x - zv.x, d1 = (double)uv.y - zv.y, d2 = (double)uv.z - zv.z;
+        e += 0.5 * (double)zv.w * (d0 * d0 + d1 * d1 + d2 * d2);
+        const float4 X = a.X[v];
+        const double x[3] = {(double)X.x + uv.x, (double)X.y + uv.y, (double)X.z + uv.z};
+        for (int p = 0; p < JGS2_MAX_PLANES; ++p) {
+            if (p >= a.n_planes) break;
             const double d = a.planes[p][0] * x[0] + a.planes[p][1] * x[1] + a.planes[p][2] * x[2] - a.planes[p][3];
             e += (d <= 0.0) ? INFINITY : (double)a.kappa * barrier<double>(d, (double)a.d_hat);
         }
@@ -511,43 +528,44 @@ static inline int n_blocks_for(const SweepArgs& a) {
 void launch_phase1(jgs2_solver* s, const SweepArgs& a, bool want_R) {
     const int nb = n_blocks_for(a);
     if (nb == 0) return;
-    hipLaunchKernelGGL(k_phase1, dim3(nb), dim3(BLOCK), 0, s->stream, a, want_R ? 1 : 0);
+    launch(s, JGS2_K_PHASE1, k_phase1, dim3(nb), dim3(BLOCK), a, want_R ? 1 : 0);
 }
 
 void launch_phase2_cubature(jgs2_solver* s, const SweepArgs& a) {
     const int nb = n_blocks_for(a);
     if (nb == 0) return;
-    hipLaunchKernelGGL(k_phase2_cubature, dim3(nb), dim3(BLOCK), 0, s->stream, a);
+    launch(s, JGS2_K_PHASE2, k_phase2_cubature, dim3(nb), dim3(BLOCK), a);
 }
 
 void launch_plain(jgs2_solver* s, const SweepArgs& a) {
     const int nb = n_blocks_for(a);
     if (nb == 0) return;
-    hipLaunchKernelGGL(k_plain, dim3(nb), dim3(BLOCK), 0, s->stream, a);
+    launch(s, JGS2_K_PLAIN, k_plain, dim3(nb), dim3(BLOCK), a);
 }
 
 void launch_commit(jgs2_solver* s, const SweepArgs& a) {
     if (a.n_list == 0) return;
-    hipLaunchKernelGGL(k_commit, dim3((a.n_list + 255) / 256), dim3(256), 0, s->stream, a);
+    launch(s, JGS2_K_COMMIT, k_commit, dim3((a.n_list + 255) / 256), dim3(256), a);
 }
 
 void launch_reduce(jgs2_solver* s, int n) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s->stream, s->d_partial, n, s->d_red);
+    launch(s, JGS2_K_REDUCE, k_reduce, dim3(1), dim3(256), (const double*)s->d_partial, n, s->d_red);
 }
 
 void launch_predict(jgs2_solver* s, float h, const float* grav) {
-    hipLaunchKernelGGL(k_predict, dim3((s->nV + 255) / 256), dim3(256), 0, s->stream, s->nV, s->d_uhat,
-                       s->d_vhat, s->d_mh2, h, grav[0], grav[1], grav[2], s->d_u, s->d_unext, s->d_zu);
+    launch(s, JGS2_K_PREDICT, k_predict, dim3((s->nV + 255) / 256), dim3(256), s->nV, (const float4*)s->d_uhat,
+           (const float4*)s->d_vhat, (const float*)s->d_mh2, h, grav[0], grav[1], grav[2], s->d_u, s->d_unext,
+           s->d_zu);
 }
 
 void launch_velocity(jgs2_solver* s, float h) {
-    hipLaunchKernelGGL(k_velocity, dim3((s->nV + 255) / 256), dim3(256), 0, s->stream, s->nV, s->d_u, s->d_uhat,
-                       s->d_vhat, 1.0f / h);
+    launch(s, JGS2_K_VELOCITY, k_velocity, dim3((s->nV + 255) / 256), dim3(256), s->nV, (const float4*)s->d_u,
+           s->d_uhat, s->d_vhat, 1.0f / h);
 }
 
 void launch_energy(jgs2_solver* s, const SweepArgs& a, int nT) {
     const int n = nT > a.nVf ? nT : a.nVf;
-    hipLaunchKernelGGL(k_energy, dim3((n + 255) / 256), dim3(256), 0, s->stream, a, nT);
+    launch(s, JGS2_K_ENERGY, k_energy, dim3((n + 255) / 256), dim3(256), a, nT);
 }
 
 }  // namespace jgs2
