@@ -190,8 +190,11 @@ def main():
                 per_sweep = sweep_bytes("plain_jacobi", **cnt)
             per_launch = per_sweep * nsweeps / n
             achieved = per_launch / (ms * 1e-3 / n) / 1e9
+            tag = "beam16x16x128_gs" if not args.small else "beam4x4x16_gs"
+            traffic = measured_traffic("k_plain", tag) if head_mode.startswith("plain_gs") else None
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_plain",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None if traffic is None else round(traffic), "kernel": "k_plain",
                     "avg_launch_us": round(ms * 1e3 / n, 3), "launches": n,
                     "bytes_per_launch": round(per_launch)}
     jgs2_sweep = measure_cubature_sweep(sc0, corr0) if corr0 is not None else None
@@ -213,6 +216,34 @@ def main():
         "precompute_s": {f"{k:g}": round(v, 3) for k, v in precompute_s.items()},
     }
     print(json.dumps(line))
+
+
+def kernel_source_sha1():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2506_06494_amd", "csrc", "sweep.hip")
+    return hashlib.sha1(open(path, "rb").read()).hexdigest()
+
+
+def measured_traffic(kernel, workload_tag):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
+    counter reads for a 1 GiB copy), or None if that summary is missing or was
+    taken on different kernel source."""
+    import re
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if not line.startswith("traffic "):
+            continue
+        kv = dict(re.findall(r"(\w+)=(\S+)", line))
+        if kv.get("kernel") != kernel or kv.get("workload") != workload_tag:
+            continue
+        if kv.get("sweep_sha1") != kernel_source_sha1():
+            return None
+        return (float(kv["fetch_kib"]) * 1024 * float(kv["fetch_scale"]) +
+                float(kv["write_kib"]) * 1024 * float(kv["write_scale"]))
+    return None
 
 
 def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches=1):

@@ -200,14 +200,33 @@ def exact_rows(model, H, verts):
     return ocorr.ubar_rows(model, _S, verts)
 
 
+def feasibility_clamp(model, x, step):
+    """Contact (Sec. 6 with the line-search remark of Sec. 8): each vertex's
+    move is scaled by min(1, 0.9 min_p d_p / (-n_p . step)) over the planes it
+    approaches, so no vertex reaches a static plane (reading: a per-vertex,
+    per-sub-problem step bound)."""
+    if model.planes.shape[0] == 0:
+        return step
+    alpha = np.ones(step.shape[0])
+    for p in range(model.planes.shape[0]):
+        n, c = model.planes[p, :3], model.planes[p, 3]
+        d = x @ n - c
+        nd = step @ n
+        m = nd < 0
+        alpha[m] = np.minimum(alpha[m], np.maximum(0.0, 0.9 * d[m] / (-nd[m])))
+    return step * alpha[:, None]
+
+
 class Sweeper:
     """Oracle sweeps for one model and a table covering all free vertices."""
 
-    def __init__(self, model, tab=None, variant=R3, omega=1.0):
+    def __init__(self, model, tab=None, variant=R3, omega=1.0, line_search=False):
         self.model = model
         self.tab = tab
         self.variant = variant
         self.omega = omega
+        self.line_search = line_search
+        self.ls_halvings = 0
         from . import mesh as omesh
         self.inc = omesh.incidence(model.tets, model.nV)
         self.ell = _Ell(model, tab, self.inc) if (tab is not None and variant == R3) else None
@@ -237,10 +256,24 @@ class Sweeper:
         return full_subspace_systems(m, U, x, g, R, H, verts)
 
     def jacobi(self, x, z):
+        """One Jacobi sweep.  With line_search, the whole move is halved while
+        the incremental potential increases (at most 8 times; reading of the
+        global backtracking)."""
+        m = self.model
         A, b = self.systems(x, z)
         dx = local_solve(A, b)
+        step = feasibility_clamp(m, x[m.free_ids], self.omega * dx)
         xn = x.copy()
-        xn[self.model.free_ids] += self.omega * dx
+        xn[m.free_ids] += step
+        if self.line_search:
+            e0 = m.energy(x, z)
+            e1 = m.energy(xn, z)
+            k = 0
+            while not (e1 <= e0) and k < 8:
+                xn[m.free_ids] = x[m.free_ids] + 0.5 * (xn[m.free_ids] - x[m.free_ids])
+                e1 = m.energy(xn, z)
+                k += 1
+                self.ls_halvings += 1
         return xn
 
     def gauss_seidel(self, x, z, color):
@@ -249,7 +282,7 @@ class Sweeper:
             verts = np.nonzero(color == c)[0]
             A, b = self.systems(xn, z, verts)
             dx = local_solve(A, b)
-            xn[verts] += self.omega * dx
+            xn[verts] += feasibility_clamp(self.model, xn[verts], self.omega * dx)
         return xn
 
 

@@ -82,6 +82,7 @@ struct jgs2_solver {
     int n_poses = 0;
     double r0 = 0.0;
     int sweeps_in_step = 0;
+    int ls_halvings = 0;
 
     // device
     float4* d_tet = nullptr;
@@ -121,6 +122,7 @@ void launch_phase1(jgs2_solver* s, const SweepArgs& a, bool want_R);
 void launch_phase2_cubature(jgs2_solver* s, const SweepArgs& a);
 void launch_plain(jgs2_solver* s, const SweepArgs& a);
 void launch_commit(jgs2_solver* s, const SweepArgs& a);
+void launch_blend(jgs2_solver* s, const SweepArgs& a, float t);
 void launch_reduce(jgs2_solver* s, int n);
 void launch_predict(jgs2_solver* s, float h, const float* grav);
 void launch_velocity(jgs2_solver* s, float h);

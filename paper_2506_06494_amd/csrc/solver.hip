@@ -129,6 +129,7 @@ static int validate_params(const jgs2_params* p, std::string& why) {
     if (p->max_sweeps < 0 || p->check_every < 1) { why = "bad sweep limits"; return JGS2_E_INVALID; }
     if (p->n_planes < 0 || p->n_planes > JGS2_MAX_PLANES) { why = "bad plane count"; return JGS2_E_INVALID; }
     if (p->n_planes > 0 && !(p->d_hat > 0 && p->kappa >= 0)) { why = "bad barrier parameters"; return JGS2_E_INVALID; }
+    if (p->line_search && p->order != JGS2_JACOBI) { why = "the energy line search supports the Jacobi order"; return JGS2_E_INVALID; }
     for (int i = 0; i < 3; ++i)
         if (!std::isfinite(p->gravity[i])) { why = "gravity must be finite"; return JGS2_E_INVALID; }
     return JGS2_OK;
@@ -617,12 +618,37 @@ int32_t jgs2_begin_step(jgs2_solver* s) {
     s->r0 = std::sqrt(g2);
     s->in_step = true;
     s->sweeps_in_step = 0;
+    s->ls_halvings = 0;
     return JGS2_OK;
 }
 
 static void swap_u(jgs2_solver* s) {
     std::swap(s->d_u, s->d_unext);
     s->phase1_valid = false;
+}
+
+static int energy_of(jgs2_solver* s, float4* state, double* e) {
+    SweepArgs a;
+    build_sweep_args(s, a);
+    a.u = state;
+    launch_energy(s, a, s->nT);
+    return read_reduced(s, (std::max(s->nT, s->nVf) + 255) / 256, e);
+}
+
+// Global backtracking on the incremental potential (FP64 sum of FP32
+// terms): halve the Jacobi move while E(x + t dx) > E(x), at most 8 times.
+static int line_search(jgs2_solver* s) {
+    double e0 = 0, e1 = 0;
+    int r;
+    if ((r = energy_of(s, s->d_u, &e0)) || (r = energy_of(s, s->d_unext, &e1))) return r;
+    for (int k = 0; k < 8 && !(e1 <= e0); ++k) {
+        SweepArgs a;
+        build_sweep_args(s, a);
+        launch_blend(s, a, 0.5f);
+        s->ls_halvings++;
+        if ((r = energy_of(s, s->d_unext, &e1))) return r;
+    }
+    return JGS2_OK;
 }
 
 // One sweep in the configured order and variant.
@@ -636,6 +662,10 @@ static int sweep_once(jgs2_solver* s) {
             launch_phase2_cubature(s, a);
         } else {
             launch_plain(s, a);
+        }
+        if (s->p.line_search) {
+            int r = line_search(s);
+            if (r != JGS2_OK) return r;
         }
         swap_u(s);
     } else {
@@ -724,6 +754,7 @@ int32_t jgs2_step(jgs2_solver* s, jgs2_step_stats* st) {
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
     loc.sweeps = s->sweeps_in_step; loc.status = JGS2_OK; loc.r0 = s->r0; loc.r_final = rel; loc.seconds = ms * 1e-3;
+    loc.ls_halvings = s->ls_halvings;
     if (st) *st = loc;
     return JGS2_OK;
 }

@@ -150,6 +150,25 @@ __device__ __forceinline__ void barrier_terms(const SweepArgs& a, int v, float4 
     }
 }
 
+// Per-vertex feasibility clamp against the static planes: the move is scaled
+// by alpha = min(1, 0.9 min_p d_p / (-n_p . step)) over planes it approaches,
+// so no vertex reaches a plane whatever the other vertices do.
+__device__ __forceinline__ void clamp_step(const SweepArgs& a, int v, float4 uv, float* step) {
+    if (a.n_planes == 0) return;
+    const float4 X = a.X[v];
+    const float x0 = X.x + uv.x, x1 = X.y + uv.y, x2 = X.z + uv.z;
+    float alpha = 1.0f;
+#pragma unroll
+    for (int p = 0; p < JGS2_MAX_PLANES; ++p) {
+        if (p >= a.n_planes) break;
+        const float n0 = a.planes[p][0], n1 = a.planes[p][1], n2 = a.planes[p][2];
+        const float d = n0 * x0 + n1 * x1 + n2 * x2 - a.planes[p][3];
+        const float nd = n0 * step[0] + n1 * step[1] + n2 * step[2];
+        if (nd < 0.0f) alpha = fminf(alpha, fmaxf(0.0f, 0.9f * d / (-nd)));
+    }
+    step[0] *= alpha; step[1] *= alpha; step[2] *= alpha;
+}
+
 __device__ __forceinline__ void block_partial(double val, bool lane0, double* partial) {
     __shared__ double sp[VPB];
     const int vloc = threadIdx.x / LPV;
@@ -356,7 +375,9 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
         const float bb[3] = {b[0] + gi.x, b[1] + gi.y, b[2] + gi.z};
         float dx[3];
         local_solve(A, bb, dx);
-        a.unext[v] = make_float4(uv.x + a.omega * dx[0], uv.y + a.omega * dx[1], uv.z + a.omega * dx[2], 0.0f);
+        float st[3] = {a.omega * dx[0], a.omega * dx[1], a.omega * dx[2]};
+        clamp_step(a, v, uv, st);
+        a.unext[v] = make_float4(uv.x + st[0], uv.y + st[1], uv.z + st[2], 0.0f);
     }
 }
 
@@ -422,8 +443,10 @@ __global__ __launch_bounds__(BLOCK) void k_plain(SweepArgs a) {
         float A[9] = {A6[0], A6[1], A6[2], A6[1], A6[3], A6[4], A6[2], A6[4], A6[5]};
         float dx[3];
         local_solve(A, g, dx);
+        float st[3] = {a.omega * dx[0], a.omega * dx[1], a.omega * dx[2]};
+        clamp_step(a, v, uv, st);
         float4* out = a.in_place ? const_cast<float4*>(a.u) : a.unext;
-        out[v] = make_float4(uv.x + a.omega * dx[0], uv.y + a.omega * dx[1], uv.z + a.omega * dx[2], 0.0f);
+        out[v] = make_float4(uv.x + st[0], uv.y + st[1], uv.z + st[2], 0.0f);
     }
     block_partial(gsq, active && lane == 0, a.partial);
 }
@@ -434,6 +457,15 @@ __global__ void k_commit(SweepArgs a) {
     if (idx >= a.n_list) return;
     const int v = a.free_ids[a.list[idx]];
     const_cast<float4*>(a.u)[v] = a.unext[v];
+}
+
+// Backtracking: unext <- u + t (unext - u) on free vertices.
+__global__ void k_blend(SweepArgs a, float t) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= a.nVf) return;
+    const int v = a.free_ids[f];
+    const float4 x = a.u[v], y = a.unext[v];
+    a.unext[v] = make_float4(x.x + t * (y.x - x.x), x.y + t * (y.y - x.y), x.z + t * (y.z - x.z), 0.0f);
 }
 
 // Fixed-order sum of n per-block partials into out[0] (one block).
@@ -546,6 +578,10 @@ void launch_plain(jgs2_solver* s, const SweepArgs& a) {
 void launch_commit(jgs2_solver* s, const SweepArgs& a) {
     if (a.n_list == 0) return;
     launch(s, JGS2_K_COMMIT, k_commit, dim3((a.n_list + 255) / 256), dim3(256), a);
+}
+
+void launch_blend(jgs2_solver* s, const SweepArgs& a, float t) {
+    launch(s, JGS2_K_COMMIT, k_blend, dim3((a.nVf + 255) / 256), dim3(256), a, t);
 }
 
 void launch_reduce(jgs2_solver* s, int n) {

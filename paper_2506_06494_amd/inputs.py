@@ -314,3 +314,18 @@ def contact_scene(seed: int = 0, radius: float = 0.3, cell: float = 0.01, n_sphe
     return Scene(mesh=m, E=E.astype(np.float64), nu=_per_tet(0.45, m.nT), rho=_per_tet(1000.0, m.nT),
                  x0=m.X.copy(), v0=np.zeros_like(m.X), gravity=(0.0, 0.0, -9.8), planes=planes,
                  steps=120, name="spheres_in_box")
+
+
+def sphere_on_floor(radius: float = 0.05, cell: float = 0.01, gap: float = 6e-4, speed: float = 1.0,
+                    E: float = 1e5, nu: float = 0.45) -> Scene:
+    """One voxel sphere whose lowest vertex sits `gap` above the plane z = 0,
+    moving down at `speed`; gravity along -z, IPC barrier d_hat 1e-3."""
+    m = sphere_mesh(radius, cell)
+    X = m.X.copy()
+    X[:, 2] += gap - X[:, 2].min()
+    m = Mesh(X=X, tets=m.tets, pinned=m.pinned, name=m.name + "_on_floor")
+    v0 = np.zeros_like(X)
+    v0[:, 2] = -speed
+    return Scene(mesh=m, E=_per_tet(E, m.nT), nu=_per_tet(nu, m.nT), rho=_per_tet(1000.0, m.nT),
+                 x0=X.copy(), v0=v0, gravity=(0.0, 0.0, -9.8),
+                 planes=np.array([[0.0, 0.0, 1.0, 0.0]]), steps=1, name="sphere_on_floor")

@@ -7,6 +7,8 @@ from paper_2506_06494_amd import jgs2
 
 def make_solver(scene, **params):
     kw = dict(dt=scene.dt, gravity=scene.gravity)
+    if scene.planes.shape[0]:
+        kw.update(planes=scene.planes, d_hat=scene.d_hat, kappa=scene.kappa)
     kw.update(params)
     s = jgs2.Solver(**kw)
     m = scene.mesh
