@@ -11,16 +11,17 @@ import numpy as np
 import scipy.sparse.linalg as spla
 
 
-def newton_solve(model, xhat, vhat, tol=1e-12, max_iter=60, project=True):
-    """Minimise E for one implicit-Euler step from x0 = xhat.
+def newton_solve(model, xhat, vhat, tol=1e-12, max_iter=60, project=True, x_start=None):
+    """Minimise E for one implicit-Euler step from x0 = xhat (or from
+    ``x_start`` when given, the residual still being scaled by |g(xhat)|).
 
     Returns (x*, residual history), the residual being |g(x)| / |g(x0)| over
     free DOFs."""
     z = model.inertial_target(xhat, vhat)
-    x = xhat.copy()
+    r0 = np.linalg.norm(model.to_free(model.gradient(xhat, z)))
+    x = xhat.copy() if x_start is None else np.array(x_start, dtype=np.float64)
     g = model.gradient(x, z)
-    r0 = np.linalg.norm(model.to_free(g))
-    hist = [1.0]
+    hist = [np.linalg.norm(model.to_free(g)) / r0 if r0 > 0 else 0.0]
     if r0 == 0.0:
         return x, hist
     for _ in range(max_iter):
@@ -31,11 +32,20 @@ def newton_solve(model, xhat, vhat, tol=1e-12, max_iter=60, project=True):
         e0 = model.energy(x, z)
         slope = float(np.sum(g * dx))
         alpha = 1.0
-        for _ls in range(40):
-            e1 = model.energy(x + alpha * dx, z)
-            if e1 <= e0 + 1e-4 * alpha * slope + 1e-14 * abs(e0):
-                break
-            alpha *= 0.5
+        if -slope <= 1e-12 * abs(e0):
+            # the predicted decrease is below what an FP64 energy sum resolves:
+            # backtrack on the gradient norm instead
+            gn = np.linalg.norm(model.to_free(g))
+            for _ls in range(40):
+                if np.linalg.norm(model.to_free(model.gradient(x + alpha * dx, z))) < gn:
+                    break
+                alpha *= 0.5
+        else:
+            for _ls in range(40):
+                e1 = model.energy(x + alpha * dx, z)
+                if e1 <= e0 + 1e-4 * alpha * slope + 1e-14 * abs(e0):
+                    break
+                alpha *= 0.5
         x = x + alpha * dx
         g = model.gradient(x, z)
         hist.append(np.linalg.norm(model.to_free(g)) / r0)
