@@ -76,6 +76,9 @@ typedef struct jgs2_params {
     int32_t n_planes;           /* static planes n . x >= c, 0..JGS2_MAX_PLANES */
     int32_t line_search;        /* 1: feasibility clamp + energy backtracking */
     double  planes[JGS2_MAX_PLANES][4];  /* (n_x, n_y, n_z, c), n unit length */
+    double  adj_rel_tol;        /* adjoint solves stop at |H y - b| / |b| <= adj_rel_tol */
+    int32_t adj_max_sweeps;     /* sweep cap per adjoint solve */
+    int32_t reserved;
 } jgs2_params;
 
 typedef struct jgs2_step_stats {
@@ -88,9 +91,19 @@ typedef struct jgs2_step_stats {
     int32_t reserved;
 } jgs2_step_stats;
 
+typedef struct jgs2_adjoint_stats {
+    int32_t steps;              /* steps pulled back */
+    int32_t status;             /* JGS2_OK or the first failure */
+    int64_t adjoint_sweeps;     /* linear sweeps over all steps */
+    int64_t forward_sweeps;     /* sweeps of the recomputed forward steps */
+    double  max_rel_res;        /* largest final |H y - b| / |b| over the steps */
+    double  seconds;            /* device time of the whole backward pass */
+} jgs2_adjoint_stats;
+
 /* Fills *p with defaults: dt 1/120, gravity (0,-9.8,0), JGS2_PLAIN,
  * JGS2_JACOBI, omega 1, rel_tol 1e-5, max_sweeps 20000, check_every 8,
- * d_hat 1e-3, kappa 1e4, no planes, no line search. */
+ * d_hat 1e-3, kappa 1e4, no planes, no line search, adj_rel_tol 1e-5,
+ * adj_max_sweeps 20000. */
 void jgs2_default_params(jgs2_params* p);
 
 /* Creates a handle.  Fails with JGS2_E_INVALID on a bad parameter set and
@@ -165,6 +178,35 @@ int32_t jgs2_end_step(jgs2_solver* s);
 
 /* |g| over free DOFs at the current iterate, and |g| / r0. */
 int32_t jgs2_residual(jgs2_solver* s, double* abs_res, double* rel_res);
+/* Differentiable rollout.  The paper defines the forward step only; its
+ * derivative is taken through the step's optimality condition
+ * G(x_{n+1}; x_n, v_n, theta) = grad E = 0 (Sec. 3, Eq. variation) with
+ * theta_e = log E_e per tet.  For cotangents (xbar_{n+1}, vbar_{n+1}) of a
+ * step's outputs, with H the Hessian of E at x_{n+1}:
+ *     H y = xbar_{n+1} + vbar_{n+1} / h
+ *     thetabar_e -= y_e . grad_{x_e}(V_e Psi_e(x_{n+1}))
+ *     xbar_n = M y / h^2 - vbar_{n+1} / h,   vbar_n = M y / h
+ * (rows of pinned vertices are zero).  H y = b is solved by linear
+ * per-vertex sweeps in the configured order and omega: the residual
+ * r = H y - b replaces the gradient and each vertex takes the 3x3 step
+ * -A_i^-1 r_i with A_i = H_ii, as in the forward plain sweeps.
+ *
+ * jgs2_rollout runs n_steps forward steps from the current state (as
+ * jgs2_step, same parameters) and keeps the state at every ckpt_every-th
+ * step on the device.  jgs2_rollout_backward pulls (xbar_N, vbar_N) (nV x 3;
+ * vbar may be NULL for zero) back through the whole rollout, recomputing the
+ * steps of each checkpoint segment from its checkpoint, and writes
+ * thetabar (nT), xbar_0 and vbar_0 (nV x 3 each; any may be NULL).  The
+ * state is left at the end of the rollout.  set_state, set_material,
+ * set_params and upload_mesh discard the rollout (JGS2_E_NOT_READY).  A
+ * recomputed step or adjoint solve that diverges (residual past 1e8 x its
+ * scale) or turns non-finite returns JGS2_E_DIVERGED / JGS2_E_NONFINITE;
+ * an adjoint solve that reaches adj_max_sweeps is not an error, and
+ * stats->max_rel_res reports the largest final relative residual. */
+int32_t jgs2_rollout(jgs2_solver* s, int32_t n_steps, int32_t ckpt_every, jgs2_step_stats* last);
+int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* vbar, double* thetabar,
+                              double* xbar0, double* vbar0, jgs2_adjoint_stats* stats);
+
 /* Incremental potential E at the current iterate (FP64 sum of FP32 terms). */
 int32_t jgs2_energy(jgs2_solver* s, double* e);
 /* Assembled gradient g (nV x 3, zero at pinned vertices) and per-vertex
@@ -188,7 +230,10 @@ int32_t jgs2_get_coloring(jgs2_solver* s, int32_t* color, int32_t* n_colors);
 #define JGS2_K_PREDICT   5
 #define JGS2_K_VELOCITY  6
 #define JGS2_K_ENERGY    7
-#define JGS2_NKERNELS    8
+#define JGS2_K_LINEAR    8   /* adjoint: linear per-vertex sweep on H y = b */
+#define JGS2_K_PARAMGRAD 9   /* adjoint: per-tet stiffness gradient */
+#define JGS2_K_ADJVEC    10  /* adjoint: mass products, next right-hand side */
+#define JGS2_NKERNELS    11
 int32_t jgs2_set_profiling(jgs2_solver* s, int32_t on);
 int32_t jgs2_kernel_times(jgs2_solver* s, double* ms, int64_t* launches);
 

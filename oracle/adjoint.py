@@ -27,10 +27,9 @@ the dot-product identity against the forward-mode tangent in this module and
 by the symmetry of H.
 """
 import numpy as np
-import scipy.sparse.linalg as spla
 
 from . import snh
-from .newton import newton_solve
+from .newton import newton_solve, sparse_solve
 
 
 def elastic_element_forces(model, x):
@@ -56,14 +55,15 @@ def initial_velocity(model, u):
 
 
 def forward(model, x0, v0, n_steps, tol=1e-12):
-    """Implicit-Euler steps with the global Newton solve (projected Hessian,
-    then the exact one near the minimiser, where it is positive definite, to
-    get past the linear tail of the projected iteration); returns the lists
-    of positions and velocities x_0..x_N, v_0..v_N."""
+    """Implicit-Euler steps with the global Newton solve (projected Hessian;
+    if that stalls in a linear tail, the exact Hessian from there on, which
+    is positive definite near the minimiser); returns the lists of
+    positions and velocities x_0..x_N, v_0..v_N."""
     xs, vs = [np.array(x0, dtype=np.float64)], [np.array(v0, dtype=np.float64)]
     for _ in range(n_steps):
-        x, hist = newton_solve(model, xs[-1], vs[-1], tol=1e-6)
-        x, hist = newton_solve(model, xs[-1], vs[-1], tol=tol, project=False, x_start=x)
+        x, hist = newton_solve(model, xs[-1], vs[-1], tol=tol, max_iter=12)
+        if hist[-1] > tol:
+            x, hist = newton_solve(model, xs[-1], vs[-1], tol=tol, project=False, x_start=x)
         g = np.linalg.norm(model.to_free(model.gradient(x, model.inertial_target(xs[-1], vs[-1]))))
         if hist[-1] > 1e-8 and g > 1e-10:                   # second test: rounding floor near rest [N]
             raise RuntimeError(f"forward Newton stalled at {hist[-1]:.3e} (|g| = {g:.3e} N)")
@@ -79,7 +79,7 @@ def step_adjoint(model, x_next, xbar, vbar):
     x_next.  Returns (dthetabar (T,), xbar_n, vbar_n, y)."""
     H = model.hessian(x_next, project=False)
     rhs = model.to_free(xbar + vbar / model.h)
-    y = model.from_free(spla.spsolve(H.tocsc(), rhs))
+    y = model.from_free(sparse_solve(H, rhs))
     fe = elastic_element_forces(model, x_next)
     dtheta = -np.einsum("tai,tai->t", y[model.tets], fe)
     My = model.mass[:, None] * y
@@ -117,7 +117,7 @@ def tangent(model, xs, dtheta, dx0, dv0):
         np.add.at(f, model.tets.ravel(),
                   (np.asarray(dtheta)[:, None, None] * elastic_element_forces(model, xs[n])).reshape(-1, 3))
         rhs = model.mass[:, None] * (dx + model.h * dv) / model.h ** 2 - f
-        dxn = model.from_free(spla.spsolve(H.tocsc(), model.to_free(rhs)))
+        dxn = model.from_free(sparse_solve(H, model.to_free(rhs)))
         dv = (dxn - dx) / model.h
         dx = dxn
     return dx, dv

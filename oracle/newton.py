@@ -11,6 +11,11 @@ import numpy as np
 import scipy.sparse.linalg as spla
 
 
+def sparse_solve(H, b):
+    """Direct sparse solve (SuperLU, minimum-degree ordering on H + H^T)."""
+    return spla.splu(H.tocsc(), permc_spec="MMD_AT_PLUS_A").solve(b)
+
+
 def newton_solve(model, xhat, vhat, tol=1e-12, max_iter=60, project=True, x_start=None):
     """Minimise E for one implicit-Euler step from x0 = xhat (or from
     ``x_start`` when given, the residual still being scaled by |g(xhat)|).
@@ -28,7 +33,7 @@ def newton_solve(model, xhat, vhat, tol=1e-12, max_iter=60, project=True, x_star
         if hist[-1] <= tol:
             break
         H = model.hessian(x, project=project)
-        dx = model.from_free(spla.spsolve(H.tocsc(), -model.to_free(g)))
+        dx = model.from_free(sparse_solve(H, -model.to_free(g)))
         e0 = model.energy(x, z)
         slope = float(np.sum(g * dx))
         alpha = 1.0

@@ -49,6 +49,12 @@ struct SweepArgs {
     int n_planes;
     float planes[JGS2_MAX_PLANES][4];
     float d_hat, kappa;
+    // linear (adjoint) sweeps on H(u) y = rhs
+    const float4* ly;       // [nV] current y
+    float4* lynext;         // [nV] Jacobi output
+    const float4* lrhs;     // [nV] right-hand side
+    const float* mh2;       // [nV] m_a / h^2 (0 if pinned)
+    int no_write;           // residual partials only, no update
 };
 
 }  // namespace jgs2
@@ -106,6 +112,13 @@ struct jgs2_solver {
     struct Pending { int k; hipEvent_t a, b; };
     std::vector<Pending> kt_pending;
     std::vector<hipEvent_t> ev_pool;
+    // differentiable rollout: checkpoints [n_ck + 1][nV] (last = end state),
+    // recomputed segment states [ckpt_every][nV], adjoint vectors
+    int ro_steps = 0, ro_every = 0, ro_nck = 0;
+    bool ro_valid = false;
+    float4 *d_ck_u = nullptr, *d_ck_v = nullptr, *d_seg = nullptr;
+    float4 *d_y = nullptr, *d_ynext = nullptr, *d_xbar = nullptr, *d_vbar = nullptr, *d_rhs = nullptr;
+    double* d_thbar = nullptr;
 
     int fail(int code, const std::string& msg) {
         err = msg;
@@ -122,6 +135,10 @@ void launch_phase1(jgs2_solver* s, const SweepArgs& a, bool want_R);
 void launch_phase2_cubature(jgs2_solver* s, const SweepArgs& a);
 void launch_plain(jgs2_solver* s, const SweepArgs& a);
 void launch_commit(jgs2_solver* s, const SweepArgs& a);
+void launch_linear(jgs2_solver* s, const SweepArgs& a);
+void launch_param_grad(jgs2_solver* s, const float4* u, const float4* y, double* thbar);
+void launch_adj_vec(jgs2_solver* s, const float4* y, float4* xbar, float4* vbar, float4* rhs);
+void launch_norm2(jgs2_solver* s, const float4* w);
 void launch_blend(jgs2_solver* s, const SweepArgs& a, float t);
 void launch_reduce(jgs2_solver* s, int n);
 void launch_predict(jgs2_solver* s, float h, const float* grav);

@@ -30,6 +30,9 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_zu); dfree(s->d_mh2); dfree(s->d_g); dfree(s->d_R); dfree(s->d_free); dfree(s->d_inc);
     dfree(s->d_inc_n); dfree(s->d_ring); dfree(s->d_ring_n); dfree(s->d_incslot); dfree(s->d_colperm);
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
+    dfree(s->d_ck_u); dfree(s->d_ck_v); dfree(s->d_seg); dfree(s->d_y); dfree(s->d_ynext); dfree(s->d_xbar);
+    dfree(s->d_vbar); dfree(s->d_rhs); dfree(s->d_thbar);
+    s->ro_valid = false;
 }
 
 void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
@@ -130,6 +133,7 @@ static int validate_params(const jgs2_params* p, std::string& why) {
     if (p->n_planes < 0 || p->n_planes > JGS2_MAX_PLANES) { why = "bad plane count"; return JGS2_E_INVALID; }
     if (p->n_planes > 0 && !(p->d_hat > 0 && p->kappa >= 0)) { why = "bad barrier parameters"; return JGS2_E_INVALID; }
     if (p->line_search && p->order != JGS2_JACOBI) { why = "the energy line search supports the Jacobi order"; return JGS2_E_INVALID; }
+    if (!(p->adj_rel_tol > 0) || p->adj_max_sweeps < 0) { why = "bad adjoint solve limits"; return JGS2_E_INVALID; }
     for (int i = 0; i < 3; ++i)
         if (!std::isfinite(p->gravity[i])) { why = "gravity must be finite"; return JGS2_E_INVALID; }
     return JGS2_OK;
@@ -184,6 +188,8 @@ void jgs2_default_params(jgs2_params* p) {
     p->check_every = 8;
     p->d_hat = 1e-3;
     p->kappa = 1e4;
+    p->adj_rel_tol = 1e-5;
+    p->adj_max_sweeps = 20000;
 }
 
 int32_t jgs2_create(const jgs2_params* p, jgs2_solver** out) {
@@ -227,6 +233,7 @@ int32_t jgs2_set_params(jgs2_solver* s, const jgs2_params* p) {
         return s->fail(JGS2_E_INVALID, "dt and gravity cannot change inside a step");
     const bool dt_changed = p->dt != s->p.dt;
     s->p = *p;
+    s->ro_valid = false;
     if (dt_changed && s->have_material) {
         if ((r = upload_material_records(s)) != JGS2_OK) return r;
     }
@@ -407,6 +414,7 @@ int32_t jgs2_set_material(jgs2_solver* s, const double* E, const double* nu, con
     if (r != JGS2_OK) return r;
     s->have_material = true;
     s->have_corr = false;
+    s->ro_valid = false;
     return JGS2_OK;
 }
 
@@ -545,6 +553,7 @@ int32_t jgs2_set_state(jgs2_solver* s, const double* x, const double* v) {
     s->have_state = true;
     s->in_step = false;
     s->phase1_valid = false;
+    s->ro_valid = false;
     return JGS2_OK;
 }
 
@@ -831,6 +840,218 @@ int32_t jgs2_get_coloring(jgs2_solver* s, int32_t* color, int32_t* n_colors) {
     if (color) std::copy(s->color.begin(), s->color.end(), color);
     if (n_colors) *n_colors = s->n_colors;
     return JGS2_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Differentiable rollout (adjoint of the step map through its optimality
+// condition) with checkpointed recomputation.
+// ---------------------------------------------------------------------------
+static int copy_v4(jgs2_solver* s, float4* dst, const float4* src) {
+    return jgs2::hip_check(s, hipMemcpyAsync(dst, src, (size_t)s->nV * sizeof(float4), hipMemcpyDeviceToDevice,
+                                             s->stream), "state copy");
+}
+
+static int save_checkpoint(jgs2_solver* s, int slot) {
+    const size_t off = (size_t)slot * s->nV;
+    int r;
+    if ((r = copy_v4(s, s->d_ck_u + off, s->d_uhat)) || (r = copy_v4(s, s->d_ck_v + off, s->d_vhat))) return r;
+    return JGS2_OK;
+}
+
+static int load_checkpoint(jgs2_solver* s, int slot) {
+    const size_t off = (size_t)slot * s->nV;
+    int r;
+    if ((r = copy_v4(s, s->d_uhat, s->d_ck_u + off)) || (r = copy_v4(s, s->d_u, s->d_ck_u + off)) ||
+        (r = copy_v4(s, s->d_unext, s->d_ck_u + off)) || (r = copy_v4(s, s->d_vhat, s->d_ck_v + off)))
+        return r;
+    s->in_step = false;
+    s->phase1_valid = false;
+    return JGS2_OK;
+}
+
+// |H y - rhs|^2 over free DOFs at the displacement a.u (no update).
+static int linear_residual2(jgs2_solver* s, SweepArgs a, double* r2) {
+    a.list = nullptr;
+    a.n_list = 0;
+    a.no_write = 1;
+    a.ly = s->d_y;
+    launch_linear(s, a);
+    return read_reduced(s, (s->nVf + VPB - 1) / VPB, r2);
+}
+
+// Solves H(xstar) y = rhs (device d_rhs) by linear sweeps, warm-started from
+// the y already in d_y.
+static int adjoint_solve(jgs2_solver* s, const float4* xstar, int64_t* sweeps, double* rel) {
+    SweepArgs a;
+    build_sweep_args(s, a);
+    a.u = xstar;
+    a.lrhs = s->d_rhs;
+    a.mh2 = s->d_mh2;
+    double b2 = 0.0, r2 = 0.0;
+    launch_norm2(s, s->d_rhs);
+    int r = read_reduced(s, (s->nVf + 255) / 256, &b2);
+    if (r != JGS2_OK) return r;
+    if (!std::isfinite(b2)) return s->fail(JGS2_E_NONFINITE, "non-finite adjoint right-hand side");
+    *rel = 0.0;
+    if (b2 == 0.0) {
+        HIPCHK(hipMemsetAsync(s->d_y, 0, (size_t)s->nV * sizeof(float4), s->stream));
+        return JGS2_OK;
+    }
+    if ((r = linear_residual2(s, a, &r2)) != JGS2_OK) return r;
+    *rel = std::sqrt(r2 / b2);
+    int k = 0;
+    while (*rel > s->p.adj_rel_tol && k < s->p.adj_max_sweeps) {
+        const int n = std::min(s->p.check_every, s->p.adj_max_sweeps - k);
+        for (int i = 0; i < n; ++i) {
+            if (s->p.order == JGS2_JACOBI) {
+                SweepArgs aj = a;
+                aj.ly = s->d_y;
+                aj.lynext = s->d_ynext;
+                launch_linear(s, aj);
+                std::swap(s->d_y, s->d_ynext);
+            } else {
+                for (int c = 0; c < s->n_colors; ++c) {
+                    SweepArgs ac = a;
+                    ac.ly = s->d_y;
+                    ac.in_place = 1;
+                    ac.list = s->d_colperm + s->col_off[c];
+                    ac.n_list = s->col_off[c + 1] - s->col_off[c];
+                    launch_linear(s, ac);
+                }
+            }
+        }
+        HIPCHK(hipGetLastError());
+        k += n;
+        if ((r = linear_residual2(s, a, &r2)) != JGS2_OK) return r;
+        *rel = std::sqrt(r2 / b2);
+        if (!std::isfinite(*rel)) return s->fail(JGS2_E_NONFINITE, "non-finite adjoint residual");
+        if (*rel > 1e8) return s->fail(JGS2_E_DIVERGED, "adjoint residual exceeded 1e8 x |b|");
+    }
+    *sweeps += k;
+    return JGS2_OK;
+}
+
+extern "C" {
+
+int32_t jgs2_rollout(jgs2_solver* s, int32_t n_steps, int32_t ckpt_every, jgs2_step_stats* last) {
+    if (!s) return JGS2_E_INVALID;
+    if (n_steps < 1 || ckpt_every < 1) return s->fail(JGS2_E_INVALID, "n_steps and ckpt_every must be >= 1");
+    if (!ready_to_step(s)) return JGS2_E_NOT_READY;
+    if (s->in_step) return s->fail(JGS2_E_NOT_READY, "rollout inside begin_step/end_step");
+    s->ro_valid = false;
+    const int n_ck = (n_steps + ckpt_every - 1) / ckpt_every;
+    const size_t nV = s->nV;
+    int r;
+    if ((r = dalloc(s, s->d_ck_u, (n_ck + 1) * nV)) || (r = dalloc(s, s->d_ck_v, (n_ck + 1) * nV)) ||
+        (r = dalloc(s, s->d_seg, (size_t)std::min(ckpt_every, n_steps) * nV)))
+        return r;
+    jgs2_step_stats st;
+    std::memset(&st, 0, sizeof(st));
+    for (int n = 0; n < n_steps; ++n) {
+        if (n % ckpt_every == 0 && (r = save_checkpoint(s, n / ckpt_every)) != JGS2_OK) return r;
+        if ((r = jgs2_step(s, &st)) != JGS2_OK) {
+            if (last) *last = st;
+            return r;
+        }
+    }
+    if ((r = save_checkpoint(s, n_ck)) != JGS2_OK) return r;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->ro_steps = n_steps;
+    s->ro_every = ckpt_every;
+    s->ro_nck = n_ck;
+    s->ro_valid = true;
+    if (last) *last = st;
+    return JGS2_OK;
+}
+
+int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* vbar, double* thetabar,
+                              double* xbar0, double* vbar0, jgs2_adjoint_stats* stats) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->ro_valid) return s->fail(JGS2_E_NOT_READY, "no rollout to differentiate");
+    if (!xbar) return s->fail(JGS2_E_INVALID, "NULL xbar");
+    jgs2_adjoint_stats loc;
+    std::memset(&loc, 0, sizeof(loc));
+    const size_t nV = s->nV;
+    const double h = s->p.dt;
+    std::vector<float4> xb(nV), vb(nV), rhs(nV);
+    for (size_t a = 0; a < nV; ++a) {
+        double x3[3] = {0, 0, 0}, v3[3] = {0, 0, 0};
+        if (!s->pinned[a])
+            for (int i = 0; i < 3; ++i) {
+                x3[i] = xbar[3 * a + i];
+                v3[i] = vbar ? vbar[3 * a + i] : 0.0;
+                if (!std::isfinite(x3[i]) || !std::isfinite(v3[i])) return s->fail(JGS2_E_INVALID, "non-finite cotangent");
+            }
+        xb[a] = make_float4((float)x3[0], (float)x3[1], (float)x3[2], 0.f);
+        vb[a] = make_float4((float)v3[0], (float)v3[1], (float)v3[2], 0.f);
+        rhs[a] = make_float4((float)(x3[0] + v3[0] / h), (float)(x3[1] + v3[1] / h), (float)(x3[2] + v3[2] / h), 0.f);
+    }
+    int r;
+    if ((r = dalloc(s, s->d_y, nV)) || (r = dalloc(s, s->d_ynext, nV)) || (r = dalloc(s, s->d_xbar, nV)) ||
+        (r = dalloc(s, s->d_vbar, nV)) || (r = dalloc(s, s->d_rhs, nV)) || (r = dalloc(s, s->d_thbar, (size_t)s->nT)))
+        return r;
+    hipEvent_t e0 = pool_event(s), e1 = pool_event(s);
+    HIPCHK(hipEventRecord(e0, s->stream));
+    if ((r = upload(s, s->d_xbar, xb.data(), nV)) || (r = upload(s, s->d_vbar, vb.data(), nV)) ||
+        (r = upload(s, s->d_rhs, rhs.data(), nV)))
+        return r;
+    HIPCHK(hipMemsetAsync(s->d_y, 0, nV * sizeof(float4), s->stream));
+    HIPCHK(hipMemsetAsync(s->d_ynext, 0, nV * sizeof(float4), s->stream));
+    HIPCHK(hipMemsetAsync(s->d_thbar, 0, (size_t)s->nT * sizeof(double), s->stream));
+    int status = JGS2_OK;
+    for (int k = s->ro_nck - 1; k >= 0 && status == JGS2_OK; --k) {
+        const int n0 = k * s->ro_every, n1 = std::min(n0 + s->ro_every, s->ro_steps);
+        if ((r = load_checkpoint(s, k)) != JGS2_OK) return r;
+        for (int n = n0; n < n1 && status == JGS2_OK; ++n) {
+            jgs2_step_stats st;
+            status = jgs2_step(s, &st);
+            loc.forward_sweeps += st.sweeps;
+            if (status == JGS2_OK && (r = copy_v4(s, s->d_seg + (size_t)(n - n0) * nV, s->d_uhat)) != JGS2_OK)
+                return r;
+        }
+        for (int n = n1 - 1; n >= n0 && status == JGS2_OK; --n) {
+            const float4* xstar = s->d_seg + (size_t)(n - n0) * nV;
+            double rel = 0.0;
+            status = adjoint_solve(s, xstar, &loc.adjoint_sweeps, &rel);
+            if (status != JGS2_OK) break;
+            loc.max_rel_res = std::max(loc.max_rel_res, rel);
+            launch_param_grad(s, xstar, s->d_y, s->d_thbar);
+            launch_adj_vec(s, s->d_y, s->d_xbar, s->d_vbar, s->d_rhs);
+            HIPCHK(hipGetLastError());
+            loc.steps++;
+        }
+    }
+    // leave the state at the end of the rollout
+    if ((r = load_checkpoint(s, s->ro_nck)) != JGS2_OK) return r;
+    HIPCHK(hipEventRecord(e1, s->stream));
+    if (status == JGS2_OK) {
+        std::vector<double> th((size_t)s->nT);
+        HIPCHK(hipMemcpyAsync(th.data(), s->d_thbar, th.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipMemcpyAsync(xb.data(), s->d_xbar, nV * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipMemcpyAsync(vb.data(), s->d_vbar, nV * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        if (thetabar) std::memcpy(thetabar, th.data(), th.size() * sizeof(double));
+        for (size_t a = 0; a < nV; ++a) {
+            const float x3[3] = {xb[a].x, xb[a].y, xb[a].z}, v3[3] = {vb[a].x, vb[a].y, vb[a].z};
+            for (int i = 0; i < 3; ++i) {
+                if (xbar0) xbar0[3 * a + i] = x3[i];
+                if (vbar0) vbar0[3 * a + i] = v3[i];
+            }
+        }
+    }
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    s->ev_pool.push_back(e0);
+    s->ev_pool.push_back(e1);
+    loc.seconds = ms * 1e-3;
+    loc.status = status;
+    if (stats) *stats = loc;
+    // a recompute that differs from the rollout would leave ro_valid wrong;
+    // the forward is deterministic, so the rollout stays usable
+    return status;
 }
 
 }  // extern "C"

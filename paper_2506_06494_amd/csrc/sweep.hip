@@ -386,7 +386,14 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
 // x_i <- x_i - omega H_ii^-1 g_i.  Also leaves per-block |g|^2 partials of
 // the iterate it read.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_plain(SweepArgs a) {
+// Plain per-vertex Newton relaxation, A_i = H_ii, fused in one pass.
+// LIN = false: b_i = g_i (forward sweep on the displacement u).
+// LIN = true : b_i = (H y - rhs)_i with H the Hessian at u (held fixed): a
+//              linear sweep on H y = rhs for the adjoint; the incident
+//              tets contribute dP[dF(y)] grad N, the vertex m/h^2 y and the
+//              barrier Hessian times y.
+template <bool LIN>
+__device__ __forceinline__ void plain_body(const SweepArgs& a) {
     const int lane = threadIdx.x % LPV;
     const int vloc = threadIdx.x / LPV;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -402,14 +409,25 @@ __global__ __launch_bounds__(BLOCK) void k_plain(SweepArgs a) {
             const int c = pk & 3;
             Tet T;
             load_tet(a.tet, pk >> 2, T);
-            float H[9], cH[9], P[9], gn[3];
+            float H[9], cH[9], gn[3];
             Kin<float> K;
             dispgrad(a.u, T, H);
             kinematics(H, K, cH);
-            snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
             gradN(T.D, c, gn);
+            if (LIN) {
+                float dY[9], dP[9];
+                dispgrad(a.ly, T, dY);
+                snh_dstress(K.F, K.C, 1.0f + K.Jm1, T.vmu, T.vlam, dY, dP);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) g[i] += P[3 * i] * gn[0] + P[3 * i + 1] * gn[1] + P[3 * i + 2] * gn[2];
+                for (int i = 0; i < 3; ++i)
+                    g[i] += dP[3 * i] * gn[0] + dP[3 * i + 1] * gn[1] + dP[3 * i + 2] * gn[2];
+            } else {
+                float P[9];
+                snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    g[i] += P[3 * i] * gn[0] + P[3 * i + 1] * gn[1] + P[3 * i + 2] * gn[2];
+            }
             int k = 0;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -432,23 +450,115 @@ __global__ __launch_bounds__(BLOCK) void k_plain(SweepArgs a) {
     double gsq = 0.0;
     if (active && lane == 0) {
         const int v = a.free_ids[f];
-        const float4 uv = a.u[v], zv = a.zu[v];
-        const float m = zv.w;
-        g[0] += m * (uv.x - zv.x);
-        g[1] += m * (uv.y - zv.y);
-        g[2] += m * (uv.z - zv.z);
-        A6[0] += m; A6[3] += m; A6[5] += m;
-        barrier_terms(a, v, uv, g, A6);
+        const float4 uv = a.u[v];
+        float4 base;
+        if (LIN) {
+            const float4 yv = a.ly[v], rv = a.lrhs[v];
+            const float m = a.mh2[v];
+            float Hb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, gb[3] = {0.f, 0.f, 0.f};
+            barrier_terms(a, v, uv, gb, Hb);
+            g[0] += m * yv.x - rv.x + Hb[0] * yv.x + Hb[1] * yv.y + Hb[2] * yv.z;
+            g[1] += m * yv.y - rv.y + Hb[1] * yv.x + Hb[3] * yv.y + Hb[4] * yv.z;
+            g[2] += m * yv.z - rv.z + Hb[2] * yv.x + Hb[4] * yv.y + Hb[5] * yv.z;
+            A6[0] += m + Hb[0]; A6[1] += Hb[1]; A6[2] += Hb[2];
+            A6[3] += m + Hb[3]; A6[4] += Hb[4]; A6[5] += m + Hb[5];
+            base = yv;
+        } else {
+            const float4 zv = a.zu[v];
+            const float m = zv.w;
+            g[0] += m * (uv.x - zv.x);
+            g[1] += m * (uv.y - zv.y);
+            g[2] += m * (uv.z - zv.z);
+            A6[0] += m; A6[3] += m; A6[5] += m;
+            barrier_terms(a, v, uv, g, A6);
+            base = uv;
+        }
         gsq = (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
-        float A[9] = {A6[0], A6[1], A6[2], A6[1], A6[3], A6[4], A6[2], A6[4], A6[5]};
-        float dx[3];
-        local_solve(A, g, dx);
-        float st[3] = {a.omega * dx[0], a.omega * dx[1], a.omega * dx[2]};
-        clamp_step(a, v, uv, st);
-        float4* out = a.in_place ? const_cast<float4*>(a.u) : a.unext;
-        out[v] = make_float4(uv.x + st[0], uv.y + st[1], uv.z + st[2], 0.0f);
+        if (!a.no_write) {
+            float A[9] = {A6[0], A6[1], A6[2], A6[1], A6[3], A6[4], A6[2], A6[4], A6[5]};
+            float dx[3];
+            local_solve(A, g, dx);
+            float st[3] = {a.omega * dx[0], a.omega * dx[1], a.omega * dx[2]};
+            if (!LIN) clamp_step(a, v, uv, st);
+            float4* out = LIN ? (a.in_place ? const_cast<float4*>(a.ly) : a.lynext)
+                              : (a.in_place ? const_cast<float4*>(a.u) : a.unext);
+            out[v] = make_float4(base.x + st[0], base.y + st[1], base.z + st[2], 0.0f);
+        }
     }
     block_partial(gsq, active && lane == 0, a.partial);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_plain(SweepArgs a) { plain_body<false>(a); }
+__global__ __launch_bounds__(BLOCK) void k_linear(SweepArgs a) { plain_body<true>(a); }
+
+// thetabar_t -= sum_c y_c . (V_t P(F_t) grad N_c) at the displacement u:
+// the derivative of the step's optimality condition with respect to
+// log E_t is the element's elastic force, since mu and lambda scale with E.
+__global__ void k_param_grad(const float4* __restrict__ tet, int nT, const float4* __restrict__ u,
+                             const float4* __restrict__ y, double* __restrict__ thbar) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nT) return;
+    Tet T;
+    load_tet(tet, t, T);
+    float H[9], cH[9], P[9];
+    Kin<float> K;
+    dispgrad(u, T, H);
+    kinematics(H, K, cH);
+    snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
+    float acc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float gn[3];
+        gradN(T.D, c, gn);
+        const float4 yc = y[T.id[c]];
+        acc += yc.x * (P[0] * gn[0] + P[1] * gn[1] + P[2] * gn[2]) +
+               yc.y * (P[3] * gn[0] + P[4] * gn[1] + P[5] * gn[2]) +
+               yc.z * (P[6] * gn[0] + P[7] * gn[1] + P[8] * gn[2]);
+    }
+    thbar[t] -= (double)acc;
+}
+
+// Cotangents of the previous step's inputs and the next right-hand side:
+// xbar <- m/h^2 y - vbar/h, vbar <- h m/h^2 y, rhs <- xbar + vbar/h
+// (zero at pinned vertices, where m/h^2 is stored as 0).
+__global__ void k_adj_vec(int nV, const float* __restrict__ mh2, const float4* __restrict__ y,
+                          float4* __restrict__ xbar, float4* __restrict__ vbar, float4* __restrict__ rhs,
+                          float h) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nV) return;
+    const float m = mh2[v];
+    const float4 yv = y[v], vb = vbar[v];
+    const float ih = 1.0f / h;
+    float4 xn, vn;
+    if (m > 0.0f) {
+        xn = make_float4(m * yv.x - vb.x * ih, m * yv.y - vb.y * ih, m * yv.z - vb.z * ih, 0.0f);
+        vn = make_float4(h * m * yv.x, h * m * yv.y, h * m * yv.z, 0.0f);
+    } else {
+        xn = make_float4(0.f, 0.f, 0.f, 0.f);
+        vn = xn;
+    }
+    xbar[v] = xn;
+    vbar[v] = vn;
+    rhs[v] = make_float4(xn.x + vn.x * ih, xn.y + vn.y * ih, xn.z + vn.z * ih, 0.0f);
+}
+
+// Per-block FP64 partial sums of |w_v|^2 over free vertices.
+__global__ __launch_bounds__(256) void k_norm2(int nVf, const int* __restrict__ free_ids,
+                                               const float4* __restrict__ w, double* __restrict__ partial) {
+    __shared__ double s[256];
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (f < nVf) {
+        const float4 q = w[free_ids[f]];
+        e = (double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z;
+    }
+    s[threadIdx.x] = e;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
 }
 
 // Copies updated positions of the listed vertices from unext into u.
@@ -573,6 +683,27 @@ void launch_plain(jgs2_solver* s, const SweepArgs& a) {
     const int nb = n_blocks_for(a);
     if (nb == 0) return;
     launch(s, JGS2_K_PLAIN, k_plain, dim3(nb), dim3(BLOCK), a);
+}
+
+void launch_linear(jgs2_solver* s, const SweepArgs& a) {
+    const int nb = n_blocks_for(a);
+    if (nb == 0) return;
+    launch(s, JGS2_K_LINEAR, k_linear, dim3(nb), dim3(BLOCK), a);
+}
+
+void launch_param_grad(jgs2_solver* s, const float4* u, const float4* y, double* thbar) {
+    launch(s, JGS2_K_PARAMGRAD, k_param_grad, dim3((s->nT + 255) / 256), dim3(256), (const float4*)s->d_tet, s->nT,
+           u, y, thbar);
+}
+
+void launch_adj_vec(jgs2_solver* s, const float4* y, float4* xbar, float4* vbar, float4* rhs) {
+    launch(s, JGS2_K_ADJVEC, k_adj_vec, dim3((s->nV + 255) / 256), dim3(256), s->nV, (const float*)s->d_mh2, y,
+           xbar, vbar, rhs, (float)s->p.dt);
+}
+
+void launch_norm2(jgs2_solver* s, const float4* w) {
+    launch(s, JGS2_K_REDUCE, k_norm2, dim3((s->nVf + 255) / 256), dim3(256), s->nVf, (const int*)s->d_free, w,
+           s->d_partial);
 }
 
 void launch_commit(jgs2_solver* s, const SweepArgs& a) {

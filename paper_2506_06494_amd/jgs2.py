@@ -26,7 +26,8 @@ class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("gravity", C.c_double * 3), ("variant", C.c_int32), ("order", C.c_int32),
                 ("omega", C.c_double), ("rel_tol", C.c_double), ("max_sweeps", C.c_int32),
                 ("check_every", C.c_int32), ("d_hat", C.c_double), ("kappa", C.c_double),
-                ("n_planes", C.c_int32), ("line_search", C.c_int32), ("planes", (C.c_double * 4) * MAX_PLANES)]
+                ("n_planes", C.c_int32), ("line_search", C.c_int32), ("planes", (C.c_double * 4) * MAX_PLANES),
+                ("adj_rel_tol", C.c_double), ("adj_max_sweeps", C.c_int32), ("reserved", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -34,14 +35,20 @@ class StepStats(C.Structure):
                 ("seconds", C.c_double), ("ls_halvings", C.c_int32), ("reserved", C.c_int32)]
 
 
+class AdjointStats(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("status", C.c_int32), ("adjoint_sweeps", C.c_int64),
+                ("forward_sweeps", C.c_int64), ("max_rel_res", C.c_double), ("seconds", C.c_double)]
+
+
 EXPORTS = ["jgs2_default_params", "jgs2_create", "jgs2_destroy", "jgs2_last_error", "jgs2_set_params",
            "jgs2_set_stream", "jgs2_upload_mesh", "jgs2_set_material", "jgs2_precompute",
            "jgs2_import_correction", "jgs2_export_correction", "jgs2_get_ring_sizes", "jgs2_get_poses",
            "jgs2_set_state", "jgs2_get_state", "jgs2_step", "jgs2_begin_step", "jgs2_iterate", "jgs2_end_step",
            "jgs2_residual", "jgs2_energy", "jgs2_get_phase1", "jgs2_get_coloring", "jgs2_set_profiling",
-           "jgs2_kernel_times"]
+           "jgs2_kernel_times", "jgs2_rollout", "jgs2_rollout_backward"]
 
-KERNELS = ["phase1", "phase2", "plain", "commit", "reduce", "predict", "velocity", "energy"]
+KERNELS = ["phase1", "phase2", "plain", "commit", "reduce", "predict", "velocity", "energy", "linear", "paramgrad",
+           "adjvec"]
 
 _lib = None
 
@@ -82,6 +89,8 @@ def load(path: str = LIB_PATH):
         "jgs2_get_coloring": (C.c_int32, [C.c_void_p, i32, i32]),
         "jgs2_set_profiling": (C.c_int32, [C.c_void_p, C.c_int32]),
         "jgs2_kernel_times": (C.c_int32, [C.c_void_p, d, P(C.c_int64)]),
+        "jgs2_rollout": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, P(StepStats)]),
+        "jgs2_rollout_backward": (C.c_int32, [C.c_void_p, d, d, d, d, d, P(AdjointStats)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -175,6 +184,7 @@ class Solver:
         tets = np.ascontiguousarray(tets, dtype=np.int32)
         pinned = np.ascontiguousarray(pinned, dtype=np.uint8)
         self.nV, self.nT = X.shape[0], tets.shape[0]
+        self.X, self.pinned = X.copy(), pinned.astype(bool)
         self._chk(self.lib.jgs2_upload_mesh(self.h, self.nV, _dptr(X), self.nT, _iptr(tets),
                                             pinned.ctypes.data_as(C.POINTER(C.c_uint8))))
 
@@ -254,6 +264,28 @@ class Solver:
         a, r = C.c_double(), C.c_double()
         self._chk(self.lib.jgs2_residual(self.h, C.byref(a), C.byref(r)))
         return a.value, r.value
+
+    def rollout(self, n_steps, ckpt_every=5):
+        """n_steps forward steps from the current state, keeping device
+        checkpoints every ckpt_every steps; returns the last step's stats."""
+        st = StepStats()
+        self._chk(self.lib.jgs2_rollout(self.h, int(n_steps), int(ckpt_every), C.byref(st)))
+        return dict(sweeps=st.sweeps, r0=st.r0, r_final=st.r_final, seconds=st.seconds)
+
+    def rollout_backward(self, xbar, vbar=None):
+        """Pulls (xbar_N, vbar_N) back through the last rollout; returns
+        (thetabar (nT,), xbar_0, vbar_0, stats)."""
+        xbar = np.ascontiguousarray(xbar, dtype=np.float64).reshape(self.nV, 3)
+        vb = None if vbar is None else np.ascontiguousarray(vbar, dtype=np.float64).reshape(self.nV, 3)
+        th = np.zeros(self.nT)
+        xb0 = np.zeros((self.nV, 3))
+        vb0 = np.zeros((self.nV, 3))
+        st = AdjointStats()
+        self._chk(self.lib.jgs2_rollout_backward(self.h, _dptr(xbar), None if vb is None else _dptr(vb), _dptr(th),
+                                                 _dptr(xb0), _dptr(vb0), C.byref(st)))
+        return th, xb0, vb0, dict(steps=st.steps, adjoint_sweeps=st.adjoint_sweeps,
+                                  forward_sweeps=st.forward_sweeps, max_rel_res=st.max_rel_res,
+                                  seconds=st.seconds)
 
     def energy(self):
         e = C.c_double()

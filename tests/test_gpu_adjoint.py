@@ -1,0 +1,167 @@
+"""GPU differentiable rollout (checkpointed forward, linear adjoint sweeps,
+per-tet stiffness gradient) against the FP64 oracle adjoint."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import adjoint as oa, fem
+from paper_2506_06494_amd import inputs, jgs2
+
+from gpu_util import bbox_diag
+
+pytestmark = pytest.mark.gpu
+
+
+def small_problem():
+    m = inputs.beam_mesh(8, 3, 3, 0.05)
+    g = inputs.SplitMix64(11)
+    logE = np.log(1e5) + g.uniform_array(m.nT, -0.3, 0.3)
+    u = np.array([0.05, -0.1, 0.2])
+    return m, logE, u
+
+
+def gpu_solver(m, logE, order=jgs2.GS, **kw):
+    p = dict(order=order, rel_tol=1e-6, adj_rel_tol=1e-6, check_every=4, max_sweeps=5000, adj_max_sweeps=5000)
+    p.update(kw)
+    s = jgs2.Solver(**p)
+    s.upload_mesh(m.X, m.tets, m.pinned)
+    s.set_material(np.exp(logE), 0.45, 1000.0)
+    return s
+
+
+def v_init(m, u):
+    v = np.zeros_like(m.X)
+    v[~m.pinned.astype(bool)] = u
+    return v
+
+
+def test_adjoint_matches_oracle_small():
+    m, logE, u = small_problem()
+    n = 5
+    mdl = fem.Model(m.X, m.tets, m.pinned, np.exp(logE), 0.45, 1000.0, 1.0 / 120)
+    xs, _ = oa.forward(mdl, mdl.X.copy(), oa.initial_velocity(mdl, u), n)
+    rng = np.random.default_rng(3)
+    xbar = rng.standard_normal(m.X.shape)
+    vbar = 0.01 * rng.standard_normal(m.X.shape)
+    th_o, xb_o, vb_o = oa.backward(mdl, xs, xbar, vbar)
+
+    s = gpu_solver(m, logE)
+    s.set_state(m.X, v_init(m, u))
+    s.rollout(n, ckpt_every=2)                     # segments [0,2) [2,4) [4,5)
+    x, _ = s.get_state()
+    assert np.abs(x - xs[-1]).max() <= 1e-5 * bbox_diag(m.X)
+    th, xb0, vb0, st = s.rollout_backward(xbar, vbar)
+    assert st["steps"] == n and st["max_rel_res"] <= 1e-5
+    rel = np.linalg.norm(th - th_o) / np.linalg.norm(th_o)
+    cos = th @ th_o / (np.linalg.norm(th) * np.linalg.norm(th_o))
+    assert rel <= 1e-2 and cos >= 0.999, (rel, cos)
+    pin = m.pinned.astype(bool)
+    for a, b in ((xb0, xb_o), (vb0, vb_o)):
+        assert np.linalg.norm(a[~pin] - b[~pin]) <= 1e-2 * np.linalg.norm(b[~pin])
+        assert np.abs(a[pin]).max() == 0.0
+    # the state is left at the end of the rollout
+    x2, _ = s.get_state()
+    assert np.array_equal(x2, x)
+
+
+def test_checkpoint_spacing_does_not_change_the_gradient():
+    """Recomputed forward steps are bitwise those of the rollout, so the
+    gradient is the same for any checkpoint spacing."""
+    m, logE, u = small_problem()
+    xbar = np.random.default_rng(4).standard_normal(m.X.shape)
+    out = []
+    for every in (1, 3, 7):
+        s = gpu_solver(m, logE)
+        s.set_state(m.X, v_init(m, u))
+        s.rollout(7, ckpt_every=every)
+        out.append(s.rollout_backward(xbar)[:3])
+    for o in out[1:]:
+        for a, b in zip(o, out[0]):
+            assert np.array_equal(a, b)
+
+
+def test_rollout_error_paths():
+    m, logE, u = small_problem()
+    s = gpu_solver(m, logE)
+    s.set_state(m.X, v_init(m, u))
+    with pytest.raises(jgs2.JGS2Error) as e:
+        s.rollout_backward(np.zeros_like(m.X))
+    assert e.value.code == jgs2.E_NOT_READY
+    with pytest.raises(jgs2.JGS2Error) as e:
+        s.rollout(0)
+    assert e.value.code == jgs2.E_INVALID
+    s.rollout(2, 1)
+    s.set_state(m.X, v_init(m, u))                 # discards the rollout
+    with pytest.raises(jgs2.JGS2Error) as e:
+        s.rollout_backward(np.zeros_like(m.X))
+    assert e.value.code == jgs2.E_NOT_READY
+
+
+def test_autograd_function_and_directional_fd():
+    torch = pytest.importorskip("torch")
+    from paper_2506_06494_amd.autograd import Simulate
+    m, logE, u = small_problem()
+    s = gpu_solver(m, logE, rel_tol=1e-7, adj_rel_tol=1e-7)
+    tip = np.nonzero(m.X[:, 0] >= m.X[:, 0].max() - 1e-12)[0]
+    target = torch.tensor(m.X[tip].mean(0) + np.array([0.01, -0.03, 0.02]))
+    tip_t = torch.from_numpy(tip)
+
+    def loss_of(le, uu):
+        x = Simulate.apply(le, uu, s, 0.45, 1000.0, 6, 3)
+        return ((x[tip_t].mean(0) - target) ** 2).sum()
+
+    le = torch.tensor(logE, requires_grad=True)
+    ut = torch.tensor(u, requires_grad=True)
+    L = loss_of(le, ut)
+    L.backward()
+    # oracle gradient of the same loss
+    mdl = fem.Model(m.X, m.tets, m.pinned, np.exp(logE), 0.45, 1000.0, 1.0 / 120)
+    Lo, tho, uo = oa.loss_and_grad(mdl, logE, u, target.numpy(), 6)
+    assert abs(L.item() - Lo) <= 1e-4 * Lo
+    g = le.grad.numpy()
+    assert np.linalg.norm(g - tho) <= 1e-2 * np.linalg.norm(tho)
+    assert np.linalg.norm(ut.grad.numpy() - uo) <= 1e-2 * np.linalg.norm(uo)
+    # GPU central differences along the gradient direction and along u
+    with torch.no_grad():
+        d = torch.from_numpy(g / np.linalg.norm(g))
+        h = 1e-2
+        fd = (loss_of(le + h * d, ut) - loss_of(le - h * d, ut)).item() / (2 * h)
+        assert abs(fd - np.linalg.norm(g)) <= 2e-2 * np.linalg.norm(g)
+        for k in range(3):
+            e = torch.zeros(3, dtype=torch.float64); e[k] = 1e-2
+            fd = (loss_of(le, ut + e) - loss_of(le, ut - e)).item() / 2e-2
+            assert abs(fd - ut.grad[k].item()) <= 2e-2 * np.abs(ut.grad.numpy()).max()
+
+
+@pytest.mark.timeout(600)
+def test_differentiation_workload_matches_oracle_golden():
+    path = os.path.join(os.path.dirname(__file__), "golden", "beam16x16x64_adjoint.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle golden not generated")
+    gd = json.load(open(path))
+    sc, logE, target = inputs.diff_beam(0)
+    m = sc.mesh
+    s = gpu_solver(m, logE, rel_tol=1e-6, adj_rel_tol=1e-6, check_every=16)
+    s.set_state(m.X, np.zeros_like(m.X))
+    s.rollout(gd["steps"], ckpt_every=5)
+    x, _ = s.get_state()
+    v = np.array(gd["verts"])
+    assert np.abs(x[v] - np.array(gd["x"])).max() <= 1e-4 * bbox_diag(m.X)
+    tip = np.nonzero(m.X[:, 0] >= m.X[:, 0].max() - 1e-12)[0]
+    r = x[tip].mean(0) - np.array(gd["target"])
+    L = float(r @ r)
+    assert abs(L - gd["loss"]) <= 1e-3 * gd["loss"]
+    xbar = np.zeros_like(x)
+    xbar[tip] = 2.0 * r / tip.size
+    th, _, vb0, st = s.rollout_backward(xbar)
+    print("adjoint stats", st, flush=True)
+    t = np.array(gd["tets"])
+    tho = np.array(gd["thetabar"])
+    rel = np.linalg.norm(th[t] - tho) / np.linalg.norm(tho)
+    cos = th[t] @ tho / (np.linalg.norm(th[t]) * np.linalg.norm(tho))
+    assert rel <= 1e-2 and cos >= 0.999, (rel, cos)
+    assert abs(np.linalg.norm(th) - gd["thetabar_norm"]) <= 1e-2 * gd["thetabar_norm"]
+    ub = vb0[~m.pinned.astype(bool)].sum(0)
+    assert np.linalg.norm(ub - np.array(gd["ubar"])) <= 1e-2 * np.linalg.norm(gd["ubar"])

@@ -49,7 +49,8 @@ def test_full_size_precompute_matches_golden(E):
             og, oo = np.argsort(sg), np.argsort(so)
             wo = np.array(row["weights"])
             np.testing.assert_allclose(ex["weights"][f][og], wo[oo], rtol=1e-4, atol=1e-6 * wo.max())
-            np.testing.assert_allclose(ex["U_samp"][f][og], np.array(row["U_samp"])[oo], atol=1e-5)
+            np.testing.assert_allclose(ex["U_samp"][f][og], np.array(row["U_samp"]).reshape(-1, 4, 3, 3)[oo],
+                                       atol=1e-5)
             np.testing.assert_allclose(ex["fit"][f], row["fit"], rtol=1e-4, atol=1e-9)
     assert n_same >= len(g["rows"]) - 1, n_same
 
