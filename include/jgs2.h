@@ -78,14 +78,15 @@ typedef struct jgs2_params {
     double  planes[JGS2_MAX_PLANES][4];  /* (n_x, n_y, n_z, c), n unit length */
     double  adj_rel_tol;        /* adjoint solves stop at |H y - b| / |b| <= adj_rel_tol */
     int32_t adj_max_sweeps;     /* sweep cap per adjoint solve */
-    int32_t reserved;
+    int32_t use_graph;          /* 1: replay each group of check_every sweeps and its
+                                   residual check as one captured HIP graph */
 } jgs2_params;
 
 typedef struct jgs2_step_stats {
-    int32_t sweeps;             /* sweeps performed this step */
+    int32_t sweeps;             /* sweeps performed this step (the most of any body) */
     int32_t status;             /* JGS2_OK, JGS2_E_DIVERGED, ... */
     double  r0;                 /* |g(x0)| over free DOFs */
-    double  r_final;            /* |g(x)| / r0 at the end of the step */
+    double  r_final;            /* largest |g_b(x)| / |g_b(x0)| over bodies at the end */
     double  seconds;            /* device time of the step (HIP events) */
     int32_t ls_halvings;        /* energy backtracking halvings this step */
     int32_t reserved;
@@ -103,7 +104,7 @@ typedef struct jgs2_adjoint_stats {
 /* Fills *p with defaults: dt 1/120, gravity (0,-9.8,0), JGS2_PLAIN,
  * JGS2_JACOBI, omega 1, rel_tol 1e-5, max_sweeps 20000, check_every 8,
  * d_hat 1e-3, kappa 1e4, no planes, no line search, adj_rel_tol 1e-5,
- * adj_max_sweeps 20000. */
+ * adj_max_sweeps 20000, no graph capture. */
 void jgs2_default_params(jgs2_params* p);
 
 /* Creates a handle.  Fails with JGS2_E_INVALID on a bad parameter set and
@@ -123,6 +124,31 @@ int32_t jgs2_set_stream(jgs2_solver* s, void* stream);
  * material, correction and state. */
 int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X,
                          int32_t nT, const int32_t* tets, const uint8_t* pinned);
+
+/* Bodies: disjoint meshes uploaded as one (concatenated vertex and tet
+ * arrays) and solved together in the same launches.  body_of_vertex (nV
+ * entries, ids 0..n_bodies-1, in any order) assigns each vertex a body; every
+ * body keeps its own residual |g_b| / |g_b(x0)| (FP64, summed in a fixed order
+ * over the body's free vertices only) and stops sweeping (its vertices are
+ * skipped) once that reaches rel_tol at a residual check, so each body gets
+ * exactly the sweeps it would get alone.  upload_mesh resets to one body.
+ * The energy line search is refused with more than one body. */
+int32_t jgs2_set_bodies(jgs2_solver* s, int32_t n_bodies, const int32_t* body_of_vertex);
+/* Per body at the last residual check of the current or last step: sweeps
+ * done (sweeps, n_bodies entries) and |g_b| / |g_b(x0)| (rel). */
+int32_t jgs2_get_body_stats(jgs2_solver* s, int32_t* n_bodies, int32_t* sweeps, double* rel);
+
+/* Launch shape of the plain (and adjoint linear) sweep kernels: lanes_per_vertex
+ * in {4, 8, 16, 32} lanes share a vertex's incident tets, block in
+ * {64, 128, 256, 512} threads.  Results depend on the shape only through the
+ * order of the per-vertex sums.  Default 32 x 256. */
+int32_t jgs2_set_tuning(jgs2_solver* s, int32_t lanes_per_vertex, int32_t block);
+int32_t jgs2_get_tuning(jgs2_solver* s, int32_t* lanes_per_vertex, int32_t* block);
+/* Times `sweeps` sweeps of the first step from the current state in every
+ * launch shape (HIP events), keeps the fastest and reports it; the state is
+ * left unchanged.  ms (16 entries, may be NULL) receives each shape's time in
+ * the order lanes 4, 8, 16, 32 (outer) x block 64, 128, 256, 512 (inner). */
+int32_t jgs2_autotune(jgs2_solver* s, int32_t sweeps, int32_t* lanes_per_vertex, int32_t* block, double* ms);
 
 /* Per-tet Young's modulus E [Pa], Poisson ratio nu and density rho
  * [kg/m^3] (stable Neo-Hookean, Sec. 7 / Table 1 caption).  Lumped masses

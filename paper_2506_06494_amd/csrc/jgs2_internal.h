@@ -55,6 +55,9 @@ struct SweepArgs {
     const float4* lrhs;     // [nV] right-hand side
     const float* mh2;       // [nV] m_a / h^2 (0 if pinned)
     int no_write;           // residual partials only, no update
+    // bodies: a free vertex of a body whose residual reached rel_tol is skipped
+    const int* fbody;       // [nVf] body of each free vertex
+    const int* body_on;     // [n_bodies] 1 while the body iterates (nullptr: all)
 };
 
 }  // namespace jgs2
@@ -119,6 +122,26 @@ struct jgs2_solver {
     float4 *d_ck_u = nullptr, *d_ck_v = nullptr, *d_seg = nullptr;
     float4 *d_y = nullptr, *d_ynext = nullptr, *d_xbar = nullptr, *d_vbar = nullptr, *d_rhs = nullptr;
     double* d_thbar = nullptr;
+    // bodies (disjoint meshes solved together; per-body residuals and masks)
+    int n_bodies = 1;
+    std::vector<int> body_of_vertex;       // [nV]
+    std::vector<int> seg_off, seg_idx;     // free indices grouped by body
+    int* d_fbody = nullptr;                // [nVf]
+    int *d_seg_off = nullptr, *d_seg_idx = nullptr;
+    int* d_body_on = nullptr;              // [n_bodies]
+    int* d_body_sweeps = nullptr;          // [n_bodies]
+    int* d_nactive = nullptr;              // [1]
+    double *d_r2 = nullptr, *d_r0sq = nullptr;  // [n_bodies]
+    std::vector<double> r2_host, r0sq_host;
+    int n_active = 0;
+    // launch shape of the plain / linear sweep kernels
+    int tune_lpv = 32, tune_block = 256;
+    // captured sweep groups (k sweeps + residual check) per Jacobi parity
+    hipStream_t own_stream = nullptr;
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    int graph_k[2] = {0, 0};
+    float4* graph_u[2] = {nullptr, nullptr};
+    int graph_next = 0;
 
     int fail(int code, const std::string& msg) {
         err = msg;
@@ -129,6 +152,7 @@ struct jgs2_solver {
 namespace jgs2 {
 int hip_check(jgs2_solver* s, hipError_t e, const char* what);
 void free_device(jgs2_solver* s);
+void drop_graphs(jgs2_solver* s);
 void build_sweep_args(jgs2_solver* s, SweepArgs& a);
 // kernels launched from the host driver (sweep.hip)
 void launch_phase1(jgs2_solver* s, const SweepArgs& a, bool want_R);
@@ -139,6 +163,9 @@ void launch_linear(jgs2_solver* s, const SweepArgs& a);
 void launch_param_grad(jgs2_solver* s, const float4* u, const float4* y, double* thbar);
 void launch_adj_vec(jgs2_solver* s, const float4* y, float4* xbar, float4* vbar, float4* rhs);
 void launch_norm2(jgs2_solver* s, const float4* w);
+void launch_seg_norm2(jgs2_solver* s);
+void launch_mask_init(jgs2_solver* s);
+void launch_mask_update(jgs2_solver* s, int k);
 void launch_blend(jgs2_solver* s, const SweepArgs& a, float t);
 void launch_reduce(jgs2_solver* s, int n);
 void launch_predict(jgs2_solver* s, float h, const float* grav);

@@ -32,7 +32,19 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
     dfree(s->d_ck_u); dfree(s->d_ck_v); dfree(s->d_seg); dfree(s->d_y); dfree(s->d_ynext); dfree(s->d_xbar);
     dfree(s->d_vbar); dfree(s->d_rhs); dfree(s->d_thbar);
+    dfree(s->d_fbody); dfree(s->d_seg_off); dfree(s->d_seg_idx); dfree(s->d_body_on); dfree(s->d_body_sweeps);
+    dfree(s->d_nactive); dfree(s->d_r2); dfree(s->d_r0sq);
     s->ro_valid = false;
+    drop_graphs(s);
+}
+
+void drop_graphs(jgs2_solver* s) {
+    for (int i = 0; i < 2; ++i) {
+        if (s->graph_exec[i]) (void)hipGraphExecDestroy(s->graph_exec[i]);
+        s->graph_exec[i] = nullptr;
+        s->graph_k[i] = 0;
+        s->graph_u[i] = nullptr;
+    }
 }
 
 void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
@@ -47,6 +59,7 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
     for (int i = 0; i < s->p.n_planes; ++i)
         for (int k = 0; k < 4; ++k) a.planes[i][k] = (float)s->p.planes[i][k];
     a.d_hat = (float)s->p.d_hat; a.kappa = (float)s->p.kappa;
+    a.fbody = s->d_fbody; a.body_on = s->d_body_on;
 }
 
 }  // namespace jgs2
@@ -216,6 +229,7 @@ void jgs2_destroy(jgs2_solver* s) {
     (void)hipStreamSynchronize(s->stream);
     free_device(s);
     prof_collect(s);
+    if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
@@ -232,8 +246,11 @@ int32_t jgs2_set_params(jgs2_solver* s, const jgs2_params* p) {
     if (s->in_step && (p->dt != s->p.dt || std::memcmp(p->gravity, s->p.gravity, sizeof(p->gravity)) != 0))
         return s->fail(JGS2_E_INVALID, "dt and gravity cannot change inside a step");
     const bool dt_changed = p->dt != s->p.dt;
+    if (p->line_search && s->n_bodies > 1)
+        return s->fail(JGS2_E_INVALID, "the energy line search needs a single body");
     s->p = *p;
     s->ro_valid = false;
+    drop_graphs(s);
     if (dt_changed && s->have_material) {
         if ((r = upload_material_records(s)) != JGS2_OK) return r;
     }
@@ -378,7 +395,7 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
         (r = dalloc(s, s->d_ring, nf * s->K)) || (r = dalloc(s, s->d_ring_n, nf)) ||
         (r = dalloc(s, s->d_colperm, nf)) || (r = dalloc(s, s->d_tet, (size_t)nT * TET_F4)))
         return r;
-    s->n_partial = std::max<int>((s->nVf + VPB - 1) / VPB, (std::max(nT, s->nVf) + 255) / 256) + 1;
+    s->n_partial = std::max<int>((s->nVf + 1) / 2, (std::max(nT, s->nVf) + 255) / 256) + 1;
     if ((r = dalloc(s, s->d_partial, (size_t)s->n_partial)) || (r = dalloc(s, s->d_red, 4))) return r;
     std::vector<float4> Xs(V4), Rid(V4, make_float4(0.f, 0.f, 0.f, 1.f));
     for (int v = 0; v < nV; ++v)
@@ -393,6 +410,10 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
         HIPCHK(hipMemsetAsync(d, 0, V4 * sizeof(float4), s->stream));
     HIPCHK(hipMemsetAsync(s->d_mh2, 0, (size_t)nV * sizeof(float), s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    {
+        std::vector<int32_t> zero((size_t)nV, 0);
+        if ((r = jgs2_set_bodies(s, 1, zero.data())) != JGS2_OK) return r;
+    }
     s->have_mesh = true;
     return JGS2_OK;
 }
@@ -585,12 +606,43 @@ static int read_reduced(jgs2_solver* s, int n_partials, double* out) {
     return JGS2_OK;
 }
 
-static int gradient_norm2(jgs2_solver* s, double* out) {
+// Residual check, device part: gradient (and rotations) at the iterate, the
+// per-body |g_b|^2, and (mask_k > 0) the per-body stop decision after mask_k
+// sweeps.  Graph-capturable: kernels only.
+static void residual_launches(jgs2_solver* s, int mask_k) {
     SweepArgs a;
     build_sweep_args(s, a);
     launch_phase1(s, a, s->p.variant == JGS2_CUBATURE);
+    launch_seg_norm2(s);
+    if (mask_k > 0) launch_mask_update(s, mask_k);
+}
+
+// Host part: read the per-body residuals and the count of bodies still on;
+// |g|^2 over all bodies (summed in body order) into *g2.
+static int residual_readback(jgs2_solver* s, double* g2) {
+    const size_t nb = s->n_bodies;
+    HIPCHK(hipMemcpyAsync(s->r2_host.data(), s->d_r2, nb * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(&s->n_active, s->d_nactive, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    prof_collect(s);
     s->phase1_valid = true;
-    return read_reduced(s, (s->nVf + VPB - 1) / VPB, out);
+    double t = 0.0;
+    for (size_t b = 0; b < nb; ++b) t += s->r2_host[b];
+    *g2 = t;
+    return JGS2_OK;
+}
+
+// Largest per-body relative residual at the last readback.
+static double max_rel(jgs2_solver* s) {
+    double m = 0.0;
+    for (int b = 0; b < s->n_bodies; ++b)
+        if (s->r0sq_host[b] > 0) m = std::max(m, std::sqrt(s->r2_host[b] / s->r0sq_host[b]));
+    return m;
+}
+
+static int gradient_norm2(jgs2_solver* s, double* out) {
+    residual_launches(s, 0);
+    return residual_readback(s, out);
 }
 
 static bool ready_to_step(jgs2_solver* s) {
@@ -620,10 +672,13 @@ int32_t jgs2_begin_step(jgs2_solver* s) {
         }
     }
     launch_predict(s, (float)s->p.dt, grav);
+    residual_launches(s, 0);
+    launch_mask_init(s);
     double g2 = 0;
-    int r = gradient_norm2(s, &g2);
+    int r = residual_readback(s, &g2);
     if (r != JGS2_OK) return r;
     if (!std::isfinite(g2)) return s->fail(JGS2_E_NONFINITE, "non-finite residual at the start of the step");
+    s->r0sq_host = s->r2_host;
     s->r0 = std::sqrt(g2);
     s->in_step = true;
     s->sweeps_in_step = 0;
@@ -698,18 +753,76 @@ static int sweep_once(jgs2_solver* s) {
     return jgs2::hip_check(s, hipGetLastError(), "sweep launch");
 }
 
+// k sweeps followed by the residual launches (with the per-body stop
+// decision); replayed from a captured graph when use_graph is set.
+static int sweep_group(jgs2_solver* s, int k) {
+    const bool graphable = s->p.use_graph && !s->prof && !s->p.line_search;
+    if (!graphable) {
+        for (int i = 0; i < k; ++i) {
+            int r = sweep_once(s);
+            if (r != JGS2_OK) return r;
+        }
+        residual_launches(s, k);
+        return jgs2::hip_check(s, hipGetLastError(), "sweep launch");
+    }
+    // a Jacobi group of odd length leaves u and unext swapped: graphs are
+    // keyed by the group length and the buffer holding the iterate
+    if (s->stream == nullptr) {
+        if (!s->own_stream) HIPCHK(hipStreamCreate(&s->own_stream));
+        s->stream = s->own_stream;
+    }
+    int par = -1;
+    for (int i = 0; i < 2; ++i)
+        if (s->graph_exec[i] && s->graph_k[i] == k && s->graph_u[i] == s->d_u) par = i;
+    if (par < 0) {
+        par = !s->graph_exec[0] ? 0 : (!s->graph_exec[1] ? 1 : s->graph_next);
+        s->graph_next = par ^ 1;
+        if (s->graph_exec[par]) (void)hipGraphExecDestroy(s->graph_exec[par]);
+        s->graph_exec[par] = nullptr;
+        float4* u0 = s->d_u;
+        const int sw0 = s->sweeps_in_step;
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+        int r = JGS2_OK;
+        for (int i = 0; i < k && r == JGS2_OK; ++i) r = sweep_once(s);
+        if (r == JGS2_OK) residual_launches(s, k);
+        hipError_t e = hipStreamEndCapture(s->stream, &g);
+        // capture only recorded the launches: put the bookkeeping back
+        if (s->d_u != u0) std::swap(s->d_u, s->d_unext);
+        s->sweeps_in_step = sw0;
+        if (r != JGS2_OK) { if (g) (void)hipGraphDestroy(g); return r; }
+        HIPCHK(e);
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+        s->graph_exec[par] = ex;
+        s->graph_k[par] = k;
+        s->graph_u[par] = u0;
+    }
+    HIPCHK(hipGraphLaunch(s->graph_exec[par], s->stream));
+    if (s->p.order == JGS2_JACOBI && (k & 1)) std::swap(s->d_u, s->d_unext);
+    s->sweeps_in_step += k;
+    s->phase1_valid = false;
+    return JGS2_OK;
+}
+
 int32_t jgs2_iterate(jgs2_solver* s, int32_t n_sweeps, double* rel_res) {
     if (!s) return JGS2_E_INVALID;
     if (!s->in_step) return s->fail(JGS2_E_NOT_READY, "iterate outside begin_step/end_step");
     if (n_sweeps < 0) return s->fail(JGS2_E_INVALID, "negative sweep count");
-    for (int k = 0; k < n_sweeps; ++k) {
-        int r = sweep_once(s);
+    if (n_sweeps == 0) {
+        double g2 = 0;
+        int r = gradient_norm2(s, &g2);
         if (r != JGS2_OK) return r;
+        if (rel_res) *rel_res = max_rel(s);
+        return std::isfinite(g2) ? JGS2_OK : s->fail(JGS2_E_NONFINITE, "non-finite residual");
     }
-    double g2 = 0;
-    int r = gradient_norm2(s, &g2);
+    int r = sweep_group(s, n_sweeps);
     if (r != JGS2_OK) return r;
-    const double rel = s->r0 > 0 ? std::sqrt(g2) / s->r0 : 0.0;
+    double g2 = 0;
+    if ((r = residual_readback(s, &g2)) != JGS2_OK) return r;
+    const double rel = max_rel(s);
     if (rel_res) *rel_res = rel;
     if (!std::isfinite(g2)) return s->fail(JGS2_E_NONFINITE, "non-finite residual");
     if (rel > 1e8) return s->fail(JGS2_E_DIVERGED, "residual exceeded 1e8 x its start value");
@@ -744,9 +857,8 @@ int32_t jgs2_step(jgs2_solver* s, jgs2_step_stats* st) {
     HIPCHK(hipEventRecord(s->ev0, s->stream));
     int r = jgs2_begin_step(s);
     if (r != JGS2_OK) { loc.status = r; if (st) *st = loc; return r; }
-    double rel = 1.0;
-    if (s->r0 == 0.0) rel = 0.0;
-    while (rel > s->p.rel_tol && s->sweeps_in_step < s->p.max_sweeps) {
+    double rel = s->r0 == 0.0 ? 0.0 : 1.0;
+    while (s->n_active > 0 && s->sweeps_in_step < s->p.max_sweeps) {
         const int k = std::min(s->p.check_every, s->p.max_sweeps - s->sweeps_in_step);
         r = jgs2_iterate(s, k, &rel);
         if (r != JGS2_OK) {
@@ -878,7 +990,8 @@ static int linear_residual2(jgs2_solver* s, SweepArgs a, double* r2) {
     a.no_write = 1;
     a.ly = s->d_y;
     launch_linear(s, a);
-    return read_reduced(s, (s->nVf + VPB - 1) / VPB, r2);
+    const int nv_blk = s->tune_block / s->tune_lpv;
+    return read_reduced(s, (s->nVf + nv_blk - 1) / nv_blk, r2);
 }
 
 // Solves H(xstar) y = rhs (device d_rhs) by linear sweeps, warm-started from
@@ -1052,6 +1165,142 @@ int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* 
     // a recompute that differs from the rollout would leave ro_valid wrong;
     // the forward is deterministic, so the rollout stays usable
     return status;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Bodies, launch shape, autotuning
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int32_t jgs2_set_bodies(jgs2_solver* s, int32_t n_bodies, const int32_t* body_of_vertex) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_mesh && s->nV == 0) return s->fail(JGS2_E_NOT_READY, "no mesh");
+    if (n_bodies < 1 || !body_of_vertex) return s->fail(JGS2_E_INVALID, "n_bodies must be >= 1");
+    if (n_bodies > 1 && s->p.line_search) return s->fail(JGS2_E_INVALID, "the energy line search needs a single body");
+    for (int v = 0; v < s->nV; ++v)
+        if (body_of_vertex[v] < 0 || body_of_vertex[v] >= n_bodies) return s->fail(JGS2_E_INVALID, "body id out of range");
+    for (int t = 0; t < s->nT; ++t) {
+        const int b0 = body_of_vertex[s->tets[4 * (size_t)t]];
+        for (int c = 1; c < 4; ++c)
+            if (body_of_vertex[s->tets[4 * (size_t)t + c]] != b0) return s->fail(JGS2_E_INVALID, "a tet spans two bodies");
+    }
+    const int nf = s->nVf;
+    std::vector<int> fbody(nf), off(n_bodies + 1, 0), idx(nf);
+    for (int f = 0; f < nf; ++f) {
+        fbody[f] = body_of_vertex[s->free_ids[f]];
+        off[fbody[f] + 1]++;
+    }
+    for (int b = 0; b < n_bodies; ++b) off[b + 1] += off[b];
+    std::vector<int> pos(off.begin(), off.end() - 1);
+    for (int f = 0; f < nf; ++f) idx[pos[fbody[f]]++] = f;  // stable: ascending free index within a body
+    int r;
+    const size_t nb = n_bodies;
+    if ((r = dalloc(s, s->d_fbody, (size_t)nf)) || (r = dalloc(s, s->d_seg_off, nb + 1)) ||
+        (r = dalloc(s, s->d_seg_idx, (size_t)nf)) || (r = dalloc(s, s->d_body_on, nb)) ||
+        (r = dalloc(s, s->d_body_sweeps, nb)) || (r = dalloc(s, s->d_nactive, 1)) || (r = dalloc(s, s->d_r2, nb)) ||
+        (r = dalloc(s, s->d_r0sq, nb)))
+        return r;
+    std::vector<int> ones(nb, 1), zeros(nb, 0);
+    if ((r = upload(s, s->d_fbody, fbody.data(), (size_t)nf)) || (r = upload(s, s->d_seg_off, off.data(), nb + 1)) ||
+        (r = upload(s, s->d_seg_idx, idx.data(), (size_t)nf)) || (r = upload(s, s->d_body_on, ones.data(), nb)) ||
+        (r = upload(s, s->d_body_sweeps, zeros.data(), nb)))
+        return r;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->n_bodies = n_bodies;
+    s->body_of_vertex.assign(body_of_vertex, body_of_vertex + s->nV);
+    s->seg_off = off;
+    s->seg_idx = idx;
+    s->r2_host.assign(nb, 0.0);
+    s->r0sq_host.assign(nb, 0.0);
+    s->n_active = n_bodies;
+    s->in_step = false;
+    s->ro_valid = false;
+    drop_graphs(s);
+    return JGS2_OK;
+}
+
+int32_t jgs2_get_body_stats(jgs2_solver* s, int32_t* n_bodies, int32_t* sweeps, double* rel) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_mesh) return s->fail(JGS2_E_NOT_READY, "no mesh");
+    if (n_bodies) *n_bodies = s->n_bodies;
+    if (sweeps) {
+        HIPCHK(hipMemcpyAsync(sweeps, s->d_body_sweeps, (size_t)s->n_bodies * sizeof(int), hipMemcpyDeviceToHost,
+                              s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    if (rel)
+        for (int b = 0; b < s->n_bodies; ++b)
+            rel[b] = s->r0sq_host[b] > 0 ? std::sqrt(s->r2_host[b] / s->r0sq_host[b]) : 0.0;
+    return JGS2_OK;
+}
+
+static bool valid_shape(int lpv, int block) {
+    return (lpv == 4 || lpv == 8 || lpv == 16 || lpv == 32) &&
+           (block == 64 || block == 128 || block == 256 || block == 512);
+}
+
+int32_t jgs2_set_tuning(jgs2_solver* s, int32_t lanes_per_vertex, int32_t block) {
+    if (!s) return JGS2_E_INVALID;
+    if (!valid_shape(lanes_per_vertex, block)) return s->fail(JGS2_E_INVALID, "unsupported launch shape");
+    s->tune_lpv = lanes_per_vertex;
+    s->tune_block = block;
+    drop_graphs(s);
+    return JGS2_OK;
+}
+
+int32_t jgs2_get_tuning(jgs2_solver* s, int32_t* lanes_per_vertex, int32_t* block) {
+    if (!s) return JGS2_E_INVALID;
+    if (lanes_per_vertex) *lanes_per_vertex = s->tune_lpv;
+    if (block) *block = s->tune_block;
+    return JGS2_OK;
+}
+
+int32_t jgs2_autotune(jgs2_solver* s, int32_t sweeps, int32_t* lanes_per_vertex, int32_t* block, double* ms) {
+    if (!s) return JGS2_E_INVALID;
+    if (sweeps < 1) return s->fail(JGS2_E_INVALID, "sweeps must be >= 1");
+    if (s->in_step) return s->fail(JGS2_E_NOT_READY, "autotune inside begin_step/end_step");
+    int r = jgs2_begin_step(s);
+    if (r != JGS2_OK) return r;
+    const int lanes[4] = {4, 8, 16, 32}, blocks[4] = {64, 128, 256, 512};
+    const int keep_l = s->tune_lpv, keep_b = s->tune_block;
+    double best = 1e300;
+    int bl = keep_l, bb = keep_b;
+    hipEvent_t e0 = pool_event(s), e1 = pool_event(s);
+    for (int i = 0; i < 4 && r == JGS2_OK; ++i)
+        for (int j = 0; j < 4 && r == JGS2_OK; ++j) {
+            s->tune_lpv = lanes[i];
+            s->tune_block = blocks[j];
+            // every shape starts from the same iterate
+            if ((r = copy_v4(s, s->d_u, s->d_uhat)) || (r = copy_v4(s, s->d_unext, s->d_uhat))) break;
+            r = sweep_once(s);  // warm-up
+            if (r != JGS2_OK) break;
+            if ((r = copy_v4(s, s->d_u, s->d_uhat)) || (r = copy_v4(s, s->d_unext, s->d_uhat))) break;
+            if ((r = jgs2::hip_check(s, hipEventRecord(e0, s->stream), "event"))) break;
+            for (int k = 0; k < sweeps && r == JGS2_OK; ++k) r = sweep_once(s);
+            if (r != JGS2_OK) break;
+            if ((r = jgs2::hip_check(s, hipEventRecord(e1, s->stream), "event"))) break;
+            if ((r = jgs2::hip_check(s, hipEventSynchronize(e1), "event"))) break;
+            float t = 0.0f;
+            if ((r = jgs2::hip_check(s, hipEventElapsedTime(&t, e0, e1), "event"))) break;
+            if (ms) ms[4 * i + j] = t;
+            if (t < best) { best = t; bl = lanes[i]; bb = blocks[j]; }
+        }
+    s->ev_pool.push_back(e0);
+    s->ev_pool.push_back(e1);
+    abandon_step(s);
+    if (r != JGS2_OK) {
+        s->tune_lpv = keep_l;
+        s->tune_block = keep_b;
+        return r;
+    }
+    s->tune_lpv = bl;
+    s->tune_block = bb;
+    drop_graphs(s);
+    if (lanes_per_vertex) *lanes_per_vertex = bl;
+    if (block) *block = bb;
+    return JGS2_OK;
 }
 
 }  // extern "C"

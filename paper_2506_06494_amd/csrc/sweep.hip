@@ -46,6 +46,19 @@ __device__ __forceinline__ float lane_sum(float v) {
     return v;
 }
 
+// Sum over the W lanes of one vertex sub-problem (xor butterfly).
+template <int W>
+__device__ __forceinline__ float lane_sum_w(float v) {
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+    return v;
+}
+
+// Whether free vertex f belongs to a body that is still iterating.
+__device__ __forceinline__ bool body_on(const SweepArgs& a, int f) {
+    return a.body_on == nullptr || a.body_on[a.fbody[f]] != 0;
+}
+
 struct Tet {
     int id[4];
     float D[9];
@@ -169,16 +182,21 @@ __device__ __forceinline__ void clamp_step(const SweepArgs& a, int v, float4 uv,
     step[0] *= alpha; step[1] *= alpha; step[2] *= alpha;
 }
 
-__device__ __forceinline__ void block_partial(double val, bool lane0, double* partial) {
-    __shared__ double sp[VPB];
-    const int vloc = threadIdx.x / LPV;
+template <int NV, int W>
+__device__ __forceinline__ void block_partial_t(double val, bool lane0, double* partial) {
+    __shared__ double sp[NV];
+    const int vloc = threadIdx.x / W;
     if (lane0) sp[vloc] = val;
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int i = 0; i < VPB; ++i) s += sp[i];
+        for (int i = 0; i < NV; ++i) s += sp[i];
         partial[blockIdx.x] = s;
     }
+}
+
+__device__ __forceinline__ void block_partial(double val, bool lane0, double* partial) {
+    block_partial_t<VPB, LPV>(val, lane0, partial);
 }
 
 // ---------------------------------------------------------------------------
@@ -275,9 +293,11 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int idx = blk * VPB + vloc;
     const int nidx = a.list ? a.n_list : a.nVf;
-    const bool active = idx < nidx;
-    const int f = active ? (a.list ? a.list[idx] : idx) : 0;
+    const bool in_range = idx < nidx;
+    const int f = in_range ? (a.list ? a.list[idx] : idx) : 0;
+    const bool active = in_range && body_on(a, f);
     const int v = a.free_ids[f];
+    if (in_range && !active && lane == 0) a.unext[v] = a.u[v];  // converged body: unchanged
     float Ri[9];
     load_rot(a.R, v, Ri);
     float A6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, b[3] = {0.f, 0.f, 0.f};
@@ -382,29 +402,35 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Plain variant, one fused pass: g_i and H_ii from the incident tets, then
-// x_i <- x_i - omega H_ii^-1 g_i.  Also leaves per-block |g|^2 partials of
-// the iterate it read.
-// ---------------------------------------------------------------------------
-// Plain per-vertex Newton relaxation, A_i = H_ii, fused in one pass.
-// LIN = false: b_i = g_i (forward sweep on the displacement u).
+// Plain per-vertex Newton relaxation, A_i = H_ii, fused in one pass; also
+// leaves per-block |b|^2 partials of the iterate it read.
+// LIN = false: b_i = g_i, x_i <- x_i - omega H_ii^-1 g_i (forward sweep).
 // LIN = true : b_i = (H y - rhs)_i with H the Hessian at u (held fixed): a
 //              linear sweep on H y = rhs for the adjoint; the incident
 //              tets contribute dP[dF(y)] grad N, the vertex m/h^2 y and the
 //              barrier Hessian times y.
-template <bool LIN>
+// W lanes share a vertex (each takes every W-th incident tet), BLK threads
+// per block hold BLK / W vertices: the launch shapes the tuner chooses from.
+// ---------------------------------------------------------------------------
+template <bool LIN, int W, int BLK>
 __device__ __forceinline__ void plain_body(const SweepArgs& a) {
-    const int lane = threadIdx.x % LPV;
-    const int vloc = threadIdx.x / LPV;
+    constexpr int NV = BLK / W;
+    const int lane = threadIdx.x % W;
+    const int vloc = threadIdx.x / W;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int idx = blk * VPB + vloc;
+    const int idx = blk * NV + vloc;
     const int nidx = a.list ? a.n_list : a.nVf;
-    const bool active = idx < nidx;
-    const int f = active ? (a.list ? a.list[idx] : idx) : 0;
+    const bool in_range = idx < nidx;
+    const int f = in_range ? (a.list ? a.list[idx] : idx) : 0;
+    const bool active = in_range && (LIN || body_on(a, f));
+    if (!LIN && in_range && !active && lane == 0 && !a.in_place) {
+        const int v = a.free_ids[f];
+        a.unext[v] = a.u[v];  // converged body in a Jacobi sweep: carried over unchanged
+    }
     float g[3] = {0.f, 0.f, 0.f}, A6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (active) {
         const int n = a.inc_n[f];
-        for (int j = lane; j < n; j += LPV) {
+        for (int j = lane; j < n; j += W) {
             const int pk = a.inc[(size_t)f * a.maxi + j];
             const int c = pk & 3;
             Tet T;
@@ -444,9 +470,9 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
         }
     }
 #pragma unroll
-    for (int i = 0; i < 3; ++i) g[i] = lane_sum(g[i]);
+    for (int i = 0; i < 3; ++i) g[i] = lane_sum_w<W>(g[i]);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) A6[i] = lane_sum(A6[i]);
+    for (int i = 0; i < 6; ++i) A6[i] = lane_sum_w<W>(A6[i]);
     double gsq = 0.0;
     if (active && lane == 0) {
         const int v = a.free_ids[f];
@@ -485,11 +511,13 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
             out[v] = make_float4(base.x + st[0], base.y + st[1], base.z + st[2], 0.0f);
         }
     }
-    block_partial(gsq, active && lane == 0, a.partial);
+    block_partial_t<NV, W>(gsq, active && lane == 0, a.partial);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_plain(SweepArgs a) { plain_body<false>(a); }
-__global__ __launch_bounds__(BLOCK) void k_linear(SweepArgs a) { plain_body<true>(a); }
+template <int W, int BLK>
+__global__ __launch_bounds__(BLK) void k_plain(SweepArgs a) { plain_body<false, W, BLK>(a); }
+template <int W, int BLK>
+__global__ __launch_bounds__(BLK) void k_linear(SweepArgs a) { plain_body<true, W, BLK>(a); }
 
 // thetabar_t -= sum_c y_c . (V_t P(F_t) grad N_c) at the displacement u:
 // the derivative of the step's optimality condition with respect to
@@ -540,6 +568,73 @@ __global__ void k_adj_vec(int nV, const float* __restrict__ mh2, const float4* _
     xbar[v] = xn;
     vbar[v] = vn;
     rhs[v] = make_float4(xn.x + vn.x * ih, xn.y + vn.y * ih, xn.z + vn.z * ih, 0.0f);
+}
+
+// Per-body |g|^2 in FP64: block b sums its body's free vertices (grouped by
+// seg_idx) in a fixed order, so the value does not depend on the other bodies.
+__global__ __launch_bounds__(256) void k_seg_norm2(const int* __restrict__ seg_off, const int* __restrict__ seg_idx,
+                                                   const int* __restrict__ free_ids, const float4* __restrict__ g,
+                                                   double* __restrict__ r2) {
+    __shared__ double s[256];
+    const int b = blockIdx.x;
+    const int lo = seg_off[b], hi = seg_off[b + 1];
+    double e = 0.0;
+    for (int i = lo + threadIdx.x; i < hi; i += 256) {
+        const float4 q = g[free_ids[seg_idx[i]]];
+        e += (double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z;
+    }
+    s[threadIdx.x] = e;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) r2[b] = s[0];
+}
+
+// Start of a step: r0^2 per body, every body with a non-zero residual on.
+__global__ __launch_bounds__(256) void k_mask_init(int nb, const double* __restrict__ r2, double* __restrict__ r0sq,
+                                                   int* __restrict__ on, int* __restrict__ sweeps,
+                                                   int* __restrict__ n_active) {
+    __shared__ int cnt[256];
+    int c = 0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        r0sq[b] = r2[b];
+        on[b] = r2[b] > 0.0 ? 1 : 0;
+        sweeps[b] = 0;
+        c += on[b];
+    }
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) cnt[threadIdx.x] += cnt[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) n_active[0] = cnt[0];
+}
+
+// After k sweeps: count them for the bodies that ran, switch off the bodies
+// with |g_b| <= tol |g_b(x0)|, and count the bodies still on.
+__global__ __launch_bounds__(256) void k_mask_update(int nb, const double* __restrict__ r2,
+                                                     const double* __restrict__ r0sq, double tol2,
+                                                     int* __restrict__ on, int* __restrict__ sweeps, int k,
+                                                     int* __restrict__ n_active) {
+    __shared__ int cnt[256];
+    int c = 0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        if (on[b]) {
+            sweeps[b] += k;
+            if (r2[b] <= tol2 * r0sq[b]) on[b] = 0;
+        }
+        c += on[b];
+    }
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) cnt[threadIdx.x] += cnt[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) n_active[0] = cnt[0];
 }
 
 // Per-block FP64 partial sums of |w_v|^2 over free vertices.
@@ -679,17 +774,43 @@ void launch_phase2_cubature(jgs2_solver* s, const SweepArgs& a) {
     launch(s, JGS2_K_PHASE2, k_phase2_cubature, dim3(nb), dim3(BLOCK), a);
 }
 
-void launch_plain(jgs2_solver* s, const SweepArgs& a) {
-    const int nb = n_blocks_for(a);
+// Launch of a plain or linear sweep kernel in the tuned shape (W lanes per
+// vertex, BLK threads per block).
+template <bool LIN, int W, int BLK>
+static void launch_plain_t(jgs2_solver* s, const SweepArgs& a) {
+    constexpr int NV = BLK / W;
+    const int n = a.list ? a.n_list : a.nVf;
+    const int nb = (n + NV - 1) / NV;
     if (nb == 0) return;
-    launch(s, JGS2_K_PLAIN, k_plain, dim3(nb), dim3(BLOCK), a);
+    if (LIN)
+        launch(s, JGS2_K_LINEAR, k_linear<W, BLK>, dim3(nb), dim3(BLK), a);
+    else
+        launch(s, JGS2_K_PLAIN, k_plain<W, BLK>, dim3(nb), dim3(BLK), a);
 }
 
-void launch_linear(jgs2_solver* s, const SweepArgs& a) {
-    const int nb = n_blocks_for(a);
-    if (nb == 0) return;
-    launch(s, JGS2_K_LINEAR, k_linear, dim3(nb), dim3(BLOCK), a);
+template <bool LIN, int W>
+static void launch_plain_w(jgs2_solver* s, const SweepArgs& a) {
+    switch (s->tune_block) {
+        case 64: launch_plain_t<LIN, W, 64>(s, a); break;
+        case 128: launch_plain_t<LIN, W, 128>(s, a); break;
+        case 512: launch_plain_t<LIN, W, 512>(s, a); break;
+        default: launch_plain_t<LIN, W, 256>(s, a); break;
+    }
 }
+
+template <bool LIN>
+static void launch_plain_any(jgs2_solver* s, const SweepArgs& a) {
+    switch (s->tune_lpv) {
+        case 4: launch_plain_w<LIN, 4>(s, a); break;
+        case 8: launch_plain_w<LIN, 8>(s, a); break;
+        case 16: launch_plain_w<LIN, 16>(s, a); break;
+        default: launch_plain_w<LIN, 32>(s, a); break;
+    }
+}
+
+void launch_plain(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<false>(s, a); }
+
+void launch_linear(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<true>(s, a); }
 
 void launch_param_grad(jgs2_solver* s, const float4* u, const float4* y, double* thbar) {
     launch(s, JGS2_K_PARAMGRAD, k_param_grad, dim3((s->nT + 255) / 256), dim3(256), (const float4*)s->d_tet, s->nT,
@@ -704,6 +825,22 @@ void launch_adj_vec(jgs2_solver* s, const float4* y, float4* xbar, float4* vbar,
 void launch_norm2(jgs2_solver* s, const float4* w) {
     launch(s, JGS2_K_REDUCE, k_norm2, dim3((s->nVf + 255) / 256), dim3(256), s->nVf, (const int*)s->d_free, w,
            s->d_partial);
+}
+
+void launch_seg_norm2(jgs2_solver* s) {
+    launch(s, JGS2_K_REDUCE, k_seg_norm2, dim3(s->n_bodies), dim3(256), (const int*)s->d_seg_off,
+           (const int*)s->d_seg_idx, (const int*)s->d_free, (const float4*)s->d_g, s->d_r2);
+}
+
+void launch_mask_init(jgs2_solver* s) {
+    launch(s, JGS2_K_REDUCE, k_mask_init, dim3(1), dim3(256), s->n_bodies, (const double*)s->d_r2, s->d_r0sq,
+           s->d_body_on, s->d_body_sweeps, s->d_nactive);
+}
+
+void launch_mask_update(jgs2_solver* s, int k) {
+    const double tol2 = s->p.rel_tol * s->p.rel_tol;
+    launch(s, JGS2_K_REDUCE, k_mask_update, dim3(1), dim3(256), s->n_bodies, (const double*)s->d_r2,
+           (const double*)s->d_r0sq, tol2, s->d_body_on, s->d_body_sweeps, k, s->d_nactive);
 }
 
 void launch_commit(jgs2_solver* s, const SweepArgs& a) {

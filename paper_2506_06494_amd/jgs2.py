@@ -27,7 +27,7 @@ class Params(C.Structure):
                 ("omega", C.c_double), ("rel_tol", C.c_double), ("max_sweeps", C.c_int32),
                 ("check_every", C.c_int32), ("d_hat", C.c_double), ("kappa", C.c_double),
                 ("n_planes", C.c_int32), ("line_search", C.c_int32), ("planes", (C.c_double * 4) * MAX_PLANES),
-                ("adj_rel_tol", C.c_double), ("adj_max_sweeps", C.c_int32), ("reserved", C.c_int32)]
+                ("adj_rel_tol", C.c_double), ("adj_max_sweeps", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -45,7 +45,8 @@ EXPORTS = ["jgs2_default_params", "jgs2_create", "jgs2_destroy", "jgs2_last_erro
            "jgs2_import_correction", "jgs2_export_correction", "jgs2_get_ring_sizes", "jgs2_get_poses",
            "jgs2_set_state", "jgs2_get_state", "jgs2_step", "jgs2_begin_step", "jgs2_iterate", "jgs2_end_step",
            "jgs2_residual", "jgs2_energy", "jgs2_get_phase1", "jgs2_get_coloring", "jgs2_set_profiling",
-           "jgs2_kernel_times", "jgs2_rollout", "jgs2_rollout_backward"]
+           "jgs2_kernel_times", "jgs2_rollout", "jgs2_rollout_backward", "jgs2_set_bodies", "jgs2_get_body_stats",
+           "jgs2_set_tuning", "jgs2_get_tuning", "jgs2_autotune"]
 
 KERNELS = ["phase1", "phase2", "plain", "commit", "reduce", "predict", "velocity", "energy", "linear", "paramgrad",
            "adjvec"]
@@ -91,6 +92,11 @@ def load(path: str = LIB_PATH):
         "jgs2_kernel_times": (C.c_int32, [C.c_void_p, d, P(C.c_int64)]),
         "jgs2_rollout": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, P(StepStats)]),
         "jgs2_rollout_backward": (C.c_int32, [C.c_void_p, d, d, d, d, d, P(AdjointStats)]),
+        "jgs2_set_bodies": (C.c_int32, [C.c_void_p, C.c_int32, i32]),
+        "jgs2_get_body_stats": (C.c_int32, [C.c_void_p, i32, i32, d]),
+        "jgs2_set_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
+        "jgs2_get_tuning": (C.c_int32, [C.c_void_p, i32, i32]),
+        "jgs2_autotune": (C.c_int32, [C.c_void_p, C.c_int32, i32, i32, d]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -264,6 +270,36 @@ class Solver:
         a, r = C.c_double(), C.c_double()
         self._chk(self.lib.jgs2_residual(self.h, C.byref(a), C.byref(r)))
         return a.value, r.value
+
+    def set_bodies(self, body_of_vertex):
+        b = np.ascontiguousarray(body_of_vertex, dtype=np.int32)
+        self.n_bodies = int(b.max()) + 1
+        self._chk(self.lib.jgs2_set_bodies(self.h, self.n_bodies, _iptr(b)))
+
+    def body_stats(self):
+        """(sweeps per body, |g_b| / |g_b(x0)| per body) at the last check."""
+        n = C.c_int32()
+        self._chk(self.lib.jgs2_get_body_stats(self.h, C.byref(n), None, None))
+        sw = np.zeros(n.value, dtype=np.int32)
+        rel = np.zeros(n.value)
+        self._chk(self.lib.jgs2_get_body_stats(self.h, C.byref(n), _iptr(sw), _dptr(rel)))
+        return sw, rel
+
+    def set_tuning(self, lanes_per_vertex, block):
+        self._chk(self.lib.jgs2_set_tuning(self.h, int(lanes_per_vertex), int(block)))
+
+    def tuning(self):
+        a, b = C.c_int32(), C.c_int32()
+        self._chk(self.lib.jgs2_get_tuning(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def autotune(self, sweeps=16):
+        """Times every launch shape; keeps and returns the fastest
+        (lanes_per_vertex, block) and the 4 x 4 table of times (ms)."""
+        a, b = C.c_int32(), C.c_int32()
+        ms = np.zeros(16)
+        self._chk(self.lib.jgs2_autotune(self.h, int(sweeps), C.byref(a), C.byref(b), _dptr(ms)))
+        return (a.value, b.value), ms.reshape(4, 4)
 
     def rollout(self, n_steps, ckpt_every=5):
         """n_steps forward steps from the current state, keeping device
