@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--modes", default="jgs2_jacobi,jgs2_gs,plain_jacobi,plain_jacobi_w0.8,plain_gs,plain_gs_w1.5")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched many-beam leg")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the launch shape of the single-beam modes (default: 32 lanes x 256)")
     ap.add_argument("--batched-beams", type=int, default=256)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (5x) to calibrate HBM byte counters")
@@ -101,7 +103,7 @@ def main():
         corr = None
         for name, cfg in modes:
             s = jgs2.Solver(dt=sc.dt, gravity=sc.gravity, rel_tol=1e-5, max_sweeps=args.max_sweeps,
-                            check_every=16, **cfg)
+                            check_every=16, use_graph=1, **cfg)
             s.upload_mesh(m.X, m.tets, m.pinned)
             s.set_material(sc.E, sc.nu, sc.rho)
             if cfg["variant"] == jgs2.CUBATURE:
@@ -118,6 +120,9 @@ def main():
                     s.import_correction(4, corr["U_ring"].reshape(-1, 9), corr["samples"], corr["weights"],
                                         corr["U_samp"])
             s.set_state(sc.x0, sc.v0)
+            tuned = None
+            if cfg["variant"] == jgs2.PLAIN and args.tune:
+                tuned, _ = s.autotune(32)        # launch shape of the plain sweep kernel on this mesh
             # warm-up steps (untimed), then the timed steps
             failed = None
             stalled = None
@@ -158,6 +163,8 @@ def main():
             ok = failed is None and stalled is None and all(r["r_final"] <= 1e-5 for r in recs)
             entry = dict(status=jgs2.STATUS_NAMES[failed["status"]] if failed else "OK",
                          converged_all=bool(ok), steps=len(recs))
+            if tuned:
+                entry["launch_shape"] = list(tuned)
             if failed:
                 entry["sweeps_before_failure"] = failed["sweeps"]
             if stalled:
@@ -256,7 +263,7 @@ def batched_leg(n_beams=256, steps=2, max_sweeps=1000, check_every=8, omega=1.5)
     s.set_material(E, nu, 1000.0)
     s.set_bodies(u.body)
     s.set_state(u.X, np.zeros_like(u.X))
-    (lpv, blk), tune_ms = s.autotune(4)
+    (lpv, blk), tune_ms = s.autotune(8)
     print(f"[bench] batched: {u.nV} vertices, {u.nT} tets, tuned shape {lpv}x{blk}", file=sys.stderr, flush=True)
     # roofline of the sweep kernel while every beam is still iterating
     s.set_profiling(True)
@@ -309,17 +316,18 @@ def batched_leg(n_beams=256, steps=2, max_sweeps=1000, check_every=8, omega=1.5)
     return out
 
 
-def adjoint_leg(n_steps=30, ckpt_every=5):
+def adjoint_leg(n_steps=30, ckpt_every=5, omega=1.7):
     """Differentiation workload: 16x16x64 beam (18,785 vertices, 98,304
     tets), per-tet log E = log 1e6 + U(-0.3, 0.3), u = 0, 30 steps of plain
-    coloured GS to 1e-5, loss |tip centroid - target|^2; forward rollout with
-    checkpoints every 5 steps, then the adjoint (recompute + linear sweeps to
-    1e-5 + stiffness gradient), both timed with a synchronised wall clock."""
+    coloured GS (step scale omega) to 1e-5, loss |tip centroid - target|^2;
+    forward rollout with checkpoints every 5 steps, then the adjoint
+    (recompute + linear sweeps to 1e-5 + stiffness gradient), both timed with
+    a synchronised wall clock."""
     from paper_2506_06494_amd import inputs, jgs2
     sc, logE, target = inputs.diff_beam(0)
     m = sc.mesh
-    s = jgs2.Solver(dt=sc.dt, gravity=sc.gravity, order=jgs2.GS, rel_tol=1e-5, adj_rel_tol=1e-5,
-                    check_every=16)
+    s = jgs2.Solver(dt=sc.dt, gravity=sc.gravity, order=jgs2.GS, omega=omega, rel_tol=1e-5, adj_rel_tol=1e-5,
+                    check_every=16, use_graph=1)
     s.upload_mesh(m.X, m.tets, m.pinned)
     s.set_material(np.exp(logE), 0.45, 1000.0)
     tip = np.nonzero(m.X[:, 0] >= m.X[:, 0].max() - 1e-12)[0]
@@ -341,7 +349,8 @@ def adjoint_leg(n_steps=30, ckpt_every=5):
         sync()
         tb = time.perf_counter() - t0
         out = {"workload": "beam 16x16x64 (18,785 vertices, 98,304 tets), log E = log 1e6 + U(-0.3,0.3), "
-                           "30 steps, checkpoints every 5, plain coloured GS forward and adjoint to 1e-5",
+                           f"30 steps, checkpoints every 5, plain coloured GS (omega {omega}) forward and adjoint "
+                           "to 1e-5",
                "loss": float(r @ r), "forward_s_per_step": tf / n_steps, "adjoint_s_per_step": tb / n_steps,
                "ratio": tb / tf, "adjoint_sweeps_per_step": st["adjoint_sweeps"] / n_steps,
                "recompute_sweeps_per_step": st["forward_sweeps"] / n_steps,
@@ -384,15 +393,16 @@ def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches
     """Compulsory (algorithmic) bytes moved by one launch of a sweep kernel,
     counting every datum it must touch once: tet records 80 B, incidence
     entries 4 B (plus 4 B slot words in phase 2), one-ring ids + U-bar rows
-    40 B per entry, 168 B per cubature sample, and per-vertex arrays."""
-    if kind == "phase1":
-        return 80.0 * T + 4.0 * n_inc + 72.0 * Vf + 12.0 * V
-    if kind == "phase2":
-        return 80.0 * T + 8.0 * n_inc + 40.0 * ring_entries + Vf * (24.0 + 168.0 * S) + 60.0 * V
-    if kind == "plain_jacobi":
-        return 80.0 * T + 4.0 * n_inc + 36.0 * Vf + 12.0 * V
+    40 B per entry, 168 B per cubature sample, 32 B FP64 displacement and
+    inertial-target records, 16 B gradient and rotation records."""
+    if kind == "phase1":      # positions; z read, g and R written per free vertex
+        return 80.0 * T + 4.0 * n_inc + 64.0 * Vf + 32.0 * V
+    if kind == "phase2":      # positions, g, R of every vertex; own record, samples, update
+        return 80.0 * T + 8.0 * n_inc + 40.0 * ring_entries + Vf * (40.0 + 168.0 * S) + 64.0 * V
+    if kind == "plain_jacobi":  # positions; z read and update written per free vertex
+        return 80.0 * T + 4.0 * n_inc + 64.0 * Vf + 32.0 * V
     if kind == "plain_gs_sweep":  # all colour launches of one sweep
-        return 84.0 * n_inc + 36.0 * Vf + 12.0 * V * n_colors
+        return 84.0 * n_inc + 64.0 * Vf + 32.0 * V * n_colors
     raise ValueError(kind)
 
 

@@ -10,6 +10,19 @@
 
 namespace jgs2 {
 
+// Displacement record in FP64 (x, y, z; w spare or m/h^2): positions and the
+// inertial target are stored to FP64 so that the iterate can move by less than
+// an FP32 ulp of the displacement; every stress and Hessian evaluation is FP32
+// on differences taken in FP64.
+struct alignas(32) d4 {
+    double x, y, z, w;
+};
+__host__ __device__ inline d4 make_d4(double x, double y, double z, double w) {
+    d4 r;
+    r.x = x; r.y = y; r.z = z; r.w = w;
+    return r;
+}
+
 constexpr int LPV = 32;          // lanes per vertex sub-problem
 constexpr int VPB = 8;           // vertices per 256-thread block
 constexpr int BLOCK = LPV * VPB;
@@ -37,9 +50,9 @@ struct SweepArgs {
     const int* samp_e;      // [nVf * S]
     const float* samp;      // [(nVf * SREC + field) * S + s]
     const float4* X;        // [nV] rest positions (w unused)
-    const float4* u;        // [nV] current displacement x - X (w unused)
-    float4* unext;          // [nV]
-    const float4* zu;       // [nV] inertial target displacement, w = m_a / h^2 (0 if pinned)
+    const d4* u;            // [nV] current displacement x - X (w unused)
+    d4* unext;              // [nV]
+    const d4* zu;           // [nV] inertial target displacement, w = m_a / h^2 (0 if pinned)
     float4* g;              // [nV] assembled gradient (w unused)
     float4* R;              // [nV] per-vertex rotation as a unit quaternion (x, y, z, w)
     double* partial;        // [gridDim] per-block partial sums of |g|^2
@@ -95,8 +108,8 @@ struct jgs2_solver {
 
     // device
     float4* d_tet = nullptr;
-    float4 *d_X = nullptr, *d_u = nullptr, *d_unext = nullptr, *d_uhat = nullptr, *d_vhat = nullptr;
-    float4 *d_zu = nullptr, *d_g = nullptr, *d_R = nullptr;
+    float4 *d_X = nullptr, *d_vhat = nullptr, *d_g = nullptr, *d_R = nullptr;
+    jgs2::d4 *d_u = nullptr, *d_unext = nullptr, *d_uhat = nullptr, *d_zu = nullptr;
     float* d_mh2 = nullptr;
     int *d_free = nullptr, *d_inc = nullptr, *d_inc_n = nullptr, *d_ring = nullptr, *d_ring_n = nullptr;
     uint32_t* d_incslot = nullptr;
@@ -119,7 +132,8 @@ struct jgs2_solver {
     // recomputed segment states [ckpt_every][nV], adjoint vectors
     int ro_steps = 0, ro_every = 0, ro_nck = 0;
     bool ro_valid = false;
-    float4 *d_ck_u = nullptr, *d_ck_v = nullptr, *d_seg = nullptr;
+    jgs2::d4 *d_ck_u = nullptr, *d_seg = nullptr;
+    float4* d_ck_v = nullptr;
     float4 *d_y = nullptr, *d_ynext = nullptr, *d_xbar = nullptr, *d_vbar = nullptr, *d_rhs = nullptr;
     double* d_thbar = nullptr;
     // bodies (disjoint meshes solved together; per-body residuals and masks)
@@ -140,7 +154,7 @@ struct jgs2_solver {
     hipStream_t own_stream = nullptr;
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     int graph_k[2] = {0, 0};
-    float4* graph_u[2] = {nullptr, nullptr};
+    jgs2::d4* graph_u[2] = {nullptr, nullptr};
     int graph_next = 0;
 
     int fail(int code, const std::string& msg) {
@@ -160,7 +174,7 @@ void launch_phase2_cubature(jgs2_solver* s, const SweepArgs& a);
 void launch_plain(jgs2_solver* s, const SweepArgs& a);
 void launch_commit(jgs2_solver* s, const SweepArgs& a);
 void launch_linear(jgs2_solver* s, const SweepArgs& a);
-void launch_param_grad(jgs2_solver* s, const float4* u, const float4* y, double* thbar);
+void launch_param_grad(jgs2_solver* s, const d4* u, const float4* y, double* thbar);
 void launch_adj_vec(jgs2_solver* s, const float4* y, float4* xbar, float4* vbar, float4* rhs);
 void launch_norm2(jgs2_solver* s, const float4* w);
 void launch_seg_norm2(jgs2_solver* s);

@@ -406,8 +406,8 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
         (r = upload(s, s->d_ring, s->ring.data(), nf * s->K)) || (r = upload(s, s->d_ring_n, s->ring_n.data(), nf)) ||
         (r = upload(s, s->d_colperm, s->col_perm.data(), nf)))
         return r;
-    for (float4* d : {s->d_u, s->d_unext, s->d_uhat, s->d_vhat, s->d_zu, s->d_g})
-        HIPCHK(hipMemsetAsync(d, 0, V4 * sizeof(float4), s->stream));
+    for (d4* d : {s->d_u, s->d_unext, s->d_uhat, s->d_zu}) HIPCHK(hipMemsetAsync(d, 0, V4 * sizeof(d4), s->stream));
+    for (float4* d : {s->d_vhat, s->d_g}) HIPCHK(hipMemsetAsync(d, 0, V4 * sizeof(float4), s->stream));
     HIPCHK(hipMemsetAsync(s->d_mh2, 0, (size_t)nV * sizeof(float), s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     {
@@ -554,16 +554,18 @@ int32_t jgs2_set_state(jgs2_solver* s, const double* x, const double* v) {
     if (!s->have_mesh) return s->fail(JGS2_E_NOT_READY, "no mesh");
     if (!x || !v) return s->fail(JGS2_E_INVALID, "NULL state");
     const size_t nV = s->nV;
-    std::vector<float4> u(nV), vv(nV);
+    std::vector<d4> u(nV);
+    std::vector<float4> vv(nV);
     for (size_t a = 0; a < nV; ++a) {
-        float uu[3], vl[3];
+        double uu[3];
+        float vl[3];
         for (int i = 0; i < 3; ++i) {
             const double xi = x[3 * a + i], vi = v[3 * a + i];
             if (!std::isfinite(xi) || !std::isfinite(vi)) return s->fail(JGS2_E_INVALID, "non-finite state");
-            uu[i] = (float)(xi - s->X[3 * a + i]);
+            uu[i] = xi - s->X[3 * a + i];
             vl[i] = s->pinned[a] ? 0.0f : (float)vi;
         }
-        u[a] = make_float4(uu[0], uu[1], uu[2], 0.f);
+        u[a] = make_d4(uu[0], uu[1], uu[2], 0.0);
         vv[a] = make_float4(vl[0], vl[1], vl[2], 0.f);
     }
     int r;
@@ -582,15 +584,17 @@ int32_t jgs2_get_state(jgs2_solver* s, double* x, double* v) {
     if (!s) return JGS2_E_INVALID;
     if (!s->have_state) return s->fail(JGS2_E_NOT_READY, "no state");
     const size_t nV = s->nV;
-    std::vector<float4> u(nV), vv(nV);
+    std::vector<d4> u(nV);
+    std::vector<float4> vv(nV);
     // inside a step the current iterate is u; otherwise uhat == u
-    HIPCHK(hipMemcpyAsync(u.data(), s->d_u, nV * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(u.data(), s->d_u, nV * sizeof(d4), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(vv.data(), s->d_vhat, nV * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     for (size_t a = 0; a < nV; ++a) {
-        const float uu[3] = {u[a].x, u[a].y, u[a].z}, vl[3] = {vv[a].x, vv[a].y, vv[a].z};
+        const double uu[3] = {u[a].x, u[a].y, u[a].z};
+        const float vl[3] = {vv[a].x, vv[a].y, vv[a].z};
         for (int i = 0; i < 3; ++i) {
-            if (x) x[3 * a + i] = s->X[3 * a + i] + (double)uu[i];
+            if (x) x[3 * a + i] = s->X[3 * a + i] + uu[i];
             if (v) v[3 * a + i] = vl[i];
         }
     }
@@ -658,12 +662,12 @@ int32_t jgs2_begin_step(jgs2_solver* s) {
     const float grav[3] = {(float)s->p.gravity[0], (float)s->p.gravity[1], (float)s->p.gravity[2]};
     // contact feasibility of the start state
     if (s->p.n_planes > 0) {
-        std::vector<float4> u((size_t)s->nV);
-        HIPCHK(hipMemcpyAsync(u.data(), s->d_uhat, u.size() * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
+        std::vector<d4> u((size_t)s->nV);
+        HIPCHK(hipMemcpyAsync(u.data(), s->d_uhat, u.size() * sizeof(d4), hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
         for (int f = 0; f < s->nVf; ++f) {
             const int v = s->free_ids[f];
-            const float uu[3] = {u[v].x, u[v].y, u[v].z};
+            const double uu[3] = {u[v].x, u[v].y, u[v].z};
             for (int p = 0; p < s->p.n_planes; ++p) {
                 double d = -s->p.planes[p][3];
                 for (int i = 0; i < 3; ++i) d += s->p.planes[p][i] * (s->X[3 * (size_t)v + i] + uu[i]);
@@ -691,7 +695,7 @@ static void swap_u(jgs2_solver* s) {
     s->phase1_valid = false;
 }
 
-static int energy_of(jgs2_solver* s, float4* state, double* e) {
+static int energy_of(jgs2_solver* s, d4* state, double* e) {
     SweepArgs a;
     build_sweep_args(s, a);
     a.u = state;
@@ -779,7 +783,7 @@ static int sweep_group(jgs2_solver* s, int k) {
         s->graph_next = par ^ 1;
         if (s->graph_exec[par]) (void)hipGraphExecDestroy(s->graph_exec[par]);
         s->graph_exec[par] = nullptr;
-        float4* u0 = s->d_u;
+        d4* u0 = s->d_u;
         const int sw0 = s->sweeps_in_step;
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
@@ -834,7 +838,7 @@ int32_t jgs2_end_step(jgs2_solver* s) {
     if (!s->in_step) return s->fail(JGS2_E_NOT_READY, "end_step without begin_step");
     launch_velocity(s, (float)s->p.dt);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(s->d_unext, s->d_u, (size_t)s->nV * sizeof(float4), hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_unext, s->d_u, (size_t)s->nV * sizeof(d4), hipMemcpyDeviceToDevice, s->stream));
     s->in_step = false;
     s->phase1_valid = false;
     return JGS2_OK;
@@ -842,8 +846,8 @@ int32_t jgs2_end_step(jgs2_solver* s) {
 
 static int abandon_step(jgs2_solver* s) {
     // restore the iterate to the start of the step
-    (void)hipMemcpyAsync(s->d_u, s->d_uhat, (size_t)s->nV * sizeof(float4), hipMemcpyDeviceToDevice, s->stream);
-    (void)hipMemcpyAsync(s->d_unext, s->d_uhat, (size_t)s->nV * sizeof(float4), hipMemcpyDeviceToDevice, s->stream);
+    (void)hipMemcpyAsync(s->d_u, s->d_uhat, (size_t)s->nV * sizeof(d4), hipMemcpyDeviceToDevice, s->stream);
+    (void)hipMemcpyAsync(s->d_unext, s->d_uhat, (size_t)s->nV * sizeof(d4), hipMemcpyDeviceToDevice, s->stream);
     (void)hipStreamSynchronize(s->stream);
     s->in_step = false;
     s->phase1_valid = false;
@@ -960,9 +964,10 @@ int32_t jgs2_get_coloring(jgs2_solver* s, int32_t* color, int32_t* n_colors) {
 // Differentiable rollout (adjoint of the step map through its optimality
 // condition) with checkpointed recomputation.
 // ---------------------------------------------------------------------------
-static int copy_v4(jgs2_solver* s, float4* dst, const float4* src) {
-    return jgs2::hip_check(s, hipMemcpyAsync(dst, src, (size_t)s->nV * sizeof(float4), hipMemcpyDeviceToDevice,
-                                             s->stream), "state copy");
+template <typename T>
+static int copy_v4(jgs2_solver* s, T* dst, const T* src) {
+    return jgs2::hip_check(s, hipMemcpyAsync(dst, src, (size_t)s->nV * sizeof(T), hipMemcpyDeviceToDevice, s->stream),
+                           "state copy");
 }
 
 static int save_checkpoint(jgs2_solver* s, int slot) {
@@ -996,7 +1001,7 @@ static int linear_residual2(jgs2_solver* s, SweepArgs a, double* r2) {
 
 // Solves H(xstar) y = rhs (device d_rhs) by linear sweeps, warm-started from
 // the y already in d_y.
-static int adjoint_solve(jgs2_solver* s, const float4* xstar, int64_t* sweeps, double* rel) {
+static int adjoint_solve(jgs2_solver* s, const d4* xstar, int64_t* sweeps, double* rel) {
     SweepArgs a;
     build_sweep_args(s, a);
     a.u = xstar;
@@ -1125,7 +1130,7 @@ int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* 
                 return r;
         }
         for (int n = n1 - 1; n >= n0 && status == JGS2_OK; --n) {
-            const float4* xstar = s->d_seg + (size_t)(n - n0) * nV;
+            const d4* xstar = s->d_seg + (size_t)(n - n0) * nV;
             double rel = 0.0;
             status = adjoint_solve(s, xstar, &loc.adjoint_sweeps, &rel);
             if (status != JGS2_OK) break;

@@ -86,7 +86,21 @@ __device__ __forceinline__ void gradN(const float* D, int c, float* gn) {
     }
 }
 
-// H = F - I = [u1-u0, u2-u0, u3-u0] Dm^-1 (displacement gradient)
+// H = F - I = [u1-u0, u2-u0, u3-u0] Dm^-1 (displacement gradient); the edge
+// differences of FP64 displacements are taken in FP64, then rounded
+__device__ __forceinline__ void dispgrad(const d4* __restrict__ u, const Tet& T, float* H) {
+    const d4 u0 = u[T.id[0]], u1 = u[T.id[1]], u2 = u[T.id[2]], u3 = u[T.id[3]];
+    const float du[3][3] = {{(float)(u1.x - u0.x), (float)(u1.y - u0.y), (float)(u1.z - u0.z)},
+                            {(float)(u2.x - u0.x), (float)(u2.y - u0.y), (float)(u2.z - u0.z)},
+                            {(float)(u3.x - u0.x), (float)(u3.y - u0.y), (float)(u3.z - u0.z)}};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            H[3 * i + j] = du[0][i] * T.D[j] + du[1][i] * T.D[3 + j] + du[2][i] * T.D[6 + j];
+}
+
+// The same for an FP32 field (the adjoint's y).
 __device__ __forceinline__ void dispgrad(const float4* __restrict__ u, const Tet& T, float* H) {
     const float4 u0 = u[T.id[0]], u1 = u[T.id[1]], u2 = u[T.id[2]], u3 = u[T.id[3]];
     const float du[3][3] = {{u1.x - u0.x, u1.y - u0.y, u1.z - u0.z},
@@ -142,10 +156,10 @@ __device__ __forceinline__ void galerkin_hessian(const Tet& T, const Kin<float>&
 
 // IPC plane barriers of vertex v at displacement uv: gradient into g and,
 // if H6 is given, the Hessian kappa B'' n n^T into H6.
-__device__ __forceinline__ void barrier_terms(const SweepArgs& a, int v, float4 uv, float* g, float* H6) {
+__device__ __forceinline__ void barrier_terms(const SweepArgs& a, int v, const d4& uv, float* g, float* H6) {
     if (a.n_planes == 0) return;
     const float4 X = a.X[v];
-    const float x0 = X.x + uv.x, x1 = X.y + uv.y, x2 = X.z + uv.z;
+    const float x0 = (float)(X.x + uv.x), x1 = (float)(X.y + uv.y), x2 = (float)(X.z + uv.z);
 #pragma unroll
     for (int p = 0; p < JGS2_MAX_PLANES; ++p) {
         if (p >= a.n_planes) break;
@@ -166,10 +180,10 @@ __device__ __forceinline__ void barrier_terms(const SweepArgs& a, int v, float4 
 // Per-vertex feasibility clamp against the static planes: the move is scaled
 // by alpha = min(1, 0.9 min_p d_p / (-n_p . step)) over planes it approaches,
 // so no vertex reaches a plane whatever the other vertices do.
-__device__ __forceinline__ void clamp_step(const SweepArgs& a, int v, float4 uv, float* step) {
+__device__ __forceinline__ void clamp_step(const SweepArgs& a, int v, const d4& uv, float* step) {
     if (a.n_planes == 0) return;
     const float4 X = a.X[v];
-    const float x0 = X.x + uv.x, x1 = X.y + uv.y, x2 = X.z + uv.z;
+    const float x0 = (float)(X.x + uv.x), x1 = (float)(X.y + uv.y), x2 = (float)(X.z + uv.z);
     float alpha = 1.0f;
 #pragma unroll
     for (int p = 0; p < JGS2_MAX_PLANES; ++p) {
@@ -241,10 +255,11 @@ __global__ __launch_bounds__(BLOCK) void k_phase1(SweepArgs a, int want_R) {
     double gsq = 0.0;
     if (active && lane == 0) {
         const int v = a.free_ids[f];
-        const float4 uv = a.u[v], zv = a.zu[v];
-        g[0] += zv.w * (uv.x - zv.x);
-        g[1] += zv.w * (uv.y - zv.y);
-        g[2] += zv.w * (uv.z - zv.z);
+        const d4 uv = a.u[v], zv = a.zu[v];
+        const float m = (float)zv.w;
+        g[0] += m * (float)(uv.x - zv.x);
+        g[1] += m * (float)(uv.y - zv.y);
+        g[2] += m * (float)(uv.z - zv.z);
         barrier_terms(a, v, uv, g, nullptr);
         a.g[v] = make_float4(g[0], g[1], g[2], 0.0f);
         gsq = (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
@@ -387,7 +402,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) b[i] = lane_sum(b[i]);
     if (active && lane == 0) {
-        const float4 uv = a.u[v];
+        const d4 uv = a.u[v];
         float gv[3] = {0.f, 0.f, 0.f};
         barrier_terms(a, v, uv, gv, A6);  // barrier Hessian of vertex i only (g already holds its gradient)
         float A[9] = {A6[0], A6[1], A6[2], A6[1], A6[3], A6[4], A6[2], A6[4], A6[5]};
@@ -397,7 +412,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
         local_solve(A, bb, dx);
         float st[3] = {a.omega * dx[0], a.omega * dx[1], a.omega * dx[2]};
         clamp_step(a, v, uv, st);
-        a.unext[v] = make_float4(uv.x + st[0], uv.y + st[1], uv.z + st[2], 0.0f);
+        a.unext[v] = make_d4(uv.x + st[0], uv.y + st[1], uv.z + st[2], 0.0);
     }
 }
 
@@ -476,10 +491,11 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     double gsq = 0.0;
     if (active && lane == 0) {
         const int v = a.free_ids[f];
-        const float4 uv = a.u[v];
-        float4 base;
+        const d4 uv = a.u[v];
+        float4 yv = make_float4(0.f, 0.f, 0.f, 0.f);
         if (LIN) {
-            const float4 yv = a.ly[v], rv = a.lrhs[v];
+            const float4 rv = a.lrhs[v];
+            yv = a.ly[v];
             const float m = a.mh2[v];
             float Hb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, gb[3] = {0.f, 0.f, 0.f};
             barrier_terms(a, v, uv, gb, Hb);
@@ -488,16 +504,14 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
             g[2] += m * yv.z - rv.z + Hb[2] * yv.x + Hb[4] * yv.y + Hb[5] * yv.z;
             A6[0] += m + Hb[0]; A6[1] += Hb[1]; A6[2] += Hb[2];
             A6[3] += m + Hb[3]; A6[4] += Hb[4]; A6[5] += m + Hb[5];
-            base = yv;
         } else {
-            const float4 zv = a.zu[v];
-            const float m = zv.w;
-            g[0] += m * (uv.x - zv.x);
-            g[1] += m * (uv.y - zv.y);
-            g[2] += m * (uv.z - zv.z);
+            const d4 zv = a.zu[v];
+            const float m = (float)zv.w;
+            g[0] += m * (float)(uv.x - zv.x);
+            g[1] += m * (float)(uv.y - zv.y);
+            g[2] += m * (float)(uv.z - zv.z);
             A6[0] += m; A6[3] += m; A6[5] += m;
             barrier_terms(a, v, uv, g, A6);
-            base = uv;
         }
         gsq = (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
         if (!a.no_write) {
@@ -505,10 +519,14 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
             float dx[3];
             local_solve(A, g, dx);
             float st[3] = {a.omega * dx[0], a.omega * dx[1], a.omega * dx[2]};
-            if (!LIN) clamp_step(a, v, uv, st);
-            float4* out = LIN ? (a.in_place ? const_cast<float4*>(a.ly) : a.lynext)
-                              : (a.in_place ? const_cast<float4*>(a.u) : a.unext);
-            out[v] = make_float4(base.x + st[0], base.y + st[1], base.z + st[2], 0.0f);
+            if (LIN) {
+                float4* out = a.in_place ? const_cast<float4*>(a.ly) : a.lynext;
+                out[v] = make_float4(yv.x + st[0], yv.y + st[1], yv.z + st[2], 0.0f);
+            } else {
+                clamp_step(a, v, uv, st);
+                d4* out = a.in_place ? const_cast<d4*>(a.u) : a.unext;
+                out[v] = make_d4(uv.x + st[0], uv.y + st[1], uv.z + st[2], 0.0);
+            }
         }
     }
     block_partial_t<NV, W>(gsq, active && lane == 0, a.partial);
@@ -522,7 +540,7 @@ __global__ __launch_bounds__(BLK) void k_linear(SweepArgs a) { plain_body<true, 
 // thetabar_t -= sum_c y_c . (V_t P(F_t) grad N_c) at the displacement u:
 // the derivative of the step's optimality condition with respect to
 // log E_t is the element's elastic force, since mu and lambda scale with E.
-__global__ void k_param_grad(const float4* __restrict__ tet, int nT, const float4* __restrict__ u,
+__global__ void k_param_grad(const float4* __restrict__ tet, int nT, const d4* __restrict__ u,
                              const float4* __restrict__ y, double* __restrict__ thbar) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nT) return;
@@ -661,7 +679,7 @@ __global__ void k_commit(SweepArgs a) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.n_list) return;
     const int v = a.free_ids[a.list[idx]];
-    const_cast<float4*>(a.u)[v] = a.unext[v];
+    const_cast<d4*>(a.u)[v] = a.unext[v];
 }
 
 // Backtracking: unext <- u + t (unext - u) on free vertices.
@@ -669,8 +687,9 @@ __global__ void k_blend(SweepArgs a, float t) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= a.nVf) return;
     const int v = a.free_ids[f];
-    const float4 x = a.u[v], y = a.unext[v];
-    a.unext[v] = make_float4(x.x + t * (y.x - x.x), x.y + t * (y.y - x.y), x.z + t * (y.z - x.z), 0.0f);
+    const d4 x = a.u[v], y = a.unext[v];
+    const double tt = t;
+    a.unext[v] = make_d4(x.x + tt * (y.x - x.x), x.y + tt * (y.y - x.y), x.z + tt * (y.z - x.z), 0.0);
 }
 
 // Fixed-order sum of n per-block partials into out[0] (one block).
@@ -689,31 +708,32 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ in, i
 
 // z = xhat + h vhat + h^2 g on free vertices (displacement form; w = m/h^2),
 // x0 = xhat.
-__global__ void k_predict(int nV, const float4* __restrict__ uhat, const float4* __restrict__ vhat,
+__global__ void k_predict(int nV, const d4* __restrict__ uhat, const float4* __restrict__ vhat,
                           const float* __restrict__ mh2, float h, float g0, float g1, float g2,
-                          float4* __restrict__ u, float4* __restrict__ unext, float4* __restrict__ zu) {
+                          d4* __restrict__ u, d4* __restrict__ unext, d4* __restrict__ zu) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nV) return;
-    const float4 x = uhat[v];
+    const d4 x = uhat[v];
     u[v] = x;
     unext[v] = x;
     const float m = mh2[v];
     if (m > 0.0f) {
         const float4 vv = vhat[v];
-        const float h2 = h * h;
-        zu[v] = make_float4(x.x + h * vv.x + h2 * g0, x.y + h * vv.y + h2 * g1, x.z + h * vv.z + h2 * g2, m);
+        const double hd = h, h2 = hd * hd;
+        zu[v] = make_d4(x.x + hd * vv.x + h2 * g0, x.y + hd * vv.y + h2 * g1, x.z + hd * vv.z + h2 * g2, m);
     } else {
-        zu[v] = make_float4(x.x, x.y, x.z, 0.0f);
+        zu[v] = make_d4(x.x, x.y, x.z, 0.0);
     }
 }
 
 // v = (x - xhat) / h ; xhat <- x
-__global__ void k_velocity(int nV, const float4* __restrict__ u, float4* __restrict__ uhat,
-                           float4* __restrict__ vhat, float inv_h) {
+__global__ void k_velocity(int nV, const d4* __restrict__ u, d4* __restrict__ uhat, float4* __restrict__ vhat,
+                           double inv_h) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nV) return;
-    const float4 x = u[v], x0 = uhat[v];
-    vhat[v] = make_float4((x.x - x0.x) * inv_h, (x.y - x0.y) * inv_h, (x.z - x0.z) * inv_h, 0.0f);
+    const d4 x = u[v], x0 = uhat[v];
+    vhat[v] = make_float4((float)((x.x - x0.x) * inv_h), (float)((x.y - x0.y) * inv_h), (float)((x.z - x0.z) * inv_h),
+                          0.0f);
     uhat[v] = x;
 }
 
@@ -734,9 +754,9 @@ __global__ __launch_bounds__(256) void k_energy(SweepArgs a, int nT) {
     }
     if (i < a.nVf) {
         const int v = a.free_ids[i];
-        const float4 uv = a.u[v], zv = a.zu[v];
-        const double d0 = (double)uv.x - zv.x, d1 = (double)uv.y - zv.y, d2 = (double)uv.z - zv.z;
-        e += 0.5 * (double)zv.w * (d0 * d0 + d1 * d1 + d2 * d2);
+        const d4 uv = a.u[v], zv = a.zu[v];
+        const double d0 = uv.x - zv.x, d1 = uv.y - zv.y, d2 = uv.z - zv.z;
+        e += 0.5 * zv.w * (d0 * d0 + d1 * d1 + d2 * d2);
         const float4 X = a.X[v];
         const double x[3] = {(double)X.x + uv.x, (double)X.y + uv.y, (double)X.z + uv.z};
         for (int p = 0; p < JGS2_MAX_PLANES; ++p) {
@@ -812,7 +832,7 @@ void launch_plain(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<false>(
 
 void launch_linear(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<true>(s, a); }
 
-void launch_param_grad(jgs2_solver* s, const float4* u, const float4* y, double* thbar) {
+void launch_param_grad(jgs2_solver* s, const d4* u, const float4* y, double* thbar) {
     launch(s, JGS2_K_PARAMGRAD, k_param_grad, dim3((s->nT + 255) / 256), dim3(256), (const float4*)s->d_tet, s->nT,
            u, y, thbar);
 }
@@ -857,14 +877,14 @@ void launch_reduce(jgs2_solver* s, int n) {
 }
 
 void launch_predict(jgs2_solver* s, float h, const float* grav) {
-    launch(s, JGS2_K_PREDICT, k_predict, dim3((s->nV + 255) / 256), dim3(256), s->nV, (const float4*)s->d_uhat,
+    launch(s, JGS2_K_PREDICT, k_predict, dim3((s->nV + 255) / 256), dim3(256), s->nV, (const d4*)s->d_uhat,
            (const float4*)s->d_vhat, (const float*)s->d_mh2, h, grav[0], grav[1], grav[2], s->d_u, s->d_unext,
            s->d_zu);
 }
 
 void launch_velocity(jgs2_solver* s, float h) {
-    launch(s, JGS2_K_VELOCITY, k_velocity, dim3((s->nV + 255) / 256), dim3(256), s->nV, (const float4*)s->d_u,
-           s->d_uhat, s->d_vhat, 1.0f / h);
+    launch(s, JGS2_K_VELOCITY, k_velocity, dim3((s->nV + 255) / 256), dim3(256), s->nV, (const d4*)s->d_u,
+           s->d_uhat, s->d_vhat, 1.0 / (double)h);
 }
 
 void launch_energy(jgs2_solver* s, const SweepArgs& a, int nT) {
