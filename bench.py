@@ -399,10 +399,10 @@ def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches
         return 80.0 * T + 4.0 * n_inc + 64.0 * Vf + 32.0 * V
     if kind == "phase2":      # positions, g, R of every vertex; own record, samples, update
         return 80.0 * T + 8.0 * n_inc + 40.0 * ring_entries + Vf * (40.0 + 168.0 * S) + 64.0 * V
-    if kind == "plain_jacobi":  # positions; z read and update written per free vertex
-        return 80.0 * T + 4.0 * n_inc + 64.0 * Vf + 32.0 * V
-    if kind == "plain_gs_sweep":  # all colour launches of one sweep
-        return 84.0 * n_inc + 64.0 * Vf + 32.0 * V * n_colors
+    if kind == "plain_jacobi":  # 64 B records (no id word), 16 B incidences with corner ids
+        return 64.0 * T + 16.0 * n_inc + 64.0 * Vf + 32.0 * V
+    if kind == "plain_gs_sweep":  # all colour launches of one sweep; a tet is read once per incident corner
+        return 80.0 * n_inc + 64.0 * Vf + 32.0 * V * n_colors
     raise ValueError(kind)
 
 

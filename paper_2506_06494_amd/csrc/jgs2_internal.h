@@ -42,6 +42,7 @@ struct SweepArgs {
     int n_list;
     const float4* tet;      // [nT * TET_F4]
     const int* inc;         // [nVf * maxi] packed (tet << 2 | corner), -1 pad
+    const int4* inc4;       // [nVf * maxi] (tet << 2 | corner c, ids of corners c+1, c+2, c+3 mod 4)
     const uint32_t* incslot;// [nVf * maxi] one-ring slot byte per corner
     const int* inc_n;       // [nVf]
     const int* ring;        // [nVf * K] vertex ids
@@ -88,6 +89,7 @@ struct jgs2_solver {
     std::vector<uint8_t> pinned;
     std::vector<int> free_ids, free_index;
     std::vector<int> inc, inc_n, ring, ring_n;
+    std::vector<int4> inc4;
     std::vector<uint32_t> incslot;
     std::vector<int> color, col_perm, col_off;  // colour per vertex, free idx sorted by colour
     int n_colors = 0;
@@ -112,6 +114,7 @@ struct jgs2_solver {
     jgs2::d4 *d_u = nullptr, *d_unext = nullptr, *d_uhat = nullptr, *d_zu = nullptr;
     float* d_mh2 = nullptr;
     int *d_free = nullptr, *d_inc = nullptr, *d_inc_n = nullptr, *d_ring = nullptr, *d_ring_n = nullptr;
+    int4* d_inc4 = nullptr;
     uint32_t* d_incslot = nullptr;
     int* d_colperm = nullptr;
     float* d_Uring = nullptr;
@@ -156,6 +159,10 @@ struct jgs2_solver {
     int graph_k[2] = {0, 0};
     jgs2::d4* graph_u[2] = {nullptr, nullptr};
     int graph_next = 0;
+    // pinned residual readback slots (two sweep groups in flight)
+    double* h_r2[2] = {nullptr, nullptr};
+    int* h_nact[2] = {nullptr, nullptr};
+    hipEvent_t rb_ev[2] = {nullptr, nullptr};
 
     int fail(int code, const std::string& msg) {
         err = msg;
@@ -167,6 +174,7 @@ namespace jgs2 {
 int hip_check(jgs2_solver* s, hipError_t e, const char* what);
 void free_device(jgs2_solver* s);
 void drop_graphs(jgs2_solver* s);
+void free_readback(jgs2_solver* s);
 void build_sweep_args(jgs2_solver* s, SweepArgs& a);
 // kernels launched from the host driver (sweep.hip)
 void launch_phase1(jgs2_solver* s, const SweepArgs& a, bool want_R);

@@ -29,6 +29,7 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_tet); dfree(s->d_X); dfree(s->d_u); dfree(s->d_unext); dfree(s->d_uhat); dfree(s->d_vhat);
     dfree(s->d_zu); dfree(s->d_mh2); dfree(s->d_g); dfree(s->d_R); dfree(s->d_free); dfree(s->d_inc);
     dfree(s->d_inc_n); dfree(s->d_ring); dfree(s->d_ring_n); dfree(s->d_incslot); dfree(s->d_colperm);
+    dfree(s->d_inc4);
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
     dfree(s->d_ck_u); dfree(s->d_ck_v); dfree(s->d_seg); dfree(s->d_y); dfree(s->d_ynext); dfree(s->d_xbar);
     dfree(s->d_vbar); dfree(s->d_rhs); dfree(s->d_thbar);
@@ -36,6 +37,16 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_nactive); dfree(s->d_r2); dfree(s->d_r0sq);
     s->ro_valid = false;
     drop_graphs(s);
+    free_readback(s);
+}
+
+void free_readback(jgs2_solver* s) {
+    for (int i = 0; i < 2; ++i) {
+        if (s->h_r2[i]) (void)hipHostFree(s->h_r2[i]);
+        if (s->h_nact[i]) (void)hipHostFree(s->h_nact[i]);
+        s->h_r2[i] = nullptr;
+        s->h_nact[i] = nullptr;
+    }
 }
 
 void drop_graphs(jgs2_solver* s) {
@@ -51,7 +62,7 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
     std::memset(&a, 0, sizeof(a));
     a.nV = s->nV; a.nVf = s->nVf; a.maxi = s->maxi; a.K = s->K; a.S = s->have_corr ? s->S : 0;
     a.free_ids = s->d_free; a.list = nullptr; a.n_list = 0;
-    a.tet = s->d_tet; a.inc = s->d_inc; a.incslot = s->d_incslot; a.inc_n = s->d_inc_n;
+    a.tet = s->d_tet; a.inc = s->d_inc; a.inc4 = s->d_inc4; a.incslot = s->d_incslot; a.inc_n = s->d_inc_n;
     a.ring = s->d_ring; a.ring_n = s->d_ring_n; a.Uring = s->d_Uring; a.samp_e = s->d_samp_e; a.samp = s->d_samp;
     a.X = s->d_X; a.u = s->d_u; a.unext = s->d_unext; a.zu = s->d_zu; a.g = s->d_g; a.R = s->d_R;
     a.partial = s->d_partial; a.omega = (float)s->p.omega; a.in_place = 0;
@@ -230,6 +241,8 @@ void jgs2_destroy(jgs2_solver* s) {
     free_device(s);
     prof_collect(s);
     if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
+    for (hipEvent_t e : s->rb_ev)
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
@@ -335,6 +348,7 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
     if (s->K == 0) s->K = 1;
     const size_t nf = s->nVf;
     s->inc.assign(nf * s->maxi, -1);
+    s->inc4.assign(nf * s->maxi, make_int4(-1, 0, 0, 0));
     s->incslot.assign(nf * s->maxi, 0xFFFFFFFFu);
     s->inc_n.assign(nf, 0);
     s->ring.assign(nf * s->K, -1);
@@ -349,6 +363,11 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
             const int pk = incall[k];
             const int t = pk >> 2;
             s->inc[(size_t)f * s->maxi + j] = pk;
+            {
+                const int c0 = pk & 3;
+                s->inc4[(size_t)f * s->maxi + j] = make_int4(pk, tets[4 * t + ((c0 + 1) & 3)],
+                                                             tets[4 * t + ((c0 + 2) & 3)], tets[4 * t + ((c0 + 3) & 3)]);
+            }
             uint32_t sl = 0;
             for (int c = 0; c < 4; ++c) {
                 const int a = tets[4 * t + c];
@@ -393,7 +412,8 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
         (r = dalloc(s, s->d_free, nf)) || (r = dalloc(s, s->d_inc, nf * s->maxi)) ||
         (r = dalloc(s, s->d_incslot, nf * s->maxi)) || (r = dalloc(s, s->d_inc_n, nf)) ||
         (r = dalloc(s, s->d_ring, nf * s->K)) || (r = dalloc(s, s->d_ring_n, nf)) ||
-        (r = dalloc(s, s->d_colperm, nf)) || (r = dalloc(s, s->d_tet, (size_t)nT * TET_F4)))
+        (r = dalloc(s, s->d_colperm, nf)) || (r = dalloc(s, s->d_tet, (size_t)nT * TET_F4)) ||
+        (r = dalloc(s, s->d_inc4, nf * s->maxi)))
         return r;
     s->n_partial = std::max<int>((s->nVf + 1) / 2, (std::max(nT, s->nVf) + 255) / 256) + 1;
     if ((r = dalloc(s, s->d_partial, (size_t)s->n_partial)) || (r = dalloc(s, s->d_red, 4))) return r;
@@ -404,7 +424,7 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
         (r = upload(s, s->d_free, s->free_ids.data(), nf)) || (r = upload(s, s->d_inc, s->inc.data(), nf * s->maxi)) ||
         (r = upload(s, s->d_incslot, s->incslot.data(), nf * s->maxi)) || (r = upload(s, s->d_inc_n, s->inc_n.data(), nf)) ||
         (r = upload(s, s->d_ring, s->ring.data(), nf * s->K)) || (r = upload(s, s->d_ring_n, s->ring_n.data(), nf)) ||
-        (r = upload(s, s->d_colperm, s->col_perm.data(), nf)))
+        (r = upload(s, s->d_colperm, s->col_perm.data(), nf)) || (r = upload(s, s->d_inc4, s->inc4.data(), nf * s->maxi)))
         return r;
     for (d4* d : {s->d_u, s->d_unext, s->d_uhat, s->d_zu}) HIPCHK(hipMemsetAsync(d, 0, V4 * sizeof(d4), s->stream));
     for (float4* d : {s->d_vhat, s->d_g}) HIPCHK(hipMemsetAsync(d, 0, V4 * sizeof(float4), s->stream));
@@ -854,6 +874,31 @@ static int abandon_step(jgs2_solver* s) {
     return JGS2_OK;
 }
 
+// Residual readback of a sweep group into pinned slot `slot`, without waiting.
+static int enqueue_readback(jgs2_solver* s, int slot) {
+    const size_t nb = s->n_bodies;
+    HIPCHK(hipMemcpyAsync(s->h_r2[slot], s->d_r2, nb * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(s->h_nact[slot], s->d_nactive, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipEventRecord(s->rb_ev[slot], s->stream));
+    return JGS2_OK;
+}
+
+// Waits for a readback and takes it as the current per-body residuals.
+static int finish_readback(jgs2_solver* s, int slot, double* rel) {
+    HIPCHK(hipEventSynchronize(s->rb_ev[slot]));
+    prof_collect(s);
+    double g2 = 0.0;
+    for (int b = 0; b < s->n_bodies; ++b) {
+        s->r2_host[b] = s->h_r2[slot][b];
+        g2 += s->r2_host[b];
+    }
+    s->n_active = *s->h_nact[slot];
+    *rel = max_rel(s);
+    if (!std::isfinite(g2)) return s->fail(JGS2_E_NONFINITE, "non-finite residual");
+    if (*rel > 1e8) return s->fail(JGS2_E_DIVERGED, "residual exceeded 1e8 x its start value");
+    return JGS2_OK;
+}
+
 int32_t jgs2_step(jgs2_solver* s, jgs2_step_stats* st) {
     if (!s) return JGS2_E_INVALID;
     jgs2_step_stats loc;
@@ -862,23 +907,54 @@ int32_t jgs2_step(jgs2_solver* s, jgs2_step_stats* st) {
     int r = jgs2_begin_step(s);
     if (r != JGS2_OK) { loc.status = r; if (st) *st = loc; return r; }
     double rel = s->r0 == 0.0 ? 0.0 : 1.0;
-    while (s->n_active > 0 && s->sweeps_in_step < s->p.max_sweeps) {
-        const int k = std::min(s->p.check_every, s->p.max_sweeps - s->sweeps_in_step);
-        r = jgs2_iterate(s, k, &rel);
-        if (r != JGS2_OK) {
-            loc.status = r; loc.sweeps = s->sweeps_in_step; loc.r0 = s->r0; loc.r_final = rel;
-            abandon_step(s);
-            if (st) *st = loc;
-            return r;
+    auto failed = [&](int code) {
+        loc.status = code; loc.sweeps = s->sweeps_in_step; loc.r0 = s->r0; loc.r_final = rel;
+        abandon_step(s);
+        if (st) *st = loc;
+        return code;
+    };
+    if (s->p.line_search) {
+        // the energy search reads back inside every sweep: plain synchronous loop
+        while (s->n_active > 0 && s->sweeps_in_step < s->p.max_sweeps) {
+            const int k = std::min(s->p.check_every, s->p.max_sweeps - s->sweeps_in_step);
+            r = jgs2_iterate(s, k, &rel);
+            if (r != JGS2_OK) return failed(r);
+        }
+    } else {
+        // one sweep group stays in flight while the previous group's residuals
+        // come back; the stop decision itself is taken on the device (per-body
+        // masks), so a group issued after convergence changes nothing
+        int pending = -1, slot = 0;
+        for (;;) {
+            int issued = -1;
+            if (s->n_active > 0 && s->sweeps_in_step < s->p.max_sweeps) {
+                const int k = std::min(s->p.check_every, s->p.max_sweeps - s->sweeps_in_step);
+                if ((r = sweep_group(s, k)) != JGS2_OK || (r = enqueue_readback(s, slot)) != JGS2_OK) {
+                    (void)hipStreamSynchronize(s->stream);
+                    return failed(r);
+                }
+                issued = slot;
+                slot ^= 1;
+            }
+            if (pending >= 0 && (r = finish_readback(s, pending, &rel)) != JGS2_OK) {
+                (void)hipStreamSynchronize(s->stream);
+                return failed(r);
+            }
+            if (issued < 0) break;
+            pending = issued;
         }
     }
+    std::vector<int> bsw((size_t)s->n_bodies);
+    HIPCHK(hipMemcpyAsync(bsw.data(), s->d_body_sweeps, bsw.size() * sizeof(int), hipMemcpyDeviceToHost, s->stream));
     r = jgs2_end_step(s);
     if (r != JGS2_OK) return r;
     HIPCHK(hipEventRecord(s->ev1, s->stream));
     HIPCHK(hipEventSynchronize(s->ev1));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
-    loc.sweeps = s->sweeps_in_step; loc.status = JGS2_OK; loc.r0 = s->r0; loc.r_final = rel; loc.seconds = ms * 1e-3;
+    int most = 0;
+    for (int b : bsw) most = std::max(most, b);
+    loc.sweeps = most; loc.status = JGS2_OK; loc.r0 = s->r0; loc.r_final = rel; loc.seconds = ms * 1e-3;
     loc.ls_halvings = s->ls_halvings;
     if (st) *st = loc;
     return JGS2_OK;
@@ -1207,6 +1283,12 @@ int32_t jgs2_set_bodies(jgs2_solver* s, int32_t n_bodies, const int32_t* body_of
         (r = dalloc(s, s->d_body_sweeps, nb)) || (r = dalloc(s, s->d_nactive, 1)) || (r = dalloc(s, s->d_r2, nb)) ||
         (r = dalloc(s, s->d_r0sq, nb)))
         return r;
+    free_readback(s);
+    for (int i = 0; i < 2; ++i) {
+        HIPCHK(hipHostMalloc((void**)&s->h_r2[i], nb * sizeof(double), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&s->h_nact[i], sizeof(int), hipHostMallocDefault));
+        if (!s->rb_ev[i]) HIPCHK(hipEventCreateWithFlags(&s->rb_ev[i], hipEventDisableTiming));
+    }
     std::vector<int> ones(nb, 1), zeros(nb, 0);
     if ((r = upload(s, s->d_fbody, fbody.data(), (size_t)nf)) || (r = upload(s, s->d_seg_off, off.data(), nb + 1)) ||
         (r = upload(s, s->d_seg_idx, idx.data(), (size_t)nf)) || (r = upload(s, s->d_body_on, ones.data(), nb)) ||

@@ -75,6 +75,23 @@ __device__ __forceinline__ void load_tet(const float4* __restrict__ tet, int t, 
     T.D[8] = d.x; T.vol = d.y; T.vmu = d.z; T.vlam = d.w; T.mi = e.x;
 }
 
+// Tet record without its id word, with the corner ids taken from an
+// incidence entry (own corner c is vertex v): the record and the corner
+// positions can then be fetched together.
+__device__ __forceinline__ void load_tet_inc(const float4* __restrict__ tet, int4 e, int v, Tet& T) {
+    const float4* r = tet + (size_t)(e.x >> 2) * TET_F4;
+    const float4 b = r[1], c = r[2], d = r[3], f = r[4];
+    const int c0 = e.x & 3;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int q = (k - c0) & 3;
+        T.id[k] = q == 0 ? v : (q == 1 ? e.y : (q == 2 ? e.z : e.w));
+    }
+    T.D[0] = b.x; T.D[1] = b.y; T.D[2] = b.z; T.D[3] = b.w;
+    T.D[4] = c.x; T.D[5] = c.y; T.D[6] = c.z; T.D[7] = c.w;
+    T.D[8] = d.x; T.vol = d.y; T.vmu = d.z; T.vlam = d.w; T.mi = f.x;
+}
+
 // grad N of corner c: rows of Dm^-1 for corners 1..3, minus their sum for 0.
 // (Static selects: indexing D with a runtime corner would move the record
 // to scratch memory.)
@@ -445,11 +462,12 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     float g[3] = {0.f, 0.f, 0.f}, A6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (active) {
         const int n = a.inc_n[f];
+        const int vself = a.free_ids[f];
         for (int j = lane; j < n; j += W) {
-            const int pk = a.inc[(size_t)f * a.maxi + j];
-            const int c = pk & 3;
+            const int4 e = a.inc4[(size_t)f * a.maxi + j];
+            const int c = e.x & 3;
             Tet T;
-            load_tet(a.tet, pk >> 2, T);
+            load_tet_inc(a.tet, e, vself, T);
             float H[9], cH[9], gn[3];
             Kin<float> K;
             dispgrad(a.u, T, H);
