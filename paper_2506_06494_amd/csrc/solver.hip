@@ -925,8 +925,25 @@ int32_t jgs2_step(jgs2_solver* s, jgs2_step_stats* st) {
         // come back; the stop decision itself is taken on the device (per-body
         // masks), so a group issued after convergence changes nothing
         int pending = -1, slot = 0;
+        double rel_prev = -1.0, rel_last = -1.0;  // residuals of the last two groups read back
         for (;;) {
             int issued = -1;
+            // issue the next group before the in-flight one's residual is known
+            // unless the rate so far says the in-flight group reaches rel_tol
+            bool speculate = true;
+            if (pending >= 0 && rel_prev > 0.0 && rel_last > 0.0) {
+                const double predicted = rel_last * std::min(1.0, rel_last / rel_prev);
+                speculate = predicted > s->p.rel_tol;
+            }
+            if (pending >= 0 && !speculate) {
+                if ((r = finish_readback(s, pending, &rel)) != JGS2_OK) {
+                    (void)hipStreamSynchronize(s->stream);
+                    return failed(r);
+                }
+                rel_prev = rel_last;
+                rel_last = rel;
+                pending = -1;
+            }
             if (s->n_active > 0 && s->sweeps_in_step < s->p.max_sweeps) {
                 const int k = std::min(s->p.check_every, s->p.max_sweeps - s->sweeps_in_step);
                 if ((r = sweep_group(s, k)) != JGS2_OK || (r = enqueue_readback(s, slot)) != JGS2_OK) {
@@ -936,9 +953,13 @@ int32_t jgs2_step(jgs2_solver* s, jgs2_step_stats* st) {
                 issued = slot;
                 slot ^= 1;
             }
-            if (pending >= 0 && (r = finish_readback(s, pending, &rel)) != JGS2_OK) {
-                (void)hipStreamSynchronize(s->stream);
-                return failed(r);
+            if (pending >= 0) {
+                if ((r = finish_readback(s, pending, &rel)) != JGS2_OK) {
+                    (void)hipStreamSynchronize(s->stream);
+                    return failed(r);
+                }
+                rel_prev = rel_last;
+                rel_last = rel;
             }
             if (issued < 0) break;
             pending = issued;
