@@ -145,6 +145,9 @@ struct jgs2_solver {
     std::vector<int> seg_off, seg_idx;     // free indices grouped by body
     int* d_fbody = nullptr;                // [nVf]
     int *d_seg_off = nullptr, *d_seg_idx = nullptr;
+    int n_chunks = 0;                      // fixed chunks of the per-body residual sums
+    int *d_chunk_lo = nullptr, *d_chunk_hi = nullptr, *d_body_chunk_off = nullptr;
+    double* d_r2c = nullptr;
     int* d_body_on = nullptr;              // [n_bodies]
     int* d_body_sweeps = nullptr;          // [n_bodies]
     int* d_nactive = nullptr;              // [1]
@@ -186,6 +189,7 @@ void launch_param_grad(jgs2_solver* s, const d4* u, const float4* y, double* thb
 void launch_adj_vec(jgs2_solver* s, const float4* y, float4* xbar, float4* vbar, float4* rhs);
 void launch_norm2(jgs2_solver* s, const float4* w);
 void launch_seg_norm2(jgs2_solver* s);
+int seg_chunk_size();
 void launch_mask_init(jgs2_solver* s);
 void launch_mask_update(jgs2_solver* s, int k);
 void launch_blend(jgs2_solver* s, const SweepArgs& a, float t);

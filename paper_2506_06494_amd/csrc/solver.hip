@@ -35,6 +35,7 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_vbar); dfree(s->d_rhs); dfree(s->d_thbar);
     dfree(s->d_fbody); dfree(s->d_seg_off); dfree(s->d_seg_idx); dfree(s->d_body_on); dfree(s->d_body_sweeps);
     dfree(s->d_nactive); dfree(s->d_r2); dfree(s->d_r0sq);
+    dfree(s->d_chunk_lo); dfree(s->d_chunk_hi); dfree(s->d_body_chunk_off); dfree(s->d_r2c);
     s->ro_valid = false;
     drop_graphs(s);
     free_readback(s);
@@ -1297,8 +1298,26 @@ int32_t jgs2_set_bodies(jgs2_solver* s, int32_t n_bodies, const int32_t* body_of
     for (int b = 0; b < n_bodies; ++b) off[b + 1] += off[b];
     std::vector<int> pos(off.begin(), off.end() - 1);
     for (int f = 0; f < nf; ++f) idx[pos[fbody[f]]++] = f;  // stable: ascending free index within a body
+    // fixed chunks of each body's free vertices for the residual sums
+    const int CH = seg_chunk_size();
+    std::vector<int> clo, chi, boff(n_bodies + 1, 0);
+    for (int b = 0; b < n_bodies; ++b) {
+        for (int i = off[b]; i < off[b + 1]; i += CH) {
+            clo.push_back(i);
+            chi.push_back(std::min(i + CH, off[b + 1]));
+        }
+        boff[b + 1] = (int)clo.size();
+    }
+    const size_t nch = clo.size();
     int r;
     const size_t nb = n_bodies;
+    if ((r = dalloc(s, s->d_chunk_lo, nch)) || (r = dalloc(s, s->d_chunk_hi, nch)) ||
+        (r = dalloc(s, s->d_body_chunk_off, nb + 1)) || (r = dalloc(s, s->d_r2c, nch)))
+        return r;
+    if (nch > 0 && ((r = upload(s, s->d_chunk_lo, clo.data(), nch)) || (r = upload(s, s->d_chunk_hi, chi.data(), nch))))
+        return r;
+    if ((r = upload(s, s->d_body_chunk_off, boff.data(), nb + 1))) return r;
+    s->n_chunks = (int)nch;
     if ((r = dalloc(s, s->d_fbody, (size_t)nf)) || (r = dalloc(s, s->d_seg_off, nb + 1)) ||
         (r = dalloc(s, s->d_seg_idx, (size_t)nf)) || (r = dalloc(s, s->d_body_on, nb)) ||
         (r = dalloc(s, s->d_body_sweeps, nb)) || (r = dalloc(s, s->d_nactive, 1)) || (r = dalloc(s, s->d_r2, nb)) ||

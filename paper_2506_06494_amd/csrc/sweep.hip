@@ -606,14 +606,17 @@ __global__ void k_adj_vec(int nV, const float* __restrict__ mh2, const float4* _
     rhs[v] = make_float4(xn.x + vn.x * ih, xn.y + vn.y * ih, xn.z + vn.z * ih, 0.0f);
 }
 
-// Per-body |g|^2 in FP64: block b sums its body's free vertices (grouped by
-// seg_idx) in a fixed order, so the value does not depend on the other bodies.
-__global__ __launch_bounds__(256) void k_seg_norm2(const int* __restrict__ seg_off, const int* __restrict__ seg_idx,
-                                                   const int* __restrict__ free_ids, const float4* __restrict__ g,
-                                                   double* __restrict__ r2) {
+// Per-body |g|^2 in FP64, in two fixed-order passes so the value does not
+// depend on the other bodies: block c sums chunk c (at most CHUNK free
+// vertices of one body, grouped by seg_idx), then one thread per body adds
+// its chunks in order.
+constexpr int CHUNK = 1024;
+__global__ __launch_bounds__(256) void k_chunk_norm2(const int* __restrict__ chunk_lo, const int* __restrict__ chunk_hi,
+                                                     const int* __restrict__ seg_idx, const int* __restrict__ free_ids,
+                                                     const float4* __restrict__ g, double* __restrict__ r2c) {
     __shared__ double s[256];
-    const int b = blockIdx.x;
-    const int lo = seg_off[b], hi = seg_off[b + 1];
+    const int c = blockIdx.x;
+    const int lo = chunk_lo[c], hi = chunk_hi[c];
     double e = 0.0;
     for (int i = lo + threadIdx.x; i < hi; i += 256) {
         const float4 q = g[free_ids[seg_idx[i]]];
@@ -625,7 +628,16 @@ __global__ __launch_bounds__(256) void k_seg_norm2(const int* __restrict__ seg_o
         if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) r2[b] = s[0];
+    if (threadIdx.x == 0) r2c[c] = s[0];
+}
+
+__global__ void k_seg_finish(int nb, const int* __restrict__ body_chunk_off, const double* __restrict__ r2c,
+                             double* __restrict__ r2) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    double t = 0.0;
+    for (int c = body_chunk_off[b]; c < body_chunk_off[b + 1]; ++c) t += r2c[c];
+    r2[b] = t;
 }
 
 // Start of a step: r0^2 per body, every body with a non-zero residual on.
@@ -866,9 +878,15 @@ void launch_norm2(jgs2_solver* s, const float4* w) {
 }
 
 void launch_seg_norm2(jgs2_solver* s) {
-    launch(s, JGS2_K_REDUCE, k_seg_norm2, dim3(s->n_bodies), dim3(256), (const int*)s->d_seg_off,
-           (const int*)s->d_seg_idx, (const int*)s->d_free, (const float4*)s->d_g, s->d_r2);
+    if (s->n_chunks > 0)
+        launch(s, JGS2_K_REDUCE, k_chunk_norm2, dim3(s->n_chunks), dim3(256), (const int*)s->d_chunk_lo,
+               (const int*)s->d_chunk_hi, (const int*)s->d_seg_idx, (const int*)s->d_free, (const float4*)s->d_g,
+               s->d_r2c);
+    launch(s, JGS2_K_REDUCE, k_seg_finish, dim3((s->n_bodies + 255) / 256), dim3(256), s->n_bodies,
+           (const int*)s->d_body_chunk_off, (const double*)s->d_r2c, s->d_r2);
 }
+
+int seg_chunk_size() { return CHUNK; }
 
 void launch_mask_init(jgs2_solver* s) {
     launch(s, JGS2_K_REDUCE, k_mask_init, dim3(1), dim3(256), s->n_bodies, (const double*)s->d_r2, s->d_r0sq,
