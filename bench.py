@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--tune", action="store_true",
                     help="autotune the launch shape of the single-beam modes (default: 32 lanes x 256)")
     ap.add_argument("--batched-beams", type=int, default=256)
+    ap.add_argument("--no-contact", action="store_true", help="skip the 10-sphere contact leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (5x) to calibrate HBM byte counters")
     return ap.parse_args()
@@ -220,6 +221,7 @@ def main():
 
     adj = None if args.no_adjoint or args.small else adjoint_leg()
     bat = None if args.no_batched or args.small else batched_leg(args.batched_beams)
+    con = None if args.no_contact or args.small else contact_leg()
 
     cpu = None
     if not args.no_cpu_baseline and head_mode is not None and head_mode.startswith("plain_gs"):
@@ -234,7 +236,7 @@ def main():
                                f"dt 1/120, twist 2 rad/s, to rel. residual 1e-5",
                    "mode": head_mode, "stiffness": stiff},
         "roofline": roof, "cpu_baseline": cpu,
-        "modes": results, "jgs2_sweep": jgs2_sweep, "adjoint": adj, "batched": bat,
+        "modes": results, "jgs2_sweep": jgs2_sweep, "adjoint": adj, "batched": bat, "contact": con,
         "precompute_s": {f"{k:g}": round(v, 3) for k, v in precompute_s.items()},
     }
     print(json.dumps(line))
@@ -313,6 +315,62 @@ def batched_leg(n_beams=256, steps=2, max_sweeps=1000, check_every=8, omega=1.5)
            "sweeps_last_step_mean": float(sw.mean()), "status": [st["status"] for st in stats],
            "roofline": roof}
     print(f"[bench] batched: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
+def contact_leg(steps=3, max_sweeps=3000, check_every=16):
+    """Contact workload: the 10 voxelised spheres of radius 0.3 m (0.01 m grid,
+    1,217,690 vertices, 6,786,240 tets; five with E 2e6, five with E 1e5,
+    nu 0.45, centres drawn with seed 0 in the 2 x 2 x 4 m box), each lowered
+    until its lowest vertex is 0.6 mm above the floor and moving down at
+    1 m/s, so the floor barrier (d_hat 1e-3 m, kappa 1e4) is active from the
+    first step; floor and four walls as planes, gravity -z, dt 1/120; plain
+    coloured GS with the per-vertex feasibility clamp, per-sphere residuals."""
+    from paper_2506_06494_amd import inputs, jgs2
+    sc = inputs.contact_scene(0)
+    m = sc.mesh
+    X = m.X.copy()
+    for b in range(int(m.body.max()) + 1):
+        idx = m.body == b
+        X[idx, 2] -= X[idx, 2].min() - 6e-4
+    v0 = np.zeros_like(X)
+    v0[:, 2] = -1.0
+    s = jgs2.Solver(dt=sc.dt, gravity=sc.gravity, planes=sc.planes, d_hat=sc.d_hat, kappa=sc.kappa, order=jgs2.GS,
+                    omega=1.0, rel_tol=1e-5, max_sweeps=max_sweeps, check_every=check_every, use_graph=1)
+    s.upload_mesh(X, m.tets, m.pinned)
+    s.set_material(sc.E, sc.nu, sc.rho)
+    s.set_bodies(m.body)
+    s.set_state(X, v0)
+    (lpv, blk), _ = s.autotune(8)
+    s.set_profiling(True)
+    s.begin_step()
+    s.iterate(check_every)
+    kt = s.kernel_times()
+    s.set_profiling(False)
+    ms, n = kt["plain"]
+    cnt = mesh_counts(m)
+    ncol = s.coloring()[1]
+    per_launch = sweep_bytes("plain_gs_sweep", **cnt, n_colors=ncol) / ncol
+    roof = {"bound": "hbm", "kernel": "k_plain", "avg_launch_us": round(ms * 1e3 / n, 3), "launches": n,
+            "bytes_per_launch": round(per_launch), "achieved": round(per_launch / (ms * 1e-3 / n) / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = round(roof["achieved"] / HBM_PEAK_GBS, 4)
+    s.set_state(X, v0)
+    sync()
+    t0 = time.perf_counter()
+    stats = [s.step(raise_on_error=False) for _ in range(steps)]
+    sync()
+    tc = (time.perf_counter() - t0) / steps
+    x, _ = s.get_state()
+    sw, rel = s.body_stats()
+    s.close()
+    out = {"workload": f"10 spheres r 0.3 m (0.01 m grid): {m.nV:,} vertices, {m.nT:,} tets, lowered to 0.6 mm above "
+                       "the floor at 1 m/s down, planes z=0, x=0,2, y=0,2, d_hat 1e-3, kappa 1e4",
+           "steps": steps, "s_per_step": tc, "status": [st["status"] for st in stats],
+           "sweeps_per_step": [st["sweeps"] for st in stats], "r_final": [st["r_final"] for st in stats],
+           "min_floor_distance_m": float(x[:, 2].min()), "colours": int(ncol), "tuned_shape": [lpv, blk],
+           "roofline": roof}
+    print(f"[bench] contact: {json.dumps(out)}", file=sys.stderr, flush=True)
     return out
 
 

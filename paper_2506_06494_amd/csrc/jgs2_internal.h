@@ -63,6 +63,7 @@ struct SweepArgs {
     int n_planes;
     float planes[JGS2_MAX_PLANES][4];
     float d_hat, kappa;
+    double planes_d[JGS2_MAX_PLANES][4];  // the same planes in FP64 (feasibility test)
     // linear (adjoint) sweeps on H(u) y = rhs
     const float4* ly;       // [nV] current y
     float4* lynext;         // [nV] Jacobi output

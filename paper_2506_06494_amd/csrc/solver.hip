@@ -72,6 +72,8 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
         for (int k = 0; k < 4; ++k) a.planes[i][k] = (float)s->p.planes[i][k];
     a.d_hat = (float)s->p.d_hat; a.kappa = (float)s->p.kappa;
     a.fbody = s->d_fbody; a.body_on = s->d_body_on;
+    for (int i = 0; i < s->p.n_planes; ++i)
+        for (int k = 0; k < 4; ++k) a.planes_d[i][k] = s->p.planes[i][k];
 }
 
 }  // namespace jgs2
@@ -677,24 +679,36 @@ static bool ready_to_step(jgs2_solver* s) {
     return true;
 }
 
+// Sets *bad when a free vertex is on or behind a plane (FP64 distances).
+__global__ void k_infeasible(SweepArgs a, int* __restrict__ bad) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= a.nVf) return;
+    const int v = a.free_ids[f];
+    const d4 u = a.u[v];
+    const float4 X = a.X[v];
+    for (int p = 0; p < a.n_planes; ++p) {
+        const double d = (double)a.planes_d[p][0] * ((double)X.x + u.x) + (double)a.planes_d[p][1] * ((double)X.y + u.y) +
+                         (double)a.planes_d[p][2] * ((double)X.z + u.z) - a.planes_d[p][3];
+        if (!(d > 0.0)) atomicOr(bad, 1);
+    }
+}
+
 int32_t jgs2_begin_step(jgs2_solver* s) {
     if (!s) return JGS2_E_INVALID;
     if (!ready_to_step(s)) return JGS2_E_NOT_READY;
     const float grav[3] = {(float)s->p.gravity[0], (float)s->p.gravity[1], (float)s->p.gravity[2]};
-    // contact feasibility of the start state
+    // contact feasibility of the start state (on the device: one flag)
     if (s->p.n_planes > 0) {
-        std::vector<d4> u((size_t)s->nV);
-        HIPCHK(hipMemcpyAsync(u.data(), s->d_uhat, u.size() * sizeof(d4), hipMemcpyDeviceToHost, s->stream));
+        SweepArgs a;
+        build_sweep_args(s, a);
+        a.u = s->d_uhat;
+        HIPCHK(hipMemsetAsync(s->d_nactive, 0, sizeof(int), s->stream));
+        hipLaunchKernelGGL(k_infeasible, dim3((s->nVf + 255) / 256), dim3(256), 0, s->stream, a, s->d_nactive);
+        HIPCHK(hipGetLastError());
+        int bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, s->d_nactive, sizeof(int), hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
-        for (int f = 0; f < s->nVf; ++f) {
-            const int v = s->free_ids[f];
-            const double uu[3] = {u[v].x, u[v].y, u[v].z};
-            for (int p = 0; p < s->p.n_planes; ++p) {
-                double d = -s->p.planes[p][3];
-                for (int i = 0; i < 3; ++i) d += s->p.planes[p][i] * (s->X[3 * (size_t)v + i] + uu[i]);
-                if (!(d > 0)) return s->fail(JGS2_E_INFEASIBLE, "a vertex is on or behind a contact plane");
-            }
-        }
+        if (bad) return s->fail(JGS2_E_INFEASIBLE, "a vertex is on or behind a contact plane");
     }
     launch_predict(s, (float)s->p.dt, grav);
     residual_launches(s, 0);
