@@ -43,6 +43,12 @@ struct SweepArgs {
     const float4* tet;      // [nT * TET_F4]
     const int* inc;         // [nVf * maxi] packed (tet << 2 | corner), -1 pad
     const int4* inc4;       // [nVf * maxi] (tet << 2 | corner c, ids of corners c+1, c+2, c+3 mod 4)
+    // the plain sweep's rows in colour order (position q = rank in the colour permutation)
+    const int4* inc4_c;     // [nVf * maxi]
+    const int* incn_c;      // [nVf]
+    const int* vid_c;       // [nVf] vertex id
+    const int* fbody_c;     // [nVf] body
+    int cbase;              // first row of the launched colour (0 for a whole sweep)
     const uint32_t* incslot;// [nVf * maxi] one-ring slot byte per corner
     const int* inc_n;       // [nVf]
     const int* ring;        // [nVf * K] vertex ids
@@ -116,6 +122,8 @@ struct jgs2_solver {
     float* d_mh2 = nullptr;
     int *d_free = nullptr, *d_inc = nullptr, *d_inc_n = nullptr, *d_ring = nullptr, *d_ring_n = nullptr;
     int4* d_inc4 = nullptr;
+    int4* d_inc4_c = nullptr;
+    int *d_incn_c = nullptr, *d_vid_c = nullptr, *d_fbody_c = nullptr;
     uint32_t* d_incslot = nullptr;
     int* d_colperm = nullptr;
     float* d_Uring = nullptr;

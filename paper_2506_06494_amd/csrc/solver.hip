@@ -29,7 +29,7 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_tet); dfree(s->d_X); dfree(s->d_u); dfree(s->d_unext); dfree(s->d_uhat); dfree(s->d_vhat);
     dfree(s->d_zu); dfree(s->d_mh2); dfree(s->d_g); dfree(s->d_R); dfree(s->d_free); dfree(s->d_inc);
     dfree(s->d_inc_n); dfree(s->d_ring); dfree(s->d_ring_n); dfree(s->d_incslot); dfree(s->d_colperm);
-    dfree(s->d_inc4);
+    dfree(s->d_inc4); dfree(s->d_inc4_c); dfree(s->d_incn_c); dfree(s->d_vid_c); dfree(s->d_fbody_c);
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
     dfree(s->d_ck_u); dfree(s->d_ck_v); dfree(s->d_seg); dfree(s->d_y); dfree(s->d_ynext); dfree(s->d_xbar);
     dfree(s->d_vbar); dfree(s->d_rhs); dfree(s->d_thbar);
@@ -64,6 +64,7 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
     a.nV = s->nV; a.nVf = s->nVf; a.maxi = s->maxi; a.K = s->K; a.S = s->have_corr ? s->S : 0;
     a.free_ids = s->d_free; a.list = nullptr; a.n_list = 0;
     a.tet = s->d_tet; a.inc = s->d_inc; a.inc4 = s->d_inc4; a.incslot = s->d_incslot; a.inc_n = s->d_inc_n;
+    a.inc4_c = s->d_inc4_c; a.incn_c = s->d_incn_c; a.vid_c = s->d_vid_c; a.fbody_c = s->d_fbody_c; a.cbase = 0;
     a.ring = s->d_ring; a.ring_n = s->d_ring_n; a.Uring = s->d_Uring; a.samp_e = s->d_samp_e; a.samp = s->d_samp;
     a.X = s->d_X; a.u = s->d_u; a.unext = s->d_unext; a.zu = s->d_zu; a.g = s->d_g; a.R = s->d_R;
     a.partial = s->d_partial; a.omega = (float)s->p.omega; a.in_place = 0;
@@ -93,8 +94,15 @@ hipEvent_t pool_event(jgs2_solver* s) {
 }
 
 // Accumulates finished event pairs (call after the stream is synchronised).
+// Pairs whose end event has not completed yet (work still queued behind a
+// partial synchronisation) stay pending.
 void prof_collect(jgs2_solver* s) {
+    std::vector<jgs2_solver::Pending> keep;
     for (auto& p : s->kt_pending) {
+        if (hipEventQuery(p.b) == hipErrorNotReady) {
+            keep.push_back(p);
+            continue;
+        }
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             s->kt_ms[p.k] += ms;
@@ -103,7 +111,7 @@ void prof_collect(jgs2_solver* s) {
         s->ev_pool.push_back(p.a);
         s->ev_pool.push_back(p.b);
     }
-    s->kt_pending.clear();
+    s->kt_pending.swap(keep);
 }
 }  // namespace jgs2
 
@@ -429,6 +437,22 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
         (r = upload(s, s->d_ring, s->ring.data(), nf * s->K)) || (r = upload(s, s->d_ring_n, s->ring_n.data(), nf)) ||
         (r = upload(s, s->d_colperm, s->col_perm.data(), nf)) || (r = upload(s, s->d_inc4, s->inc4.data(), nf * s->maxi)))
         return r;
+    {
+        std::vector<int4> inc4c(nf * s->maxi);
+        std::vector<int> incnc(nf), vidc(nf);
+        for (size_t q = 0; q < nf; ++q) {
+            const int f = s->col_perm[q];
+            std::copy(s->inc4.begin() + (size_t)f * s->maxi, s->inc4.begin() + (size_t)(f + 1) * s->maxi,
+                      inc4c.begin() + q * s->maxi);
+            incnc[q] = s->inc_n[f];
+            vidc[q] = s->free_ids[f];
+        }
+        if ((r = dalloc(s, s->d_inc4_c, nf * s->maxi)) || (r = dalloc(s, s->d_incn_c, nf)) ||
+            (r = dalloc(s, s->d_vid_c, nf)) || (r = dalloc(s, s->d_fbody_c, nf)) ||
+            (r = upload(s, s->d_inc4_c, inc4c.data(), nf * s->maxi)) || (r = upload(s, s->d_incn_c, incnc.data(), nf)) ||
+            (r = upload(s, s->d_vid_c, vidc.data(), nf)))
+            return r;
+    }
     for (d4* d : {s->d_u, s->d_unext, s->d_uhat, s->d_zu}) HIPCHK(hipMemsetAsync(d, 0, V4 * sizeof(d4), s->stream));
     for (float4* d : {s->d_vhat, s->d_g}) HIPCHK(hipMemsetAsync(d, 0, V4 * sizeof(float4), s->stream));
     HIPCHK(hipMemsetAsync(s->d_mh2, 0, (size_t)nV * sizeof(float), s->stream));
@@ -783,6 +807,7 @@ static int sweep_once(jgs2_solver* s) {
                 launch_commit(s, ac);
             } else {
                 ac.in_place = 1;
+                ac.cbase = s->col_off[c];
                 launch_plain(s, ac);
             }
         }
@@ -1148,6 +1173,7 @@ static int adjoint_solve(jgs2_solver* s, const d4* xstar, int64_t* sweeps, doubl
                     ac.in_place = 1;
                     ac.list = s->d_colperm + s->col_off[c];
                     ac.n_list = s->col_off[c + 1] - s->col_off[c];
+                    ac.cbase = s->col_off[c];
                     launch_linear(s, ac);
                 }
             }
@@ -1344,6 +1370,9 @@ int32_t jgs2_set_bodies(jgs2_solver* s, int32_t n_bodies, const int32_t* body_of
         if (!s->rb_ev[i]) HIPCHK(hipEventCreateWithFlags(&s->rb_ev[i], hipEventDisableTiming));
     }
     std::vector<int> ones(nb, 1), zeros(nb, 0);
+    std::vector<int> fbodyc(nf);
+    for (int q = 0; q < nf; ++q) fbodyc[q] = fbody[s->col_perm[q]];
+    if ((r = upload(s, s->d_fbody_c, fbodyc.data(), (size_t)nf))) return r;
     if ((r = upload(s, s->d_fbody, fbody.data(), (size_t)nf)) || (r = upload(s, s->d_seg_off, off.data(), nb + 1)) ||
         (r = upload(s, s->d_seg_idx, idx.data(), (size_t)nf)) || (r = upload(s, s->d_body_on, ones.data(), nb)) ||
         (r = upload(s, s->d_body_sweeps, zeros.data(), nb)))

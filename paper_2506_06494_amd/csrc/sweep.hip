@@ -450,21 +450,21 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     const int lane = threadIdx.x % W;
     const int vloc = threadIdx.x / W;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    // rows in colour order: a colour is the contiguous range [cbase, cbase + n),
+    // a Jacobi sweep the whole range, so no list is read before the rows
     const int idx = blk * NV + vloc;
     const int nidx = a.list ? a.n_list : a.nVf;
     const bool in_range = idx < nidx;
-    const int f = in_range ? (a.list ? a.list[idx] : idx) : 0;
-    const bool active = in_range && (LIN || body_on(a, f));
-    if (!LIN && in_range && !active && lane == 0 && !a.in_place) {
-        const int v = a.free_ids[f];
-        a.unext[v] = a.u[v];  // converged body in a Jacobi sweep: carried over unchanged
-    }
+    const int q = in_range ? a.cbase + idx : 0;
+    const int vself = a.vid_c[q];
+    const bool active = in_range && (LIN || a.body_on == nullptr || a.body_on[a.fbody_c[q]] != 0);
+    if (!LIN && in_range && !active && lane == 0 && !a.in_place)
+        a.unext[vself] = a.u[vself];  // converged body in a Jacobi sweep: carried over unchanged
     float g[3] = {0.f, 0.f, 0.f}, A6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (active) {
-        const int n = a.inc_n[f];
-        const int vself = a.free_ids[f];
+        const int n = a.incn_c[q];
         for (int j = lane; j < n; j += W) {
-            const int4 e = a.inc4[(size_t)f * a.maxi + j];
+            const int4 e = a.inc4_c[(size_t)q * a.maxi + j];
             const int c = e.x & 3;
             Tet T;
             load_tet_inc(a.tet, e, vself, T);
@@ -508,7 +508,7 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     for (int i = 0; i < 6; ++i) A6[i] = lane_sum_w<W>(A6[i]);
     double gsq = 0.0;
     if (active && lane == 0) {
-        const int v = a.free_ids[f];
+        const int v = vself;
         const d4 uv = a.u[v];
         float4 yv = make_float4(0.f, 0.f, 0.f, 0.f);
         if (LIN) {
