@@ -44,12 +44,10 @@ def parse():
 
 
 def sync():
-    try:
-        import torch
-        if torch.cuda.is_available():
-            torch.cuda.synchronize()
-    except ImportError:
-        pass
+    """Device-wide synchronisation in the library's HIP runtime (torch may
+    bring a runtime of its own that does not see the library's queues)."""
+    from paper_2506_06494_amd import jgs2
+    jgs2.device_synchronize()
 
 
 def calibrate_copy():

@@ -106,6 +106,23 @@ def load(path: str = LIB_PATH):
     return lib
 
 
+_hip = None
+
+
+def device_synchronize():
+    """hipDeviceSynchronize in the HIP runtime libjgs2 is linked against (the
+    system ROCm one; a torch build may carry a runtime of its own, which does
+    not see work queued through this one)."""
+    global _hip
+    load()
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so.7")
+        _hip.hipDeviceSynchronize.restype = C.c_int
+    r = _hip.hipDeviceSynchronize()
+    if r != 0:
+        raise JGS2Error(E_HIP, f"hipDeviceSynchronize returned {r}")
+
+
 class JGS2Error(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
