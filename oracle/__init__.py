@@ -21,7 +21,7 @@ Modules:
   mesh       adjacency and greedy vertex colouring
   rng        counter-based SplitMix64 draws used by cubature training
   correction rest Hessian, co-rotated basis U-bar, training poses, cubature
-  sweep      per-vertex local systems (variants R0, R1, R3, P0), Jacobi and
+  sweep      per-vertex local systems (variants R0, R1, R2, R2G1, R3, P0), Jacobi and
              coloured Gauss-Seidel sweeps, the time-step loop
   adjoint    implicit-function adjoint of the time-step map
 

@@ -46,7 +46,7 @@ import scipy.sparse.linalg as spla
 
 from . import correction as ocorr
 
-P0, R0, R1, R3 = "P0", "R0", "R1", "R3"
+P0, R0, R1, R2, R2G1, R3 = "P0", "R0", "R1", "R2", "R2G1", "R3"
 
 
 def polar(F):
@@ -168,6 +168,37 @@ def r3_systems(model, tab, ell, x, g, R, He, Hb, rows=None):
     return A, b
 
 
+def r2_systems(model, tab, ell, x, z, g, R, He, Hb, H, rows, own_gradient=False):
+    """The literal form of Eqs. reduced_local and cubature (variant R2):
+    A_i = H_ii + sum_s w_s U_s^T H_s U_s (samples never contain i, so no ii
+    block is removed), b_i = g_i + g-tilde_i with g-tilde_i the sampled
+    remote gradient, either from the assembled residual (g_a / n_a at sample
+    corners outside the closed one-ring, as in R3; R2) or from the sample's
+    own element gradient over its four corners (R2G1).  Uses the cubature
+    tables trained for R3."""
+    v = tab.verts[rows]
+    Ri = R[v]
+    n = rows.size
+    A = np.zeros((n, 3, 3))
+    for k, f in enumerate(rows):
+        A[k] = H[3 * f:3 * f + 3, 3 * f:3 * f + 3].toarray()
+    if Hb is not None:
+        A += Hb[v]
+    s = ell.samp[rows]
+    corners = model.tets[s]
+    Us = np.einsum("nscab,nscbd,ned->nscae", R[corners], tab.U_samp[rows], Ri)
+    w = tab.weights[rows] * ell.samp_ok[rows]
+    Us12 = Us.reshape(n, ell.S, 12, 3)
+    A += np.einsum("ns,nspa,nspq,nsqb->nab", w, Us12, He[s], Us12)
+    b = g[v].copy()
+    if own_gradient:
+        ge = model.element_gradients(x, z).reshape(model.nT, 12)
+        b += np.einsum("ns,nspa,nsp->na", w, Us12, ge[s])
+    else:
+        b += np.einsum("nsc,nscab,nsca->nb", tab.gcoef[rows] * ell.samp_ok[rows][:, :, None], Us, g[corners])
+    return A, b
+
+
 def full_subspace_systems(model, U_rows, x, g, R, H, verts):
     """A_i = U_i^T H U_i and b_i = U_i^T g from full row blocks U_rows
     (n, V, 3, 3), using the assembled sparse Hessian H (free DOFs)."""
@@ -229,7 +260,7 @@ class Sweeper:
         self.ls_halvings = 0
         from . import mesh as omesh
         self.inc = omesh.incidence(model.tets, model.nV)
-        self.ell = _Ell(model, tab, self.inc) if (tab is not None and variant == R3) else None
+        self.ell = _Ell(model, tab, self.inc) if (tab is not None and variant in (R3, R2, R2G1)) else None
         if tab is not None:
             assert np.array_equal(tab.verts, model.free_ids)
 
@@ -242,6 +273,9 @@ class Sweeper:
         if self.variant == R3:
             He = m.element_hessians(x)
             return r3_systems(m, self.tab, self.ell, x, g, R, He, Hb, rows)
+        if self.variant in (R2, R2G1):
+            return r2_systems(m, self.tab, self.ell, x, z, g, R, m.element_hessians(x), Hb, m.hessian(x), rows,
+                              own_gradient=self.variant == R2G1)
         if self.variant == P0:
             H = m.hessian(x)
             A = np.zeros((verts.size, 3, 3))

@@ -153,7 +153,7 @@ struct jgs2_solver {
     std::vector<int> body_of_vertex;       // [nV]
     std::vector<int> seg_off, seg_idx;     // free indices grouped by body
     int* d_fbody = nullptr;                // [nVf]
-    int *d_seg_off = nullptr, *d_seg_idx = nullptr;
+    int* d_seg_idx = nullptr;
     int n_chunks = 0;                      // fixed chunks of the per-body residual sums
     int *d_chunk_lo = nullptr, *d_chunk_hi = nullptr, *d_body_chunk_off = nullptr;
     double* d_r2c = nullptr;

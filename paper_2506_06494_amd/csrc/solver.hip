@@ -33,7 +33,7 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
     dfree(s->d_ck_u); dfree(s->d_ck_v); dfree(s->d_seg); dfree(s->d_y); dfree(s->d_ynext); dfree(s->d_xbar);
     dfree(s->d_vbar); dfree(s->d_rhs); dfree(s->d_thbar);
-    dfree(s->d_fbody); dfree(s->d_seg_off); dfree(s->d_seg_idx); dfree(s->d_body_on); dfree(s->d_body_sweeps);
+    dfree(s->d_fbody); dfree(s->d_seg_idx); dfree(s->d_body_on); dfree(s->d_body_sweeps);
     dfree(s->d_nactive); dfree(s->d_r2); dfree(s->d_r0sq);
     dfree(s->d_chunk_lo); dfree(s->d_chunk_hi); dfree(s->d_body_chunk_off); dfree(s->d_r2c);
     s->ro_valid = false;
@@ -1249,6 +1249,11 @@ int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* 
         (r = dalloc(s, s->d_vbar, nV)) || (r = dalloc(s, s->d_rhs, nV)) || (r = dalloc(s, s->d_thbar, (size_t)s->nT)))
         return r;
     hipEvent_t e0 = pool_event(s), e1 = pool_event(s);
+    struct EventReturn {  // the pair goes back to the pool on every return path
+        jgs2_solver* s;
+        hipEvent_t a, b;
+        ~EventReturn() { s->ev_pool.push_back(a); s->ev_pool.push_back(b); }
+    } event_return{s, e0, e1};
     HIPCHK(hipEventRecord(e0, s->stream));
     if ((r = upload(s, s->d_xbar, xb.data(), nV)) || (r = upload(s, s->d_vbar, vb.data(), nV)) ||
         (r = upload(s, s->d_rhs, rhs.data(), nV)))
@@ -1300,8 +1305,6 @@ int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* 
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.0f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    s->ev_pool.push_back(e0);
-    s->ev_pool.push_back(e1);
     loc.seconds = ms * 1e-3;
     loc.status = status;
     if (stats) *stats = loc;
@@ -1358,7 +1361,7 @@ int32_t jgs2_set_bodies(jgs2_solver* s, int32_t n_bodies, const int32_t* body_of
         return r;
     if ((r = upload(s, s->d_body_chunk_off, boff.data(), nb + 1))) return r;
     s->n_chunks = (int)nch;
-    if ((r = dalloc(s, s->d_fbody, (size_t)nf)) || (r = dalloc(s, s->d_seg_off, nb + 1)) ||
+    if ((r = dalloc(s, s->d_fbody, (size_t)nf)) ||
         (r = dalloc(s, s->d_seg_idx, (size_t)nf)) || (r = dalloc(s, s->d_body_on, nb)) ||
         (r = dalloc(s, s->d_body_sweeps, nb)) || (r = dalloc(s, s->d_nactive, 1)) || (r = dalloc(s, s->d_r2, nb)) ||
         (r = dalloc(s, s->d_r0sq, nb)))
@@ -1373,7 +1376,7 @@ int32_t jgs2_set_bodies(jgs2_solver* s, int32_t n_bodies, const int32_t* body_of
     std::vector<int> fbodyc(nf);
     for (int q = 0; q < nf; ++q) fbodyc[q] = fbody[s->col_perm[q]];
     if ((r = upload(s, s->d_fbody_c, fbodyc.data(), (size_t)nf))) return r;
-    if ((r = upload(s, s->d_fbody, fbody.data(), (size_t)nf)) || (r = upload(s, s->d_seg_off, off.data(), nb + 1)) ||
+    if ((r = upload(s, s->d_fbody, fbody.data(), (size_t)nf)) ||
         (r = upload(s, s->d_seg_idx, idx.data(), (size_t)nf)) || (r = upload(s, s->d_body_on, ones.data(), nb)) ||
         (r = upload(s, s->d_body_sweeps, zeros.data(), nb)))
         return r;

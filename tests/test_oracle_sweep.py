@@ -74,9 +74,30 @@ def test_solution_is_fixed_point_of_every_variant(tiny):
     xs, hist = newton.newton_solve(mdl, sc.x0, sc.v0, tol=1e-11)
     z = mdl.inertial_target(sc.x0, sc.v0)
     diag = np.linalg.norm(mdl.X.max(0) - mdl.X.min(0))
-    for var in [osw.R0, osw.R1, osw.R3, osw.P0]:
+    for var in [osw.R0, osw.R1, osw.R3, osw.R2, osw.P0]:
         x1 = osw.Sweeper(mdl, tab, var).jacobi(xs, z)
         assert np.abs(x1 - xs).max() < 1e-9 * diag, var
+    # the literal form with element-own sample gradients is not stationary at
+    # the solution: element forces do not vanish where the assembled residual does
+    x1 = osw.Sweeper(mdl, tab, osw.R2G1).jacobi(xs, z)
+    assert np.abs(x1 - xs).max() > 1e-6 * diag
+
+
+def test_literal_form_without_samples_is_plain_jacobi(tiny):
+    """With every cubature weight zero, R2 reduces to A_i = H_ii, b_i = g_i."""
+    import copy
+    sc, mdl, tab = tiny
+    t0 = copy.copy(tab)
+    t0.weights = np.zeros_like(tab.weights)
+    t0.gcoef = np.zeros_like(tab.gcoef)
+    z = mdl.inertial_target(sc.x0, sc.v0)
+    x = sc.x0 + 1e-4 * np.random.default_rng(5).standard_normal(sc.x0.shape)
+    x[mdl.pinned] = mdl.X[mdl.pinned]
+    for var in (osw.R2, osw.R2G1):
+        A, b = osw.Sweeper(mdl, t0, var).systems(x, z)
+        A0, b0 = osw.Sweeper(mdl, None, osw.P0).systems(x, z)
+        np.testing.assert_allclose(A, A0, rtol=1e-13, atol=1e-9)
+        np.testing.assert_allclose(b, b0, rtol=1e-13, atol=1e-12)
 
 
 def test_zero_force_at_rest_gives_zero_step(tiny):
