@@ -90,6 +90,8 @@ typedef struct jgs2_step_stats {
     double  seconds;            /* device time of the step (HIP events) */
     int32_t ls_halvings;        /* energy backtracking halvings this step */
     int32_t reserved;
+    double  dx_norm;            /* |x_k - x_{k-1}| over free DOFs of the last sweep [m]
+                                   (the convergence measure of Sec. 7 / Table 1) */
 } jgs2_step_stats;
 
 typedef struct jgs2_adjoint_stats {

@@ -157,6 +157,9 @@ struct jgs2_solver {
     int n_chunks = 0;                      // fixed chunks of the per-body residual sums
     int *d_chunk_lo = nullptr, *d_chunk_hi = nullptr, *d_body_chunk_off = nullptr;
     double* d_r2c = nullptr;
+    jgs2::d4* d_uprev = nullptr;           // iterate before the last sweep of a group
+    double *d_dx2c = nullptr, *d_dx2 = nullptr;
+    double dx_norm = 0.0;
     int* d_body_on = nullptr;              // [n_bodies]
     int* d_body_sweeps = nullptr;          // [n_bodies]
     int* d_nactive = nullptr;              // [1]
@@ -174,6 +177,7 @@ struct jgs2_solver {
     // pinned residual readback slots (two sweep groups in flight)
     double* h_r2[2] = {nullptr, nullptr};
     int* h_nact[2] = {nullptr, nullptr};
+    double* h_dx2[2] = {nullptr, nullptr};
     hipEvent_t rb_ev[2] = {nullptr, nullptr};
 
     int fail(int code, const std::string& msg) {

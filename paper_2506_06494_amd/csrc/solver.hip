@@ -36,6 +36,7 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_fbody); dfree(s->d_seg_idx); dfree(s->d_body_on); dfree(s->d_body_sweeps);
     dfree(s->d_nactive); dfree(s->d_r2); dfree(s->d_r0sq);
     dfree(s->d_chunk_lo); dfree(s->d_chunk_hi); dfree(s->d_body_chunk_off); dfree(s->d_r2c);
+    dfree(s->d_uprev); dfree(s->d_dx2c); dfree(s->d_dx2);
     s->ro_valid = false;
     drop_graphs(s);
     free_readback(s);
@@ -45,8 +46,10 @@ void free_readback(jgs2_solver* s) {
     for (int i = 0; i < 2; ++i) {
         if (s->h_r2[i]) (void)hipHostFree(s->h_r2[i]);
         if (s->h_nact[i]) (void)hipHostFree(s->h_nact[i]);
+        if (s->h_dx2[i]) (void)hipHostFree(s->h_dx2[i]);
         s->h_r2[i] = nullptr;
         s->h_nact[i] = nullptr;
+        s->h_dx2[i] = nullptr;
     }
 }
 
@@ -424,8 +427,9 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
         (r = dalloc(s, s->d_incslot, nf * s->maxi)) || (r = dalloc(s, s->d_inc_n, nf)) ||
         (r = dalloc(s, s->d_ring, nf * s->K)) || (r = dalloc(s, s->d_ring_n, nf)) ||
         (r = dalloc(s, s->d_colperm, nf)) || (r = dalloc(s, s->d_tet, (size_t)nT * TET_F4)) ||
-        (r = dalloc(s, s->d_inc4, nf * s->maxi)))
+        (r = dalloc(s, s->d_inc4, nf * s->maxi)) || (r = dalloc(s, s->d_uprev, V4)) || (r = dalloc(s, s->d_dx2, 1)))
         return r;
+    HIPCHK(hipMemsetAsync(s->d_dx2, 0, sizeof(double), s->stream));
     s->n_partial = std::max<int>((s->nVf + 1) / 2, (std::max(nT, s->nVf) + 255) / 256) + 1;
     if ((r = dalloc(s, s->d_partial, (size_t)s->n_partial)) || (r = dalloc(s, s->d_red, 4))) return r;
     std::vector<float4> Xs(V4), Rid(V4, make_float4(0.f, 0.f, 0.f, 1.f));
@@ -660,12 +664,61 @@ static int read_reduced(jgs2_solver* s, int n_partials, double* out) {
 // Residual check, device part: gradient (and rotations) at the iterate, the
 // per-body |g_b|^2, and (mask_k > 0) the per-body stop decision after mask_k
 // sweeps.  Graph-capturable: kernels only.
+// |x_k - x_{k-1}|^2 of the last sweep (the paper's convergence measure), in
+// the same fixed chunks as the residual, then summed in chunk order.
+__global__ __launch_bounds__(256) void k_chunk_dx2(const int* __restrict__ chunk_lo, const int* __restrict__ chunk_hi,
+                                                   const int* __restrict__ seg_idx, const int* __restrict__ free_ids,
+                                                   const d4* __restrict__ u, const d4* __restrict__ uprev,
+                                                   double* __restrict__ out) {
+    __shared__ double sh[256];
+    const int c = blockIdx.x;
+    double e = 0.0;
+    for (int i = chunk_lo[c] + threadIdx.x; i < chunk_hi[c]; i += 256) {
+        const int v = free_ids[seg_idx[i]];
+        const double dx = u[v].x - uprev[v].x, dy = u[v].y - uprev[v].y, dz = u[v].z - uprev[v].z;
+        e += dx * dx + dy * dy + dz * dz;
+    }
+    sh[threadIdx.x] = e;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = sh[0];
+}
+
+__global__ void k_sum_in_order(int n, const double* __restrict__ in, double* __restrict__ out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += in[i];
+    out[0] = t;
+}
+
+__global__ void k_copy_d4(int n, const d4* __restrict__ src, d4* __restrict__ dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+static void keep_iterate(jgs2_solver* s) {
+    hipLaunchKernelGGL(k_copy_d4, dim3((s->nV + 255) / 256), dim3(256), 0, s->stream, s->nV, (const d4*)s->d_u,
+                       s->d_uprev);
+}
+
 static void residual_launches(jgs2_solver* s, int mask_k) {
     SweepArgs a;
     build_sweep_args(s, a);
     launch_phase1(s, a, s->p.variant == JGS2_CUBATURE);
     launch_seg_norm2(s);
-    if (mask_k > 0) launch_mask_update(s, mask_k);
+    if (mask_k > 0) {
+        launch_mask_update(s, mask_k);
+        if (s->n_chunks > 0) {
+            hipLaunchKernelGGL(k_chunk_dx2, dim3(s->n_chunks), dim3(256), 0, s->stream, (const int*)s->d_chunk_lo,
+                               (const int*)s->d_chunk_hi, (const int*)s->d_seg_idx, (const int*)s->d_free,
+                               (const d4*)s->d_u, (const d4*)s->d_uprev, s->d_dx2c);
+            hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(64), 0, s->stream, s->n_chunks, (const double*)s->d_dx2c,
+                               s->d_dx2);
+        }
+    }
 }
 
 // Host part: read the per-body residuals and the count of bodies still on;
@@ -674,7 +727,10 @@ static int residual_readback(jgs2_solver* s, double* g2) {
     const size_t nb = s->n_bodies;
     HIPCHK(hipMemcpyAsync(s->r2_host.data(), s->d_r2, nb * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(&s->n_active, s->d_nactive, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    double dx2 = 0.0;
+    HIPCHK(hipMemcpyAsync(&dx2, s->d_dx2, sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    s->dx_norm = std::sqrt(dx2);
     prof_collect(s);
     s->phase1_valid = true;
     double t = 0.0;
@@ -743,6 +799,7 @@ int32_t jgs2_begin_step(jgs2_solver* s) {
     if (!std::isfinite(g2)) return s->fail(JGS2_E_NONFINITE, "non-finite residual at the start of the step");
     s->r0sq_host = s->r2_host;
     s->r0 = std::sqrt(g2);
+    s->dx_norm = 0.0;
     s->in_step = true;
     s->sweeps_in_step = 0;
     s->ls_halvings = 0;
@@ -823,6 +880,7 @@ static int sweep_group(jgs2_solver* s, int k) {
     const bool graphable = s->p.use_graph && !s->prof && !s->p.line_search;
     if (!graphable) {
         for (int i = 0; i < k; ++i) {
+            if (i == k - 1) keep_iterate(s);
             int r = sweep_once(s);
             if (r != JGS2_OK) return r;
         }
@@ -848,7 +906,10 @@ static int sweep_group(jgs2_solver* s, int k) {
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
         int r = JGS2_OK;
-        for (int i = 0; i < k && r == JGS2_OK; ++i) r = sweep_once(s);
+        for (int i = 0; i < k && r == JGS2_OK; ++i) {
+            if (i == k - 1) keep_iterate(s);
+            r = sweep_once(s);
+        }
         if (r == JGS2_OK) residual_launches(s, k);
         hipError_t e = hipStreamEndCapture(s->stream, &g);
         // capture only recorded the launches: put the bookkeeping back
@@ -919,6 +980,7 @@ static int enqueue_readback(jgs2_solver* s, int slot) {
     const size_t nb = s->n_bodies;
     HIPCHK(hipMemcpyAsync(s->h_r2[slot], s->d_r2, nb * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(s->h_nact[slot], s->d_nactive, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(s->h_dx2[slot], s->d_dx2, sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipEventRecord(s->rb_ev[slot], s->stream));
     return JGS2_OK;
 }
@@ -933,6 +995,7 @@ static int finish_readback(jgs2_solver* s, int slot, double* rel) {
         g2 += s->r2_host[b];
     }
     s->n_active = *s->h_nact[slot];
+    s->dx_norm = std::sqrt(*s->h_dx2[slot]);
     *rel = max_rel(s);
     if (!std::isfinite(g2)) return s->fail(JGS2_E_NONFINITE, "non-finite residual");
     if (*rel > 1e8) return s->fail(JGS2_E_DIVERGED, "residual exceeded 1e8 x its start value");
@@ -1017,6 +1080,7 @@ int32_t jgs2_step(jgs2_solver* s, jgs2_step_stats* st) {
     for (int b : bsw) most = std::max(most, b);
     loc.sweeps = most; loc.status = JGS2_OK; loc.r0 = s->r0; loc.r_final = rel; loc.seconds = ms * 1e-3;
     loc.ls_halvings = s->ls_halvings;
+    loc.dx_norm = s->dx_norm;
     if (st) *st = loc;
     return JGS2_OK;
 }
@@ -1355,7 +1419,8 @@ int32_t jgs2_set_bodies(jgs2_solver* s, int32_t n_bodies, const int32_t* body_of
     int r;
     const size_t nb = n_bodies;
     if ((r = dalloc(s, s->d_chunk_lo, nch)) || (r = dalloc(s, s->d_chunk_hi, nch)) ||
-        (r = dalloc(s, s->d_body_chunk_off, nb + 1)) || (r = dalloc(s, s->d_r2c, nch)))
+        (r = dalloc(s, s->d_body_chunk_off, nb + 1)) || (r = dalloc(s, s->d_r2c, nch)) ||
+        (r = dalloc(s, s->d_dx2c, nch)))
         return r;
     if (nch > 0 && ((r = upload(s, s->d_chunk_lo, clo.data(), nch)) || (r = upload(s, s->d_chunk_hi, chi.data(), nch))))
         return r;
@@ -1370,6 +1435,8 @@ int32_t jgs2_set_bodies(jgs2_solver* s, int32_t n_bodies, const int32_t* body_of
     for (int i = 0; i < 2; ++i) {
         HIPCHK(hipHostMalloc((void**)&s->h_r2[i], nb * sizeof(double), hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void**)&s->h_nact[i], sizeof(int), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&s->h_dx2[i], sizeof(double), hipHostMallocDefault));
+        *s->h_dx2[i] = 0.0;
         if (!s->rb_ev[i]) HIPCHK(hipEventCreateWithFlags(&s->rb_ev[i], hipEventDisableTiming));
     }
     std::vector<int> ones(nb, 1), zeros(nb, 0);

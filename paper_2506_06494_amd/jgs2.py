@@ -32,7 +32,8 @@ class Params(C.Structure):
 
 class StepStats(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("status", C.c_int32), ("r0", C.c_double), ("r_final", C.c_double),
-                ("seconds", C.c_double), ("ls_halvings", C.c_int32), ("reserved", C.c_int32)]
+                ("seconds", C.c_double), ("ls_halvings", C.c_int32), ("reserved", C.c_int32),
+                ("dx_norm", C.c_double)]
 
 
 class AdjointStats(C.Structure):
@@ -268,7 +269,7 @@ class Solver:
         if raise_on_error:
             self._chk(r)
         return dict(status=r, sweeps=st.sweeps, r0=st.r0, r_final=st.r_final, seconds=st.seconds,
-                    ls_halvings=st.ls_halvings)
+                    ls_halvings=st.ls_halvings, dx_norm=st.dx_norm)
 
     def begin_step(self):
         self._chk(self.lib.jgs2_begin_step(self.h))

@@ -150,3 +150,23 @@ def test_error_paths(tiny):
     with pytest.raises(jgs2.JGS2Error) as e:
         s.upload_mesh(mdl.X, bad, sc.mesh.pinned)
     assert e.value.code == jgs2.E_INVALID
+
+
+def test_step_reports_last_sweep_update_norm(tiny):
+    """dx_norm = |x_K - x_{K-1}| over free DOFs of the step's last sweep."""
+    sc, mdl, tab = tiny
+    s = make_solver(sc, variant=jgs2.PLAIN, order=jgs2.GS, max_sweeps=16, check_every=16, rel_tol=1e-12)
+    s.set_state(sc.x0, sc.v0)
+    st = s.step()
+    assert st["sweeps"] == 16
+    s2 = make_solver(sc, variant=jgs2.PLAIN, order=jgs2.GS)
+    s2.set_state(sc.x0, sc.v0)
+    s2.begin_step()
+    s2.iterate(15)
+    x1, _ = s2.get_state()
+    s2.iterate(1)
+    x2, _ = s2.get_state()
+    free = ~sc.mesh.pinned.astype(bool)
+    ref = np.linalg.norm((x2 - x1)[free])
+    assert ref > 0
+    np.testing.assert_allclose(st["dx_norm"], ref, rtol=1e-9)

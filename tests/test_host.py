@@ -31,7 +31,7 @@ int main(void) {
     F(jgs2_params, planes); F(jgs2_params, adj_rel_tol); F(jgs2_params, adj_max_sweeps); F(jgs2_params, use_graph);
     printf("jgs2_step_stats size %zu\\n", sizeof(jgs2_step_stats));
     F(jgs2_step_stats, sweeps); F(jgs2_step_stats, status); F(jgs2_step_stats, r0); F(jgs2_step_stats, r_final);
-    F(jgs2_step_stats, seconds); F(jgs2_step_stats, ls_halvings);
+    F(jgs2_step_stats, seconds); F(jgs2_step_stats, ls_halvings); F(jgs2_step_stats, dx_norm);
     printf("jgs2_adjoint_stats size %zu\\n", sizeof(jgs2_adjoint_stats));
     F(jgs2_adjoint_stats, steps); F(jgs2_adjoint_stats, status); F(jgs2_adjoint_stats, adjoint_sweeps);
     F(jgs2_adjoint_stats, forward_sweeps); F(jgs2_adjoint_stats, max_rel_res); F(jgs2_adjoint_stats, seconds);
