@@ -38,6 +38,7 @@ def parse():
                     help="autotune the launch shape of the single-beam modes (default: 32 lanes x 256)")
     ap.add_argument("--batched-beams", type=int, default=256)
     ap.add_argument("--no-contact", action="store_true", help="skip the 10-sphere contact leg")
+    ap.add_argument("--leg", choices=["contact"], help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (5x) to calibrate HBM byte counters")
     return ap.parse_args()
@@ -67,10 +68,16 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
+    if args.leg == "contact":                  # child process of the default run
+        print(json.dumps(contact_leg()))
+        return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
+    # the contact leg runs first, in a child process started before this one
+    # touches the GPU, so that a failure there cannot take the whole run down
+    con = None if args.no_contact or args.small else contact_leg_child()
     from paper_2506_06494_amd import inputs, jgs2
 
     stiff = [float(e) for e in args.stiffness.split(",")]
@@ -219,7 +226,6 @@ def main():
 
     adj = None if args.no_adjoint or args.small else adjoint_leg()
     bat = None if args.no_batched or args.small else batched_leg(args.batched_beams)
-    con = None if args.no_contact or args.small else contact_leg()
 
     cpu = None
     if not args.no_cpu_baseline and head_mode is not None and head_mode.startswith("plain_gs"):
@@ -314,6 +320,21 @@ def batched_leg(n_beams=256, steps=2, max_sweeps=1000, check_every=8, omega=1.5)
            "roofline": roof}
     print(f"[bench] batched: {json.dumps(out)}", file=sys.stderr, flush=True)
     return out
+
+
+def contact_leg_child(timeout_s=900):
+    import subprocess
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--leg", "contact"], capture_output=True,
+                           text=True, timeout=timeout_s)
+    except subprocess.TimeoutExpired:
+        return {"error": f"contact leg exceeded {timeout_s} s"}
+    sys.stderr.write(r.stderr)
+    sys.stderr.flush()
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"error": f"contact leg exited with status {r.returncode}"}
+    return json.loads(lines[-1])
 
 
 def contact_leg(steps=3, max_sweeps=3000, check_every=16):
