@@ -344,6 +344,7 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
     s->maxi = 0; s->K = 0;
     for (int f = 0; f < s->nVf; ++f) {
         const int v = s->free_ids[f];
+        if (off[v + 1] == off[v]) return s->fail(JGS2_E_INVALID, "a free vertex belongs to no tet (it has no mass)");
         auto& r = ringv[f];
         for (int64_t k = off[v]; k < off[v + 1]; ++k) {
             const int t = incall[k] >> 2;

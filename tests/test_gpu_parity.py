@@ -170,3 +170,34 @@ def test_step_reports_last_sweep_update_norm(tiny):
     ref = np.linalg.norm((x2 - x1)[free])
     assert ref > 0
     np.testing.assert_allclose(st["dx_norm"], ref, rtol=1e-9)
+
+
+def test_degenerate_meshes(tiny):
+    sc, mdl, tab = tiny
+    # every vertex pinned: nothing to solve, the step is a no-op
+    s = make_solver(sc, variant=jgs2.PLAIN, order=jgs2.GS)
+    s.upload_mesh(mdl.X, mdl.tets, np.ones(mdl.nV, dtype=np.uint8))
+    s.set_material(sc.E, sc.nu, sc.rho)
+    s.set_state(mdl.X, np.zeros_like(mdl.X))
+    st = s.step()
+    assert st["status"] == 0 and st["sweeps"] == 0
+    x, v = s.get_state()
+    assert np.array_equal(x, mdl.X) and not v.any()
+    # a free vertex outside every tet has no mass: refused at upload
+    X2 = np.vstack([mdl.X, [[9.0, 9.0, 9.0]]])
+    with pytest.raises(jgs2.JGS2Error) as e:
+        s.upload_mesh(X2, mdl.tets, np.concatenate([sc.mesh.pinned, [0]]).astype(np.uint8))
+    assert e.value.code == jgs2.E_INVALID
+    # a single free vertex (one tet, three corners pinned) against the oracle
+    X1 = np.array([[0, 0, 0], [0.1, 0, 0], [0, 0.1, 0], [0, 0, 0.1]], dtype=np.float64)
+    T1 = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    P1 = np.array([1, 1, 1, 0], dtype=np.uint8)
+    s1 = jgs2.Solver(order=jgs2.GS, rel_tol=1e-6, max_sweeps=100, check_every=1)
+    s1.upload_mesh(X1, T1, P1)
+    s1.set_material(1e5, 0.3, 1000.0)
+    s1.set_state(X1, np.zeros_like(X1))
+    st = s1.step()
+    x1, _ = s1.get_state()
+    m1 = fem.Model(X1, T1, P1, 1e5, 0.3, 1000.0, 1.0 / 120)
+    xs, _ = newton.newton_solve(m1, X1, np.zeros_like(X1), tol=1e-12)
+    assert st["status"] == 0 and np.abs(x1 - xs).max() <= 1e-5 * bbox_diag(X1)
