@@ -4,8 +4,9 @@ Calls only the FP64 oracle (``oracle/``) on the seeded single-beam workload
 (16x16 cross-section, 128 long, 0.05 m cells; nu 0.45, E 1e5 and 1e8 Pa,
 rho 1000, dt 1/120, initial twist 2 rad/s): the precompute on a sample of
 free vertices (training-pose eigenvalues, one-ring U-bar rows, cubature
-samples, weights, fit residuals) and the positions of sampled vertices after
-two plain Jacobi sweeps (omega 0.8) of the first step.
+samples, weights, fit residuals), the positions of sampled vertices after
+two plain Jacobi sweeps (omega 0.8) of the first step, and (E 1e5) after four
+coloured GS sweeps with step scale 1.5 (the benchmark's headline sweep).
 
     python tests/golden/make_goldens.py        # a few minutes on one core
 """
@@ -55,8 +56,22 @@ def golden_plain_jacobi(E, sweeps=2, omega=0.8):
             "rel_res": hist}
 
 
+def golden_plain_gs(E, sweeps=4, omega=1.5):
+    """Sampled positions after a few over-relaxed coloured GS sweeps (the
+    benchmark's headline sweep) of the first step."""
+    from oracle import mesh as omesh
+    sc = inputs.single_beam(E)
+    mdl = fem.model_from_scene(sc)
+    col = omesh.greedy_coloring(omesh.one_ring(mdl.tets, mdl.nV), mdl.free)
+    sw = osw.Sweeper(mdl, None, osw.P0, omega=omega)
+    x, v, hist = osw.run_step(sw, sc.x0, sc.v0, sweeps=sweeps, mode="gs", color=col)
+    verts = sampled_vertices(mdl, 200, 3)
+    return {"E": E, "sweeps": sweeps, "omega": omega, "verts": verts.tolist(), "x": x[verts].tolist(),
+            "rel_res": hist}
+
+
 def main():
-    which = sys.argv[1:] or ["precompute", "jacobi"]
+    which = sys.argv[1:] or ["precompute", "jacobi", "gs"]
     for E in (1e5, 1e8):
         if "precompute" in which:
             path = os.path.join(HERE, f"beam16x16x128_E{E:g}_precompute.json")
@@ -65,6 +80,10 @@ def main():
         if "jacobi" in which:
             path = os.path.join(HERE, f"beam16x16x128_E{E:g}_plain_jacobi.json")
             json.dump(golden_plain_jacobi(E), open(path, "w"))
+            print("wrote", path, flush=True)
+        if "gs" in which and E == 1e5:
+            path = os.path.join(HERE, f"beam16x16x128_E{E:g}_plain_gs_w1.5.json")
+            json.dump(golden_plain_gs(E), open(path, "w"))
             print("wrote", path, flush=True)
 
 

@@ -77,3 +77,19 @@ def test_full_size_plain_jacobi_matches_golden(E):
     assert np.abs(x[v] - np.array(g["x"])).max() <= 1e-5 * bbox_diag(mdl.X)
     _, rel = s.residual()                                   # |g| / |g(x0)| in FP64
     np.testing.assert_allclose(rel, g["rel_res"][-1], rtol=1e-3)
+
+
+def test_full_size_headline_sweeps_match_golden():
+    """The benchmark's headline configuration (coloured GS, step scale 1.5,
+    captured sweep groups, default launch shape) on the full beam."""
+    g = load(1e5, "plain_gs_w1.5")
+    sc = inputs.single_beam(1e5)
+    mdl = fem.model_from_scene(sc)
+    s = make_solver(sc, variant=jgs2.PLAIN, order=jgs2.GS, omega=g["omega"], use_graph=1, check_every=g["sweeps"])
+    s.set_state(sc.x0, sc.v0)
+    s.begin_step()
+    rel = s.iterate(g["sweeps"])
+    x, _ = s.get_state()
+    v = np.array(g["verts"])
+    assert np.abs(x[v] - np.array(g["x"])).max() <= 1e-5 * bbox_diag(mdl.X)
+    np.testing.assert_allclose(rel, g["rel_res"][-1], rtol=1e-3)
