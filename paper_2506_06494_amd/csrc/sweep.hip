@@ -487,19 +487,19 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
                 for (int i = 0; i < 3; ++i)
                     g[i] += P[3 * i] * gn[0] + P[3 * i + 1] * gn[1] + P[3 * i + 2] * gn[2];
             }
-            int k = 0;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                float dF[9], dP[9];
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int jj = 0; jj < 3; ++jj) dF[3 * i + jj] = (i == d) ? gn[jj] : 0.0f;
-                snh_dstress(K.F, K.C, 1.0f + K.Jm1, T.vmu, T.vlam, dF, dP);
-#pragma unroll
-                for (int e = d; e < 3; ++e)
-                    A6[k++] += dP[3 * e] * gn[0] + dP[3 * e + 1] * gn[1] + dP[3 * e + 2] * gn[2];
-            }
+            // own diagonal block: dP[e_d gn^T] : e_e gn^T.  The cofactor-derivative
+            // term is (e_e x e_d)^T F (gn x gn) = 0 here, leaving
+            // V mu |gn|^2 I + V lam (cof F gn)(cof F gn)^T
+            const float c0 = K.C[0] * gn[0] + K.C[1] * gn[1] + K.C[2] * gn[2];
+            const float c1 = K.C[3] * gn[0] + K.C[4] * gn[1] + K.C[5] * gn[2];
+            const float c2 = K.C[6] * gn[0] + K.C[7] * gn[1] + K.C[8] * gn[2];
+            const float mg = T.vmu * (gn[0] * gn[0] + gn[1] * gn[1] + gn[2] * gn[2]);
+            A6[0] += mg + T.vlam * c0 * c0;
+            A6[1] += T.vlam * c0 * c1;
+            A6[2] += T.vlam * c0 * c2;
+            A6[3] += mg + T.vlam * c1 * c1;
+            A6[4] += T.vlam * c1 * c2;
+            A6[5] += mg + T.vlam * c2 * c2;
         }
     }
 #pragma unroll

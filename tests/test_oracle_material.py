@@ -104,3 +104,25 @@ def test_barrier_derivatives_by_fd():
         assert abs(fd - m.barrier_gradient(x)[0, 2]) < 1e-6 * max(1.0, abs(fd))
         fd2 = (m.barrier_gradient(xp)[0, 2] - m.barrier_gradient(xm)[0, 2]) / (2 * h)
         assert abs(fd2 - m.barrier_hessian_blocks(x)[0, 2, 2]) < 1e-5 * abs(fd2)
+
+
+def test_own_diagonal_block_closed_form():
+    """For dF = e_d g^T and dF' = e_e g^T (a corner's own 3x3 block) the
+    cofactor-derivative term of dP vanishes, (e_e x e_d)^T F (g x g) = 0, so
+    the block is mu |g|^2 I + lam (cof F g)(cof F g)^T for any F (inverted
+    included): the form the plain sweep kernel evaluates."""
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        F = rng.standard_normal((3, 3))
+        g = rng.standard_normal(3)
+        mu, lam = rng.uniform(0.1, 5.0, 2)
+        A = np.zeros((3, 3))
+        for d in range(3):
+            D = np.zeros((3, 3)); D[d] = g
+            dP = snh.dstress(F[None], D[None], np.array([mu]), np.array([lam]))[0]
+            for e in range(3):
+                De = np.zeros((3, 3)); De[e] = g
+                A[d, e] = np.sum(dP * De)
+        c = snh.cof(F[None])[0] @ g
+        np.testing.assert_allclose(A, mu * (g @ g) * np.eye(3) + lam * np.outer(c, c), rtol=1e-12,
+                                   atol=1e-12 * np.abs(A).max())
