@@ -31,7 +31,8 @@ def parse():
     ap.add_argument("--max-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="4x4x16 beam instead (quick check)")
-    ap.add_argument("--modes", default="jgs2_jacobi,jgs2_gs,plain_jacobi,plain_jacobi_w0.8,plain_gs,plain_gs_w1.5")
+    ap.add_argument("--modes", default="jgs2_jacobi,jgs2_gs,plain_jacobi,plain_jacobi_w0.8,plain_jacobi_w0.5,"
+                                       "plain_jacobi_w0.3,plain_gs,plain_gs_w1.5")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched many-beam leg")
     ap.add_argument("--tune", action="store_true",
@@ -93,6 +94,8 @@ def main():
         ("jgs2_gs", dict(variant=jgs2.CUBATURE, order=jgs2.GS, omega=1.0)),
         ("plain_jacobi", dict(variant=jgs2.PLAIN, order=jgs2.JACOBI, omega=1.0)),
         ("plain_jacobi_w0.8", dict(variant=jgs2.PLAIN, order=jgs2.JACOBI, omega=0.8)),
+        ("plain_jacobi_w0.5", dict(variant=jgs2.PLAIN, order=jgs2.JACOBI, omega=0.5)),
+        ("plain_jacobi_w0.3", dict(variant=jgs2.PLAIN, order=jgs2.JACOBI, omega=0.3)),
         ("plain_gs", dict(variant=jgs2.PLAIN, order=jgs2.GS, omega=1.0)),
         # the same coloured GS with every vertex step scaled by 1.5 (successive over-relaxation)
         ("plain_gs_w1.5", dict(variant=jgs2.PLAIN, order=jgs2.GS, omega=1.5)),
