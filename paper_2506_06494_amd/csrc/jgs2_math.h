@@ -318,26 +318,35 @@ template <typename T> JGS2_HD void rot_from_quat(T x, T y, T z, T w, T* R) {
     R[6] = T(2) * (x * z - y * w); R[7] = T(2) * (y * z + x * w); R[8] = T(1) - T(2) * (x * x + y * y);
 }
 
-// LDL^T pivots of a symmetric 3x3 (lower triangle used).
-template <typename T> JGS2_HD void ldl_pivots(const T* A, T* d, T* l10, T* l20, T* l21) {
+// Reciprocal: v_rcp_f32 (within 1 ulp) for float, exact division for double.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// LDL^T pivots of a symmetric 3x3 (lower triangle used) and their
+// reciprocals (a zero pivot has a zero multiplier column).
+template <typename T> __device__ __forceinline__ void ldl_pivots(const T* A, T* d, T* inv, T* l10, T* l20, T* l21) {
     d[0] = A[0];
-    *l10 = d[0] != T(0) ? A[3] / d[0] : T(0);
-    *l20 = d[0] != T(0) ? A[6] / d[0] : T(0);
+    inv[0] = recip(d[0]);
+    const T i0 = d[0] != T(0) ? inv[0] : T(0);
+    *l10 = A[3] * i0;
+    *l20 = A[6] * i0;
     d[1] = A[4] - (*l10) * (*l10) * d[0];
-    *l21 = d[1] != T(0) ? (A[7] - (*l20) * (*l10) * d[0]) / d[1] : T(0);
+    inv[1] = recip(d[1]);
+    *l21 = d[1] != T(0) ? (A[7] - (*l20) * (*l10) * d[0]) * inv[1] : T(0);
     d[2] = A[8] - (*l20) * (*l20) * d[0] - (*l21) * (*l21) * d[1];
+    inv[2] = recip(d[2]);
 }
 
 // dx = -A^-1 b for a symmetric 3x3 A.  If A is not safely positive definite
 // (an LDL^T pivot <= 1e-6 |tr A|), A is shifted by (|d_min| + 1e-6 |tr A|) I,
 // the shift doubling until it is.
-template <typename T> JGS2_HD void local_solve(const T* A_in, const T* b, T* dx) {
+template <typename T> __device__ __forceinline__ void local_solve(const T* A_in, const T* b, T* dx) {
     T A[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) A[i] = A_in[i];
     const T tr = fabs(A[0] + A[4] + A[8]);
-    T d[3], l10, l20, l21;
-    ldl_pivots(A, d, &l10, &l20, &l21);
+    T d[3], inv[3], l10, l20, l21;
+    ldl_pivots(A, d, inv, &l10, &l20, &l21);
     T dmin = fmin(d[0], fmin(d[1], d[2]));
     if (!(dmin > T(1e-6) * tr)) {
         T shift = fabs(dmin) + T(1e-6) * tr;
@@ -346,7 +355,7 @@ template <typename T> JGS2_HD void local_solve(const T* A_in, const T* b, T* dx)
 #pragma unroll
             for (int i = 0; i < 9; ++i) As[i] = A[i];
             As[0] += shift; As[4] += shift; As[8] += shift;
-            ldl_pivots(As, d, &l10, &l20, &l21);
+            ldl_pivots(As, d, inv, &l10, &l20, &l21);
             dmin = fmin(d[0], fmin(d[1], d[2]));
             if (dmin > T(1e-6) * tr) break;
             shift *= T(2);
@@ -356,7 +365,7 @@ template <typename T> JGS2_HD void local_solve(const T* A_in, const T* b, T* dx)
     T y0 = b[0];
     T y1 = b[1] - l10 * y0;
     T y2 = b[2] - l20 * y0 - l21 * y1;
-    y0 /= d[0]; y1 /= d[1]; y2 /= d[2];
+    y0 *= inv[0]; y1 *= inv[1]; y2 *= inv[2];
     T x2 = y2;
     T x1 = y1 - l21 * x2;
     T x0 = y0 - l10 * x1 - l20 * x2;

@@ -40,19 +40,30 @@ __device__ __forceinline__ int xcd_remap(int i, int nb) {
     return x * q + (x < r ? x : r) + j;
 }
 
-__device__ __forceinline__ float lane_sum(float v) {
-#pragma unroll
-    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, LPV);
+// v from another lane of the same 16-lane row (DPP move; every lane of a
+// wave is active where these are called).
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the W lanes of one vertex sub-problem; every lane of the group
+// ends with the same total.  Within a row the partners come from DPP moves
+// (lane ^ 1, lane ^ 2, then the mirrored lane in the 8- and 16-lane halves,
+// each pairing two partial sums that are already equal across their lanes);
+// only the step across 16-lane rows goes through ds_bpermute.
+template <int W>
+__device__ __forceinline__ float lane_sum_w(float v) {
+    static_assert(W == 4 || W == 8 || W == 16 || W == 32, "lanes per vertex");
+    v += dpp_mov<0xB1>(v);                         // quad_perm(1, 0, 3, 2)
+    v += dpp_mov<0x4E>(v);                         // quad_perm(2, 3, 0, 1)
+    if constexpr (W >= 8) v += dpp_mov<0x141>(v);  // row_half_mirror
+    if constexpr (W >= 16) v += dpp_mov<0x140>(v); // row_mirror
+    if constexpr (W >= 32) v += __shfl_xor(v, 16, 32);
     return v;
 }
 
-// Sum over the W lanes of one vertex sub-problem (xor butterfly).
-template <int W>
-__device__ __forceinline__ float lane_sum_w(float v) {
-#pragma unroll
-    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
-    return v;
-}
+__device__ __forceinline__ float lane_sum(float v) { return lane_sum_w<LPV>(v); }
 
 // Whether free vertex f belongs to a body that is still iterating.
 __device__ __forceinline__ bool body_on(const SweepArgs& a, int f) {
@@ -457,50 +468,67 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     const bool in_range = idx < nidx;
     const int q = in_range ? a.cbase + idx : 0;
     const int vself = a.vid_c[q];
+    const int n = in_range ? a.incn_c[q] : 0;
+    // Everything that needs only the row index is fetched up front, together:
+    // this lane's first incidence entry (rows are padded to maxi entries, so
+    // the load is in bounds before n is known) and lane 0's own records, so
+    // that a lane waits on two levels of indirection (row -> corners ->
+    // positions), not on a chain of five.
+    int4 e0 = make_int4(-1, 0, 0, 0);
+    if (in_range && lane < a.maxi) e0 = a.inc4_c[(size_t)q * a.maxi + lane];
+    d4 uv = make_d4(0.0, 0.0, 0.0, 0.0), zv = uv;
+    float4 yv = make_float4(0.f, 0.f, 0.f, 0.f), rv = yv;
+    float mlin = 0.f;
+    if (in_range && lane == 0) {
+        uv = a.u[vself];
+        if (LIN) { yv = a.ly[vself]; rv = a.lrhs[vself]; mlin = a.mh2[vself]; }
+        else zv = a.zu[vself];
+    }
     const bool active = in_range && (LIN || a.body_on == nullptr || a.body_on[a.fbody_c[q]] != 0);
     if (!LIN && in_range && !active && lane == 0 && !a.in_place)
-        a.unext[vself] = a.u[vself];  // converged body in a Jacobi sweep: carried over unchanged
+        a.unext[vself] = uv;  // converged body in a Jacobi sweep: carried over unchanged
     float g[3] = {0.f, 0.f, 0.f}, A6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (active) {
-        const int n = a.incn_c[q];
-        for (int j = lane; j < n; j += W) {
-            const int4 e = a.inc4_c[(size_t)q * a.maxi + j];
-            const int c = e.x & 3;
-            Tet T;
-            load_tet_inc(a.tet, e, vself, T);
-            float H[9], cH[9], gn[3];
-            Kin<float> K;
-            dispgrad(a.u, T, H);
-            kinematics(H, K, cH);
-            gradN(T.D, c, gn);
-            if (LIN) {
-                float dY[9], dP[9];
-                dispgrad(a.ly, T, dY);
-                snh_dstress(K.F, K.C, 1.0f + K.Jm1, T.vmu, T.vlam, dY, dP);
+    auto tet_term = [&](const int4 e) {
+        const int c = e.x & 3;
+        Tet T;
+        load_tet_inc(a.tet, e, vself, T);
+        float H[9], cH[9], gn[3];
+        Kin<float> K;
+        dispgrad(a.u, T, H);
+        kinematics(H, K, cH);
+        gradN(T.D, c, gn);
+        if (LIN) {
+            float dY[9], dP[9];
+            dispgrad(a.ly, T, dY);
+            snh_dstress(K.F, K.C, 1.0f + K.Jm1, T.vmu, T.vlam, dY, dP);
 #pragma unroll
-                for (int i = 0; i < 3; ++i)
-                    g[i] += dP[3 * i] * gn[0] + dP[3 * i + 1] * gn[1] + dP[3 * i + 2] * gn[2];
-            } else {
-                float P[9];
-                snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
+            for (int i = 0; i < 3; ++i)
+                g[i] += dP[3 * i] * gn[0] + dP[3 * i + 1] * gn[1] + dP[3 * i + 2] * gn[2];
+        } else {
+            float P[9];
+            snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
 #pragma unroll
-                for (int i = 0; i < 3; ++i)
-                    g[i] += P[3 * i] * gn[0] + P[3 * i + 1] * gn[1] + P[3 * i + 2] * gn[2];
-            }
-            // own diagonal block: dP[e_d gn^T] : e_e gn^T.  The cofactor-derivative
-            // term is (e_e x e_d)^T F (gn x gn) = 0 here, leaving
-            // V mu |gn|^2 I + V lam (cof F gn)(cof F gn)^T
-            const float c0 = K.C[0] * gn[0] + K.C[1] * gn[1] + K.C[2] * gn[2];
-            const float c1 = K.C[3] * gn[0] + K.C[4] * gn[1] + K.C[5] * gn[2];
-            const float c2 = K.C[6] * gn[0] + K.C[7] * gn[1] + K.C[8] * gn[2];
-            const float mg = T.vmu * (gn[0] * gn[0] + gn[1] * gn[1] + gn[2] * gn[2]);
-            A6[0] += mg + T.vlam * c0 * c0;
-            A6[1] += T.vlam * c0 * c1;
-            A6[2] += T.vlam * c0 * c2;
-            A6[3] += mg + T.vlam * c1 * c1;
-            A6[4] += T.vlam * c1 * c2;
-            A6[5] += mg + T.vlam * c2 * c2;
+            for (int i = 0; i < 3; ++i)
+                g[i] += P[3 * i] * gn[0] + P[3 * i + 1] * gn[1] + P[3 * i + 2] * gn[2];
         }
+        // own diagonal block: dP[e_d gn^T] : e_e gn^T.  The cofactor-derivative
+        // term is (e_e x e_d)^T F (gn x gn) = 0 here, leaving
+        // V mu |gn|^2 I + V lam (cof F gn)(cof F gn)^T
+        const float c0 = K.C[0] * gn[0] + K.C[1] * gn[1] + K.C[2] * gn[2];
+        const float c1 = K.C[3] * gn[0] + K.C[4] * gn[1] + K.C[5] * gn[2];
+        const float c2 = K.C[6] * gn[0] + K.C[7] * gn[1] + K.C[8] * gn[2];
+        const float mg = T.vmu * (gn[0] * gn[0] + gn[1] * gn[1] + gn[2] * gn[2]);
+        A6[0] += mg + T.vlam * c0 * c0;
+        A6[1] += T.vlam * c0 * c1;
+        A6[2] += T.vlam * c0 * c2;
+        A6[3] += mg + T.vlam * c1 * c1;
+        A6[4] += T.vlam * c1 * c2;
+        A6[5] += mg + T.vlam * c2 * c2;
+    };
+    if (active) {
+        // lane l takes entries l, l + W, ... (the order of its partial sums)
+        if (lane < n) tet_term(e0);
+        for (int j = lane + W; j < n; j += W) tet_term(a.inc4_c[(size_t)q * a.maxi + j]);
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) g[i] = lane_sum_w<W>(g[i]);
@@ -509,12 +537,8 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     double gsq = 0.0;
     if (active && lane == 0) {
         const int v = vself;
-        const d4 uv = a.u[v];
-        float4 yv = make_float4(0.f, 0.f, 0.f, 0.f);
         if (LIN) {
-            const float4 rv = a.lrhs[v];
-            yv = a.ly[v];
-            const float m = a.mh2[v];
+            const float m = mlin;
             float Hb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, gb[3] = {0.f, 0.f, 0.f};
             barrier_terms(a, v, uv, gb, Hb);
             g[0] += m * yv.x - rv.x + Hb[0] * yv.x + Hb[1] * yv.y + Hb[2] * yv.z;
@@ -523,7 +547,6 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
             A6[0] += m + Hb[0]; A6[1] += Hb[1]; A6[2] += Hb[2];
             A6[3] += m + Hb[3]; A6[4] += Hb[4]; A6[5] += m + Hb[5];
         } else {
-            const d4 zv = a.zu[v];
             const float m = (float)zv.w;
             g[0] += m * (float)(uv.x - zv.x);
             g[1] += m * (float)(uv.y - zv.y);
