@@ -78,7 +78,9 @@ struct SweepArgs {
     int no_write;           // residual partials only, no update
     // bodies: a free vertex of a body whose residual reached rel_tol is skipped
     const int* fbody;       // [nVf] body of each free vertex
-    const int* body_on;     // [n_bodies] 1 while the body iterates (nullptr: all)
+    const int* body_on;     // [n_bodies] 1 while the body iterates (nullptr: all; the
+                            // plain forward sweep requires it)
+    int one_body;           // every free vertex is in body 0 (its flag is read once per wave)
 };
 
 }  // namespace jgs2

@@ -75,7 +75,7 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
     for (int i = 0; i < s->p.n_planes; ++i)
         for (int k = 0; k < 4; ++k) a.planes[i][k] = (float)s->p.planes[i][k];
     a.d_hat = (float)s->p.d_hat; a.kappa = (float)s->p.kappa;
-    a.fbody = s->d_fbody; a.body_on = s->d_body_on;
+    a.fbody = s->d_fbody; a.body_on = s->d_body_on; a.one_body = s->n_bodies == 1;
     for (int i = 0; i < s->p.n_planes; ++i)
         for (int k = 0; k < 4; ++k) a.planes_d[i][k] = s->p.planes[i][k];
 }

@@ -96,7 +96,11 @@ __device__ __forceinline__ void load_tet_inc(const float4* __restrict__ tet, int
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int q = (k - c0) & 3;
-        T.id[k] = q == 0 ? v : (q == 1 ? e.y : (q == 2 ? e.z : e.w));
+        int id = v;
+        id = q == 1 ? e.y : id;
+        id = q == 2 ? e.z : id;
+        id = q == 3 ? e.w : id;
+        T.id[k] = id;
     }
     T.D[0] = b.x; T.D[1] = b.y; T.D[2] = b.z; T.D[3] = b.w;
     T.D[4] = c.x; T.D[5] = c.y; T.D[6] = c.z; T.D[7] = c.w;
@@ -445,8 +449,9 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Plain per-vertex Newton relaxation, A_i = H_ii, fused in one pass; also
-// leaves per-block |b|^2 partials of the iterate it read.
+// Plain per-vertex Newton relaxation, A_i = H_ii, fused in one pass; in the
+// residual-only mode (no_write) it leaves per-block |b|^2 partials of the
+// iterate it read instead of updating it.
 // LIN = false: b_i = g_i, x_i <- x_i - omega H_ii^-1 g_i (forward sweep).
 // LIN = true : b_i = (H y - rhs)_i with H the Hessian at u (held fixed): a
 //              linear sweep on H y = rhs for the adjoint; the incident
@@ -455,7 +460,48 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
 // W lanes share a vertex (each takes every W-th incident tet), BLK threads
 // per block hold BLK / W vertices: the launch shapes the tuner chooses from.
 // ---------------------------------------------------------------------------
-template <bool LIN, int W, int BLK>
+// Terms of incidence e (own corner e.x & 3 is vertex v) for the plain and
+// linear sweeps, added with weight w (1 or 0: a zero weight keeps the
+// gathers unconditional): the element's share of g_v (or of (H y)_v) and of
+// the diagonal block H_vv.
+template <bool LIN>
+__device__ __forceinline__ void plain_tet_term(const SweepArgs& a, const int4 e, int v, float w, float* g, float* A6) {
+    const int c = e.x & 3;
+    Tet T;
+    load_tet_inc(a.tet, e, v, T);
+    float H[9], cH[9], gn[3], t[3];
+    Kin<float> K;
+    dispgrad(a.u, T, H);
+    kinematics(H, K, cH);
+    gradN(T.D, c, gn);
+    if (LIN) {
+        float dY[9], dP[9];
+        dispgrad(a.ly, T, dY);
+        snh_dstress(K.F, K.C, 1.0f + K.Jm1, T.vmu, T.vlam, dY, dP);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) t[i] = dP[3 * i] * gn[0] + dP[3 * i + 1] * gn[1] + dP[3 * i + 2] * gn[2];
+    } else {
+        float P[9];
+        snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) t[i] = P[3 * i] * gn[0] + P[3 * i + 1] * gn[1] + P[3 * i + 2] * gn[2];
+    }
+    // own diagonal block: dP[e_d gn^T] : e_e gn^T.  The cofactor-derivative
+    // term is (e_e x e_d)^T F (gn x gn) = 0 here, leaving
+    // V mu |gn|^2 I + V lam (cof F gn)(cof F gn)^T
+    const float c0 = K.C[0] * gn[0] + K.C[1] * gn[1] + K.C[2] * gn[2];
+    const float c1 = K.C[3] * gn[0] + K.C[4] * gn[1] + K.C[5] * gn[2];
+    const float c2 = K.C[6] * gn[0] + K.C[7] * gn[1] + K.C[8] * gn[2];
+    const float mg = T.vmu * (gn[0] * gn[0] + gn[1] * gn[1] + gn[2] * gn[2]);
+    const float h[6] = {mg + T.vlam * c0 * c0, T.vlam * c0 * c1, T.vlam * c0 * c2,
+                        mg + T.vlam * c1 * c1, T.vlam * c1 * c2, mg + T.vlam * c2 * c2};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) g[i] = fmaf(w, t[i], g[i]);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) A6[i] = fmaf(w, h[i], A6[i]);
+}
+
+template <bool LIN, int W, int BLK, bool SPEC>
 __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     constexpr int NV = BLK / W;
     const int lane = threadIdx.x % W;
@@ -467,73 +513,44 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     const int nidx = a.list ? a.n_list : a.nVf;
     const bool in_range = idx < nidx;
     const int q = in_range ? a.cbase + idx : 0;
+    // Everything that needs only the row index is fetched up front and
+    // without branches (q is a valid row even out of range; rows are padded
+    // to maxi entries): the row's count, this lane's first incidence entry
+    // and the vertex's own records.  SPEC (one body, or a linear sweep): the
+    // stop flag is the same for every row, and the first entry's tet record
+    // and corner positions are gathered by every lane before the flag or n is
+    // tested (padding reads tet 0 and vertex 0 and adds with weight 0), so a
+    // lane waits on two levels of indirection, row -> corners -> positions.
     const int vself = a.vid_c[q];
-    const int n = in_range ? a.incn_c[q] : 0;
-    // Everything that needs only the row index is fetched up front, together:
-    // this lane's first incidence entry (rows are padded to maxi entries, so
-    // the load is in bounds before n is known) and lane 0's own records, so
-    // that a lane waits on two levels of indirection (row -> corners ->
-    // positions), not on a chain of five.
-    int4 e0 = make_int4(-1, 0, 0, 0);
-    if (in_range && lane < a.maxi) e0 = a.inc4_c[(size_t)q * a.maxi + lane];
-    d4 uv = make_d4(0.0, 0.0, 0.0, 0.0), zv = uv;
+    const int n = a.incn_c[q];
+    const int4 e0 = SPEC ? a.inc4_c[(size_t)q * a.maxi + min(lane, a.maxi - 1)] : make_int4(0, 0, 0, 0);
+    const d4 uv = a.u[vself];
+    d4 zv = make_d4(0.0, 0.0, 0.0, 0.0);
     float4 yv = make_float4(0.f, 0.f, 0.f, 0.f), rv = yv;
     float mlin = 0.f;
-    if (in_range && lane == 0) {
-        uv = a.u[vself];
-        if (LIN) { yv = a.ly[vself]; rv = a.lrhs[vself]; mlin = a.mh2[vself]; }
-        else zv = a.zu[vself];
-    }
-    const bool active = in_range && (LIN || a.body_on == nullptr || a.body_on[a.fbody_c[q]] != 0);
-    if (!LIN && in_range && !active && lane == 0 && !a.in_place)
-        a.unext[vself] = uv;  // converged body in a Jacobi sweep: carried over unchanged
+    if (LIN) { yv = a.ly[vself]; rv = a.lrhs[vself]; mlin = a.mh2[vself]; }
+    else zv = a.zu[vself];
+    const int flag = LIN ? 1 : (SPEC ? a.body_on[0] : a.body_on[a.fbody_c[q]]);
+    const bool active = in_range & (flag != 0);
     float g[3] = {0.f, 0.f, 0.f}, A6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    auto tet_term = [&](const int4 e) {
-        const int c = e.x & 3;
-        Tet T;
-        load_tet_inc(a.tet, e, vself, T);
-        float H[9], cH[9], gn[3];
-        Kin<float> K;
-        dispgrad(a.u, T, H);
-        kinematics(H, K, cH);
-        gradN(T.D, c, gn);
-        if (LIN) {
-            float dY[9], dP[9];
-            dispgrad(a.ly, T, dY);
-            snh_dstress(K.F, K.C, 1.0f + K.Jm1, T.vmu, T.vlam, dY, dP);
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-                g[i] += dP[3 * i] * gn[0] + dP[3 * i + 1] * gn[1] + dP[3 * i + 2] * gn[2];
-        } else {
-            float P[9];
-            snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-                g[i] += P[3 * i] * gn[0] + P[3 * i + 1] * gn[1] + P[3 * i + 2] * gn[2];
-        }
-        // own diagonal block: dP[e_d gn^T] : e_e gn^T.  The cofactor-derivative
-        // term is (e_e x e_d)^T F (gn x gn) = 0 here, leaving
-        // V mu |gn|^2 I + V lam (cof F gn)(cof F gn)^T
-        const float c0 = K.C[0] * gn[0] + K.C[1] * gn[1] + K.C[2] * gn[2];
-        const float c1 = K.C[3] * gn[0] + K.C[4] * gn[1] + K.C[5] * gn[2];
-        const float c2 = K.C[6] * gn[0] + K.C[7] * gn[1] + K.C[8] * gn[2];
-        const float mg = T.vmu * (gn[0] * gn[0] + gn[1] * gn[1] + gn[2] * gn[2]);
-        A6[0] += mg + T.vlam * c0 * c0;
-        A6[1] += T.vlam * c0 * c1;
-        A6[2] += T.vlam * c0 * c2;
-        A6[3] += mg + T.vlam * c1 * c1;
-        A6[4] += T.vlam * c1 * c2;
-        A6[5] += mg + T.vlam * c2 * c2;
-    };
-    if (active) {
-        // lane l takes entries l, l + W, ... (the order of its partial sums)
-        if (lane < n) tet_term(e0);
-        for (int j = lane + W; j < n; j += W) tet_term(a.inc4_c[(size_t)q * a.maxi + j]);
+    // Lane l takes entries l, l + W, ... (the order of its partial sums).  The
+    // sums of an inactive row are never used, so with SPEC the first entry is
+    // added with a weight that needs only n.
+    int j0 = lane;
+    if constexpr (SPEC) {
+        const bool has = lane < n;
+        const int4 e = make_int4(has ? e0.x : 0, has ? e0.y : 0, has ? e0.z : 0, has ? e0.w : 0);
+        plain_tet_term<LIN>(a, e, vself, has ? 1.0f : 0.0f, g, A6);
+        j0 += W;
     }
+    if (active)
+        for (int j = j0; j < n; j += W) plain_tet_term<LIN>(a, a.inc4_c[(size_t)q * a.maxi + j], vself, 1.0f, g, A6);
 #pragma unroll
     for (int i = 0; i < 3; ++i) g[i] = lane_sum_w<W>(g[i]);
 #pragma unroll
     for (int i = 0; i < 6; ++i) A6[i] = lane_sum_w<W>(A6[i]);
+    if (!LIN && in_range && !active && lane == 0 && !a.in_place)
+        a.unext[vself] = uv;  // converged body in a Jacobi sweep: carried over unchanged
     double gsq = 0.0;
     if (active && lane == 0) {
         const int v = vself;
@@ -570,13 +587,13 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
             }
         }
     }
-    block_partial_t<NV, W>(gsq, active && lane == 0, a.partial);
+    if (a.no_write) block_partial_t<NV, W>(gsq, active && lane == 0, a.partial);  // uniform branch
 }
 
+template <int W, int BLK, bool SPEC>
+__global__ __launch_bounds__(BLK) void k_plain(SweepArgs a) { plain_body<false, W, BLK, SPEC>(a); }
 template <int W, int BLK>
-__global__ __launch_bounds__(BLK) void k_plain(SweepArgs a) { plain_body<false, W, BLK>(a); }
-template <int W, int BLK>
-__global__ __launch_bounds__(BLK) void k_linear(SweepArgs a) { plain_body<true, W, BLK>(a); }
+__global__ __launch_bounds__(BLK) void k_linear(SweepArgs a) { plain_body<true, W, BLK, true>(a); }
 
 // thetabar_t -= sum_c y_c . (V_t P(F_t) grad N_c) at the displacement u:
 // the derivative of the step's optimality condition with respect to
@@ -857,8 +874,10 @@ static void launch_plain_t(jgs2_solver* s, const SweepArgs& a) {
     if (nb == 0) return;
     if (LIN)
         launch(s, JGS2_K_LINEAR, k_linear<W, BLK>, dim3(nb), dim3(BLK), a);
+    else if (a.one_body)
+        launch(s, JGS2_K_PLAIN, k_plain<W, BLK, true>, dim3(nb), dim3(BLK), a);
     else
-        launch(s, JGS2_K_PLAIN, k_plain<W, BLK>, dim3(nb), dim3(BLK), a);
+        launch(s, JGS2_K_PLAIN, k_plain<W, BLK, false>, dim3(nb), dim3(BLK), a);
 }
 
 template <bool LIN, int W>
