@@ -250,6 +250,25 @@ __device__ __forceinline__ void block_partial(double val, bool lane0, double* pa
 // volume-weighted mean deformation gradient of the incident tets and its
 // polar rotation R_a; per-block partial sums of |g|^2 (FP64).
 // ---------------------------------------------------------------------------
+// One incident tet's share of g_v and of the volume-weighted F sum, added
+// with weight w (own corner e.x & 3 is vertex v).
+__device__ __forceinline__ void phase1_term(const SweepArgs& a, const int4 e, int v, float w, float* g, float* Fs) {
+    const int c = e.x & 3;
+    Tet T;
+    load_tet_inc(a.tet, e, v, T);
+    float H[9], cH[9], P[9], gn[3];
+    Kin<float> K;
+    dispgrad(a.u, T, H);
+    kinematics(H, K, cH);
+    snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
+    gradN(T.D, c, gn);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) g[i] = fmaf(w, P[3 * i] * gn[0] + P[3 * i + 1] * gn[1] + P[3 * i + 2] * gn[2], g[i]);
+    const float wv = w * T.vol;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Fs[i] = fmaf(wv, K.F[i], Fs[i]);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_phase1(SweepArgs a, int want_R) {
     const int lane = threadIdx.x % LPV;
     const int vloc = threadIdx.x / LPV;
@@ -258,26 +277,22 @@ __global__ __launch_bounds__(BLOCK) void k_phase1(SweepArgs a, int want_R) {
     const int nidx = a.list ? a.n_list : a.nVf;
     const bool active = idx < nidx;
     const int f = active ? (a.list ? a.list[idx] : idx) : 0;
+    // Row-level loads first and without branches (f is a valid row even out
+    // of range; rows are padded to maxi entries); every lane then gathers its
+    // first incident tet before n is tested (padding reads tet 0 and vertex 0
+    // and adds with weight 0), so a lane waits on row -> corners -> positions.
+    const int v = a.free_ids[f];
+    const int n = a.inc_n[f];
+    const int4 e0 = a.inc4[(size_t)f * a.maxi + min(lane, a.maxi - 1)];
+    const d4 uv = a.u[v], zv = a.zu[v];
     float g[3] = {0.f, 0.f, 0.f}, Fs[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (active) {
-        const int n = a.inc_n[f];
-        for (int j = lane; j < n; j += LPV) {
-            const int pk = a.inc[(size_t)f * a.maxi + j];
-            const int t = pk >> 2, c = pk & 3;
-            Tet T;
-            load_tet(a.tet, t, T);
-            float H[9], cH[9], P[9], gn[3];
-            Kin<float> K;
-            dispgrad(a.u, T, H);
-            kinematics(H, K, cH);
-            snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
-            gradN(T.D, c, gn);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) g[i] += P[3 * i] * gn[0] + P[3 * i + 1] * gn[1] + P[3 * i + 2] * gn[2];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) Fs[i] += T.vol * K.F[i];
-        }
+    {
+        const bool has = lane < n;
+        const int4 e = make_int4(has ? e0.x : 0, has ? e0.y : 0, has ? e0.z : 0, has ? e0.w : 0);
+        phase1_term(a, e, v, has ? 1.0f : 0.0f, g, Fs);
     }
+    if (active)
+        for (int j = lane + LPV; j < n; j += LPV) phase1_term(a, a.inc4[(size_t)f * a.maxi + j], v, 1.0f, g, Fs);
 #pragma unroll
     for (int i = 0; i < 3; ++i) g[i] = lane_sum(g[i]);
     if (want_R) {
@@ -286,8 +301,6 @@ __global__ __launch_bounds__(BLOCK) void k_phase1(SweepArgs a, int want_R) {
     }
     double gsq = 0.0;
     if (active && lane == 0) {
-        const int v = a.free_ids[f];
-        const d4 uv = a.u[v], zv = a.zu[v];
         const float m = (float)zv.w;
         g[0] += m * (float)(uv.x - zv.x);
         g[1] += m * (float)(uv.y - zv.y);
