@@ -471,18 +471,20 @@ def measured_traffic(kernel, workload_tag):
 
 def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches=1):
     """Compulsory (algorithmic) bytes moved by one launch of a sweep kernel,
-    counting every datum it must touch once: tet records 80 B, incidence
-    entries 4 B (plus 4 B slot words in phase 2), one-ring ids + U-bar rows
-    40 B per entry, 168 B per cubature sample, 32 B FP64 displacement and
-    inertial-target records, 16 B gradient and rotation records."""
+    counting every datum it must touch once: tet records 80 B (64 B without
+    the id word), incidence entries 4 B or 16 B with corner ids (plus 4 B
+    slot words in phase 2), 64 B incidence records of the plain sweeps,
+    one-ring ids + U-bar rows 40 B per entry, 168 B per cubature sample, 32 B
+    FP64 displacement and inertial-target records, 16 B gradient and rotation
+    records."""
     if kind == "phase1":      # positions; z read, g and R written per free vertex
-        return 80.0 * T + 4.0 * n_inc + 64.0 * Vf + 32.0 * V
+        return 64.0 * T + 16.0 * n_inc + 64.0 * Vf + 32.0 * V
     if kind == "phase2":      # positions, g, R of every vertex; own record, samples, update
         return 80.0 * T + 8.0 * n_inc + 40.0 * ring_entries + Vf * (40.0 + 168.0 * S) + 64.0 * V
-    if kind == "plain_jacobi":  # 64 B records (no id word), 16 B incidences with corner ids
-        return 64.0 * T + 16.0 * n_inc + 64.0 * Vf + 32.0 * V
-    if kind == "plain_gs_sweep":  # all colour launches of one sweep; a tet is read once per incident corner
-        return 80.0 * n_inc + 64.0 * Vf + 32.0 * V * n_colors
+    if kind == "plain_jacobi":  # one 64 B incidence record per (free vertex, incident tet)
+        return 64.0 * n_inc + 64.0 * Vf + 32.0 * V
+    if kind == "plain_gs_sweep":  # all colour launches of one sweep; positions read once per colour
+        return 64.0 * n_inc + 64.0 * Vf + 32.0 * V * n_colors
     raise ValueError(kind)
 
 

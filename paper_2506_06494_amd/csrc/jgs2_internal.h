@@ -34,6 +34,11 @@ constexpr uint8_t SLOT_NONE = 0xFF;
 
 // Tet record: 5 x float4 = ids(bitcast) | Dm^-1 (9) | vol | V mu | V lam | rho V / (4 h^2)
 constexpr int TET_F4 = 5;
+// Incidence record of the plain and linear sweeps, one per (free vertex, incident tet):
+// Dm^-1 (9) | V mu | V lam | own corner c (bitcast) | the tet's 4 corner ids (bitcast),
+// as 4 float4 planes; rows in colour order, padded with zero records to maxi entries.
+// Plane k of entry j of row q is at [(q * IREC_F4 + k) * maxi + j].
+constexpr int IREC_F4 = 4;
 
 struct SweepArgs {
     int nV, nVf, maxi, K, S;
@@ -44,7 +49,7 @@ struct SweepArgs {
     const int* inc;         // [nVf * maxi] packed (tet << 2 | corner), -1 pad
     const int4* inc4;       // [nVf * maxi] (tet << 2 | corner c, ids of corners c+1, c+2, c+3 mod 4)
     // the plain sweep's rows in colour order (position q = rank in the colour permutation)
-    const int4* inc4_c;     // [nVf * maxi]
+    const float4* irec_c;   // [nVf * IREC_F4 * maxi] incidence records
     const int* incn_c;      // [nVf]
     const int* vid_c;       // [nVf] vertex id
     const int* fbody_c;     // [nVf] body
@@ -124,7 +129,7 @@ struct jgs2_solver {
     float* d_mh2 = nullptr;
     int *d_free = nullptr, *d_inc = nullptr, *d_inc_n = nullptr, *d_ring = nullptr, *d_ring_n = nullptr;
     int4* d_inc4 = nullptr;
-    int4* d_inc4_c = nullptr;
+    float4* d_irec_c = nullptr;
     int *d_incn_c = nullptr, *d_vid_c = nullptr, *d_fbody_c = nullptr;
     uint32_t* d_incslot = nullptr;
     int* d_colperm = nullptr;

@@ -29,7 +29,7 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_tet); dfree(s->d_X); dfree(s->d_u); dfree(s->d_unext); dfree(s->d_uhat); dfree(s->d_vhat);
     dfree(s->d_zu); dfree(s->d_mh2); dfree(s->d_g); dfree(s->d_R); dfree(s->d_free); dfree(s->d_inc);
     dfree(s->d_inc_n); dfree(s->d_ring); dfree(s->d_ring_n); dfree(s->d_incslot); dfree(s->d_colperm);
-    dfree(s->d_inc4); dfree(s->d_inc4_c); dfree(s->d_incn_c); dfree(s->d_vid_c); dfree(s->d_fbody_c);
+    dfree(s->d_inc4); dfree(s->d_irec_c); dfree(s->d_incn_c); dfree(s->d_vid_c); dfree(s->d_fbody_c);
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
     dfree(s->d_ck_u); dfree(s->d_ck_v); dfree(s->d_seg); dfree(s->d_y); dfree(s->d_ynext); dfree(s->d_xbar);
     dfree(s->d_vbar); dfree(s->d_rhs); dfree(s->d_thbar);
@@ -67,7 +67,7 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
     a.nV = s->nV; a.nVf = s->nVf; a.maxi = s->maxi; a.K = s->K; a.S = s->have_corr ? s->S : 0;
     a.free_ids = s->d_free; a.list = nullptr; a.n_list = 0;
     a.tet = s->d_tet; a.inc = s->d_inc; a.inc4 = s->d_inc4; a.incslot = s->d_incslot; a.inc_n = s->d_inc_n;
-    a.inc4_c = s->d_inc4_c; a.incn_c = s->d_incn_c; a.vid_c = s->d_vid_c; a.fbody_c = s->d_fbody_c; a.cbase = 0;
+    a.irec_c = s->d_irec_c; a.incn_c = s->d_incn_c; a.vid_c = s->d_vid_c; a.fbody_c = s->d_fbody_c; a.cbase = 0;
     a.ring = s->d_ring; a.ring_n = s->d_ring_n; a.Uring = s->d_Uring; a.samp_e = s->d_samp_e; a.samp = s->d_samp;
     a.X = s->d_X; a.u = s->d_u; a.unext = s->d_unext; a.zu = s->d_zu; a.g = s->d_g; a.R = s->d_R;
     a.partial = s->d_partial; a.omega = (float)s->p.omega; a.in_place = 0;
@@ -181,6 +181,35 @@ static float bits_as_float(int i) {
     float f;
     std::memcpy(&f, &i, sizeof(f));
     return f;
+}
+
+// Incidence records of the plain and linear sweeps (rows in colour order,
+// zero-padded to maxi entries) from the current material.
+static int upload_incidence_records(jgs2_solver* s) {
+    const size_t nf = s->nVf, mi = s->maxi;
+    std::vector<float4> rec(nf * IREC_F4 * mi, make_float4(0.f, 0.f, 0.f, 0.f));
+    for (size_t q = 0; q < nf; ++q) {
+        const int f = s->col_perm[q];
+        for (int j = 0; j < s->inc_n[f]; ++j) {
+            const int pk = s->inc[(size_t)f * mi + j];
+            const int t = pk >> 2, c = pk & 3;
+            const double E = s->E[t], nu = s->nu[t];
+            const double mu_l = E / (2.0 * (1.0 + nu));
+            const double lam_l = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+            const double mu = mu_l, lam = lam_l + mu_l;
+            const double V = s->vol[t];
+            const double* D = &s->Dm_inv[9 * (size_t)t];
+            float4* r = &rec[q * IREC_F4 * mi + j];
+            r[0] = make_float4((float)D[0], (float)D[1], (float)D[2], (float)D[3]);
+            r[mi] = make_float4((float)D[4], (float)D[5], (float)D[6], (float)D[7]);
+            r[2 * mi] = make_float4((float)D[8], (float)(V * mu), (float)(V * lam), bits_as_float(c));
+            r[3 * mi] = make_float4(bits_as_float(s->tets[4 * t]), bits_as_float(s->tets[4 * t + 1]),
+                                    bits_as_float(s->tets[4 * t + 2]), bits_as_float(s->tets[4 * t + 3]));
+        }
+    }
+    int r = upload(s, s->d_irec_c, rec.data(), rec.size());
+    if (r != JGS2_OK) return r;
+    return jgs2::hip_check(s, hipStreamSynchronize(s->stream), "upload incidence records");
 }
 
 // Per-tet device record and per-vertex m/h^2 from the current material and dt.
@@ -443,19 +472,15 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
         (r = upload(s, s->d_colperm, s->col_perm.data(), nf)) || (r = upload(s, s->d_inc4, s->inc4.data(), nf * s->maxi)))
         return r;
     {
-        std::vector<int4> inc4c(nf * s->maxi);
         std::vector<int> incnc(nf), vidc(nf);
         for (size_t q = 0; q < nf; ++q) {
             const int f = s->col_perm[q];
-            std::copy(s->inc4.begin() + (size_t)f * s->maxi, s->inc4.begin() + (size_t)(f + 1) * s->maxi,
-                      inc4c.begin() + q * s->maxi);
             incnc[q] = s->inc_n[f];
             vidc[q] = s->free_ids[f];
         }
-        if ((r = dalloc(s, s->d_inc4_c, nf * s->maxi)) || (r = dalloc(s, s->d_incn_c, nf)) ||
+        if ((r = dalloc(s, s->d_irec_c, nf * IREC_F4 * s->maxi)) || (r = dalloc(s, s->d_incn_c, nf)) ||
             (r = dalloc(s, s->d_vid_c, nf)) || (r = dalloc(s, s->d_fbody_c, nf)) ||
-            (r = upload(s, s->d_inc4_c, inc4c.data(), nf * s->maxi)) || (r = upload(s, s->d_incn_c, incnc.data(), nf)) ||
-            (r = upload(s, s->d_vid_c, vidc.data(), nf)))
+            (r = upload(s, s->d_incn_c, incnc.data(), nf)) || (r = upload(s, s->d_vid_c, vidc.data(), nf)))
             return r;
     }
     for (d4* d : {s->d_u, s->d_unext, s->d_uhat, s->d_zu}) HIPCHK(hipMemsetAsync(d, 0, V4 * sizeof(d4), s->stream));
@@ -485,6 +510,7 @@ int32_t jgs2_set_material(jgs2_solver* s, const double* E, const double* nu, con
         for (int c = 0; c < 4; ++c) s->mass[s->tets[4 * t + c]] += rho[t] * s->vol[t] / 4.0;
     int r = upload_material_records(s);
     if (r != JGS2_OK) return r;
+    if ((r = upload_incidence_records(s)) != JGS2_OK) return r;
     s->have_material = true;
     s->have_corr = false;
     s->ro_valid = false;

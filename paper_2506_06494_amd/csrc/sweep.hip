@@ -473,15 +473,24 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
 // W lanes share a vertex (each takes every W-th incident tet), BLK threads
 // per block hold BLK / W vertices: the launch shapes the tuner chooses from.
 // ---------------------------------------------------------------------------
-// Terms of incidence e (own corner e.x & 3 is vertex v) for the plain and
-// linear sweeps, added with weight w (1 or 0: a zero weight keeps the
-// gathers unconditional): the element's share of g_v (or of (H y)_v) and of
-// the diagonal block H_vv.
+// Terms of one incidence (tet T, own corner c) for the plain and linear
+// sweeps, added with weight w (1 or 0: a zero weight keeps the gathers
+// unconditional): the element's share of g_v (or of (H y)_v) and of the
+// diagonal block H_vv.
+// Incidence record (planes stride apart): the tet's Dm^-1, V mu, V lam and
+// corner ids, and the own corner c.
+__device__ __forceinline__ void load_irec(const float4* __restrict__ r, int stride, Tet& T, int& c) {
+    const float4 p0 = r[0], p1 = r[stride], p2 = r[2 * stride], p3 = r[3 * stride];
+    T.D[0] = p0.x; T.D[1] = p0.y; T.D[2] = p0.z; T.D[3] = p0.w;
+    T.D[4] = p1.x; T.D[5] = p1.y; T.D[6] = p1.z; T.D[7] = p1.w;
+    T.D[8] = p2.x; T.vmu = p2.y; T.vlam = p2.z; c = __float_as_int(p2.w);
+    T.id[0] = __float_as_int(p3.x); T.id[1] = __float_as_int(p3.y);
+    T.id[2] = __float_as_int(p3.z); T.id[3] = __float_as_int(p3.w);
+    T.vol = 0.0f; T.mi = 0.0f;
+}
+
 template <bool LIN>
-__device__ __forceinline__ void plain_tet_term(const SweepArgs& a, const int4 e, int v, float w, float* g, float* A6) {
-    const int c = e.x & 3;
-    Tet T;
-    load_tet_inc(a.tet, e, v, T);
+__device__ __forceinline__ void plain_tet_term(const SweepArgs& a, const Tet& T, int c, float w, float* g, float* A6) {
     float H[9], cH[9], gn[3], t[3];
     Kin<float> K;
     dispgrad(a.u, T, H);
@@ -528,15 +537,18 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     const int q = in_range ? a.cbase + idx : 0;
     // Everything that needs only the row index is fetched up front and
     // without branches (q is a valid row even out of range; rows are padded
-    // to maxi entries): the row's count, this lane's first incidence entry
-    // and the vertex's own records.  SPEC (one body, or a linear sweep): the
-    // stop flag is the same for every row, and the first entry's tet record
-    // and corner positions are gathered by every lane before the flag or n is
-    // tested (padding reads tet 0 and vertex 0 and adds with weight 0), so a
-    // lane waits on two levels of indirection, row -> corners -> positions.
+    // to maxi entries): the row's count, this lane's first incidence record
+    // (contiguous across the lanes of a row) and the vertex's own records.
+    // SPEC (one body, or a linear sweep): the stop flag is the same for every
+    // row, and the first record's corner positions are gathered by every lane
+    // before the flag or n is tested (zero records name vertex 0 and add with
+    // weight 0), so a lane waits on two levels: records -> positions.
     const int vself = a.vid_c[q];
     const int n = a.incn_c[q];
-    const int4 e0 = SPEC ? a.inc4_c[(size_t)q * a.maxi + min(lane, a.maxi - 1)] : make_int4(0, 0, 0, 0);
+    const float4* row = a.irec_c + (size_t)q * IREC_F4 * a.maxi;
+    Tet T0;
+    int c0 = 0;
+    if constexpr (SPEC) load_irec(row + min(lane, a.maxi - 1), a.maxi, T0, c0);
     const d4 uv = a.u[vself];
     d4 zv = make_d4(0.0, 0.0, 0.0, 0.0);
     float4 yv = make_float4(0.f, 0.f, 0.f, 0.f), rv = yv;
@@ -551,13 +563,17 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     // added with a weight that needs only n.
     int j0 = lane;
     if constexpr (SPEC) {
-        const bool has = lane < n;
-        const int4 e = make_int4(has ? e0.x : 0, has ? e0.y : 0, has ? e0.z : 0, has ? e0.w : 0);
-        plain_tet_term<LIN>(a, e, vself, has ? 1.0f : 0.0f, g, A6);
+        // entries past n are zero records or a repeat of the row's last one
+        plain_tet_term<LIN>(a, T0, c0, lane < n ? 1.0f : 0.0f, g, A6);
         j0 += W;
     }
     if (active)
-        for (int j = j0; j < n; j += W) plain_tet_term<LIN>(a, a.inc4_c[(size_t)q * a.maxi + j], vself, 1.0f, g, A6);
+        for (int j = j0; j < n; j += W) {
+            Tet T;
+            int c;
+            load_irec(row + j, a.maxi, T, c);
+            plain_tet_term<LIN>(a, T, c, 1.0f, g, A6);
+        }
 #pragma unroll
     for (int i = 0; i < 3; ++i) g[i] = lane_sum_w<W>(g[i]);
 #pragma unroll

@@ -117,7 +117,7 @@ def test_bench_byte_accounting_and_traffic_parser(tmp_path, monkeypatch):
     # every incidence of a free vertex, summed over the free vertices
     assert cnt["n_inc"] == np.bincount(m.tets.ravel(), minlength=m.nV)[~m.pinned.astype(bool)].sum()
     gs = bench.sweep_bytes("plain_gs_sweep", **cnt, n_colors=8)
-    assert gs == 80 * cnt["n_inc"] + 64 * 400 + 32 * 425 * 8
+    assert gs == 64 * cnt["n_inc"] + 64 * 400 + 32 * 425 * 8
     prof = tmp_path / "profiles"
     prof.mkdir()
     (prof / "pmc_traffic.md").write_text(
