@@ -146,6 +146,14 @@ int32_t jgs2_get_body_stats(jgs2_solver* s, int32_t* n_bodies, int32_t* sweeps, 
  * order of the per-vertex sums.  Default 32 x 256. */
 int32_t jgs2_set_tuning(jgs2_solver* s, int32_t lanes_per_vertex, int32_t block);
 int32_t jgs2_get_tuning(jgs2_solver* s, int32_t* lanes_per_vertex, int32_t* block);
+/* Cache hint for the incidence records the plain and linear sweeps read (one
+ * 64-byte record per free vertex and incident tet, read once per sweep):
+ * mode 1 streams them with non-temporal loads, which keeps the reused vertex
+ * records in L2 when the records outgrow the cache; 0 uses ordinary loads;
+ * -1 (default) streams them once they exceed 128 MiB, half of the last-level
+ * cache.  Results are bitwise the same in every mode.  Errors: JGS2_E_INVALID
+ * for any other mode. */
+int32_t jgs2_set_streaming(jgs2_solver* s, int32_t mode);
 /* Times `sweeps` sweeps of the first step from the current state in every
  * launch shape (HIP events), keeps the fastest and reports it; the state is
  * left unchanged.  ms (16 entries, may be NULL) receives each shape's time in

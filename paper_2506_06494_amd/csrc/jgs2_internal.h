@@ -50,6 +50,7 @@ struct SweepArgs {
     const int4* inc4;       // [nVf * maxi] (tet << 2 | corner c, ids of corners c+1, c+2, c+3 mod 4)
     // the plain sweep's rows in colour order (position q = rank in the colour permutation)
     const float4* irec_c;   // [nVf * IREC_F4 * maxi] incidence records
+    int nt_records;         // stream the records (non-temporal loads): they outgrow the cache
     const int* incn_c;      // [nVf]
     const int* vid_c;       // [nVf] vertex id
     const int* fbody_c;     // [nVf] body
@@ -175,6 +176,7 @@ struct jgs2_solver {
     int n_active = 0;
     // launch shape of the plain / linear sweep kernels
     int tune_lpv = 32, tune_block = 256;
+    int stream_mode = -1;  // incidence records: -1 auto (> 128 MiB), 0 cached, 1 streamed
     // captured sweep groups (k sweeps + residual check) per Jacobi parity
     hipStream_t own_stream = nullptr;
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};

@@ -67,6 +67,10 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
     a.nV = s->nV; a.nVf = s->nVf; a.maxi = s->maxi; a.K = s->K; a.S = s->have_corr ? s->S : 0;
     a.free_ids = s->d_free; a.list = nullptr; a.n_list = 0;
     a.tet = s->d_tet; a.inc = s->d_inc; a.inc4 = s->d_inc4; a.incslot = s->d_incslot; a.inc_n = s->d_inc_n;
+    // records beyond half of the 256 MB last-level cache are streamed
+    a.nt_records = s->stream_mode >= 0
+                       ? s->stream_mode
+                       : (double)s->nVf * s->maxi * IREC_F4 * sizeof(float4) > 128.0 * 1024 * 1024;
     a.irec_c = s->d_irec_c; a.incn_c = s->d_incn_c; a.vid_c = s->d_vid_c; a.fbody_c = s->d_fbody_c; a.cbase = 0;
     a.ring = s->d_ring; a.ring_n = s->d_ring_n; a.Uring = s->d_Uring; a.samp_e = s->d_samp_e; a.samp = s->d_samp;
     a.X = s->d_X; a.u = s->d_u; a.unext = s->d_unext; a.zu = s->d_zu; a.g = s->d_g; a.R = s->d_R;
@@ -1514,6 +1518,14 @@ int32_t jgs2_set_tuning(jgs2_solver* s, int32_t lanes_per_vertex, int32_t block)
     s->tune_lpv = lanes_per_vertex;
     s->tune_block = block;
     drop_graphs(s);
+    return JGS2_OK;
+}
+
+int32_t jgs2_set_streaming(jgs2_solver* s, int32_t mode) {
+    if (!s) return JGS2_E_INVALID;
+    if (mode < -1 || mode > 1) return s->fail(JGS2_E_INVALID, "streaming mode must be -1, 0 or 1");
+    s->stream_mode = mode;
+    drop_graphs(s);  // captured launches hold the kernel variant
     return JGS2_OK;
 }
 

@@ -477,10 +477,26 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
 // sweeps, added with weight w (1 or 0: a zero weight keeps the gathers
 // unconditional): the element's share of g_v (or of (H y)_v) and of the
 // diagonal block H_vv.
+// 16-byte load marked non-temporal (streamed data, read once).
+__device__ __forceinline__ float4 load_nt(const float4* p) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // Incidence record (planes stride apart): the tet's Dm^-1, V mu, V lam and
 // corner ids, and the own corner c.
+template <bool NT>
 __device__ __forceinline__ void load_irec(const float4* __restrict__ r, int stride, Tet& T, int& c) {
-    const float4 p0 = r[0], p1 = r[stride], p2 = r[2 * stride], p3 = r[3 * stride];
+    // each record is read once per sweep; when the records outgrow the
+    // last-level cache (NT) they are streamed (non-temporal), which keeps the
+    // reused corner positions resident
+    float4 p0, p1, p2, p3;
+    if constexpr (NT) {
+        p0 = load_nt(r); p1 = load_nt(r + stride); p2 = load_nt(r + 2 * stride); p3 = load_nt(r + 3 * stride);
+    } else {
+        p0 = r[0]; p1 = r[stride]; p2 = r[2 * stride]; p3 = r[3 * stride];
+    }
     T.D[0] = p0.x; T.D[1] = p0.y; T.D[2] = p0.z; T.D[3] = p0.w;
     T.D[4] = p1.x; T.D[5] = p1.y; T.D[6] = p1.z; T.D[7] = p1.w;
     T.D[8] = p2.x; T.vmu = p2.y; T.vlam = p2.z; c = __float_as_int(p2.w);
@@ -523,7 +539,7 @@ __device__ __forceinline__ void plain_tet_term(const SweepArgs& a, const Tet& T,
     for (int i = 0; i < 6; ++i) A6[i] = fmaf(w, h[i], A6[i]);
 }
 
-template <bool LIN, int W, int BLK, bool SPEC>
+template <bool LIN, int W, int BLK, bool SPEC, bool NT>
 __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     constexpr int NV = BLK / W;
     const int lane = threadIdx.x % W;
@@ -548,7 +564,7 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     const float4* row = a.irec_c + (size_t)q * IREC_F4 * a.maxi;
     Tet T0;
     int c0 = 0;
-    if constexpr (SPEC) load_irec(row + min(lane, a.maxi - 1), a.maxi, T0, c0);
+    if constexpr (SPEC) load_irec<NT>(row + min(lane, a.maxi - 1), a.maxi, T0, c0);
     const d4 uv = a.u[vself];
     d4 zv = make_d4(0.0, 0.0, 0.0, 0.0);
     float4 yv = make_float4(0.f, 0.f, 0.f, 0.f), rv = yv;
@@ -571,7 +587,7 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
         for (int j = j0; j < n; j += W) {
             Tet T;
             int c;
-            load_irec(row + j, a.maxi, T, c);
+            load_irec<NT>(row + j, a.maxi, T, c);
             plain_tet_term<LIN>(a, T, c, 1.0f, g, A6);
         }
 #pragma unroll
@@ -619,10 +635,10 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     if (a.no_write) block_partial_t<NV, W>(gsq, active && lane == 0, a.partial);  // uniform branch
 }
 
-template <int W, int BLK, bool SPEC>
-__global__ __launch_bounds__(BLK) void k_plain(SweepArgs a) { plain_body<false, W, BLK, SPEC>(a); }
-template <int W, int BLK>
-__global__ __launch_bounds__(BLK) void k_linear(SweepArgs a) { plain_body<true, W, BLK, true>(a); }
+template <int W, int BLK, bool SPEC, bool NT>
+__global__ __launch_bounds__(BLK) void k_plain(SweepArgs a) { plain_body<false, W, BLK, SPEC, NT>(a); }
+template <int W, int BLK, bool NT>
+__global__ __launch_bounds__(BLK) void k_linear(SweepArgs a) { plain_body<true, W, BLK, true, NT>(a); }
 
 // thetabar_t -= sum_c y_c . (V_t P(F_t) grad N_c) at the displacement u:
 // the derivative of the step's optimality condition with respect to
@@ -901,12 +917,17 @@ static void launch_plain_t(jgs2_solver* s, const SweepArgs& a) {
     const int n = a.list ? a.n_list : a.nVf;
     const int nb = (n + NV - 1) / NV;
     if (nb == 0) return;
-    if (LIN)
-        launch(s, JGS2_K_LINEAR, k_linear<W, BLK>, dim3(nb), dim3(BLK), a);
-    else if (a.one_body)
-        launch(s, JGS2_K_PLAIN, k_plain<W, BLK, true>, dim3(nb), dim3(BLK), a);
-    else
-        launch(s, JGS2_K_PLAIN, k_plain<W, BLK, false>, dim3(nb), dim3(BLK), a);
+    const dim3 g(nb), b(BLK);
+    if (LIN) {
+        if (a.nt_records) launch(s, JGS2_K_LINEAR, k_linear<W, BLK, true>, g, b, a);
+        else launch(s, JGS2_K_LINEAR, k_linear<W, BLK, false>, g, b, a);
+    } else if (a.one_body) {
+        if (a.nt_records) launch(s, JGS2_K_PLAIN, k_plain<W, BLK, true, true>, g, b, a);
+        else launch(s, JGS2_K_PLAIN, k_plain<W, BLK, true, false>, g, b, a);
+    } else {
+        if (a.nt_records) launch(s, JGS2_K_PLAIN, k_plain<W, BLK, false, true>, g, b, a);
+        else launch(s, JGS2_K_PLAIN, k_plain<W, BLK, false, false>, g, b, a);
+    }
 }
 
 template <bool LIN, int W>

@@ -47,7 +47,7 @@ EXPORTS = ["jgs2_default_params", "jgs2_create", "jgs2_destroy", "jgs2_last_erro
            "jgs2_set_state", "jgs2_get_state", "jgs2_step", "jgs2_begin_step", "jgs2_iterate", "jgs2_end_step",
            "jgs2_residual", "jgs2_energy", "jgs2_get_phase1", "jgs2_get_coloring", "jgs2_set_profiling",
            "jgs2_kernel_times", "jgs2_rollout", "jgs2_rollout_backward", "jgs2_set_bodies", "jgs2_get_body_stats",
-           "jgs2_set_tuning", "jgs2_get_tuning", "jgs2_autotune"]
+           "jgs2_set_tuning", "jgs2_get_tuning", "jgs2_autotune", "jgs2_set_streaming"]
 
 KERNELS = ["phase1", "phase2", "plain", "commit", "reduce", "predict", "velocity", "energy", "linear", "paramgrad",
            "adjvec"]
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH):
         "jgs2_get_body_stats": (C.c_int32, [C.c_void_p, i32, i32, d]),
         "jgs2_set_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
         "jgs2_get_tuning": (C.c_int32, [C.c_void_p, i32, i32]),
+        "jgs2_set_streaming": (C.c_int32, [C.c_void_p, C.c_int32]),
         "jgs2_autotune": (C.c_int32, [C.c_void_p, C.c_int32, i32, i32, d]),
     }
     for name, (res, args) in sig.items():
@@ -305,6 +306,10 @@ class Solver:
 
     def set_tuning(self, lanes_per_vertex, block):
         self._chk(self.lib.jgs2_set_tuning(self.h, int(lanes_per_vertex), int(block)))
+
+    def set_streaming(self, mode):
+        """-1 auto, 0 cached, 1 streamed incidence records (cache hint only)."""
+        self._chk(self.lib.jgs2_set_streaming(self.h, int(mode)))
 
     def tuning(self):
         a, b = C.c_int32(), C.c_int32()

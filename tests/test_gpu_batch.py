@@ -131,3 +131,27 @@ def test_body_errors():
         s.set_bodies(np.arange(m.nV) % 2)          # tets would span two bodies
     with pytest.raises(jgs2.JGS2Error):
         s.set_tuning(3, 256)
+
+
+@pytest.mark.parametrize("bodies", [False, True])
+def test_streamed_records_are_bitwise_cached(bodies):
+    """Streaming the incidence records (non-temporal loads) is a cache hint
+    only: two steps with it forced on, forced off and on the automatic
+    setting agree bit for bit, for one body and for batched bodies."""
+    parts = beam_parts()
+    out = []
+    for mode in (0, 1, -1):
+        if bodies:
+            s, _ = batched(parts, order=jgs2.GS, omega=1.5, use_graph=1)
+        else:
+            m, E, nu, v0 = parts[0]
+            s = solver_for(m, E, nu, order=jgs2.GS, omega=1.5, use_graph=1)
+            s.set_state(m.X, v0)
+        s.set_streaming(mode)
+        stats = [s.step() for _ in range(2)]
+        out.append((s.get_state(), [st["sweeps"] for st in stats]))
+    (x0, v0), sw0 = out[0]
+    for (x, v), sw in out[1:]:
+        assert np.array_equal(x, x0) and np.array_equal(v, v0) and sw == sw0
+    with pytest.raises(jgs2.JGS2Error):
+        s.set_streaming(2)
