@@ -202,7 +202,9 @@ void drop_graphs(jgs2_solver* s);
 void free_readback(jgs2_solver* s);
 void build_sweep_args(jgs2_solver* s, SweepArgs& a);
 // kernels launched from the host driver (sweep.hip)
-void launch_phase1(jgs2_solver* s, const SweepArgs& a, bool want_R);
+// gate: skip the rows of stopped bodies (only inside a step's sweeps, after
+// the stop flags were set for this step)
+void launch_phase1(jgs2_solver* s, const SweepArgs& a, bool want_R, bool gate = false);
 void launch_phase2_cubature(jgs2_solver* s, const SweepArgs& a);
 void launch_plain(jgs2_solver* s, const SweepArgs& a);
 void launch_commit(jgs2_solver* s, const SweepArgs& a);

@@ -718,11 +718,19 @@ __global__ __launch_bounds__(256) void k_chunk_dx2(const int* __restrict__ chunk
     if (threadIdx.x == 0) out[c] = sh[0];
 }
 
-__global__ void k_sum_in_order(int n, const double* __restrict__ in, double* __restrict__ out) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// Sum of n partials in a fixed order (thread t sums t, t + 256, ..., then a
+// fixed tree), so repeated runs agree bit for bit.
+__global__ __launch_bounds__(256) void k_sum_fixed(int n, const double* __restrict__ in, double* __restrict__ out) {
+    __shared__ double sh[256];
     double t = 0.0;
-    for (int i = 0; i < n; ++i) t += in[i];
-    out[0] = t;
+    for (int i = threadIdx.x; i < n; i += 256) t += in[i];
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
 }
 
 __global__ void k_copy_d4(int n, const d4* __restrict__ src, d4* __restrict__ dst) {
@@ -738,7 +746,7 @@ static void keep_iterate(jgs2_solver* s) {
 static void residual_launches(jgs2_solver* s, int mask_k) {
     SweepArgs a;
     build_sweep_args(s, a);
-    launch_phase1(s, a, s->p.variant == JGS2_CUBATURE);
+    launch_phase1(s, a, s->p.variant == JGS2_CUBATURE, mask_k > 0);
     launch_seg_norm2(s);
     if (mask_k > 0) {
         launch_mask_update(s, mask_k);
@@ -746,7 +754,7 @@ static void residual_launches(jgs2_solver* s, int mask_k) {
             hipLaunchKernelGGL(k_chunk_dx2, dim3(s->n_chunks), dim3(256), 0, s->stream, (const int*)s->d_chunk_lo,
                                (const int*)s->d_chunk_hi, (const int*)s->d_seg_idx, (const int*)s->d_free,
                                (const d4*)s->d_u, (const d4*)s->d_uprev, s->d_dx2c);
-            hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(64), 0, s->stream, s->n_chunks, (const double*)s->d_dx2c,
+            hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, s->stream, s->n_chunks, (const double*)s->d_dx2c,
                                s->d_dx2);
         }
     }
@@ -873,7 +881,7 @@ static int sweep_once(jgs2_solver* s) {
     const bool cub = s->p.variant == JGS2_CUBATURE;
     if (s->p.order == JGS2_JACOBI) {
         if (cub) {
-            if (!s->phase1_valid) launch_phase1(s, a, true);
+            if (!s->phase1_valid) launch_phase1(s, a, true, true);
             launch_phase2_cubature(s, a);
         } else {
             launch_plain(s, a);
@@ -890,7 +898,7 @@ static int sweep_once(jgs2_solver* s) {
             ac.n_list = s->col_off[c + 1] - s->col_off[c];
             if (cub) {
                 SweepArgs all = a;
-                launch_phase1(s, all, true);
+                launch_phase1(s, all, true, true);
                 launch_phase2_cubature(s, ac);
                 launch_commit(s, ac);
             } else {

@@ -269,30 +269,38 @@ __device__ __forceinline__ void phase1_term(const SweepArgs& a, const int4 e, in
     for (int i = 0; i < 9; ++i) Fs[i] = fmaf(wv, K.F[i], Fs[i]);
 }
 
+// GATED (several bodies, inside a step's sweeps): rows of bodies that have
+// stopped are skipped before any gather; their g and R are those of their
+// frozen positions already.  Otherwise every lane gathers its first incident
+// tet unconditionally.
+template <bool GATED>
 __global__ __launch_bounds__(BLOCK) void k_phase1(SweepArgs a, int want_R) {
     const int lane = threadIdx.x % LPV;
     const int vloc = threadIdx.x / LPV;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int idx = blk * VPB + vloc;
     const int nidx = a.list ? a.n_list : a.nVf;
-    const bool active = idx < nidx;
-    const int f = active ? (a.list ? a.list[idx] : idx) : 0;
+    const bool in_range = idx < nidx;
+    const int f = in_range ? (a.list ? a.list[idx] : idx) : 0;
+    const bool active = GATED ? (in_range && a.body_on[a.fbody[f]] != 0) : in_range;
     // Row-level loads first and without branches (f is a valid row even out
     // of range; rows are padded to maxi entries); every lane then gathers its
     // first incident tet before n is tested (padding reads tet 0 and vertex 0
     // and adds with weight 0), so a lane waits on row -> corners -> positions.
     const int v = a.free_ids[f];
     const int n = a.inc_n[f];
-    const int4 e0 = a.inc4[(size_t)f * a.maxi + min(lane, a.maxi - 1)];
+    const int4 e0 = GATED ? make_int4(0, 0, 0, 0) : a.inc4[(size_t)f * a.maxi + min(lane, a.maxi - 1)];
     const d4 uv = a.u[v], zv = a.zu[v];
     float g[3] = {0.f, 0.f, 0.f}, Fs[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    {
+    int j0 = lane;
+    if constexpr (!GATED) {
         const bool has = lane < n;
         const int4 e = make_int4(has ? e0.x : 0, has ? e0.y : 0, has ? e0.z : 0, has ? e0.w : 0);
         phase1_term(a, e, v, has ? 1.0f : 0.0f, g, Fs);
+        j0 += LPV;
     }
     if (active)
-        for (int j = lane + LPV; j < n; j += LPV) phase1_term(a, a.inc4[(size_t)f * a.maxi + j], v, 1.0f, g, Fs);
+        for (int j = j0; j < n; j += LPV) phase1_term(a, a.inc4[(size_t)f * a.maxi + j], v, 1.0f, g, Fs);
 #pragma unroll
     for (int i = 0; i < 3; ++i) g[i] = lane_sum(g[i]);
     if (want_R) {
@@ -897,10 +905,13 @@ static inline int n_blocks_for(const SweepArgs& a) {
     return (n + VPB - 1) / VPB;
 }
 
-void launch_phase1(jgs2_solver* s, const SweepArgs& a, bool want_R) {
+void launch_phase1(jgs2_solver* s, const SweepArgs& a, bool want_R, bool gate) {
     const int nb = n_blocks_for(a);
     if (nb == 0) return;
-    launch(s, JGS2_K_PHASE1, k_phase1, dim3(nb), dim3(BLOCK), a, want_R ? 1 : 0);
+    if (gate && !a.one_body && a.body_on != nullptr)
+        launch(s, JGS2_K_PHASE1, k_phase1<true>, dim3(nb), dim3(BLOCK), a, want_R ? 1 : 0);
+    else
+        launch(s, JGS2_K_PHASE1, k_phase1<false>, dim3(nb), dim3(BLOCK), a, want_R ? 1 : 0);
 }
 
 void launch_phase2_cubature(jgs2_solver* s, const SweepArgs& a) {
