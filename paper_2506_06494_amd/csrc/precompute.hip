@@ -265,6 +265,105 @@ __global__ __launch_bounds__(256) void k_band_solve(const double* __restrict__ L
     }
 }
 
+// The same solve for CW columns of one 64-column right-hand-side block per
+// workgroup (64 / CW workgroups per block), for a single block, which one
+// workgroup would otherwise walk alone.  Thread t owns row t / 4 and columns
+// 2 (t % 4), 2 (t % 4) + 1 of the slice (CW = 8); L blocks are staged in LDS
+// with a padded row stride (conflict-free row and column reads), and the next
+// block pair is fetched into registers while the current one is multiplied.
+// Every output is the same chain of FMAs, in the same order, as in
+// k_band_solve.
+constexpr int BS_CW = 8;
+constexpr int BS_LD = NB + 1;  // padded LDS row stride of a staged L block
+
+__device__ __forceinline__ void bs_fetch(const double* __restrict__ Lg, const double* __restrict__ Yg, int c0,
+                                         double2 (&pl)[8], double2& py) {
+    const double2* l2 = reinterpret_cast<const double2*>(Lg);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) pl[q] = l2[threadIdx.x + 256 * q];
+    py = *reinterpret_cast<const double2*>(Yg + (threadIdx.x / 4) * NB + c0 + 2 * (threadIdx.x % 4));
+}
+
+__device__ __forceinline__ void bs_stage(double* __restrict__ sL, double* __restrict__ sY, const double2 (&pl)[8],
+                                         const double2& py) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int e = 2 * (threadIdx.x + 256 * q);
+        sL[(e / NB) * BS_LD + e % NB] = pl[q].x;
+        sL[(e / NB) * BS_LD + e % NB + 1] = pl[q].y;
+    }
+    *reinterpret_cast<double2*>(sY + (threadIdx.x / 4) * BS_CW + 2 * (threadIdx.x % 4)) = py;
+}
+
+// acc[j] = fma(sign * op(L)[r][k], Y[k][c_j], acc[j]) over k = 0..63
+template <bool TA>
+__device__ __forceinline__ void bs_gemm(const double* __restrict__ sL, const double* __restrict__ sY, double sign,
+                                        double (&acc)[2]) {
+    const int r = threadIdx.x / 4, c = 2 * (threadIdx.x % 4);
+    for (int k = 0; k < NB; ++k) {
+        const double a = sign * (TA ? sL[k * BS_LD + r] : sL[r * BS_LD + k]);
+        acc[0] = fma(a, sY[k * BS_CW + c], acc[0]);
+        acc[1] = fma(a, sY[k * BS_CW + c + 1], acc[1]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_band_solve_cols(const double* __restrict__ Lb, const double* __restrict__ Linv,
+                                                         int nB, int w, int n_pad, double* __restrict__ Xall) {
+    __shared__ double sL[NB * BS_LD], sY[NB * BS_CW];
+    constexpr int SLICES = NB / BS_CW;
+    double* X = Xall + (size_t)(blockIdx.x / SLICES) * n_pad * NB;
+    const int c0 = (blockIdx.x % SLICES) * BS_CW;
+    const int r = threadIdx.x / 4, c = c0 + 2 * (threadIdx.x % 4);
+    double2 pl[8], py;
+    // forward: Y_I = L_II^-1 (B_I - sum_d L(I, I-d) Y_{I-d})
+    for (int I = 0; I < nB; ++I) {
+        double* XI = X + (size_t)I * NB2;
+        double acc[2] = {XI[r * NB + c], XI[r * NB + c + 1]};
+        const int dmax = min(w, I);
+        if (dmax >= 1) bs_fetch(Lb + ((size_t)(I - 1) * (w + 1) + 1) * NB2, X + (size_t)(I - 1) * NB2, c0, pl, py);
+        for (int d = 1; d <= dmax; ++d) {
+            bs_stage(sL, sY, pl, py);
+            __syncthreads();
+            if (d < dmax)
+                bs_fetch(Lb + ((size_t)(I - d - 1) * (w + 1) + d + 1) * NB2, X + (size_t)(I - d - 1) * NB2, c0, pl, py);
+            bs_gemm<false>(sL, sY, -1.0, acc);
+            __syncthreads();
+        }
+        bs_fetch(Linv + (size_t)I * NB2, X, c0, pl, py);
+        py = make_double2(acc[0], acc[1]);
+        bs_stage(sL, sY, pl, py);
+        __syncthreads();
+        double y[2] = {0.0, 0.0};
+        bs_gemm<false>(sL, sY, 1.0, y);
+        XI[r * NB + c] = y[0];
+        XI[r * NB + c + 1] = y[1];
+        __syncthreads();
+    }
+    // backward: X_I = L_II^-T (Y_I - sum_d L(I+d, I)^T X_{I+d})
+    for (int I = nB - 1; I >= 0; --I) {
+        double* XI = X + (size_t)I * NB2;
+        double acc[2] = {XI[r * NB + c], XI[r * NB + c + 1]};
+        const int dmax = min(w, nB - 1 - I);
+        if (dmax >= 1) bs_fetch(Lb + ((size_t)I * (w + 1) + 1) * NB2, X + (size_t)(I + 1) * NB2, c0, pl, py);
+        for (int d = 1; d <= dmax; ++d) {
+            bs_stage(sL, sY, pl, py);
+            __syncthreads();
+            if (d < dmax) bs_fetch(Lb + ((size_t)I * (w + 1) + d + 1) * NB2, X + (size_t)(I + d + 1) * NB2, c0, pl, py);
+            bs_gemm<true>(sL, sY, -1.0, acc);
+            __syncthreads();
+        }
+        bs_fetch(Linv + (size_t)I * NB2, X, c0, pl, py);
+        py = make_double2(acc[0], acc[1]);
+        bs_stage(sL, sY, pl, py);
+        __syncthreads();
+        double y[2] = {0.0, 0.0};
+        bs_gemm<true>(sL, sY, 1.0, y);
+        XI[r * NB + c] = y[0];
+        XI[r * NB + c + 1] = y[1];
+        __syncthreads();
+    }
+}
+
 // Unit right-hand sides: batch b holds vertices at permuted positions
 // p0 + 21 b + j (j < 21), column 3 j + c is e at DOF 3 p + c.
 __global__ void k_unit_rhs(double* __restrict__ Xall, int n_pad, int p0, int n_vert, int nbatch) {
@@ -1071,8 +1170,7 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
             double* Qj = dQ.p + (size_t)j * blk;
             double* Wj = dKW.p + (size_t)j * blk;
             PCHK(hipMemcpyAsync(Wj, Qj, blk * 8, hipMemcpyDeviceToDevice, st));
-            hipLaunchKernelGGL(k_band_solve, dim3(1), dim3(256), 0, st, dL.p, dLinv.p, nB, w, n_pad, Wj,
-                               (const int*)nullptr);
+            hipLaunchKernelGGL(k_band_solve_cols, dim3(NB / BS_CW), dim3(256), 0, st, dL.p, dLinv.p, nB, w, n_pad, Wj);
             PCHK(hipGetLastError());
             if (j + 1 < MB) {
                 PCHK(hipMemcpyAsync(dV.p, Wj, blk * 8, hipMemcpyDeviceToDevice, st));
