@@ -215,7 +215,9 @@ void launch_norm2(jgs2_solver* s, const float4* w);
 void launch_seg_norm2(jgs2_solver* s);
 int seg_chunk_size();
 void launch_mask_init(jgs2_solver* s);
-void launch_mask_update(jgs2_solver* s, int k);
+// residual check after k sweeps inside a step: per-body |g_b|^2, stop flags,
+// sweep counts, bodies still on and |u - u_prev|^2 (two launches)
+void launch_check(jgs2_solver* s, int k);
 void launch_blend(jgs2_solver* s, const SweepArgs& a, float t);
 void launch_reduce(jgs2_solver* s, int n);
 void launch_predict(jgs2_solver* s, float h, const float* grav);

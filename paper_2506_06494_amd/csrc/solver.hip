@@ -692,47 +692,6 @@ static int read_reduced(jgs2_solver* s, int n_partials, double* out) {
     return JGS2_OK;
 }
 
-// Residual check, device part: gradient (and rotations) at the iterate, the
-// per-body |g_b|^2, and (mask_k > 0) the per-body stop decision after mask_k
-// sweeps.  Graph-capturable: kernels only.
-// |x_k - x_{k-1}|^2 of the last sweep (the paper's convergence measure), in
-// the same fixed chunks as the residual, then summed in chunk order.
-__global__ __launch_bounds__(256) void k_chunk_dx2(const int* __restrict__ chunk_lo, const int* __restrict__ chunk_hi,
-                                                   const int* __restrict__ seg_idx, const int* __restrict__ free_ids,
-                                                   const d4* __restrict__ u, const d4* __restrict__ uprev,
-                                                   double* __restrict__ out) {
-    __shared__ double sh[256];
-    const int c = blockIdx.x;
-    double e = 0.0;
-    for (int i = chunk_lo[c] + threadIdx.x; i < chunk_hi[c]; i += 256) {
-        const int v = free_ids[seg_idx[i]];
-        const double dx = u[v].x - uprev[v].x, dy = u[v].y - uprev[v].y, dz = u[v].z - uprev[v].z;
-        e += dx * dx + dy * dy + dz * dz;
-    }
-    sh[threadIdx.x] = e;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[c] = sh[0];
-}
-
-// Sum of n partials in a fixed order (thread t sums t, t + 256, ..., then a
-// fixed tree), so repeated runs agree bit for bit.
-__global__ __launch_bounds__(256) void k_sum_fixed(int n, const double* __restrict__ in, double* __restrict__ out) {
-    __shared__ double sh[256];
-    double t = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) t += in[i];
-    sh[threadIdx.x] = t;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = sh[0];
-}
-
 __global__ void k_copy_d4(int n, const d4* __restrict__ src, d4* __restrict__ dst) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
@@ -743,21 +702,18 @@ static void keep_iterate(jgs2_solver* s) {
                        s->d_uprev);
 }
 
+// Residual check, device part: gradient (and rotations) at the iterate, the
+// per-body |g_b|^2, and (mask_k > 0) the per-body stop decision after mask_k
+// sweeps and |x_k - x_{k-1}|^2 of the last sweep (the paper's convergence
+// measure), in fixed chunk order.  Graph-capturable: kernels only.
 static void residual_launches(jgs2_solver* s, int mask_k) {
     SweepArgs a;
     build_sweep_args(s, a);
     launch_phase1(s, a, s->p.variant == JGS2_CUBATURE, mask_k > 0);
-    launch_seg_norm2(s);
-    if (mask_k > 0) {
-        launch_mask_update(s, mask_k);
-        if (s->n_chunks > 0) {
-            hipLaunchKernelGGL(k_chunk_dx2, dim3(s->n_chunks), dim3(256), 0, s->stream, (const int*)s->d_chunk_lo,
-                               (const int*)s->d_chunk_hi, (const int*)s->d_seg_idx, (const int*)s->d_free,
-                               (const d4*)s->d_u, (const d4*)s->d_uprev, s->d_dx2c);
-            hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, s->stream, s->n_chunks, (const double*)s->d_dx2c,
-                               s->d_dx2);
-        }
-    }
+    if (mask_k > 0)
+        launch_check(s, mask_k);  // per-body residuals, stop flags, update norm
+    else
+        launch_seg_norm2(s);
 }
 
 // Host part: read the per-body residuals and the count of bodies still on;

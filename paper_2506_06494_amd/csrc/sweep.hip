@@ -733,6 +733,81 @@ __global__ void k_seg_finish(int nb, const int* __restrict__ body_chunk_off, con
     r2[b] = t;
 }
 
+// A residual check inside a step, in two launches: per chunk the |g|^2 and
+// |u - u_prev|^2 partials (the |g|^2 sums as in k_chunk_norm2), then one
+// block for the per-body sums (each body's chunks in order, as in
+// k_seg_finish), the sweep counts of the bodies that ran, the stop flags
+// (|g_b| <= tol |g_b(x0)|), the count of bodies still on, and the update norm
+// (partials in a fixed order).
+__global__ __launch_bounds__(256) void k_check_chunks(const int* __restrict__ chunk_lo, const int* __restrict__ chunk_hi,
+                                                      const int* __restrict__ seg_idx, const int* __restrict__ free_ids,
+                                                      const float4* __restrict__ g, const d4* __restrict__ u,
+                                                      const d4* __restrict__ uprev, double* __restrict__ r2c,
+                                                      double* __restrict__ dx2c) {
+    __shared__ double s[256], t[256];
+    const int c = blockIdx.x;
+    const int lo = chunk_lo[c], hi = chunk_hi[c];
+    double e = 0.0, f = 0.0;
+    for (int i = lo + threadIdx.x; i < hi; i += 256) {
+        const int v = free_ids[seg_idx[i]];
+        const float4 q = g[v];
+        e += (double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z;
+        const double dx = u[v].x - uprev[v].x, dy = u[v].y - uprev[v].y, dz = u[v].z - uprev[v].z;
+        f += dx * dx + dy * dy + dz * dz;
+    }
+    s[threadIdx.x] = e;
+    t[threadIdx.x] = f;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            s[threadIdx.x] += s[threadIdx.x + o];
+            t[threadIdx.x] += t[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        r2c[c] = s[0];
+        dx2c[c] = t[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_check_finish(int nb, const int* __restrict__ body_chunk_off,
+                                                      const double* __restrict__ r2c, double* __restrict__ r2,
+                                                      const double* __restrict__ r0sq, double tol2, int* __restrict__ on,
+                                                      int* __restrict__ sweeps, int k, int* __restrict__ n_active,
+                                                      int n_chunks, const double* __restrict__ dx2c,
+                                                      double* __restrict__ dx2) {
+    __shared__ int cnt[256];
+    __shared__ double sh[256];
+    int c = 0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        double t = 0.0;
+        for (int q = body_chunk_off[b]; q < body_chunk_off[b + 1]; ++q) t += r2c[q];
+        r2[b] = t;
+        if (on[b]) {
+            sweeps[b] += k;
+            if (t <= tol2 * r0sq[b]) on[b] = 0;
+        }
+        c += on[b];
+    }
+    double d = 0.0;
+    for (int i = threadIdx.x; i < n_chunks; i += 256) d += dx2c[i];
+    cnt[threadIdx.x] = c;
+    sh[threadIdx.x] = d;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            cnt[threadIdx.x] += cnt[threadIdx.x + o];
+            sh[threadIdx.x] += sh[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        n_active[0] = cnt[0];
+        dx2[0] = sh[0];
+    }
+}
+
 // Start of a step: r0^2 per body, every body with a non-zero residual on.
 __global__ __launch_bounds__(256) void k_mask_init(int nb, const double* __restrict__ r2, double* __restrict__ r0sq,
                                                    int* __restrict__ on, int* __restrict__ sweeps,
@@ -743,30 +818,6 @@ __global__ __launch_bounds__(256) void k_mask_init(int nb, const double* __restr
         r0sq[b] = r2[b];
         on[b] = r2[b] > 0.0 ? 1 : 0;
         sweeps[b] = 0;
-        c += on[b];
-    }
-    cnt[threadIdx.x] = c;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) cnt[threadIdx.x] += cnt[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) n_active[0] = cnt[0];
-}
-
-// After k sweeps: count them for the bodies that ran, switch off the bodies
-// with |g_b| <= tol |g_b(x0)|, and count the bodies still on.
-__global__ __launch_bounds__(256) void k_mask_update(int nb, const double* __restrict__ r2,
-                                                     const double* __restrict__ r0sq, double tol2,
-                                                     int* __restrict__ on, int* __restrict__ sweeps, int k,
-                                                     int* __restrict__ n_active) {
-    __shared__ int cnt[256];
-    int c = 0;
-    for (int b = threadIdx.x; b < nb; b += 256) {
-        if (on[b]) {
-            sweeps[b] += k;
-            if (r2[b] <= tol2 * r0sq[b]) on[b] = 0;
-        }
         c += on[b];
     }
     cnt[threadIdx.x] = c;
@@ -991,15 +1042,20 @@ void launch_seg_norm2(jgs2_solver* s) {
 
 int seg_chunk_size() { return CHUNK; }
 
+void launch_check(jgs2_solver* s, int k) {
+    if (s->n_chunks > 0)
+        launch(s, JGS2_K_REDUCE, k_check_chunks, dim3(s->n_chunks), dim3(256), (const int*)s->d_chunk_lo,
+               (const int*)s->d_chunk_hi, (const int*)s->d_seg_idx, (const int*)s->d_free, (const float4*)s->d_g,
+               (const d4*)s->d_u, (const d4*)s->d_uprev, s->d_r2c, s->d_dx2c);
+    const double tol2 = s->p.rel_tol * s->p.rel_tol;
+    launch(s, JGS2_K_REDUCE, k_check_finish, dim3(1), dim3(256), s->n_bodies, (const int*)s->d_body_chunk_off,
+           (const double*)s->d_r2c, s->d_r2, (const double*)s->d_r0sq, tol2, s->d_body_on, s->d_body_sweeps, k,
+           s->d_nactive, s->n_chunks, (const double*)s->d_dx2c, s->d_dx2);
+}
+
 void launch_mask_init(jgs2_solver* s) {
     launch(s, JGS2_K_REDUCE, k_mask_init, dim3(1), dim3(256), s->n_bodies, (const double*)s->d_r2, s->d_r0sq,
            s->d_body_on, s->d_body_sweeps, s->d_nactive);
-}
-
-void launch_mask_update(jgs2_solver* s, int k) {
-    const double tol2 = s->p.rel_tol * s->p.rel_tol;
-    launch(s, JGS2_K_REDUCE, k_mask_update, dim3(1), dim3(256), s->n_bodies, (const double*)s->d_r2,
-           (const double*)s->d_r0sq, tol2, s->d_body_on, s->d_body_sweeps, k, s->d_nactive);
 }
 
 void launch_commit(jgs2_solver* s, const SweepArgs& a) {
