@@ -35,8 +35,10 @@ def parse():
                                        "plain_jacobi_w0.3,plain_gs,plain_gs_w1.5")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched many-beam leg")
-    ap.add_argument("--tune", action="store_true",
-                    help="autotune the launch shape of the single-beam modes (default: 32 lanes x 256)")
+    ap.add_argument("--shape", default="16x64",
+                    help="launch shape (lanes per vertex x block) of the single-beam plain modes; 16x64 is what "
+                         "the autotuner picks on the 16x16x128 beam on MI355X")
+    ap.add_argument("--tune", action="store_true", help="run the autotuner instead of using --shape")
     ap.add_argument("--batched-beams", type=int, default=256)
     ap.add_argument("--no-contact", action="store_true", help="skip the 10-sphere contact leg")
     ap.add_argument("--leg", choices=["contact"], help=argparse.SUPPRESS)
@@ -130,8 +132,12 @@ def main():
                                         corr["U_samp"])
             s.set_state(sc.x0, sc.v0)
             tuned = None
-            if cfg["variant"] == jgs2.PLAIN and args.tune:
-                tuned, _ = s.autotune(32)        # launch shape of the plain sweep kernel on this mesh
+            if cfg["variant"] == jgs2.PLAIN:
+                if args.tune:
+                    tuned, _ = s.autotune(32)    # launch shape of the plain sweep kernel on this mesh
+                else:
+                    tuned = tuple(int(v) for v in args.shape.split("x"))
+                    s.set_tuning(*tuned)
             # warm-up steps (untimed), then the timed steps
             failed = None
             stalled = None
@@ -219,12 +225,13 @@ def main():
             per_launch = per_sweep * nsweeps / n
             achieved = per_launch / (ms * 1e-3 / n) / 1e9
             tag = "beam16x16x128_gs" if not args.small else "beam4x4x16_gs"
-            traffic = measured_traffic("k_plain", tag) if head_mode.startswith("plain_gs") else None
+            shape = results[head_mode][E0].get("launch_shape") or [32, 256]
+            traffic = measured_traffic("k_plain", tag, shape) if head_mode.startswith("plain_gs") else None
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": None if traffic is None else round(traffic), "kernel": "k_plain",
                     "avg_launch_us": round(ms * 1e3 / n, 3), "launches": n,
-                    "bytes_per_launch": round(per_launch)}
+                    "bytes_per_launch": round(per_launch), "launch_shape": shape}
     jgs2_sweep = measure_cubature_sweep(sc0, corr0) if corr0 is not None else None
 
     adj = None if args.no_adjoint or args.small else adjoint_leg()
@@ -447,11 +454,12 @@ def kernel_source_sha1():
     return hashlib.sha1(open(path, "rb").read()).hexdigest()
 
 
-def measured_traffic(kernel, workload_tag):
+def measured_traffic(kernel, workload_tag, shape=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
     summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
-    counter reads for a 1 GiB copy), or None if that summary is missing or was
-    taken on different kernel source."""
+    counter reads for a 1 GiB copy), or None if that summary is missing, was
+    taken on different kernel source or (when both name one) in another
+    launch shape."""
     import re
     path = os.path.join(ROOT, "profiles", "pmc_traffic.md")
     if not os.path.exists(path):
@@ -463,6 +471,8 @@ def measured_traffic(kernel, workload_tag):
         if kv.get("kernel") != kernel or kv.get("workload") != workload_tag:
             continue
         if kv.get("sweep_sha1") != kernel_source_sha1():
+            return None
+        if shape is not None and "shape" in kv and kv["shape"] != "x".join(str(v) for v in shape):
             return None
         return (float(kv["fetch_kib"]) * 1024 * float(kv["fetch_scale"]) +
                 float(kv["write_kib"]) * 1024 * float(kv["write_scale"]))

@@ -122,12 +122,14 @@ def test_bench_byte_accounting_and_traffic_parser(tmp_path, monkeypatch):
     prof.mkdir()
     (prof / "pmc_traffic.md").write_text(
         "x\ntraffic kernel=k_plain workload=w fetch_kib=10 write_kib=2 fetch_scale=2.0 write_scale=1.0 "
-        f"sweep_sha1={bench.kernel_source_sha1()}\n"
+        f"shape=16x64 sweep_sha1={bench.kernel_source_sha1()}\n"
         "traffic kernel=k_plain workload=old fetch_kib=10 write_kib=2 fetch_scale=2.0 write_scale=1.0 "
         "sweep_sha1=0000\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_sha1", lambda: open(prof / "pmc_traffic.md").read().split("sweep_sha1=")[1].split()[0])
     assert bench.measured_traffic("k_plain", "w") == (10 * 2.0 + 2 * 1.0) * 1024
+    assert bench.measured_traffic("k_plain", "w", [16, 64]) == (10 * 2.0 + 2 * 1.0) * 1024
+    assert bench.measured_traffic("k_plain", "w", [32, 256]) is None   # counters taken in another launch shape
     assert bench.measured_traffic("k_plain", "old") is None      # counters taken on other kernel source
     assert bench.measured_traffic("k_phase1", "w") is None
 
