@@ -79,13 +79,16 @@ def test_full_size_plain_jacobi_matches_golden(E):
     np.testing.assert_allclose(rel, g["rel_res"][-1], rtol=1e-3)
 
 
-def test_full_size_headline_sweeps_match_golden():
+@pytest.mark.parametrize("shape", [(16, 64), (32, 256)])
+def test_full_size_headline_sweeps_match_golden(shape):
     """The benchmark's headline configuration (coloured GS, step scale 1.5,
-    captured sweep groups, default launch shape) on the full beam."""
+    captured sweep groups, its 16 x 64 launch shape; and the library's
+    default shape) on the full beam."""
     g = load(1e5, "plain_gs_w1.5")
     sc = inputs.single_beam(1e5)
     mdl = fem.model_from_scene(sc)
     s = make_solver(sc, variant=jgs2.PLAIN, order=jgs2.GS, omega=g["omega"], use_graph=1, check_every=g["sweeps"])
+    s.set_tuning(*shape)
     s.set_state(sc.x0, sc.v0)
     s.begin_step()
     rel = s.iterate(g["sweeps"])
