@@ -570,9 +570,10 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     const int vself = a.vid_c[q];
     const int n = a.incn_c[q];
     const float4* row = a.irec_c + (size_t)q * IREC_F4 * a.maxi;
-    Tet T0;
-    int c0 = 0;
+    Tet T0, T1;
+    int c0 = 0, c1 = 0;
     if constexpr (SPEC) load_irec<NT>(row + min(lane, a.maxi - 1), a.maxi, T0, c0);
+    if constexpr (SPEC && W < 32) load_irec<NT>(row + min(lane + W, a.maxi - 1), a.maxi, T1, c1);
     const d4 uv = a.u[vself];
     d4 zv = make_d4(0.0, 0.0, 0.0, 0.0);
     float4 yv = make_float4(0.f, 0.f, 0.f, 0.f), rv = yv;
@@ -590,6 +591,11 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
         // entries past n are zero records or a repeat of the row's last one
         plain_tet_term<LIN>(a, T0, c0, lane < n ? 1.0f : 0.0f, g, A6);
         j0 += W;
+        if constexpr (W < 32) {
+            // a second round, also gathered before n or the flag is known
+            plain_tet_term<LIN>(a, T1, c1, j0 < n ? 1.0f : 0.0f, g, A6);
+            j0 += W;
+        }
     }
     if (active)
         for (int j = j0; j < n; j += W) {
