@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="4x4x16 beam instead (quick check)")
     ap.add_argument("--modes", default="jgs2_jacobi,jgs2_gs,plain_jacobi,plain_jacobi_w0.8,plain_jacobi_w0.5,"
-                                       "plain_jacobi_w0.3,plain_gs,plain_gs_w1.5")
+                                       "plain_jacobi_w0.3,plain_gs,plain_gs_w1.5,plain_gs_w1.6")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched many-beam leg")
     ap.add_argument("--shape", default="16x64",
@@ -99,8 +99,10 @@ def main():
         ("plain_jacobi_w0.5", dict(variant=jgs2.PLAIN, order=jgs2.JACOBI, omega=0.5)),
         ("plain_jacobi_w0.3", dict(variant=jgs2.PLAIN, order=jgs2.JACOBI, omega=0.3)),
         ("plain_gs", dict(variant=jgs2.PLAIN, order=jgs2.GS, omega=1.0)),
-        # the same coloured GS with every vertex step scaled by 1.5 (successive over-relaxation)
+        # the same coloured GS with every vertex step scaled by 1.5 and 1.6 (successive
+        # over-relaxation; on the 16x16x128 beam 1.6 needs the fewest sweeps of 1.5..1.9)
         ("plain_gs_w1.5", dict(variant=jgs2.PLAIN, order=jgs2.GS, omega=1.5)),
+        ("plain_gs_w1.6", dict(variant=jgs2.PLAIN, order=jgs2.GS, omega=1.6)),
     ]
     wanted = args.modes.split(",")
     modes = [m for m in modes if m[0] in wanted]

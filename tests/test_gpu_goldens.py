@@ -79,12 +79,13 @@ def test_full_size_plain_jacobi_matches_golden(E):
     np.testing.assert_allclose(rel, g["rel_res"][-1], rtol=1e-3)
 
 
-@pytest.mark.parametrize("shape", [(16, 64), (32, 256)])
-def test_full_size_headline_sweeps_match_golden(shape):
-    """The benchmark's headline configuration (coloured GS, step scale 1.5,
-    captured sweep groups, its 16 x 64 launch shape; and the library's
-    default shape) on the full beam."""
-    g = load(1e5, "plain_gs_w1.5")
+@pytest.mark.parametrize("mode,shape", [("plain_gs_w1.6", (16, 64)), ("plain_gs_w1.5", (16, 64)),
+                                        ("plain_gs_w1.5", (32, 256))])
+def test_full_size_headline_sweeps_match_golden(mode, shape):
+    """The benchmark's fastest configurations (coloured GS, step scales 1.6
+    and 1.5, captured sweep groups, its 16 x 64 launch shape; and the
+    library's default shape) on the full beam."""
+    g = load(1e5, mode)
     sc = inputs.single_beam(1e5)
     mdl = fem.model_from_scene(sc)
     s = make_solver(sc, variant=jgs2.PLAIN, order=jgs2.GS, omega=g["omega"], use_graph=1, check_every=g["sweeps"])
