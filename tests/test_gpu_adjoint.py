@@ -37,7 +37,10 @@ def v_init(m, u):
     return v
 
 
-def test_adjoint_matches_oracle_small():
+@pytest.mark.parametrize("shape", [None, (16, 64), (4, 128)])
+def test_adjoint_matches_oracle_small(shape):
+    """Also in launch shapes whose lane groups take several rounds of
+    incident tets (the first two gathered speculatively)."""
     m, logE, u = small_problem()
     n = 5
     mdl = fem.Model(m.X, m.tets, m.pinned, np.exp(logE), 0.45, 1000.0, 1.0 / 120)
@@ -48,6 +51,8 @@ def test_adjoint_matches_oracle_small():
     th_o, xb_o, vb_o = oa.backward(mdl, xs, xbar, vbar)
 
     s = gpu_solver(m, logE)
+    if shape:
+        s.set_tuning(*shape)
     s.set_state(m.X, v_init(m, u))
     s.rollout(n, ckpt_every=2)                     # segments [0,2) [2,4) [4,5)
     x, _ = s.get_state()
