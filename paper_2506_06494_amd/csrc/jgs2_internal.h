@@ -170,6 +170,10 @@ struct jgs2_solver {
     double dx_norm = 0.0;
     int* d_body_on = nullptr;              // [n_bodies]
     int* d_body_sweeps = nullptr;          // [n_bodies]
+    // one block read back after a check: [0] |u - u_prev|^2, [1] bodies still on
+    // (an int in its first 4 bytes), [2..) per-body |g_b|^2; d_dx2, d_nactive and
+    // d_r2 point into it
+    double* d_rb = nullptr;
     int* d_nactive = nullptr;              // [1]
     double *d_r2 = nullptr, *d_r0sq = nullptr;  // [n_bodies]
     std::vector<double> r2_host, r0sq_host;
@@ -184,6 +188,8 @@ struct jgs2_solver {
     jgs2::d4* graph_u[2] = {nullptr, nullptr};
     int graph_next = 0;
     // pinned residual readback slots (two sweep groups in flight)
+    // pinned readback slots, each one block laid out like d_rb (aliases into h_rb)
+    double* h_rb[2] = {nullptr, nullptr};
     double* h_r2[2] = {nullptr, nullptr};
     int* h_nact[2] = {nullptr, nullptr};
     double* h_dx2[2] = {nullptr, nullptr};

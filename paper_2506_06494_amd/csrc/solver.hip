@@ -34,9 +34,9 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_ck_u); dfree(s->d_ck_v); dfree(s->d_seg); dfree(s->d_y); dfree(s->d_ynext); dfree(s->d_xbar);
     dfree(s->d_vbar); dfree(s->d_rhs); dfree(s->d_thbar);
     dfree(s->d_fbody); dfree(s->d_seg_idx); dfree(s->d_body_on); dfree(s->d_body_sweeps);
-    dfree(s->d_nactive); dfree(s->d_r2); dfree(s->d_r0sq);
+    dfree(s->d_rb); s->d_nactive = nullptr; s->d_r2 = nullptr; s->d_dx2 = nullptr; dfree(s->d_r0sq);
     dfree(s->d_chunk_lo); dfree(s->d_chunk_hi); dfree(s->d_body_chunk_off); dfree(s->d_r2c);
-    dfree(s->d_uprev); dfree(s->d_dx2c); dfree(s->d_dx2);
+    dfree(s->d_uprev); dfree(s->d_dx2c);
     s->ro_valid = false;
     drop_graphs(s);
     free_readback(s);
@@ -44,9 +44,8 @@ void free_device(jgs2_solver* s) {
 
 void free_readback(jgs2_solver* s) {
     for (int i = 0; i < 2; ++i) {
-        if (s->h_r2[i]) (void)hipHostFree(s->h_r2[i]);
-        if (s->h_nact[i]) (void)hipHostFree(s->h_nact[i]);
-        if (s->h_dx2[i]) (void)hipHostFree(s->h_dx2[i]);
+        if (s->h_rb[i]) (void)hipHostFree(s->h_rb[i]);
+        s->h_rb[i] = nullptr;
         s->h_r2[i] = nullptr;
         s->h_nact[i] = nullptr;
         s->h_dx2[i] = nullptr;
@@ -461,9 +460,8 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
         (r = dalloc(s, s->d_incslot, nf * s->maxi)) || (r = dalloc(s, s->d_inc_n, nf)) ||
         (r = dalloc(s, s->d_ring, nf * s->K)) || (r = dalloc(s, s->d_ring_n, nf)) ||
         (r = dalloc(s, s->d_colperm, nf)) || (r = dalloc(s, s->d_tet, (size_t)nT * TET_F4)) ||
-        (r = dalloc(s, s->d_inc4, nf * s->maxi)) || (r = dalloc(s, s->d_uprev, V4)) || (r = dalloc(s, s->d_dx2, 1)))
+        (r = dalloc(s, s->d_inc4, nf * s->maxi)) || (r = dalloc(s, s->d_uprev, V4)))
         return r;
-    HIPCHK(hipMemsetAsync(s->d_dx2, 0, sizeof(double), s->stream));
     s->n_partial = std::max<int>((s->nVf + 1) / 2, (std::max(nT, s->nVf) + 255) / 256) + 1;
     if ((r = dalloc(s, s->d_partial, (size_t)s->n_partial)) || (r = dalloc(s, s->d_red, 4))) return r;
     std::vector<float4> Xs(V4), Rid(V4, make_float4(0.f, 0.f, 0.f, 1.f));
@@ -720,12 +718,12 @@ static void residual_launches(jgs2_solver* s, int mask_k) {
 // |g|^2 over all bodies (summed in body order) into *g2.
 static int residual_readback(jgs2_solver* s, double* g2) {
     const size_t nb = s->n_bodies;
-    HIPCHK(hipMemcpyAsync(s->r2_host.data(), s->d_r2, nb * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipMemcpyAsync(&s->n_active, s->d_nactive, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-    double dx2 = 0.0;
-    HIPCHK(hipMemcpyAsync(&dx2, s->d_dx2, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    std::vector<double> rb(nb + 2);
+    HIPCHK(hipMemcpyAsync(rb.data(), s->d_rb, (nb + 2) * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
-    s->dx_norm = std::sqrt(dx2);
+    std::copy(rb.begin() + 2, rb.end(), s->r2_host.begin());
+    std::memcpy(&s->n_active, &rb[1], sizeof(int));
+    s->dx_norm = std::sqrt(rb[0]);
     prof_collect(s);
     s->phase1_valid = true;
     double t = 0.0;
@@ -973,9 +971,7 @@ static int abandon_step(jgs2_solver* s) {
 // Residual readback of a sweep group into pinned slot `slot`, without waiting.
 static int enqueue_readback(jgs2_solver* s, int slot) {
     const size_t nb = s->n_bodies;
-    HIPCHK(hipMemcpyAsync(s->h_r2[slot], s->d_r2, nb * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipMemcpyAsync(s->h_nact[slot], s->d_nactive, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipMemcpyAsync(s->h_dx2[slot], s->d_dx2, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(s->h_rb[slot], s->d_rb, (nb + 2) * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipEventRecord(s->rb_ev[slot], s->stream));
     return JGS2_OK;
 }
@@ -1423,15 +1419,19 @@ int32_t jgs2_set_bodies(jgs2_solver* s, int32_t n_bodies, const int32_t* body_of
     s->n_chunks = (int)nch;
     if ((r = dalloc(s, s->d_fbody, (size_t)nf)) ||
         (r = dalloc(s, s->d_seg_idx, (size_t)nf)) || (r = dalloc(s, s->d_body_on, nb)) ||
-        (r = dalloc(s, s->d_body_sweeps, nb)) || (r = dalloc(s, s->d_nactive, 1)) || (r = dalloc(s, s->d_r2, nb)) ||
-        (r = dalloc(s, s->d_r0sq, nb)))
+        (r = dalloc(s, s->d_body_sweeps, nb)) || (r = dalloc(s, s->d_rb, nb + 2)) || (r = dalloc(s, s->d_r0sq, nb)))
         return r;
+    s->d_dx2 = s->d_rb;
+    s->d_nactive = reinterpret_cast<int*>(s->d_rb + 1);
+    s->d_r2 = s->d_rb + 2;
+    HIPCHK(hipMemsetAsync(s->d_rb, 0, (nb + 2) * sizeof(double), s->stream));
     free_readback(s);
     for (int i = 0; i < 2; ++i) {
-        HIPCHK(hipHostMalloc((void**)&s->h_r2[i], nb * sizeof(double), hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void**)&s->h_nact[i], sizeof(int), hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void**)&s->h_dx2[i], sizeof(double), hipHostMallocDefault));
-        *s->h_dx2[i] = 0.0;
+        HIPCHK(hipHostMalloc((void**)&s->h_rb[i], (nb + 2) * sizeof(double), hipHostMallocDefault));
+        s->h_dx2[i] = s->h_rb[i];
+        s->h_nact[i] = reinterpret_cast<int*>(s->h_rb[i] + 1);
+        s->h_r2[i] = s->h_rb[i] + 2;
+        std::memset(s->h_rb[i], 0, (nb + 2) * sizeof(double));
         if (!s->rb_ev[i]) HIPCHK(hipEventCreateWithFlags(&s->rb_ev[i], hipEventDisableTiming));
     }
     std::vector<int> ones(nb, 1), zeros(nb, 0);
