@@ -748,6 +748,8 @@ static int gradient_norm2(jgs2_solver* s, double* out) {
 static bool ready_to_step(jgs2_solver* s) {
     if (!s->have_mesh || !s->have_material) { s->err = "no mesh or material"; return false; }
     if (!s->have_state) { s->err = "no state"; return false; }
+    // the sweep kernels read the bodies' stop flags (a failed set_bodies leaves none)
+    if (!s->d_body_on || !s->d_rb) { s->err = "no body tables (set_bodies failed)"; return false; }
     if (s->p.variant == JGS2_CUBATURE && !s->have_corr) { s->err = "no correction (precompute or import)"; return false; }
     return true;
 }
