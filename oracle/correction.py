@@ -1,6 +1,6 @@
 """Precomputed overshoot correction (oracle, float64).
 
-Follows Sec. 4.2 (local perturbation subspace, Eqs. cms and phi), Sec. 4.4
+Follows Sec. 4.1 (local perturbation subspace, Eqs. cms and phi), Sec. 4.3
 (co-rotated subspace, Eq. tilde_phi), Sec. 5 (cubature, Eqs. cubature and
 cubature_weight) and Sec. 6's full-coordinate precompute (Eqs.
 cms_multiplier, block_inv and u).

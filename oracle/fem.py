@@ -12,7 +12,7 @@ Readings (the paper does not spell these out):
   * f_ext is gravity only; pinned vertices are held at their rest position
     and carry no unknowns (their inertia term, a constant, is dropped by
     taking z = x there).
-  * IPC plane contact (Sec. 6, Eq. barrier): for every vertex a and plane
+  * IPC plane contact (Sec. 7, Eq. barrier): for every vertex a and plane
     (n_p, c_p) with signed distance d = n_p . x_a - c_p, the potential gains
     kappa * B(d, d_hat) with B = -(d - d_hat)^2 log(d / d_hat) on
     0 < d < d_hat and 0 beyond.  kappa is not given by the paper (see the

@@ -1,8 +1,8 @@
 """Mesh adjacency and greedy vertex colouring (oracle).
 
-Sub-problems sit at vertices (Sec. 7.1), so each needs its incident tets and
+Sub-problems sit at vertices (Sec. 8.1), so each needs its incident tets and
 its one-ring (vertices sharing a tet).  Gauss-Seidel groups independent
-sub-problems by graph colouring (Sec. 7.1): two vertices of one colour never
+sub-problems by graph colouring (Sec. 8.1): two vertices of one colour never
 share a tet.  Reading: greedy colouring of the free vertices in ascending id
 order, each taking the smallest colour unused by its already-coloured free
 one-ring neighbours.

@@ -2,7 +2,7 @@
 
 Sec. 4 (Eq. newton, Eq. newton_system): the second-order step solves
 H dx = -g.  The paper's own baseline is projected Newton with a sparse
-direct (Cholesky) solver (Sec. 7, comparison with projected Newton).  Here:
+direct (Cholesky) solver (Sec. 8.4, comparison with projected Newton).  Here:
 per-element PSD projection of the elastic Hessian, a sparse direct solve
 (SuperLU through scipy), and backtracking on E.  The projection changes the
 path, not the minimiser x*.

@@ -1,14 +1,14 @@
 """Per-vertex local solves and parallel sweeps (oracle, float64).
 
 Sub-problem = one vertex with N_i = 3 DOFs and an analytic 3x3 Newton solve
-(Sec. 7.1).  The global-aware local system (Eqs. reduced_local and
+(Sec. 8.1).  The global-aware local system (Eqs. reduced_local and
 reduced_h_g) is the Galerkin projection of the Newton system onto the
 perturbation subspace U_i:
 
     (U_i^T H U_i) dx_i = -U_i^T g,
 
 which, with the exact subspace of Eq. phi, is the i-block of the Newton step
-(Sec. 4.3).  Row blocks of the co-rotated subspace (Eq. tilde_phi) are
+(Sec. 4.2).  Row blocks of the co-rotated subspace (Eq. tilde_phi) are
 Phi_{i,a} = R_a U-bar_{i,a} R_i^T with per-vertex rotations R_a from the
 polar decomposition of a per-vertex deformation gradient.
 
@@ -24,10 +24,14 @@ Variants (same enum as the HIP library):
               + sum_{s in S_i} w_s sum_{a in s, a not in Nbar(i)} Phi_{i,a}^T g_a / n_a
       Reading: the paper's sampled "[grad E_C]_e" is taken as the assembled
       residual at e's corners shared by valence, so that b_i = 0 at the
-      solution and the solution is a fixed point; with every remote element
-      sampled at weight 1 this is exactly R1.
+      solution and the solution is a fixed point; with every element not
+      containing i sampled at weight 1 this is exactly R1 (the cubature
+      candidates are those with a free corner outside Nbar(i); the other
+      non-incident elements add Hessian terms only).
+  R2, R2G1, R2D  the literal H_ii-plus-sampled forms (see ``r2_systems``);
+      R2D is the library's DAMPER variant.
 
-Readings of the per-vertex rotation (Sec. 4.4 names a polar decomposition of
+Readings of the per-vertex rotation (Sec. 4.3 names a polar decomposition of
 a per-vertex deformation gradient without defining the latter): F-bar_a is
 the volume-weighted mean of the F_e of the tets around a, and R_a =
 U diag(1, 1, det(U V^T)) V^T from the SVD F-bar_a = U Sigma V^T.
@@ -46,7 +50,7 @@ import scipy.sparse.linalg as spla
 
 from . import correction as ocorr
 
-P0, R0, R1, R2, R2G1, R3 = "P0", "R0", "R1", "R2", "R2G1", "R3"
+P0, R0, R1, R2, R2G1, R2D, R3 = "P0", "R0", "R1", "R2", "R2G1", "R2D", "R3"
 
 
 def polar(F):
@@ -168,14 +172,17 @@ def r3_systems(model, tab, ell, x, g, R, He, Hb, rows=None):
     return A, b
 
 
-def r2_systems(model, tab, ell, x, z, g, R, He, Hb, H, rows, own_gradient=False):
+def r2_systems(model, tab, ell, x, z, g, R, He, Hb, H, rows, gradient="assembled"):
     """The literal form of Eqs. reduced_local and cubature (variant R2):
     A_i = H_ii + sum_s w_s U_s^T H_s U_s (samples never contain i, so no ii
     block is removed), b_i = g_i + g-tilde_i with g-tilde_i the sampled
     remote gradient, either from the assembled residual (g_a / n_a at sample
-    corners outside the closed one-ring, as in R3; R2) or from the sample's
-    own element gradient over its four corners (R2G1).  Uses the cubature
-    tables trained for R3."""
+    corners outside the closed one-ring, as in R3; gradient="assembled", R2)
+    or from the sample's own element gradient over its four corners
+    (gradient="own", R2G1); gradient="none" leaves it out (R2D: the sampled
+    reduced Hessian only damps the plain local solve, Sec. 5's closing
+    remark that the cubature gradient matters less than this damping
+    Hessian).  Uses the cubature tables trained for R3."""
     v = tab.verts[rows]
     Ri = R[v]
     n = rows.size
@@ -191,11 +198,13 @@ def r2_systems(model, tab, ell, x, z, g, R, He, Hb, H, rows, own_gradient=False)
     Us12 = Us.reshape(n, ell.S, 12, 3)
     A += np.einsum("ns,nspa,nspq,nsqb->nab", w, Us12, He[s], Us12)
     b = g[v].copy()
-    if own_gradient:
+    if gradient == "own":
         ge = model.element_gradients(x, z).reshape(model.nT, 12)
         b += np.einsum("ns,nspa,nsp->na", w, Us12, ge[s])
-    else:
+    elif gradient == "assembled":
         b += np.einsum("nsc,nscab,nsca->nb", tab.gcoef[rows] * ell.samp_ok[rows][:, :, None], Us, g[corners])
+    elif gradient != "none":
+        raise ValueError(gradient)
     return A, b
 
 
@@ -232,7 +241,7 @@ def exact_rows(model, H, verts):
 
 
 def feasibility_clamp(model, x, step):
-    """Contact (Sec. 6 with the line-search remark of Sec. 8): each vertex's
+    """Contact (Sec. 7 with the line-search remark of Sec. 9): each vertex's
     move is scaled by min(1, 0.9 min_p d_p / (-n_p . step)) over the planes it
     approaches, so no vertex reaches a static plane (reading: a per-vertex,
     per-sub-problem step bound)."""
@@ -260,7 +269,7 @@ class Sweeper:
         self.ls_halvings = 0
         from . import mesh as omesh
         self.inc = omesh.incidence(model.tets, model.nV)
-        self.ell = _Ell(model, tab, self.inc) if (tab is not None and variant in (R3, R2, R2G1)) else None
+        self.ell = _Ell(model, tab, self.inc) if (tab is not None and variant in (R3, R2, R2G1, R2D)) else None
         if tab is not None:
             assert np.array_equal(tab.verts, model.free_ids)
 
@@ -273,9 +282,9 @@ class Sweeper:
         if self.variant == R3:
             He = m.element_hessians(x)
             return r3_systems(m, self.tab, self.ell, x, g, R, He, Hb, rows)
-        if self.variant in (R2, R2G1):
+        if self.variant in (R2, R2G1, R2D):
             return r2_systems(m, self.tab, self.ell, x, z, g, R, m.element_hessians(x), Hb, m.hessian(x), rows,
-                              own_gradient=self.variant == R2G1)
+                              gradient={R2: "assembled", R2G1: "own", R2D: "none"}[self.variant])
         if self.variant == P0:
             H = m.hessian(x)
             A = np.zeros((verts.size, 3, 3))

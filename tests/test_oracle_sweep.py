@@ -21,7 +21,7 @@ def test_polar_properties():
 
 def test_exact_subspace_sweep_is_newton_step(tiny):
     """R0 (Eq. phi with the current Hessian): one Jacobi sweep equals the
-    global Newton step -H^-1 g (Sec. 4.3)."""
+    global Newton step -H^-1 g (Sec. 4.2)."""
     sc, mdl, tab = tiny
     z = mdl.inertial_target(sc.x0, sc.v0)
     x = sc.x0 + 1e-3 * rng.standard_normal(sc.x0.shape); x[mdl.pinned] = mdl.X[mdl.pinned]
