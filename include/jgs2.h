@@ -4,7 +4,7 @@
  * Method: Lan et al., "JGS2: Near Second-order Converging Jacobi/Gauss-Seidel
  * for GPU Elastodynamics" (arXiv 2506.06494).  Each implicit-Euler step
  * minimises the incremental potential E = I + Psi (Sec. 3, Eq. variation) by
- * parallel per-vertex 3x3 Newton sweeps (Sec. 7.1), optionally corrected by
+ * parallel per-vertex 3x3 Newton sweeps (Sec. 8.1), optionally corrected by
  * the precomputed co-rotated, cubature-sampled subspace of Secs. 4-6
  * (Eqs. tilde_phi, reduced_local, reduced_h_g, cubature, u).
  *
@@ -30,7 +30,10 @@
 extern "C" {
 #endif
 
-/* Status codes. */
+/* Status codes.  JGS2_NOT_CONVERGED is positive: the call completed and
+ * kept its results, but a solve stopped at its sweep cap above its
+ * tolerance; the negative codes are failures. */
+#define JGS2_NOT_CONVERGED 1
 #define JGS2_OK            0
 #define JGS2_E_INVALID    -1  /* bad argument, size, order of calls, non-finite input */
 #define JGS2_E_OOM        -2  /* device allocation failed */
@@ -40,7 +43,7 @@ extern "C" {
 #define JGS2_E_INFEASIBLE -6  /* a vertex is on or behind a contact plane */
 #define JGS2_E_NONFINITE  -7  /* NaN/Inf appeared in the residual */
 
-/* Local system of a vertex sub-problem (Sec. 7.1: one sub-problem per vertex,
+/* Local system of a vertex sub-problem (Sec. 8.1: one sub-problem per vertex,
  * N_i = 3).
  *   JGS2_PLAIN    A_i = H_ii (assembled diagonal block), b_i = g_i: the plain
  *                 per-vertex Newton relaxation without overshoot correction.
@@ -48,11 +51,17 @@ extern "C" {
  *                 R_a Ubar_{i,a} R_i^T (Eq. tilde_phi): incident elements and
  *                 one-ring gradients exactly, remote elements by the
  *                 cubature samples of Eq. cubature (reading R3, see the
- *                 design notes).                                            */
+ *                 design notes).
+ *   JGS2_DAMPER   A_i = H_ii + sum_s w_s Phi_s^T H_s Phi_s over the cubature
+ *                 samples (the sampled reduced Hessian of Eq. cubature as a
+ *                 damper on the local solve, Sec. 5's closing remark),
+ *                 b_i = g_i (the sampled gradient left out).  Uses the same
+ *                 correction tables as JGS2_CUBATURE.                       */
 #define JGS2_PLAIN     0
 #define JGS2_CUBATURE  3
+#define JGS2_DAMPER    4
 
-/* Parallel order (Sec. 7.1): Jacobi (all vertices from one iterate) or
+/* Parallel order (Sec. 8.1): Jacobi (all vertices from one iterate) or
  * coloured Gauss-Seidel (greedy colours in ascending order; gradients and
  * rotations refreshed before each colour). */
 #define JGS2_JACOBI    0
@@ -65,7 +74,7 @@ typedef struct jgs2_solver jgs2_solver;
 typedef struct jgs2_params {
     double  dt;                 /* time step h [s] */
     double  gravity[3];         /* f_ext / m [m/s^2] */
-    int32_t variant;            /* JGS2_PLAIN or JGS2_CUBATURE */
+    int32_t variant;            /* JGS2_PLAIN, JGS2_CUBATURE or JGS2_DAMPER */
     int32_t order;              /* JGS2_JACOBI or JGS2_GS */
     double  omega;              /* step scale: x_i += omega dx_i (1 = none) */
     double  rel_tol;            /* stop when |g| / |g(x0)| <= rel_tol */
@@ -84,14 +93,14 @@ typedef struct jgs2_params {
 
 typedef struct jgs2_step_stats {
     int32_t sweeps;             /* sweeps performed this step (the most of any body) */
-    int32_t status;             /* JGS2_OK, JGS2_E_DIVERGED, ... */
+    int32_t status;             /* JGS2_OK, JGS2_NOT_CONVERGED, JGS2_E_DIVERGED, ... */
     double  r0;                 /* |g(x0)| over free DOFs */
     double  r_final;            /* largest |g_b(x)| / |g_b(x0)| over bodies at the end */
     double  seconds;            /* device time of the step (HIP events) */
     int32_t ls_halvings;        /* energy backtracking halvings this step */
     int32_t reserved;
     double  dx_norm;            /* |x_k - x_{k-1}| over free DOFs of the last sweep [m]
-                                   (the convergence measure of Sec. 7 / Table 1) */
+                                   (the convergence measure of Sec. 8 / Table 1) */
 } jgs2_step_stats;
 
 typedef struct jgs2_adjoint_stats {
@@ -115,15 +124,22 @@ int32_t jgs2_create(const jgs2_params* p, jgs2_solver** out);
 void    jgs2_destroy(jgs2_solver* s);
 const char* jgs2_last_error(const jgs2_solver* s);
 
-/* Replaces the parameters; the mesh, material and correction stay. */
+/* Replaces the parameters; the mesh and material stay.  The correction
+ * stays unless dt changes: the rest Hessian it is built from carries the
+ * inertia term M / h^2 (Sec. 6 with Sec. 3), so a new dt discards it
+ * (JGS2_CUBATURE steps then return JGS2_E_NOT_READY until the next
+ * precompute or import).  dt and gravity cannot change inside a step. */
 int32_t jgs2_set_params(jgs2_solver* s, const jgs2_params* p);
 /* Orders all later work on the HIP stream `stream` (a hipStream_t). */
 int32_t jgs2_set_stream(jgs2_solver* s, void* stream);
 
 /* Mesh: nV rest positions X (nV x 3, metres), nT tets (nT x 4) with positive
  * orientation, pinned[nV] (1 = held at its rest position).  Builds vertex
- * adjacency, the greedy colouring and the device layout.  Invalidates
- * material, correction and state. */
+ * adjacency (sub-problems sit at vertices, Sec. 8.1), the greedy colouring
+ * of the Gauss-Seidel groups (Sec. 8.1) and the device layout.  Invalidates
+ * material, correction and state.  Errors: JGS2_E_INVALID for empty or
+ * non-finite input, out-of-range ids, inverted tets or free vertices that
+ * belong to no tet. */
 int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X,
                          int32_t nT, const int32_t* tets, const uint8_t* pinned);
 
@@ -134,7 +150,10 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X,
  * over the body's free vertices only) and stops sweeping (its vertices are
  * skipped) once that reaches rel_tol at a residual check, so each body gets
  * exactly the sweeps it would get alone.  upload_mesh resets to one body.
- * The energy line search is refused with more than one body. */
+ * The energy line search is refused with more than one body.  Any failure
+ * (including a rejected argument) leaves the handle without body tables:
+ * steps, residuals and body statistics return JGS2_E_NOT_READY until a
+ * later call succeeds. */
 int32_t jgs2_set_bodies(jgs2_solver* s, int32_t n_bodies, const int32_t* body_of_vertex);
 /* Per body at the last residual check of the current or last step: sweeps
  * done (sweeps, n_bodies entries) and |g_b| / |g_b(x0)| (rel). */
@@ -161,10 +180,15 @@ int32_t jgs2_set_streaming(jgs2_solver* s, int32_t mode);
 int32_t jgs2_autotune(jgs2_solver* s, int32_t sweeps, int32_t* lanes_per_vertex, int32_t* block, double* ms);
 
 /* Per-tet Young's modulus E [Pa], Poisson ratio nu and density rho
- * [kg/m^3] (stable Neo-Hookean, Sec. 7 / Table 1 caption).  Lumped masses
+ * [kg/m^3] (stable Neo-Hookean, Sec. 8 / Table 1 caption).  Lumped masses
  * follow.  Invalidates the correction. */
 int32_t jgs2_set_material(jgs2_solver* s, const double* E, const double* nu,
                           const double* rho);
+/* The same with E_t = exp(log_E[t]): the parametrisation the rollout's
+ * stiffness cotangent thetabar refers to.  JGS2_E_INVALID on a non-finite
+ * log_E. */
+int32_t jgs2_set_material_log_e(jgs2_solver* s, const double* log_E, const double* nu,
+                                const double* rho);
 
 /* Precompute of the overshoot correction on the GPU (Secs. 5-6): rest
  * Hessian, its banded Cholesky factor, training poses (smallest
@@ -203,8 +227,9 @@ int32_t jgs2_get_state(jgs2_solver* s, double* x, double* v);
 
 /* One implicit-Euler step (Sec. 3): z = xhat + h vhat + h^2 g, x0 = xhat,
  * sweeps until |g|/|g(x0)| <= rel_tol or max_sweeps, then v = (x - xhat)/h.
- * On JGS2_E_DIVERGED / NONFINITE / INFEASIBLE the state is left at the
- * start of the step. */
+ * Returns JGS2_NOT_CONVERGED (state and velocity kept, stats filled) when
+ * some body is still above rel_tol after max_sweeps.  On JGS2_E_DIVERGED /
+ * NONFINITE / INFEASIBLE the state is left at the start of the step. */
 int32_t jgs2_step(jgs2_solver* s, jgs2_step_stats* stats);
 /* The same step in pieces: begin (z, x0, r0), n sweeps (relative residual
  * of the resulting iterate in *rel_res, may be NULL), end (velocity). */
@@ -229,19 +254,24 @@ int32_t jgs2_residual(jgs2_solver* s, double* abs_res, double* rel_res);
  *
  * jgs2_rollout runs n_steps forward steps from the current state (as
  * jgs2_step, same parameters) and keeps the state at every ckpt_every-th
- * step on the device.  jgs2_rollout_backward pulls (xbar_N, vbar_N) (nV x 3;
- * vbar may be NULL for zero) back through the whole rollout, recomputing the
- * steps of each checkpoint segment from its checkpoint, and writes
- * thetabar (nT), xbar_0 and vbar_0 (nV x 3 each; any may be NULL).  The
- * state is left at the end of the rollout.  set_state, set_material,
- * set_params and upload_mesh discard the rollout (JGS2_E_NOT_READY).  A
- * recomputed step or adjoint solve that diverges (residual past 1e8 x its
- * scale) or turns non-finite returns JGS2_E_DIVERGED / JGS2_E_NONFINITE;
- * an adjoint solve that reaches adj_max_sweeps is not an error, and
- * stats->max_rel_res reports the largest final relative residual. */
+ * step on the device; it returns JGS2_NOT_CONVERGED (rollout kept) when a
+ * step stopped at max_sweeps.  jgs2_rollout_backward pulls (xbar_N, vbar_N)
+ * (nV x 3; vbar may be NULL for zero) back through the whole rollout,
+ * recomputing the steps of each checkpoint segment from its checkpoint, and
+ * writes thetabar (nT, the cotangent of theta_e = log E_e), xbar_0 and
+ * vbar_0 (nV x 3 each) and ubar (3: the cotangent of one initial velocity
+ * shared by all free vertices, i.e. vbar_0 summed over free vertices in
+ * ascending order, FP64); any output may be NULL.  The state is left at the
+ * end of the rollout.  set_state, set_material, set_params and upload_mesh
+ * discard the rollout (JGS2_E_NOT_READY).  A recomputed step or adjoint
+ * solve that diverges (residual past 1e8 x its scale) or turns non-finite
+ * returns JGS2_E_DIVERGED / JGS2_E_NONFINITE; one that stops at its sweep
+ * cap above its tolerance makes the call return JGS2_NOT_CONVERGED with
+ * every output written, and stats->max_rel_res reports the largest final
+ * relative residual of the adjoint solves. */
 int32_t jgs2_rollout(jgs2_solver* s, int32_t n_steps, int32_t ckpt_every, jgs2_step_stats* last);
 int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* vbar, double* thetabar,
-                              double* xbar0, double* vbar0, jgs2_adjoint_stats* stats);
+                              double* xbar0, double* vbar0, double* ubar, jgs2_adjoint_stats* stats);
 
 /* Incremental potential E at the current iterate (FP64 sum of FP32 terms). */
 int32_t jgs2_energy(jgs2_solver* s, double* e);

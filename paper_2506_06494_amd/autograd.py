@@ -17,8 +17,7 @@ class Simulate(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, log_E, u, solver, nu, rho, n_steps, ckpt_every):
-        E = np.exp(log_E.detach().cpu().double().numpy())
-        solver.set_material(E, nu, rho)
+        solver.set_material_log_e(log_E.detach().cpu().double().numpy(), nu, rho)
         v0 = np.zeros((solver.nV, 3))
         v0[~solver.pinned] = u.detach().cpu().double().numpy()[None, :]
         solver.set_state(solver.X, v0)
@@ -31,8 +30,7 @@ class Simulate(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gx):
         s = ctx.solver
-        th, _, vb0, stats = s.rollout_backward(gx.detach().cpu().double().numpy())
+        th, _, _, stats = s.rollout_backward(gx.detach().cpu().double().numpy())
         ctx.stats = stats
-        ubar = vb0[~s.pinned].sum(0)
-        return (torch.from_numpy(th).to(ctx.dev), torch.from_numpy(ubar).to(ctx.dev),
+        return (torch.from_numpy(th).to(ctx.dev), torch.from_numpy(stats["ubar"]).to(ctx.dev),
                 None, None, None, None, None)

@@ -114,6 +114,10 @@ struct jgs2_solver {
     std::vector<double> mass;
 
     bool have_mesh = false, have_material = false, have_corr = false, have_state = false;
+    // body tables (stop flags, chunked residual sums, readback slots) are
+    // complete: cleared on entry to set_bodies, set after its last upload
+    bool have_bodies = false;
+    double corr_dt = 0.0;             // time step the correction was built for
     bool in_step = false, phase1_valid = false;
     int S = 0;
     std::vector<double> fit;          // per free vertex NNLS residual

@@ -1,7 +1,7 @@
 // Small dense math for the JGS2 kernels (device and host), templated on the
 // scalar type: float in the sweeps, double in the precompute.
 //
-// Material: stable Neo-Hookean (Sec. 7 / Table 1 caption); the energy used
+// Material: stable Neo-Hookean (Sec. 8 / Table 1 caption); the energy used
 // is Psi = mu/2 (|F|^2 - 3) - mu (J - 1) + lam/2 (J - 1)^2 with
 // mu = mu_L, lam = lam_L + mu_L, which linearises to linear elasticity with
 // the given (E, nu).  Quantities named v* are pre-multiplied by the tet

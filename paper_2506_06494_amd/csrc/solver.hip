@@ -167,7 +167,10 @@ template <typename T> static int upload(jgs2_solver* s, T* d, const T* h, size_t
 static int validate_params(const jgs2_params* p, std::string& why) {
     if (!p) { why = "params is NULL"; return JGS2_E_INVALID; }
     if (!(p->dt > 0) || !std::isfinite(p->dt)) { why = "dt must be positive"; return JGS2_E_INVALID; }
-    if (p->variant != JGS2_PLAIN && p->variant != JGS2_CUBATURE) { why = "unknown variant"; return JGS2_E_INVALID; }
+    if (p->variant != JGS2_PLAIN && p->variant != JGS2_CUBATURE && p->variant != JGS2_DAMPER) {
+        why = "unknown variant";
+        return JGS2_E_INVALID;
+    }
     if (p->order != JGS2_JACOBI && p->order != JGS2_GS) { why = "unknown order"; return JGS2_E_INVALID; }
     if (!(p->omega > 0) || !std::isfinite(p->omega)) { why = "omega must be positive"; return JGS2_E_INVALID; }
     if (p->max_sweeps < 0 || p->check_every < 1) { why = "bad sweep limits"; return JGS2_E_INVALID; }
@@ -310,6 +313,8 @@ int32_t jgs2_set_params(jgs2_solver* s, const jgs2_params* p) {
     s->p = *p;
     s->ro_valid = false;
     drop_graphs(s);
+    // the correction's rest Hessian carries M / h^2: it belongs to the old step
+    if (dt_changed) s->have_corr = false;
     if (dt_changed && s->have_material) {
         if ((r = upload_material_records(s)) != JGS2_OK) return r;
     }
@@ -331,7 +336,7 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
     for (int64_t i = 0; i < 4LL * nT; ++i)
         if (tets[i] < 0 || tets[i] >= nV) return s->fail(JGS2_E_INVALID, "tet vertex id out of range");
     free_device(s);
-    s->have_mesh = s->have_material = s->have_corr = s->have_state = s->in_step = false;
+    s->have_mesh = s->have_material = s->have_corr = s->have_state = s->in_step = s->have_bodies = false;
     s->nV = nV; s->nT = nT;
     s->X.assign(X, X + 3 * (size_t)nV);
     s->tets.assign(tets, tets + 4 * (size_t)nT);
@@ -517,6 +522,18 @@ int32_t jgs2_set_material(jgs2_solver* s, const double* E, const double* nu, con
     s->have_corr = false;
     s->ro_valid = false;
     return JGS2_OK;
+}
+
+int32_t jgs2_set_material_log_e(jgs2_solver* s, const double* log_E, const double* nu, const double* rho) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_mesh) return s->fail(JGS2_E_NOT_READY, "no mesh");
+    if (!log_E) return s->fail(JGS2_E_INVALID, "NULL material array");
+    std::vector<double> E((size_t)s->nT);
+    for (int t = 0; t < s->nT; ++t) {
+        if (!std::isfinite(log_E[t])) return s->fail(JGS2_E_INVALID, "non-finite log E");
+        E[t] = std::exp(log_E[t]);
+    }
+    return jgs2_set_material(s, E.data(), nu, rho);
 }
 
 int32_t jgs2_get_ring_sizes(jgs2_solver* s, int32_t* nVf, int32_t* sizes) {
@@ -707,7 +724,7 @@ static void keep_iterate(jgs2_solver* s) {
 static void residual_launches(jgs2_solver* s, int mask_k) {
     SweepArgs a;
     build_sweep_args(s, a);
-    launch_phase1(s, a, s->p.variant == JGS2_CUBATURE, mask_k > 0);
+    launch_phase1(s, a, s->p.variant != JGS2_PLAIN, mask_k > 0);
     if (mask_k > 0)
         launch_check(s, mask_k);  // per-body residuals, stop flags, update norm
     else
@@ -749,8 +766,8 @@ static bool ready_to_step(jgs2_solver* s) {
     if (!s->have_mesh || !s->have_material) { s->err = "no mesh or material"; return false; }
     if (!s->have_state) { s->err = "no state"; return false; }
     // the sweep kernels read the bodies' stop flags (a failed set_bodies leaves none)
-    if (!s->d_body_on || !s->d_rb) { s->err = "no body tables (set_bodies failed)"; return false; }
-    if (s->p.variant == JGS2_CUBATURE && !s->have_corr) { s->err = "no correction (precompute or import)"; return false; }
+    if (!s->have_bodies) { s->err = "no body tables (set_bodies failed)"; return false; }
+    if (s->p.variant != JGS2_PLAIN && !s->have_corr) { s->err = "no correction (precompute or import)"; return false; }
     return true;
 }
 
@@ -834,7 +851,7 @@ static int line_search(jgs2_solver* s) {
 static int sweep_once(jgs2_solver* s) {
     SweepArgs a;
     build_sweep_args(s, a);
-    const bool cub = s->p.variant == JGS2_CUBATURE;
+    const bool cub = s->p.variant != JGS2_PLAIN;  // the two-phase corrected sweeps
     if (s->p.order == JGS2_JACOBI) {
         if (cub) {
             if (!s->phase1_valid) launch_phase1(s, a, true, true);
@@ -1071,11 +1088,14 @@ int32_t jgs2_step(jgs2_solver* s, jgs2_step_stats* st) {
     HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
     int most = 0;
     for (int b : bsw) most = std::max(most, b);
-    loc.sweeps = most; loc.status = JGS2_OK; loc.r0 = s->r0; loc.r_final = rel; loc.seconds = ms * 1e-3;
+    // a body still iterating at the last check reached max_sweeps above rel_tol
+    const int status = s->n_active > 0 ? JGS2_NOT_CONVERGED : JGS2_OK;
+    loc.sweeps = most; loc.status = status; loc.r0 = s->r0; loc.r_final = rel; loc.seconds = ms * 1e-3;
     loc.ls_halvings = s->ls_halvings;
     loc.dx_norm = s->dx_norm;
     if (st) *st = loc;
-    return JGS2_OK;
+    if (status != JGS2_OK) s->err = "max_sweeps reached above rel_tol";
+    return status;
 }
 
 int32_t jgs2_residual(jgs2_solver* s, double* abs_res, double* rel_res) {
@@ -1101,6 +1121,7 @@ int32_t jgs2_energy(jgs2_solver* s, double* e) {
 int32_t jgs2_get_phase1(jgs2_solver* s, double* g, double* R) {
     if (!s) return JGS2_E_INVALID;
     if (!s->have_mesh || !s->have_material || !s->have_state) return s->fail(JGS2_E_NOT_READY, "no state");
+    if (!s->have_bodies) return s->fail(JGS2_E_NOT_READY, "no body tables (set_bodies failed)");
     SweepArgs a;
     build_sweep_args(s, a);
     launch_phase1(s, a, true);
@@ -1262,9 +1283,13 @@ int32_t jgs2_rollout(jgs2_solver* s, int32_t n_steps, int32_t ckpt_every, jgs2_s
         return r;
     jgs2_step_stats st;
     std::memset(&st, 0, sizeof(st));
+    bool capped = false;
     for (int n = 0; n < n_steps; ++n) {
         if (n % ckpt_every == 0 && (r = save_checkpoint(s, n / ckpt_every)) != JGS2_OK) return r;
-        if ((r = jgs2_step(s, &st)) != JGS2_OK) {
+        r = jgs2_step(s, &st);
+        if (r == JGS2_NOT_CONVERGED) {
+            capped = true;
+        } else if (r != JGS2_OK) {
             if (last) *last = st;
             return r;
         }
@@ -1276,11 +1301,15 @@ int32_t jgs2_rollout(jgs2_solver* s, int32_t n_steps, int32_t ckpt_every, jgs2_s
     s->ro_nck = n_ck;
     s->ro_valid = true;
     if (last) *last = st;
+    if (capped) {
+        s->err = "a step reached max_sweeps above rel_tol";
+        return JGS2_NOT_CONVERGED;
+    }
     return JGS2_OK;
 }
 
 int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* vbar, double* thetabar,
-                              double* xbar0, double* vbar0, jgs2_adjoint_stats* stats) {
+                              double* xbar0, double* vbar0, double* ubar, jgs2_adjoint_stats* stats) {
     if (!s) return JGS2_E_INVALID;
     if (!s->ro_valid) return s->fail(JGS2_E_NOT_READY, "no rollout to differentiate");
     if (!xbar) return s->fail(JGS2_E_INVALID, "NULL xbar");
@@ -1319,12 +1348,17 @@ int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* 
     HIPCHK(hipMemsetAsync(s->d_ynext, 0, nV * sizeof(float4), s->stream));
     HIPCHK(hipMemsetAsync(s->d_thbar, 0, (size_t)s->nT * sizeof(double), s->stream));
     int status = JGS2_OK;
+    bool capped = false;  // a recomputed step or an adjoint solve ended at its sweep cap
     for (int k = s->ro_nck - 1; k >= 0 && status == JGS2_OK; --k) {
         const int n0 = k * s->ro_every, n1 = std::min(n0 + s->ro_every, s->ro_steps);
         if ((r = load_checkpoint(s, k)) != JGS2_OK) return r;
         for (int n = n0; n < n1 && status == JGS2_OK; ++n) {
             jgs2_step_stats st;
             status = jgs2_step(s, &st);
+            if (status == JGS2_NOT_CONVERGED) {
+                capped = true;
+                status = JGS2_OK;
+            }
             loc.forward_sweeps += st.sweeps;
             if (status == JGS2_OK && (r = copy_v4(s, s->d_seg + (size_t)(n - n0) * nV, s->d_uhat)) != JGS2_OK)
                 return r;
@@ -1334,6 +1368,7 @@ int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* 
             double rel = 0.0;
             status = adjoint_solve(s, xstar, &loc.adjoint_sweeps, &rel);
             if (status != JGS2_OK) break;
+            if (rel > s->p.adj_rel_tol) capped = true;
             loc.max_rel_res = std::max(loc.max_rel_res, rel);
             launch_param_grad(s, xstar, s->d_y, s->d_thbar);
             launch_adj_vec(s, s->d_y, s->d_xbar, s->d_vbar, s->d_rhs);
@@ -1351,18 +1386,28 @@ int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* 
         HIPCHK(hipMemcpyAsync(vb.data(), s->d_vbar, nV * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
         if (thetabar) std::memcpy(thetabar, th.data(), th.size() * sizeof(double));
+        // cotangent of one initial velocity shared by every free vertex:
+        // the sum of vbar_0 over free vertices, in ascending vertex order
+        double u3[3] = {0.0, 0.0, 0.0};
         for (size_t a = 0; a < nV; ++a) {
             const float x3[3] = {xb[a].x, xb[a].y, xb[a].z}, v3[3] = {vb[a].x, vb[a].y, vb[a].z};
             for (int i = 0; i < 3; ++i) {
                 if (xbar0) xbar0[3 * a + i] = x3[i];
                 if (vbar0) vbar0[3 * a + i] = v3[i];
+                if (!s->pinned[a]) u3[i] += (double)v3[i];
             }
         }
+        if (ubar)
+            for (int i = 0; i < 3; ++i) ubar[i] = u3[i];
     }
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.0f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     loc.seconds = ms * 1e-3;
+    if (status == JGS2_OK && capped) {
+        status = JGS2_NOT_CONVERGED;
+        s->err = "a recomputed step or an adjoint solve reached its sweep cap";
+    }
     loc.status = status;
     if (stats) *stats = loc;
     // a recompute that differs from the rollout would leave ro_valid wrong;
@@ -1379,6 +1424,12 @@ extern "C" {
 
 int32_t jgs2_set_bodies(jgs2_solver* s, int32_t n_bodies, const int32_t* body_of_vertex) {
     if (!s) return JGS2_E_INVALID;
+    // the tables below are replaced one by one: until the last upload has
+    // succeeded nothing may read them, and a failure leaves none
+    s->have_bodies = false;
+    s->in_step = false;
+    s->ro_valid = false;
+    drop_graphs(s);
     if (!s->have_mesh && s->nV == 0) return s->fail(JGS2_E_NOT_READY, "no mesh");
     if (n_bodies < 1 || !body_of_vertex) return s->fail(JGS2_E_INVALID, "n_bodies must be >= 1");
     if (n_bodies > 1 && s->p.line_search) return s->fail(JGS2_E_INVALID, "the energy line search needs a single body");
@@ -1452,15 +1503,14 @@ int32_t jgs2_set_bodies(jgs2_solver* s, int32_t n_bodies, const int32_t* body_of
     s->r2_host.assign(nb, 0.0);
     s->r0sq_host.assign(nb, 0.0);
     s->n_active = n_bodies;
-    s->in_step = false;
-    s->ro_valid = false;
-    drop_graphs(s);
+    s->have_bodies = true;
     return JGS2_OK;
 }
 
 int32_t jgs2_get_body_stats(jgs2_solver* s, int32_t* n_bodies, int32_t* sweeps, double* rel) {
     if (!s) return JGS2_E_INVALID;
     if (!s->have_mesh) return s->fail(JGS2_E_NOT_READY, "no mesh");
+    if (!s->have_bodies) return s->fail(JGS2_E_NOT_READY, "no body tables (set_bodies failed)");
     if (n_bodies) *n_bodies = s->n_bodies;
     if (sweeps) {
         HIPCHK(hipMemcpyAsync(sweeps, s->d_body_sweeps, (size_t)s->n_bodies * sizeof(int), hipMemcpyDeviceToHost,

@@ -354,6 +354,12 @@ __device__ __forceinline__ void corotate(const float* U, const float* Ri, const 
             Phi[3 * i + j] = Ra[3 * i] * T9[j] + Ra[3 * i + 1] * T9[3 + j] + Ra[3 * i + 2] * T9[6 + j];
 }
 
+// DAMPER (reading of Sec. 5's closing remark: the sampled reduced Hessian
+// is a damper on the plain local solve, the sampled gradient is left out):
+//   A_i = H_ii + H^B_i + sum_s w_s U_s^T H_s U_s,   b_i = g_i,
+// i.e. the incident tets contribute their own-corner blocks only (the basis
+// restricted to vertex i) and the one-ring rows are not read.
+template <bool DAMPER>
 __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
     __shared__ float sPhi[VPB][KMAX][9];
     const int lane = threadIdx.x % LPV;
@@ -371,7 +377,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
     float A6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, b[3] = {0.f, 0.f, 0.f};
 
     // one-ring rows: Phi_{i,a} into LDS, gradient projection
-    const int nr = active ? a.ring_n[f] : 0;
+    const int nr = (active && !DAMPER) ? a.ring_n[f] : 0;
     for (int k = lane; k < nr; k += LPV) {
         const int av = a.ring[(size_t)f * a.K + k];
         float U[9], Ra[9], Phi[9];
@@ -405,7 +411,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
             if (s == SLOT_SELF) {
 #pragma unroll
                 for (int q = 0; q < 9; ++q) Phi[c][q] = (q % 4 == 0) ? 1.0f : 0.0f;
-            } else if (s == SLOT_NONE) {
+            } else if (DAMPER || s == SLOT_NONE) {
 #pragma unroll
                 for (int q = 0; q < 9; ++q) Phi[c][q] = 0.0f;
             } else {
@@ -438,7 +444,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
                 for (int q = 0; q < 9; ++q) U[q] = rec[(5 + 9 * c + q) * a.S + s];
                 load_rot(a.R, av, Ra);
                 corotate(U, Ri, Ra, Phi[c]);
-                const float gc = rec[(1 + c) * a.S + s];
+                const float gc = DAMPER ? 0.0f : rec[(1 + c) * a.S + s];
                 if (gc != 0.0f) {
                     const float4 ga = a.g[av];
 #pragma unroll
@@ -974,7 +980,10 @@ void launch_phase1(jgs2_solver* s, const SweepArgs& a, bool want_R, bool gate) {
 void launch_phase2_cubature(jgs2_solver* s, const SweepArgs& a) {
     const int nb = n_blocks_for(a);
     if (nb == 0) return;
-    launch(s, JGS2_K_PHASE2, k_phase2_cubature, dim3(nb), dim3(BLOCK), a);
+    if (s->p.variant == JGS2_DAMPER)
+        launch(s, JGS2_K_PHASE2, k_phase2_cubature<true>, dim3(nb), dim3(BLOCK), a);
+    else
+        launch(s, JGS2_K_PHASE2, k_phase2_cubature<false>, dim3(nb), dim3(BLOCK), a);
 }
 
 // Launch of a plain or linear sweep kernel in the tuned shape (W lanes per

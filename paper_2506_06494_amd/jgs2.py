@@ -14,11 +14,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libjgs2.so")
 
 OK, E_INVALID, E_OOM, E_HIP, E_NOT_READY, E_DIVERGED, E_INFEASIBLE, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
-PLAIN, CUBATURE = 0, 3
+NOT_CONVERGED = 1
+PLAIN, CUBATURE, DAMPER = 0, 3, 4
 JACOBI, GS = 0, 1
 MAX_PLANES = 8
 
-STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -4: "NOT_READY", -5: "DIVERGED",
+STATUS_NAMES = {1: "NOT_CONVERGED", 0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -4: "NOT_READY", -5: "DIVERGED",
                 -6: "INFEASIBLE", -7: "NONFINITE"}
 
 
@@ -47,7 +48,7 @@ EXPORTS = ["jgs2_default_params", "jgs2_create", "jgs2_destroy", "jgs2_last_erro
            "jgs2_set_state", "jgs2_get_state", "jgs2_step", "jgs2_begin_step", "jgs2_iterate", "jgs2_end_step",
            "jgs2_residual", "jgs2_energy", "jgs2_get_phase1", "jgs2_get_coloring", "jgs2_set_profiling",
            "jgs2_kernel_times", "jgs2_rollout", "jgs2_rollout_backward", "jgs2_set_bodies", "jgs2_get_body_stats",
-           "jgs2_set_tuning", "jgs2_get_tuning", "jgs2_autotune", "jgs2_set_streaming"]
+           "jgs2_set_tuning", "jgs2_get_tuning", "jgs2_autotune", "jgs2_set_streaming", "jgs2_set_material_log_e"]
 
 KERNELS = ["phase1", "phase2", "plain", "commit", "reduce", "predict", "velocity", "energy", "linear", "paramgrad",
            "adjvec"]
@@ -74,6 +75,7 @@ def load(path: str = LIB_PATH):
         "jgs2_set_stream": (C.c_int32, [C.c_void_p, C.c_void_p]),
         "jgs2_upload_mesh": (C.c_int32, [C.c_void_p, C.c_int32, d, C.c_int32, i32, u8]),
         "jgs2_set_material": (C.c_int32, [C.c_void_p, d, d, d]),
+        "jgs2_set_material_log_e": (C.c_int32, [C.c_void_p, d, d, d]),
         "jgs2_precompute": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64]),
         "jgs2_import_correction": (C.c_int32, [C.c_void_p, C.c_int32, d, i32, d, d]),
         "jgs2_export_correction": (C.c_int32, [C.c_void_p, C.c_int32, d, i32, d, d, d]),
@@ -92,7 +94,7 @@ def load(path: str = LIB_PATH):
         "jgs2_set_profiling": (C.c_int32, [C.c_void_p, C.c_int32]),
         "jgs2_kernel_times": (C.c_int32, [C.c_void_p, d, P(C.c_int64)]),
         "jgs2_rollout": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, P(StepStats)]),
-        "jgs2_rollout_backward": (C.c_int32, [C.c_void_p, d, d, d, d, d, P(AdjointStats)]),
+        "jgs2_rollout_backward": (C.c_int32, [C.c_void_p, d, d, d, d, d, d, P(AdjointStats)]),
         "jgs2_set_bodies": (C.c_int32, [C.c_void_p, C.c_int32, i32]),
         "jgs2_get_body_stats": (C.c_int32, [C.c_void_p, i32, i32, d]),
         "jgs2_set_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
@@ -177,7 +179,9 @@ class Solver:
         self.nV = self.nT = 0
 
     def _chk(self, r):
-        if r != OK:
+        """Raises on a failure code; NOT_CONVERGED (a completed call whose
+        solve stopped at its sweep cap) is returned, not raised."""
+        if r < OK:
             raise JGS2Error(r, self.lib.jgs2_last_error(self.h).decode())
         return r
 
@@ -216,6 +220,12 @@ class Solver:
     def set_material(self, E, nu, rho):
         arr = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (self.nT,))) for a in (E, nu, rho)]
         self._chk(self.lib.jgs2_set_material(self.h, *[_dptr(a) for a in arr]))
+
+    def set_material_log_e(self, log_E, nu, rho):
+        """Per-tet E = exp(log_E), taken inside the library."""
+        arr = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (self.nT,)))
+               for a in (log_E, nu, rho)]
+        self._chk(self.lib.jgs2_set_material_log_e(self.h, *[_dptr(a) for a in arr]))
 
     def precompute(self, samples=4, n_cand=64, seed=0):
         self._chk(self.lib.jgs2_precompute(self.h, samples, n_cand, C.c_uint64(seed)))
@@ -328,23 +338,25 @@ class Solver:
         """n_steps forward steps from the current state, keeping device
         checkpoints every ckpt_every steps; returns the last step's stats."""
         st = StepStats()
-        self._chk(self.lib.jgs2_rollout(self.h, int(n_steps), int(ckpt_every), C.byref(st)))
-        return dict(sweeps=st.sweeps, r0=st.r0, r_final=st.r_final, seconds=st.seconds)
+        r = self._chk(self.lib.jgs2_rollout(self.h, int(n_steps), int(ckpt_every), C.byref(st)))
+        return dict(status=r, sweeps=st.sweeps, r0=st.r0, r_final=st.r_final, seconds=st.seconds)
 
     def rollout_backward(self, xbar, vbar=None):
         """Pulls (xbar_N, vbar_N) back through the last rollout; returns
-        (thetabar (nT,), xbar_0, vbar_0, stats)."""
+        (thetabar (nT,), xbar_0, vbar_0, stats); stats["ubar"] is the
+        cotangent of one initial velocity shared by the free vertices."""
         xbar = np.ascontiguousarray(xbar, dtype=np.float64).reshape(self.nV, 3)
         vb = None if vbar is None else np.ascontiguousarray(vbar, dtype=np.float64).reshape(self.nV, 3)
         th = np.zeros(self.nT)
         xb0 = np.zeros((self.nV, 3))
         vb0 = np.zeros((self.nV, 3))
+        ub = np.zeros(3)
         st = AdjointStats()
-        self._chk(self.lib.jgs2_rollout_backward(self.h, _dptr(xbar), None if vb is None else _dptr(vb), _dptr(th),
-                                                 _dptr(xb0), _dptr(vb0), C.byref(st)))
-        return th, xb0, vb0, dict(steps=st.steps, adjoint_sweeps=st.adjoint_sweeps,
+        r = self._chk(self.lib.jgs2_rollout_backward(self.h, _dptr(xbar), None if vb is None else _dptr(vb),
+                                                     _dptr(th), _dptr(xb0), _dptr(vb0), _dptr(ub), C.byref(st)))
+        return th, xb0, vb0, dict(status=r, steps=st.steps, adjoint_sweeps=st.adjoint_sweeps,
                                   forward_sweeps=st.forward_sweeps, max_rel_res=st.max_rel_res,
-                                  seconds=st.seconds)
+                                  seconds=st.seconds, ubar=ub)
 
     def energy(self):
         e = C.c_double()

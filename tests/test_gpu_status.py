@@ -1,0 +1,111 @@
+"""Status and state handling of the C ABI on the GPU: failed body tables,
+steps that stop at the sweep cap, a dt change discarding the correction,
+the log-E material entry and the shared initial-velocity cotangent."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2506_06494_amd import jgs2
+
+from gpu_util import make_solver, oracle_tables_to_import
+
+pytestmark = pytest.mark.gpu
+
+
+def raw_step(s):
+    st = jgs2.StepStats()
+    r = s.lib.jgs2_step(s.h, C.byref(st))
+    return r, st
+
+
+def test_failed_set_bodies_leaves_no_tables(tiny):
+    sc, mdl, tab = tiny
+    s = make_solver(sc)
+    s.set_state(sc.x0, sc.v0)
+    body = np.zeros(mdl.nV, dtype=np.int32)
+    body[mdl.tets[0, 0]] = 1                     # tet 0 now spans two bodies
+    with pytest.raises(jgs2.JGS2Error) as e:
+        s.set_bodies(body)
+    assert e.value.code == jgs2.E_INVALID
+    r, st = raw_step(s)
+    assert r == jgs2.E_NOT_READY and st.status == jgs2.E_NOT_READY
+    n = C.c_int32()
+    assert s.lib.jgs2_get_body_stats(s.h, C.byref(n), None, None) == jgs2.E_NOT_READY
+    a, b = C.c_double(), C.c_double()
+    assert s.lib.jgs2_residual(s.h, C.byref(a), C.byref(b)) == jgs2.E_NOT_READY
+    x_before, _ = s.get_state()
+    np.testing.assert_array_equal(x_before, sc.x0)  # nothing moved
+    s.set_bodies(np.zeros(mdl.nV, dtype=np.int32))
+    out = s.step()
+    assert out["status"] == jgs2.OK
+
+
+def test_sweep_cap_is_reported_and_state_kept(tiny):
+    sc, mdl, tab = tiny
+    s = make_solver(sc, variant=jgs2.PLAIN, order=jgs2.GS, max_sweeps=3, check_every=1)
+    s.set_state(sc.x0, sc.v0)
+    out = s.step()
+    assert out["status"] == jgs2.NOT_CONVERGED
+    assert out["sweeps"] == 3 and out["r_final"] > 1e-5
+    x, v = s.get_state()
+    assert np.abs(x - sc.x0).max() > 0
+    np.testing.assert_allclose(v, (x - sc.x0) / sc.dt, atol=1e-6)
+    # the same with a cap that is never reached
+    s.set_params(max_sweeps=20000, check_every=16)
+    s.set_state(sc.x0, sc.v0)
+    assert s.step()["status"] == jgs2.OK
+
+
+def test_dt_change_discards_the_correction(tiny):
+    sc, mdl, tab = tiny
+    s = make_solver(sc, variant=jgs2.DAMPER, order=jgs2.GS)
+    s.import_correction(**oracle_tables_to_import(tab))
+    s.set_state(sc.x0, sc.v0)
+    s.set_params(max_sweeps=4)
+    assert s.step()["status"] in (jgs2.OK, jgs2.NOT_CONVERGED)
+    s.set_params(dt=sc.dt / 2)
+    s.set_state(sc.x0, sc.v0)
+    r, _ = raw_step(s)
+    assert r == jgs2.E_NOT_READY
+    # the same dt again keeps what is there (nothing to discard)
+    s.import_correction(**oracle_tables_to_import(tab))
+    s.set_params(dt=sc.dt / 2)
+    assert s.step()["status"] in (jgs2.OK, jgs2.NOT_CONVERGED)
+
+
+def test_log_e_material_matches_exp(tiny):
+    sc, mdl, tab = tiny
+    rng = np.random.default_rng(3)
+    logE = np.log(1e6) + rng.uniform(-0.3, 0.3, mdl.nT)
+    energies = []
+    for use_log in (False, True):
+        s = make_solver(sc)
+        if use_log:
+            s.set_material_log_e(logE, sc.nu, sc.rho)
+        else:
+            s.set_material(np.exp(logE), sc.nu, sc.rho)
+        s.set_state(sc.x0, sc.v0)
+        s.begin_step()
+        energies.append(s.energy())
+        s.close()
+    # exp in the library and in numpy may differ in the last bit
+    assert abs(energies[0] - energies[1]) <= 1e-12 * abs(energies[0])
+    s = make_solver(sc)
+    bad = logE.copy()
+    bad[5] = np.nan
+    with pytest.raises(jgs2.JGS2Error):
+        s.set_material_log_e(bad, sc.nu, sc.rho)
+
+
+def test_shared_velocity_cotangent_is_the_free_sum(tiny):
+    sc, mdl, tab = tiny
+    s = make_solver(sc, order=jgs2.GS, rel_tol=1e-6, adj_rel_tol=1e-6, check_every=16)
+    s.set_state(sc.x0, sc.v0)
+    assert s.rollout(3, ckpt_every=2)["status"] == jgs2.OK
+    rng = np.random.default_rng(11)
+    xbar = rng.standard_normal(sc.x0.shape)
+    th, xb0, vb0, st = s.rollout_backward(xbar)
+    assert st["status"] == jgs2.OK
+    ref = vb0[~mdl.pinned].astype(np.float64).sum(0)
+    np.testing.assert_allclose(st["ubar"], ref, rtol=1e-12, atol=1e-12 * np.abs(vb0).max())
