@@ -137,12 +137,16 @@ def _nnls(A, b):
     return w, float(r)
 
 
-def train_vertex(model, ring, U, G, cid, i, S=4, n_cand=64, seed=0):
-    """Greedy NNLS cubature for vertex i.
+def cubature_system(model, ring, U, G, cid, i):
+    """The NNLS system of Eq. cubature_weight for vertex i.
 
-    U: (V,3,3) rows of U-bar_i.  Returns (samples (S,), weights (S,),
-    relative residual).  Missing samples (fewer eligible elements than S)
-    are -1 with weight 0."""
+    Returns (b, column, eligible): the normalised remote reduced gradients
+    over the poses (the right-hand side, 3 n_T entries), a function giving
+    element s's normalised share of them (a column), and the mask of
+    eligible elements (not containing i, with a free corner outside the
+    closed one-ring).  Every remote vertex a is shared by the n_a elements
+    around it, all eligible, so the columns of all eligible elements sum to
+    b."""
     tets = model.tets
     nbar = np.zeros(model.nV, dtype=bool)
     nbar[ring[i]] = True
@@ -169,6 +173,17 @@ def train_vertex(model, ring, U, G, cid, i, S=4, n_cand=64, seed=0):
                 c += coef[s, k] * (G[:, a, :] @ U[a])                    # (U^T g)^T = g^T U
         return (c * scale[:, None]).ravel()
 
+    return b, column, eligible
+
+
+def train_vertex(model, ring, U, G, cid, i, S=4, n_cand=64, seed=0, trace=None):
+    """Greedy NNLS cubature for vertex i.
+
+    U: (V,3,3) rows of U-bar_i.  Returns (samples (S,), weights (S,),
+    relative residual).  Missing samples (fewer eligible elements than S)
+    are -1 with weight 0.  If ``trace`` is a list, each round appends
+    (candidates, their NNLS residuals, the pick)."""
+    b, column, eligible = cubature_system(model, ring, U, G, cid, i)
     bnorm = float(np.linalg.norm(b))
     chosen, cols = [], []
     for k in range(S):
@@ -183,6 +198,8 @@ def train_vertex(model, ring, U, G, cid, i, S=4, n_cand=64, seed=0):
         best = res.min()
         tie = res <= best + 1e-9 * best + 1e-15 * bnorm
         s_best = min(c for c, t in zip(cands, tie) if t)
+        if trace is not None:
+            trace.append((list(cands), res.copy(), s_best))
         chosen.append(s_best)
         cols.append(column(s_best))
     samples = np.full(S, -1, dtype=np.int64)

@@ -43,7 +43,8 @@ The local 3x3 solve is a Cholesky solve; if A_i is not positive definite
 Jacobi: every free vertex solves from the same iterate.  Gauss-Seidel
 ("fresh" reading): colours in ascending order; before each colour the
 gradients and rotations are recomputed at the current iterate, then all
-vertices of that colour solve (from the same iterate) and move.
+vertices of that colour solve (from the same iterate) and move.  R2D is the
+exception for rotations: they are those of the sweep's starting iterate.
 """
 import numpy as np
 import scipy.sparse.linalg as spla
@@ -273,9 +274,12 @@ class Sweeper:
         if tab is not None:
             assert np.array_equal(tab.verts, model.free_ids)
 
-    def systems(self, x, z, verts=None):
+    def systems(self, x, z, verts=None, R=None):
+        """A_i, b_i at iterate x for ``verts``; per-vertex rotations from x
+        unless given in R."""
         m = self.model
-        g, R = phase1(m, x, z)
+        g, R_x = phase1(m, x, z)
+        R = R_x if R is None else R
         Hb = m.barrier_hessian_blocks(x) if m.planes.shape[0] else None
         verts = m.free_ids if verts is None else np.asarray(verts)
         rows = m.free_index[verts]
@@ -320,10 +324,17 @@ class Sweeper:
         return xn
 
     def gauss_seidel(self, x, z, color):
+        """One coloured sweep.  Gradients, Hessians and (except for R2D)
+        rotations are taken at the current iterate before every colour.  R2D
+        keeps the rotations of the sweep's starting iterate x^k for all
+        colours (the pose the co-rotated basis is extracted from, Sec. 4.3):
+        its local system needs no other vertex's gradient, so nothing else is
+        refreshed between colours."""
         xn = x.copy()
+        R_sweep = vertex_rotations(self.model, x) if self.variant == R2D else None
         for c in range(int(color.max()) + 1):
             verts = np.nonzero(color == c)[0]
-            A, b = self.systems(xn, z, verts)
+            A, b = self.systems(xn, z, verts, R=R_sweep)
             dx = local_solve(A, b)
             xn[verts] += feasibility_clamp(self.model, xn[verts], self.omega * dx)
         return xn
