@@ -53,6 +53,7 @@ struct SweepArgs {
     int nt_records;         // stream the records (non-temporal loads): they outgrow the cache
     const int* incn_c;      // [nVf]
     const int* vid_c;       // [nVf] vertex id
+    const int* free_c;      // [nVf] free index (row of the correction tables)
     const int* fbody_c;     // [nVf] body
     int cbase;              // first row of the launched colour (0 for a whole sweep)
     const uint32_t* incslot;// [nVf * maxi] one-ring slot byte per corner
@@ -217,6 +218,9 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a);
 void launch_phase1(jgs2_solver* s, const SweepArgs& a, bool want_R, bool gate = false);
 void launch_phase2_cubature(jgs2_solver* s, const SweepArgs& a);
 void launch_plain(jgs2_solver* s, const SweepArgs& a);
+// damper reading of the correction, fused with the plain gather (rows in
+// colour order; rotations from the last phase-1 launch)
+void launch_damper(jgs2_solver* s, const SweepArgs& a);
 void launch_commit(jgs2_solver* s, const SweepArgs& a);
 void launch_linear(jgs2_solver* s, const SweepArgs& a);
 void launch_param_grad(jgs2_solver* s, const d4* u, const float4* y, double* thbar);

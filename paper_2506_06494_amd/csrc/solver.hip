@@ -71,6 +71,7 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
                        ? s->stream_mode
                        : (double)s->nVf * s->maxi * IREC_F4 * sizeof(float4) > 128.0 * 1024 * 1024;
     a.irec_c = s->d_irec_c; a.incn_c = s->d_incn_c; a.vid_c = s->d_vid_c; a.fbody_c = s->d_fbody_c; a.cbase = 0;
+    a.free_c = s->d_colperm;
     a.ring = s->d_ring; a.ring_n = s->d_ring_n; a.Uring = s->d_Uring; a.samp_e = s->d_samp_e; a.samp = s->d_samp;
     a.X = s->d_X; a.u = s->d_u; a.unext = s->d_unext; a.zu = s->d_zu; a.g = s->d_g; a.R = s->d_R;
     a.partial = s->d_partial; a.omega = (float)s->p.omega; a.in_place = 0;
@@ -851,7 +852,33 @@ static int line_search(jgs2_solver* s) {
 static int sweep_once(jgs2_solver* s) {
     SweepArgs a;
     build_sweep_args(s, a);
-    const bool cub = s->p.variant != JGS2_PLAIN;  // the two-phase corrected sweeps
+    const bool cub = s->p.variant == JGS2_CUBATURE;  // the two-phase R3 sweeps
+    if (s->p.variant == JGS2_DAMPER) {
+        // rotations of the sweep's starting iterate x^k (Sec. 4.3), held for
+        // every colour; each row's gradient and diagonal block are gathered
+        // fresh inside the fused kernel
+        if (!s->phase1_valid) launch_phase1(s, a, true, true);
+        if (s->p.order == JGS2_JACOBI) {
+            launch_damper(s, a);
+            if (s->p.line_search) {
+                int r = line_search(s);
+                if (r != JGS2_OK) return r;
+            }
+            swap_u(s);
+        } else {
+            for (int c = 0; c < s->n_colors; ++c) {
+                SweepArgs ac = a;
+                ac.list = s->d_colperm + s->col_off[c];
+                ac.n_list = s->col_off[c + 1] - s->col_off[c];
+                ac.in_place = 1;
+                ac.cbase = s->col_off[c];
+                launch_damper(s, ac);
+            }
+            s->phase1_valid = false;
+        }
+        s->sweeps_in_step++;
+        return jgs2::hip_check(s, hipGetLastError(), "sweep launch");
+    }
     if (s->p.order == JGS2_JACOBI) {
         if (cub) {
             if (!s->phase1_valid) launch_phase1(s, a, true, true);

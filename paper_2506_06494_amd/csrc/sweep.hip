@@ -354,12 +354,6 @@ __device__ __forceinline__ void corotate(const float* U, const float* Ri, const 
             Phi[3 * i + j] = Ra[3 * i] * T9[j] + Ra[3 * i + 1] * T9[3 + j] + Ra[3 * i + 2] * T9[6 + j];
 }
 
-// DAMPER (reading of Sec. 5's closing remark: the sampled reduced Hessian
-// is a damper on the plain local solve, the sampled gradient is left out):
-//   A_i = H_ii + H^B_i + sum_s w_s U_s^T H_s U_s,   b_i = g_i,
-// i.e. the incident tets contribute their own-corner blocks only (the basis
-// restricted to vertex i) and the one-ring rows are not read.
-template <bool DAMPER>
 __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
     __shared__ float sPhi[VPB][KMAX][9];
     const int lane = threadIdx.x % LPV;
@@ -377,7 +371,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
     float A6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, b[3] = {0.f, 0.f, 0.f};
 
     // one-ring rows: Phi_{i,a} into LDS, gradient projection
-    const int nr = (active && !DAMPER) ? a.ring_n[f] : 0;
+    const int nr = active ? a.ring_n[f] : 0;
     for (int k = lane; k < nr; k += LPV) {
         const int av = a.ring[(size_t)f * a.K + k];
         float U[9], Ra[9], Phi[9];
@@ -411,7 +405,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
             if (s == SLOT_SELF) {
 #pragma unroll
                 for (int q = 0; q < 9; ++q) Phi[c][q] = (q % 4 == 0) ? 1.0f : 0.0f;
-            } else if (DAMPER || s == SLOT_NONE) {
+            } else if (s == SLOT_NONE) {
 #pragma unroll
                 for (int q = 0; q < 9; ++q) Phi[c][q] = 0.0f;
             } else {
@@ -444,7 +438,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase2_cubature(SweepArgs a) {
                 for (int q = 0; q < 9; ++q) U[q] = rec[(5 + 9 * c + q) * a.S + s];
                 load_rot(a.R, av, Ra);
                 corotate(U, Ri, Ra, Phi[c]);
-                const float gc = DAMPER ? 0.0f : rec[(1 + c) * a.S + s];
+                const float gc = rec[(1 + c) * a.S + s];
                 if (gc != 0.0f) {
                     const float4 ga = a.g[av];
 #pragma unroll
@@ -553,7 +547,12 @@ __device__ __forceinline__ void plain_tet_term(const SweepArgs& a, const Tet& T,
     for (int i = 0; i < 6; ++i) A6[i] = fmaf(w, h[i], A6[i]);
 }
 
-template <bool LIN, int W, int BLK, bool SPEC, bool NT>
+// DAMP (forward only): the damper reading of the correction fused into the
+// same pass, A_i = H_ii + sum_s w_s Phi_s^T H_s Phi_s with Phi_{i,a} =
+// R_a Ubar_{i,a} R_i^T over the row's cubature samples, b_i = g_i; the
+// samples go to the lanes with the fewest incidence entries (from lane W-1
+// down), rotations are read from the last phase-1 launch.
+template <bool LIN, int W, int BLK, bool SPEC, bool NT, bool DAMP = false>
 __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     constexpr int NV = BLK / W;
     const int lane = threadIdx.x % W;
@@ -610,6 +609,35 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
             load_irec<NT>(row + j, a.maxi, T, c);
             plain_tet_term<LIN>(a, T, c, 1.0f, g, A6);
         }
+    if constexpr (DAMP && !LIN) {
+        const int s0 = W - 1 - lane;
+        if (active && s0 < a.S) {
+            const int f = a.free_c[q];
+            const float* rec = a.samp + (size_t)f * SREC * a.S;
+            float Ri[9];
+            load_rot(a.R, vself, Ri);
+            for (int sm = s0; sm < a.S; sm += W) {
+                const int e = a.samp_e[(size_t)f * a.S + sm];
+                if (e < 0) continue;
+                Tet T;
+                load_tet(a.tet, e, T);
+                float H[9], cH[9];
+                Kin<float> K;
+                dispgrad(a.u, T, H);
+                kinematics(H, K, cH);
+                float Phi[4][9];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    float U[9], Ra[9];
+#pragma unroll
+                    for (int qq = 0; qq < 9; ++qq) U[qq] = rec[(5 + 9 * c + qq) * a.S + sm];
+                    load_rot(a.R, T.id[c], Ra);
+                    corotate(U, Ri, Ra, Phi[c]);
+                }
+                galerkin_hessian(T, K, Phi, rec[sm], A6);
+            }
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i) g[i] = lane_sum_w<W>(g[i]);
 #pragma unroll
@@ -657,6 +685,8 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
 
 template <int W, int BLK, bool SPEC, bool NT>
 __global__ __launch_bounds__(BLK) void k_plain(SweepArgs a) { plain_body<false, W, BLK, SPEC, NT>(a); }
+template <int W, int BLK, bool SPEC, bool NT>
+__global__ __launch_bounds__(BLK) void k_damper(SweepArgs a) { plain_body<false, W, BLK, SPEC, NT, true>(a); }
 template <int W, int BLK, bool NT>
 __global__ __launch_bounds__(BLK) void k_linear(SweepArgs a) { plain_body<true, W, BLK, true, NT>(a); }
 
@@ -980,22 +1010,29 @@ void launch_phase1(jgs2_solver* s, const SweepArgs& a, bool want_R, bool gate) {
 void launch_phase2_cubature(jgs2_solver* s, const SweepArgs& a) {
     const int nb = n_blocks_for(a);
     if (nb == 0) return;
-    if (s->p.variant == JGS2_DAMPER)
-        launch(s, JGS2_K_PHASE2, k_phase2_cubature<true>, dim3(nb), dim3(BLOCK), a);
-    else
-        launch(s, JGS2_K_PHASE2, k_phase2_cubature<false>, dim3(nb), dim3(BLOCK), a);
+    launch(s, JGS2_K_PHASE2, k_phase2_cubature, dim3(nb), dim3(BLOCK), a);
 }
 
 // Launch of a plain or linear sweep kernel in the tuned shape (W lanes per
 // vertex, BLK threads per block).
-template <bool LIN, int W, int BLK>
+// KIND 0: plain, 1: linear (adjoint), 2: damper.
+template <int KIND, int W, int BLK>
 static void launch_plain_t(jgs2_solver* s, const SweepArgs& a) {
+    constexpr bool LIN = KIND == 1;
     constexpr int NV = BLK / W;
     const int n = a.list ? a.n_list : a.nVf;
     const int nb = (n + NV - 1) / NV;
     if (nb == 0) return;
     const dim3 g(nb), b(BLK);
-    if (LIN) {
+    if (KIND == 2) {
+        if (a.one_body) {
+            if (a.nt_records) launch(s, JGS2_K_DAMPER, k_damper<W, BLK, true, true>, g, b, a);
+            else launch(s, JGS2_K_DAMPER, k_damper<W, BLK, true, false>, g, b, a);
+        } else {
+            if (a.nt_records) launch(s, JGS2_K_DAMPER, k_damper<W, BLK, false, true>, g, b, a);
+            else launch(s, JGS2_K_DAMPER, k_damper<W, BLK, false, false>, g, b, a);
+        }
+    } else if (LIN) {
         if (a.nt_records) launch(s, JGS2_K_LINEAR, k_linear<W, BLK, true>, g, b, a);
         else launch(s, JGS2_K_LINEAR, k_linear<W, BLK, false>, g, b, a);
     } else if (a.one_body) {
@@ -1007,29 +1044,31 @@ static void launch_plain_t(jgs2_solver* s, const SweepArgs& a) {
     }
 }
 
-template <bool LIN, int W>
+template <int KIND, int W>
 static void launch_plain_w(jgs2_solver* s, const SweepArgs& a) {
     switch (s->tune_block) {
-        case 64: launch_plain_t<LIN, W, 64>(s, a); break;
-        case 128: launch_plain_t<LIN, W, 128>(s, a); break;
-        case 512: launch_plain_t<LIN, W, 512>(s, a); break;
-        default: launch_plain_t<LIN, W, 256>(s, a); break;
+        case 64: launch_plain_t<KIND, W, 64>(s, a); break;
+        case 128: launch_plain_t<KIND, W, 128>(s, a); break;
+        case 512: launch_plain_t<KIND, W, 512>(s, a); break;
+        default: launch_plain_t<KIND, W, 256>(s, a); break;
     }
 }
 
-template <bool LIN>
+template <int KIND>
 static void launch_plain_any(jgs2_solver* s, const SweepArgs& a) {
     switch (s->tune_lpv) {
-        case 4: launch_plain_w<LIN, 4>(s, a); break;
-        case 8: launch_plain_w<LIN, 8>(s, a); break;
-        case 16: launch_plain_w<LIN, 16>(s, a); break;
-        default: launch_plain_w<LIN, 32>(s, a); break;
+        case 4: launch_plain_w<KIND, 4>(s, a); break;
+        case 8: launch_plain_w<KIND, 8>(s, a); break;
+        case 16: launch_plain_w<KIND, 16>(s, a); break;
+        default: launch_plain_w<KIND, 32>(s, a); break;
     }
 }
 
-void launch_plain(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<false>(s, a); }
+void launch_plain(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<0>(s, a); }
 
-void launch_linear(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<true>(s, a); }
+void launch_linear(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<1>(s, a); }
+
+void launch_damper(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<2>(s, a); }
 
 void launch_param_grad(jgs2_solver* s, const d4* u, const float4* y, double* thbar) {
     launch(s, JGS2_K_PARAMGRAD, k_param_grad, dim3((s->nT + 255) / 256), dim3(256), (const float4*)s->d_tet, s->nT,
