@@ -74,6 +74,21 @@ def main(out=sys.stdout):
                 r = la.spectral_radius(rs.group_gs_operator(k))
                 name = "colour-group subspace, exact" if k is None else f"colour-group subspace, {k}-ring"
                 print(f"| {name} | | | | | {r:.5g} | {la.sweeps_to(r):.0f} |", file=out)
+            # the sampled remote gradient scaled by beta between the damper (beta = 0)
+            # and the literal form (beta = 1)
+            tab = ocorr.precompute(mdl, S=4, n_cand=64, seed=0, keep_full=False)
+            A0, C0 = rs.plain()
+            A2, C2 = rs.cubature(tab.samples, tab.weights, "R2")
+            for beta in (0.02, 0.05, 0.1, 0.2, 0.5):
+                print(row(rs, f"R2 with the sampled gradient scaled by {beta}", A2, C0 + beta * (C2 - C0)),
+                      file=out)
+            # coloured GS with a step scale (over-relaxation), plain against the damper
+            Ad, Cd = rs.cubature(tab.samples, tab.weights, "R2D")
+            for om in (1.3, 1.5, 1.6, 1.7, 1.8):
+                rp = la.spectral_radius(rs.gs_operator(A0, C0, omega=om))
+                rd = la.spectral_radius(rs.gs_operator(Ad, Cd, omega=om))
+                print(f"| GS step scale {om}: P0 / R2D | | | | | {rp:.5g} / {rd:.5g} "
+                      f"| {la.sweeps_to(rp):.0f} / {la.sweeps_to(rd):.0f} |", file=out)
             out.flush()
             print(f"[{label} E={E:g}: {time.time() - t0:.0f} s]", file=sys.stderr, flush=True)
 

