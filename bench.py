@@ -41,6 +41,9 @@ def parse():
                     help="launch shape (lanes per vertex x block) of the single-beam plain modes; 16x64 is what "
                          "the autotuner picks on the 16x16x128 beam on MI355X")
     ap.add_argument("--tune", action="store_true", help="run the autotuner instead of using --shape")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every sweep kernel eagerly instead of replaying captured sweep groups (same "
+                         "kernels and arguments; used for traced runs)")
     ap.add_argument("--batched-beams", type=int, default=256)
     ap.add_argument("--no-contact", action="store_true", help="skip the 10-sphere contact leg")
     ap.add_argument("--leg", choices=["contact"], help=argparse.SUPPRESS)
@@ -122,7 +125,7 @@ def main():
         corr = None
         for name, cfg in modes:
             s = jgs2.Solver(dt=sc.dt, gravity=sc.gravity, rel_tol=1e-5, max_sweeps=args.max_sweeps,
-                            check_every=16, use_graph=1, **cfg)
+                            check_every=16, use_graph=0 if args.no_graph else 1, **cfg)
             s.upload_mesh(m.X, m.tets, m.pinned)
             s.set_material(sc.E, sc.nu, sc.rho)
             if cfg["variant"] != jgs2.PLAIN:
@@ -146,6 +149,9 @@ def main():
                 else:
                     tuned = tuple(int(v) for v in args.shape.split("x"))
                     s.set_tuning(*tuned)
+            elif cfg["variant"] == jgs2.DAMPER:
+                # the damper sweep (rotation and fused damper kernels) is tuned on this mesh
+                tuned, _ = s.autotune(8)
             # warm-up steps (untimed), then the timed steps
             failed = None
             stalled = None
@@ -243,6 +249,14 @@ def main():
             kind = "plain_gs_sweep" if "_gs" in head_mode else "plain_jacobi"
             per_launch = sweep_bytes(kind, **cnt, n_colors=n_colors) * nsweeps / n
             kname = "k_plain"
+        elif dom == "damper":     # one launch per colour (GS) or per sweep (Jacobi)
+            nsweeps = results[head_mode][E0]["sweeps_per_step"] * results[head_mode][E0]["steps"]
+            kind = "damper_gs_sweep" if "_gs" in head_mode else "damper_jacobi"
+            per_launch = sweep_bytes(kind, **cnt, n_colors=n_colors) * nsweeps / n
+            kname = "k_damper"
+        elif dom == "rot":
+            per_launch = sweep_bytes("rot", **cnt)
+            kname = "k_rot"
         else:
             per_launch, kname = None, dom
         if per_launch is not None:
@@ -271,6 +285,8 @@ def main():
                                f"dt 1/120, twist 2 rad/s, to rel. residual 1e-5",
                    "mode": head_mode, "status": head.get("status"), "stiffness": stiff},
         "roofline": roof, "cpu_baseline": cpu,
+        "headline_kernels": {k: {"avg_launch_us": round(v[0] * 1e3 / v[1], 3), "launches": v[1]}
+                             for k, v in (kernel_stats.get(head_mode, {}).get(E0) or {}).items() if v[1]},
         "jgs2_vs_plain": compare,
         "modes": results, "jgs2_sweep": jgs2_sweep, "adjoint": adj, "batched": bat, "contact": con,
         "precompute_s": {f"{k:g}": round(v, 3) for k, v in precompute_s.items()},
@@ -541,6 +557,12 @@ def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches
         return 64.0 * n_inc + 64.0 * Vf + 32.0 * V
     if kind == "plain_gs_sweep":  # all colour launches of one sweep; positions read once per colour
         return 64.0 * n_inc + 64.0 * Vf + 32.0 * V * n_colors
+    if kind == "rot":         # records and positions; row id and count read, rotation written
+        return 64.0 * n_inc + 24.0 * Vf + 32.0 * V
+    if kind == "damper_gs_sweep":  # plain terms + per sample 168 B record + 80 B tet; rotations per colour
+        return 64.0 * n_inc + 64.0 * Vf + 248.0 * S * Vf + (32.0 + 16.0) * V * n_colors
+    if kind == "damper_jacobi":
+        return 64.0 * n_inc + 64.0 * Vf + 248.0 * S * Vf + (32.0 + 16.0) * V
     raise ValueError(kind)
 
 

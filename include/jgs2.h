@@ -300,7 +300,8 @@ int32_t jgs2_get_coloring(jgs2_solver* s, int32_t* color, int32_t* n_colors);
 #define JGS2_K_PARAMGRAD 9   /* adjoint: per-tet stiffness gradient */
 #define JGS2_K_ADJVEC    10  /* adjoint: mass products, next right-hand side */
 #define JGS2_K_DAMPER    11  /* damper-corrected local solves, fused with the gather */
-#define JGS2_NKERNELS    12
+#define JGS2_K_ROT       12  /* per-vertex rotations alone (the damper sweeps' start) */
+#define JGS2_NKERNELS    13
 int32_t jgs2_set_profiling(jgs2_solver* s, int32_t on);
 int32_t jgs2_kernel_times(jgs2_solver* s, double* ms, int64_t* launches);
 

@@ -199,7 +199,7 @@ static int upload_incidence_records(jgs2_solver* s) {
         const int f = s->col_perm[q];
         for (int j = 0; j < s->inc_n[f]; ++j) {
             const int pk = s->inc[(size_t)f * mi + j];
-            const int t = pk >> 2, c = pk & 3;
+            const int t = pk >> 2;
             const double E = s->E[t], nu = s->nu[t];
             const double mu_l = E / (2.0 * (1.0 + nu));
             const double lam_l = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
@@ -209,7 +209,7 @@ static int upload_incidence_records(jgs2_solver* s) {
             float4* r = &rec[q * IREC_F4 * mi + j];
             r[0] = make_float4((float)D[0], (float)D[1], (float)D[2], (float)D[3]);
             r[mi] = make_float4((float)D[4], (float)D[5], (float)D[6], (float)D[7]);
-            r[2 * mi] = make_float4((float)D[8], (float)(V * mu), (float)(V * lam), bits_as_float(c));
+            r[2 * mi] = make_float4((float)D[8], (float)(V * mu), (float)(V * lam), (float)V);
             r[3 * mi] = make_float4(bits_as_float(s->tets[4 * t]), bits_as_float(s->tets[4 * t + 1]),
                                     bits_as_float(s->tets[4 * t + 2]), bits_as_float(s->tets[4 * t + 3]));
         }
@@ -857,7 +857,7 @@ static int sweep_once(jgs2_solver* s) {
         // rotations of the sweep's starting iterate x^k (Sec. 4.3), held for
         // every colour; each row's gradient and diagonal block are gathered
         // fresh inside the fused kernel
-        if (!s->phase1_valid) launch_phase1(s, a, true, true);
+        if (!s->phase1_valid) launch_rotations(s, a);
         if (s->p.order == JGS2_JACOBI) {
             launch_damper(s, a);
             if (s->p.line_search) {

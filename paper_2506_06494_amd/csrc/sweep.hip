@@ -492,10 +492,11 @@ __device__ __forceinline__ float4 load_nt(const float4* p) {
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
-// Incidence record (planes stride apart): the tet's Dm^-1, V mu, V lam and
-// corner ids, and the own corner c.
+// Incidence record (planes stride apart): the tet's Dm^-1, V mu, V lam, V and
+// corner ids; the own corner c is the corner whose id is the row's vertex
+// (zero padding records name vertex 0 and are added with weight 0).
 template <bool NT>
-__device__ __forceinline__ void load_irec(const float4* __restrict__ r, int stride, Tet& T, int& c) {
+__device__ __forceinline__ void load_irec(const float4* __restrict__ r, int stride, int vself, Tet& T, int& c) {
     // each record is read once per sweep; when the records outgrow the
     // last-level cache (NT) they are streamed (non-temporal), which keeps the
     // reused corner positions resident
@@ -507,10 +508,11 @@ __device__ __forceinline__ void load_irec(const float4* __restrict__ r, int stri
     }
     T.D[0] = p0.x; T.D[1] = p0.y; T.D[2] = p0.z; T.D[3] = p0.w;
     T.D[4] = p1.x; T.D[5] = p1.y; T.D[6] = p1.z; T.D[7] = p1.w;
-    T.D[8] = p2.x; T.vmu = p2.y; T.vlam = p2.z; c = __float_as_int(p2.w);
+    T.D[8] = p2.x; T.vmu = p2.y; T.vlam = p2.z; T.vol = p2.w;
     T.id[0] = __float_as_int(p3.x); T.id[1] = __float_as_int(p3.y);
     T.id[2] = __float_as_int(p3.z); T.id[3] = __float_as_int(p3.w);
-    T.vol = 0.0f; T.mi = 0.0f;
+    c = T.id[0] == vself ? 0 : (T.id[1] == vself ? 1 : (T.id[2] == vself ? 2 : 3));
+    T.mi = 0.0f;
 }
 
 template <bool LIN>
@@ -547,11 +549,82 @@ __device__ __forceinline__ void plain_tet_term(const SweepArgs& a, const Tet& T,
     for (int i = 0; i < 6; ++i) A6[i] = fmaf(w, h[i], A6[i]);
 }
 
+// One cubature sample's damper term, spread over the four lanes of a quad
+// (lane b of the quad takes tet corner b): each lane co-rotates its corner's
+// U-bar row, Phi_b = R_b U-bar_{i,b} R_i^T, and forms its share of the three
+// directional deformation-gradient differentials dF_d = sum_b Phi_b[:, d]
+// (grad N_b)^T and of the inertia product sum_b Phi_b^T Phi_b; quad sums
+// complete them, then lane d < 3 evaluates the stress differential dP[dF_d]
+// and adds w (dP[dF_d] : dF_e + m_i (Phi^T Phi)_de) for e >= d to A6.  Every
+// lane of the quad must be active (the quad sums are DPP moves inside it).
+__device__ __forceinline__ float quad_sum(float v) {
+    v += dpp_mov<0xB1>(v);  // quad_perm(1, 0, 3, 2)
+    v += dpp_mov<0x4E>(v);  // quad_perm(2, 3, 0, 1)
+    return v;
+}
+
+__device__ __forceinline__ void damper_sample_quad(const SweepArgs& a, int e, int b, const float* rec, int sm,
+                                                   const float* Ri, float* A6) {
+    Tet T;
+    load_tet(a.tet, e, T);
+    float H[9], cH[9];
+    Kin<float> K;
+    dispgrad(a.u, T, H);
+    kinematics(H, K, cH);
+    const int vb = b == 0 ? T.id[0] : (b == 1 ? T.id[1] : (b == 2 ? T.id[2] : T.id[3]));
+    float U[9], Ra[9], Phi[9], gn[3];
+#pragma unroll
+    for (int qq = 0; qq < 9; ++qq) U[qq] = rec[(5 + 9 * b + qq) * a.S + sm];
+    load_rot(a.R, vb, Ra);
+    corotate(U, Ri, Ra, Phi);
+    gradN(T.D, b, gn);
+    float dF[3][9];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) dF[d][3 * i + j] = quad_sum(Phi[3 * i + d] * gn[j]);
+    float m6[6];
+    {
+        int k = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int f = d; f < 3; ++f)
+                m6[k++] = quad_sum(Phi[d] * Phi[f] + Phi[3 + d] * Phi[3 + f] + Phi[6 + d] * Phi[6 + f]);
+    }
+    // lane b < 3 takes direction d = b (lane 3 repeats d = 0 and adds nothing)
+    float dFd[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) dFd[q] = b == 1 ? dF[1][q] : (b == 2 ? dF[2][q] : dF[0][q]);
+    float dP[9];
+    snh_dstress(K.F, K.C, 1.0f + K.Jm1, T.vmu, T.vlam, dFd, dP);
+    float s3[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc += dP[q] * dF[f][q];
+        s3[f] = acc;
+    }
+    const float w = rec[sm];
+    const float mi = T.mi;
+    // A6 = (00, 01, 02, 11, 12, 22); m6 in the same order (selects, so that
+    // A6 stays in registers)
+    A6[0] += b == 0 ? w * (s3[0] + mi * m6[0]) : 0.0f;
+    A6[1] += b == 0 ? w * (s3[1] + mi * m6[1]) : 0.0f;
+    A6[2] += b == 0 ? w * (s3[2] + mi * m6[2]) : 0.0f;
+    A6[3] += b == 1 ? w * (s3[1] + mi * m6[3]) : 0.0f;
+    A6[4] += b == 1 ? w * (s3[2] + mi * m6[4]) : 0.0f;
+    A6[5] += b == 2 ? w * (s3[2] + mi * m6[5]) : 0.0f;
+}
+
 // DAMP (forward only): the damper reading of the correction fused into the
 // same pass, A_i = H_ii + sum_s w_s Phi_s^T H_s Phi_s with Phi_{i,a} =
-// R_a Ubar_{i,a} R_i^T over the row's cubature samples, b_i = g_i; the
-// samples go to the lanes with the fewest incidence entries (from lane W-1
-// down), rotations are read from the last phase-1 launch.
+// R_a Ubar_{i,a} R_i^T over the row's cubature samples, b_i = g_i; each
+// sample goes to one quad of the row's lanes (W / 4 samples per round),
+// rotations are those of the last rotation (or phase-1) pass.
 template <bool LIN, int W, int BLK, bool SPEC, bool NT, bool DAMP = false>
 __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     constexpr int NV = BLK / W;
@@ -577,8 +650,8 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     const float4* row = a.irec_c + (size_t)q * IREC_F4 * a.maxi;
     Tet T0, T1;
     int c0 = 0, c1 = 0;
-    if constexpr (SPEC) load_irec<NT>(row + min(lane, a.maxi - 1), a.maxi, T0, c0);
-    if constexpr (SPEC && W < 32) load_irec<NT>(row + min(lane + W, a.maxi - 1), a.maxi, T1, c1);
+    if constexpr (SPEC) load_irec<NT>(row + min(lane, a.maxi - 1), a.maxi, vself, T0, c0);
+    if constexpr (SPEC && W < 32) load_irec<NT>(row + min(lane + W, a.maxi - 1), a.maxi, vself, T1, c1);
     const d4 uv = a.u[vself];
     d4 zv = make_d4(0.0, 0.0, 0.0, 0.0);
     float4 yv = make_float4(0.f, 0.f, 0.f, 0.f), rv = yv;
@@ -606,35 +679,21 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
         for (int j = j0; j < n; j += W) {
             Tet T;
             int c;
-            load_irec<NT>(row + j, a.maxi, T, c);
+            load_irec<NT>(row + j, a.maxi, vself, T, c);
             plain_tet_term<LIN>(a, T, c, 1.0f, g, A6);
         }
     if constexpr (DAMP && !LIN) {
-        const int s0 = W - 1 - lane;
-        if (active && s0 < a.S) {
+        constexpr int SPR = W / 4;  // samples per round, one quad of lanes each
+        if (active) {
             const int f = a.free_c[q];
             const float* rec = a.samp + (size_t)f * SREC * a.S;
             float Ri[9];
             load_rot(a.R, vself, Ri);
-            for (int sm = s0; sm < a.S; sm += W) {
-                const int e = a.samp_e[(size_t)f * a.S + sm];
-                if (e < 0) continue;
-                Tet T;
-                load_tet(a.tet, e, T);
-                float H[9], cH[9];
-                Kin<float> K;
-                dispgrad(a.u, T, H);
-                kinematics(H, K, cH);
-                float Phi[4][9];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    float U[9], Ra[9];
-#pragma unroll
-                    for (int qq = 0; qq < 9; ++qq) U[qq] = rec[(5 + 9 * c + qq) * a.S + sm];
-                    load_rot(a.R, T.id[c], Ra);
-                    corotate(U, Ri, Ra, Phi[c]);
-                }
-                galerkin_hessian(T, K, Phi, rec[sm], A6);
+            const int qd = lane >> 2, b = lane & 3;
+            for (int sm0 = 0; sm0 < a.S; sm0 += SPR) {
+                const int sm = sm0 + qd;
+                const int e = sm < a.S ? a.samp_e[(size_t)f * a.S + sm] : -1;
+                if (e >= 0) damper_sample_quad(a, e, b, rec, sm, Ri, A6);  // the quad's lanes agree on e
             }
         }
     }
@@ -689,6 +748,86 @@ template <int W, int BLK, bool SPEC, bool NT>
 __global__ __launch_bounds__(BLK) void k_damper(SweepArgs a) { plain_body<false, W, BLK, SPEC, NT, true>(a); }
 template <int W, int BLK, bool NT>
 __global__ __launch_bounds__(BLK) void k_linear(SweepArgs a) { plain_body<true, W, BLK, true, NT>(a); }
+
+// Per-vertex rotations alone (Sec. 4.3): R_a is the polar rotation of the
+// volume-weighted mean deformation gradient of a's incident tets, the same
+// quantity as in phase 1, gathered from the colour-ordered incidence records.
+// The damper sweeps need only these.  Rows of a stopped body (several
+// bodies) keep their rotations.  W lanes gather each row's records; the
+// block's NV = BLK / W summed gradients then go through LDS so that NV
+// threads of the first wave run one polar decomposition each (with W = 8,
+// BLK = 512 that is 64 decompositions side by side per wave).
+template <int W, int BLK, bool SPEC, bool NT>
+__global__ __launch_bounds__(BLK) void k_rot(SweepArgs a) {
+    constexpr int NV = BLK / W;
+    static_assert(NV <= 64, "one wave runs the block's decompositions");
+    __shared__ float sF[NV][9];
+    __shared__ int sV[NV];
+    const int lane = threadIdx.x % W;
+    const int vloc = threadIdx.x / W;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int idx = blk * NV + vloc;
+    const bool in_range = idx < a.nVf;
+    const int q = in_range ? idx : 0;
+    const int vself = a.vid_c[q];
+    const int n = a.incn_c[q];
+    const float4* row = a.irec_c + (size_t)q * IREC_F4 * a.maxi;
+    // the first record of every lane is gathered before n or the body flag
+    // is tested (added with weight 0 where unused)
+    Tet T0;
+    int c0 = 0;
+    load_irec<NT>(row + min(lane, a.maxi - 1), a.maxi, vself, T0, c0);
+    const int flag = SPEC ? a.body_on[0] : a.body_on[a.fbody_c[q]];
+    const bool active = in_range & (flag != 0);
+    // sums of V_e (F_e - I) and of V_e over the incident tets
+    float Hs[9], vs;
+    {
+        float H[9];
+        dispgrad(a.u, T0, H);
+        const float w = lane < n ? T0.vol : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Hs[i] = w * H[i];
+        vs = w;
+    }
+    if (active)
+        for (int j = lane + W; j < n; j += W) {
+            Tet T;
+            int c;
+            load_irec<NT>(row + j, a.maxi, vself, T, c);
+            float H[9];
+            dispgrad(a.u, T, H);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Hs[i] = fmaf(T.vol, H[i], Hs[i]);
+            vs += T.vol;
+        }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Hs[i] = lane_sum_w<W>(Hs[i]);
+    vs = lane_sum_w<W>(vs);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) sF[vloc][i] = Hs[i] + ((i % 4 == 0) ? vs : 0.0f);
+        sV[vloc] = active ? vself : -1;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int v = sV[threadIdx.x];
+        if (v >= 0) {
+            float Fs[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Fs[i] = sF[threadIdx.x][i];
+            float mx = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) mx = fmaxf(mx, fabsf(Fs[i]));
+            const float inv = mx > 0.0f ? 1.0f / mx : 1.0f;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Fs[i] *= inv;
+            float R[9], qv[4];
+            polar_rotation(Fs, R);
+            quat_from_rot(R, qv);
+            a.R[v] = make_float4(qv[0], qv[1], qv[2], qv[3]);
+        }
+    }
+}
 
 // thetabar_t -= sum_c y_c . (V_t P(F_t) grad N_c) at the displacement u:
 // the derivative of the step's optimality condition with respect to
@@ -1069,6 +1208,23 @@ void launch_plain(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<0>(s, a
 void launch_linear(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<1>(s, a); }
 
 void launch_damper(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<2>(s, a); }
+
+// Rotation pass in a fixed shape (8 lanes per row, 64 rows per block): its
+// cost is the gather plus one polar decomposition per row, which this shape
+// runs 64 to a wave.
+void launch_rotations(jgs2_solver* s, const SweepArgs& a) {
+    constexpr int W = 8, BLK = 512, NV = BLK / W;
+    const int nb = (a.nVf + NV - 1) / NV;
+    if (nb == 0) return;
+    const dim3 g(nb), b(BLK);
+    if (a.one_body) {
+        if (a.nt_records) launch(s, JGS2_K_ROT, k_rot<W, BLK, true, true>, g, b, a);
+        else launch(s, JGS2_K_ROT, k_rot<W, BLK, true, false>, g, b, a);
+    } else {
+        if (a.nt_records) launch(s, JGS2_K_ROT, k_rot<W, BLK, false, true>, g, b, a);
+        else launch(s, JGS2_K_ROT, k_rot<W, BLK, false, false>, g, b, a);
+    }
+}
 
 void launch_param_grad(jgs2_solver* s, const d4* u, const float4* y, double* thbar) {
     launch(s, JGS2_K_PARAMGRAD, k_param_grad, dim3((s->nT + 255) / 256), dim3(256), (const float4*)s->d_tet, s->nT,
