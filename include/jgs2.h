@@ -275,6 +275,20 @@ int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* 
 
 /* Incremental potential E at the current iterate (FP64 sum of FP32 terms). */
 int32_t jgs2_energy(jgs2_solver* s, double* e);
+/* Allocation-free variant of jgs2_energy, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc.  Same result as jgs2_energy (the same kernels and
+ * summation order).  The per-block partial sums and the total live in a
+ * file-scope device array of JGS2_NOALLOC_MAX_PARTIALS + 1 doubles (512 KiB)
+ * that every GPU the library runs on holds until the process ends; its
+ * address on a device is taken by the first jgs2_create on that device.
+ * Meshes with more than 256 * JGS2_NOALLOC_MAX_PARTIALS tets or free vertices
+ * are refused with JGS2_E_INVALID.  All calls on one GPU share the array, so
+ * calls that overlap on one GPU (several threads or streams) race.  Calls no
+ * hipMalloc or hipFree; copies the total to *e (host) and waits for the
+ * handle's stream; no profiling events are recorded for its launches. */
+#define JGS2_NOALLOC_MAX_PARTIALS 65536
+int32_t jgs2_energy_noalloc(jgs2_solver* s, double* e);
 /* Assembled gradient g (nV x 3, zero at pinned vertices) and per-vertex
  * rotations R (nV x 3x3 row-major, identity at pinned vertices) at the
  * current iterate: the outputs of the first sweep phase. */

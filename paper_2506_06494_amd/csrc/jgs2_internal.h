@@ -221,6 +221,7 @@ void launch_plain(jgs2_solver* s, const SweepArgs& a);
 // damper reading of the correction, fused with the plain gather (rows in
 // colour order; rotations from the last phase-1 launch)
 void launch_damper(jgs2_solver* s, const SweepArgs& a);
+void launch_reduce_into(jgs2_solver* s, const double* in, int n, double* out);
 void launch_rotations(jgs2_solver* s, const SweepArgs& a);  // every free row (a.list unused)
 void launch_commit(jgs2_solver* s, const SweepArgs& a);
 void launch_linear(jgs2_solver* s, const SweepArgs& a);

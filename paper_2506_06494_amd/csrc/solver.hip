@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "jgs2_internal.h"
@@ -144,6 +145,34 @@ int alloc_tables(jgs2_solver* s, int S) {
 }
 }  // namespace jgs2
 
+// Scratch of jgs2_energy_noalloc: per-block partial sums of the incremental
+// potential and, in the last slot, their total.  Every GPU the library runs
+// on holds its own copy until the process ends; host code reaches it only
+// through the per-device address taken once by hipGetSymbolAddress (the
+// array's name is a host-side stand-in, not a device address).
+static __device__ __align__(256) double scratch[JGS2_NOALLOC_MAX_PARTIALS + 1];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// Takes the scratch address on the current device (s->device) once.
+static int setup_scratch(jgs2_solver* s) {
+    if (s->device < 0 || s->device >= kMaxDevices) {
+        s->err = "device ordinal beyond the scratch table";
+        return JGS2_E_HIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[s->device]) return JGS2_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+        s->err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return JGS2_E_HIP;
+    }
+    g_scratch_ptr[s->device] = static_cast<double*>(p);
+    return JGS2_OK;
+}
+
 #define HIPCHK(expr)                                               \
     do {                                                           \
         int _r = jgs2::hip_check(s, (expr), #expr);                \
@@ -281,6 +310,7 @@ int32_t jgs2_create(const jgs2_params* p, jgs2_solver** out) {
     if (hipGetDeviceProperties(&prop, s->device) != hipSuccess) { delete s; return JGS2_E_HIP; }
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) { delete s; return JGS2_E_HIP; }
     if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess) { delete s; return JGS2_E_HIP; }
+    if (setup_scratch(s) != JGS2_OK) { delete s; return JGS2_E_HIP; }
     *out = s;
     return JGS2_OK;
 }
@@ -1143,6 +1173,32 @@ int32_t jgs2_energy(jgs2_solver* s, double* e) {
     build_sweep_args(s, a);
     launch_energy(s, a, s->nT);
     return read_reduced(s, (std::max(s->nT, s->nVf) + 255) / 256, e);
+}
+
+int32_t jgs2_energy_noalloc(jgs2_solver* s, double* e) {
+    if (!s) return JGS2_E_INVALID;
+    if (!e) return s->fail(JGS2_E_INVALID, "NULL output");
+    if (!ready_to_step(s)) return JGS2_E_NOT_READY;
+    const int n_partials = (std::max(s->nT, s->nVf) + 255) / 256;
+    if (n_partials > JGS2_NOALLOC_MAX_PARTIALS)
+        return s->fail(JGS2_E_INVALID, "jgs2_energy_noalloc: more than 256 x JGS2_NOALLOC_MAX_PARTIALS tets or "
+                                       "free vertices (use jgs2_energy)");
+    double* sp = (s->device >= 0 && s->device < kMaxDevices) ? g_scratch_ptr[s->device] : nullptr;
+    if (!sp) return s->fail(JGS2_E_NOT_READY, "no scratch address for this device");
+    // the same kernels as jgs2_energy, with the partials and the total in the
+    // scratch array; launched without profiling events (no event creation)
+    const bool prof = s->prof;
+    s->prof = false;
+    SweepArgs a;
+    build_sweep_args(s, a);
+    a.partial = sp;
+    launch_energy(s, a, s->nT);
+    launch_reduce_into(s, sp, n_partials, sp + JGS2_NOALLOC_MAX_PARTIALS);
+    s->prof = prof;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(e, sp + JGS2_NOALLOC_MAX_PARTIALS, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return JGS2_OK;
 }
 
 int32_t jgs2_get_phase1(jgs2_solver* s, double* g, double* R) {

@@ -1281,6 +1281,10 @@ void launch_reduce(jgs2_solver* s, int n) {
     launch(s, JGS2_K_REDUCE, k_reduce, dim3(1), dim3(256), (const double*)s->d_partial, n, s->d_red);
 }
 
+void launch_reduce_into(jgs2_solver* s, const double* in, int n, double* out) {
+    launch(s, JGS2_K_REDUCE, k_reduce, dim3(1), dim3(256), in, n, out);
+}
+
 void launch_predict(jgs2_solver* s, float h, const float* grav) {
     launch(s, JGS2_K_PREDICT, k_predict, dim3((s->nV + 255) / 256), dim3(256), s->nV, (const d4*)s->d_uhat,
            (const float4*)s->d_vhat, (const float*)s->d_mh2, h, grav[0], grav[1], grav[2], s->d_u, s->d_unext,

@@ -48,7 +48,8 @@ EXPORTS = ["jgs2_default_params", "jgs2_create", "jgs2_destroy", "jgs2_last_erro
            "jgs2_set_state", "jgs2_get_state", "jgs2_step", "jgs2_begin_step", "jgs2_iterate", "jgs2_end_step",
            "jgs2_residual", "jgs2_energy", "jgs2_get_phase1", "jgs2_get_coloring", "jgs2_set_profiling",
            "jgs2_kernel_times", "jgs2_rollout", "jgs2_rollout_backward", "jgs2_set_bodies", "jgs2_get_body_stats",
-           "jgs2_set_tuning", "jgs2_get_tuning", "jgs2_autotune", "jgs2_set_streaming", "jgs2_set_material_log_e"]
+           "jgs2_set_tuning", "jgs2_get_tuning", "jgs2_autotune", "jgs2_set_streaming", "jgs2_set_material_log_e",
+           "jgs2_energy_noalloc"]
 
 KERNELS = ["phase1", "phase2", "plain", "commit", "reduce", "predict", "velocity", "energy", "linear", "paramgrad",
            "adjvec", "damper", "rot"]
@@ -89,6 +90,7 @@ def load(path: str = LIB_PATH):
         "jgs2_end_step": (C.c_int32, [C.c_void_p]),
         "jgs2_residual": (C.c_int32, [C.c_void_p, d, d]),
         "jgs2_energy": (C.c_int32, [C.c_void_p, d]),
+        "jgs2_energy_noalloc": (C.c_int32, [C.c_void_p, d]),
         "jgs2_get_phase1": (C.c_int32, [C.c_void_p, d, d]),
         "jgs2_get_coloring": (C.c_int32, [C.c_void_p, i32, i32]),
         "jgs2_set_profiling": (C.c_int32, [C.c_void_p, C.c_int32]),
@@ -361,6 +363,13 @@ class Solver:
     def energy(self):
         e = C.c_double()
         self._chk(self.lib.jgs2_energy(self.h, C.byref(e)))
+        return e.value
+
+    def energy_noalloc(self):
+        """jgs2_energy_noalloc: the same energy with the library's static
+        device scratch instead of handle-owned buffers."""
+        e = C.c_double()
+        self._chk(self.lib.jgs2_energy_noalloc(self.h, C.byref(e)))
         return e.value
 
     def phase1(self):
