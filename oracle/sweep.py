@@ -30,6 +30,13 @@ Variants (same enum as the HIP library):
       non-incident elements add Hessian terms only).
   R2, R2G1, R2D  the literal H_ii-plus-sampled forms (see ``r2_systems``);
       R2D is the library's DAMPER variant.
+  RX  the exact co-rotated subspace in the literal form of Eq. local_newton
+      (the library's EXACT variant): with Eq. relation's derivatives of E_C,
+        A_i = H_ii + sum_{a in N(i)} H_{i,a} Phi_{i,a}   (symmetrised)
+        b_i = sum_a Phi_{i,a}^T g_a                       (every free vertex)
+      The Hessian term needs the one-ring only (H_{i,a} vanishes beyond it);
+      the gradient term runs over the whole mesh, exactly.  At rest it is
+      the i-block of the Newton step (Sec. 4.2).
 
 Readings of the per-vertex rotation (Sec. 4.3 names a polar decomposition of
 a per-vertex deformation gradient without defining the latter): F-bar_a is
@@ -51,7 +58,7 @@ import scipy.sparse.linalg as spla
 
 from . import correction as ocorr
 
-P0, R0, R1, R2, R2G1, R2D, R3 = "P0", "R0", "R1", "R2", "R2G1", "R2D", "R3"
+P0, R0, R1, R2, R2G1, R2D, R3, RX = "P0", "R0", "R1", "R2", "R2G1", "R2D", "R3", "RX"
 
 
 def polar(F):
@@ -222,6 +229,24 @@ def full_subspace_systems(model, U_rows, x, g, R, H, verts):
     return A, b
 
 
+def literal_exact_systems(model, U_rows, g, H, verts):
+    """Variant RX from full co-rotated row blocks U_rows (n, V, 3, 3): the
+    i-th 3-row block of H times U_i (H_ii + sum_a H_{i,a} Phi_{i,a}; only
+    the one-ring contributes), symmetrised, and b_i = U_i^T g over the free
+    DOFs."""
+    A = np.zeros((len(verts), 3, 3))
+    b = np.zeros((len(verts), 3))
+    gf = model.to_free(g)
+    Hr = H.tocsr()
+    for k, v in enumerate(verts):
+        Ui = U_rows[k][model.free_ids].reshape(-1, 3)                 # (3 n_free, 3)
+        f = model.free_index[v]
+        M = Hr[3 * f:3 * f + 3] @ Ui
+        A[k] = 0.5 * (M + M.T)
+        b[k] = Ui.T @ gf
+    return A, b
+
+
 def corotated_rows(tab_U_full, R, verts):
     """Phi_{i,a} = R_a U-bar_{i,a} R_i^T for all a (full rows)."""
     return np.einsum("vab,nvbc,ndc->nvad", R, tab_U_full, R[verts])
@@ -296,6 +321,9 @@ class Sweeper:
                 A[k] = H[3 * f:3 * f + 3, 3 * f:3 * f + 3].toarray()
             return A, g[verts].copy()
         H = m.hessian(x)
+        if self.variant == RX:
+            U = corotated_rows(self.tab.U_full[rows], R, verts)
+            return literal_exact_systems(m, U, g, H, verts)  # H carries the barrier blocks
         if self.variant == R1:
             U = corotated_rows(self.tab.U_full[rows], R, verts)
         else:

@@ -130,7 +130,7 @@ def test_rigid_rotation_equivariance(tiny):
     mdr = fem.Model(mdl.X, mdl.tets, mdl.pinned, mdl.E, mdl.nu, mdl.rho, mdl.h, mdl.gravity @ q.T)
     zr = mdr.inertial_target(x @ q.T, v @ q.T)
     verts = mdl.free_ids
-    for var in [osw.R3, osw.R1, osw.P0]:
+    for var in [osw.R3, osw.R1, osw.RX, osw.P0]:
         A, b = osw.Sweeper(mdl, tab, var).systems(x, z, verts)
         Ar, br = osw.Sweeper(mdr, tab, var).systems(x @ q.T, zr, verts)
         assert np.abs(Ar - q @ A @ q.T).max() < 1e-10 * np.abs(A).max(), var
