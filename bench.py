@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-HEADLINE_MODE = "jgs2_damper_gs"
+HEADLINE_MODE = "jgs2_exact_jacobi"
 METRIC = "s/step to rel. residual 1e-5 (JGS2 vs Jacobi); sweep HBM GB/s; adjoint s/step"
 
 
@@ -32,7 +32,9 @@ def parse():
     ap.add_argument("--max-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="4x4x16 beam instead (quick check)")
-    ap.add_argument("--modes", default="jgs2_damper_gs,jgs2_damper_jacobi_w0.8,jgs2_jacobi,jgs2_gs,plain_jacobi,"
+    ap.add_argument("--modes", default="jgs2_exact_jacobi,jgs2_exact_jacobi_fp16,jgs2_exact_gs,jgs2_damper_gs,"
+                                       "jgs2_damper_jacobi_w0.8,"
+                                       "jgs2_jacobi,jgs2_gs,plain_jacobi,"
                                        "plain_jacobi_w0.8,plain_jacobi_w0.5,plain_jacobi_w0.3,plain_gs,"
                                        "plain_gs_w1.5,plain_gs_w1.6")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation leg")
@@ -97,7 +99,14 @@ def main():
         wl = "beam 16x16x128 (0.05 m cells, 37,281 vertices, 196,608 tets)"
 
     modes = [
-        # the headline: the damper reading of the correction in coloured GS, no step scale
+        # the exact co-rotated subspace (every row of U-bar, no cubature), Jacobi and coloured GS
+        # (a residual check after every sweep: a sweep streams every U-bar row, so one sweep
+        # past convergence costs more than the check)
+        ("jgs2_exact_jacobi", dict(variant=jgs2.EXACT, order=jgs2.JACOBI, omega=1.0, check_every=1)),
+        ("jgs2_exact_jacobi_fp16", dict(variant=jgs2.EXACT, order=jgs2.JACOBI, omega=1.0, check_every=1,
+                                        exact_fp16=1)),
+        ("jgs2_exact_gs", dict(variant=jgs2.EXACT, order=jgs2.GS, omega=1.0, check_every=1)),
+        # the damper reading of the correction in coloured GS, no step scale
         ("jgs2_damper_gs", dict(variant=jgs2.DAMPER, order=jgs2.GS, omega=1.0)),
         ("jgs2_damper_jacobi_w0.8", dict(variant=jgs2.DAMPER, order=jgs2.JACOBI, omega=0.8)),
         # reading R3 (one-ring exact, remote sampled): diverges on these beams
@@ -124,11 +133,21 @@ def main():
         m = sc.mesh
         corr = None
         for name, cfg in modes:
+            kw = dict(check_every=16)
+            kw.update(cfg)
             s = jgs2.Solver(dt=sc.dt, gravity=sc.gravity, rel_tol=1e-5, max_sweeps=args.max_sweeps,
-                            check_every=16, use_graph=0 if args.no_graph else 1, **cfg)
+                            use_graph=0 if args.no_graph else 1, **kw)
             s.upload_mesh(m.X, m.tets, m.pinned)
             s.set_material(sc.E, sc.nu, sc.rho)
-            if cfg["variant"] != jgs2.PLAIN:
+            if cfg["variant"] == jgs2.EXACT:
+                # its own precompute: the full U-bar rows stay on the device
+                print(f"[bench] E={E:g} {name}: GPU precompute with full rows ...", file=sys.stderr, flush=True)
+                t0 = time.perf_counter()
+                s.precompute(samples=4, n_cand=64, seed=0)
+                precompute_s[f"{E:g} exact"] = time.perf_counter() - t0
+                print(f"[bench] E={E:g} precompute (full rows) {precompute_s[f'{E:g} exact']:.2f} s", file=sys.stderr,
+                      flush=True)
+            elif cfg["variant"] != jgs2.PLAIN:
                 if corr is None:
                     print(f"[bench] E={E:g} GPU precompute ...", file=sys.stderr, flush=True)
                     t0 = time.perf_counter()
@@ -257,6 +276,10 @@ def main():
         elif dom == "rot":
             per_launch = sweep_bytes("rot", **cnt)
             kname = "k_rot"
+        elif dom == "exact":      # Jacobi: one launch over every row; GS: one per colour
+            per_launch = sweep_bytes("exact", **cnt, el=2 if "fp16" in head_mode else 4) * (
+                1 if "jacobi" in head_mode else 1.0 / n_colors)
+            kname = "k_exact"
         else:
             per_launch, kname = None, dom
         if per_launch is not None:
@@ -289,7 +312,7 @@ def main():
                              for k, v in (kernel_stats.get(head_mode, {}).get(E0) or {}).items() if v[1]},
         "jgs2_vs_plain": compare,
         "modes": results, "jgs2_sweep": jgs2_sweep, "adjoint": adj, "batched": bat, "contact": con,
-        "precompute_s": {f"{k:g}": round(v, 3) for k, v in precompute_s.items()},
+        "precompute_s": {(k if isinstance(k, str) else f"{k:g}"): round(v, 3) for k, v in precompute_s.items()},
     }
     print(json.dumps(line))
 
@@ -541,7 +564,7 @@ def measured_traffic(kernel, workload_tag, shape=None):
     return None
 
 
-def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches=1):
+def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches=1, el=4):
     """Compulsory (algorithmic) bytes moved by one launch of a sweep kernel,
     counting every datum it must touch once: tet records 80 B (64 B without
     the id word), incidence entries 4 B or 16 B with corner ids (plus 4 B
@@ -557,6 +580,8 @@ def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches
         return 64.0 * n_inc + 64.0 * Vf + 32.0 * V
     if kind == "plain_gs_sweep":  # all colour launches of one sweep; positions read once per colour
         return 64.0 * n_inc + 64.0 * Vf + 32.0 * V * n_colors
+    if kind == "exact":       # every row's 9 planes of U-bar (el bytes each) + incident tets, positions, h
+        return 9.0 * el * Vf * Vf + 96.0 * n_inc + 16.0 * Vf + 64.0 * V
     if kind == "rot":         # records and positions; row id and count read, rotation written
         return 64.0 * n_inc + 24.0 * Vf + 32.0 * V
     if kind == "damper_gs_sweep":  # plain terms + per sample 168 B record + 80 B tet; rotations per colour

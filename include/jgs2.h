@@ -56,10 +56,18 @@ extern "C" {
  *                 samples (the sampled reduced Hessian of Eq. cubature as a
  *                 damper on the local solve, Sec. 5's closing remark),
  *                 b_i = g_i (the sampled gradient left out).  Uses the same
- *                 correction tables as JGS2_CUBATURE.                       */
+ *                 correction tables as JGS2_CUBATURE.
+ *   JGS2_EXACT    the exact co-rotated subspace in the literal form of
+ *                 Eq. local_newton, with Eq. relation's derivatives of E_C:
+ *                 A_i = H_ii + sum_{a in N(i)} H_{i,a} Phi_{i,a} (the one
+ *                 ring; symmetrised), b_i = sum_a Phi_{i,a}^T g_a over every
+ *                 free vertex (no cubature).  At rest a Jacobi sweep is the
+ *                 Newton step (Sec. 4.2).  Needs the full rows of U-bar from
+ *                 jgs2_precompute (nVf^2 x 9 floats on the device).          */
 #define JGS2_PLAIN     0
 #define JGS2_CUBATURE  3
 #define JGS2_DAMPER    4
+#define JGS2_EXACT     5
 
 /* Parallel order (Sec. 8.1): Jacobi (all vertices from one iterate) or
  * coloured Gauss-Seidel (greedy colours in ascending order; gradients and
@@ -74,7 +82,7 @@ typedef struct jgs2_solver jgs2_solver;
 typedef struct jgs2_params {
     double  dt;                 /* time step h [s] */
     double  gravity[3];         /* f_ext / m [m/s^2] */
-    int32_t variant;            /* JGS2_PLAIN, JGS2_CUBATURE or JGS2_DAMPER */
+    int32_t variant;            /* JGS2_PLAIN, JGS2_CUBATURE, JGS2_DAMPER or JGS2_EXACT */
     int32_t order;              /* JGS2_JACOBI or JGS2_GS */
     double  omega;              /* step scale: x_i += omega dx_i (1 = none) */
     double  rel_tol;            /* stop when |g| / |g(x0)| <= rel_tol */
@@ -89,6 +97,9 @@ typedef struct jgs2_params {
     int32_t adj_max_sweeps;     /* sweep cap per adjoint solve */
     int32_t use_graph;          /* 1: replay each group of check_every sweeps and its
                                    residual check as one captured HIP graph */
+    int32_t exact_fp16;         /* JGS2_EXACT: 1 keeps the U-bar rows in FP16 (half the
+                                   bytes streamed per sweep), 0 in FP32; read by
+                                   jgs2_precompute */
 } jgs2_params;
 
 typedef struct jgs2_step_stats {
@@ -194,7 +205,12 @@ int32_t jgs2_set_material_log_e(jgs2_solver* s, const double* log_E, const doubl
  * Hessian, its banded Cholesky factor, training poses (smallest
  * eigenvectors), U-bar by Eq. u, greedy NNLS cubature with `samples` samples
  * per vertex drawn from `n_cand` candidates per round (counter-based
- * SplitMix64 keyed by `seed`).  Needed by JGS2_CUBATURE only. */
+ * SplitMix64 keyed by `seed`).  Needed by JGS2_CUBATURE and JGS2_DAMPER.
+ * When the handle's variant is JGS2_EXACT it also keeps every row of U-bar
+ * (Eq. u) for every free vertex on the device, nVf^2 x 36 bytes in FP32 or
+ * nVf^2 x 18 bytes with params.exact_fp16 (JGS2_E_OOM when that does not
+ * fit).  U-bar is dimensionless (U-bar_{i,i} = I); the FP16 copy changes the
+ * sweep's preconditioner, not its fixed point (b_i vanishes with g). */
 int32_t jgs2_precompute(jgs2_solver* s, int32_t samples, int32_t n_cand, uint64_t seed);
 
 /* Correction tables in free-vertex order (free vertices ascending by id).
@@ -315,7 +331,9 @@ int32_t jgs2_get_coloring(jgs2_solver* s, int32_t* color, int32_t* n_colors);
 #define JGS2_K_ADJVEC    10  /* adjoint: mass products, next right-hand side */
 #define JGS2_K_DAMPER    11  /* damper-corrected local solves, fused with the gather */
 #define JGS2_K_ROT       12  /* per-vertex rotations alone (the damper sweeps' start) */
-#define JGS2_NKERNELS    13
+#define JGS2_K_EXACT     13  /* exact-subspace local solves (reduced gradient over all rows) */
+#define JGS2_K_HVEC      14  /* rest-frame gradients R_a^T g_a in the exact rows' order */
+#define JGS2_NKERNELS    15
 int32_t jgs2_set_profiling(jgs2_solver* s, int32_t on);
 int32_t jgs2_kernel_times(jgs2_solver* s, double* ms, int64_t* launches);
 

@@ -88,6 +88,13 @@ struct SweepArgs {
     const int* body_on;     // [n_bodies] 1 while the body iterates (nullptr: all; the
                             // plain forward sweep requires it)
     int one_body;           // every free vertex is in body 0 (its flag is read once per wave)
+    // exact variant: full U-bar rows [(f * 9 + comp) * nVf + qx] over the permuted
+    // positions qx of the free vertices, and the rest-frame gradients in that order
+    const void* Ufull;      // float, or _Float16 when full_fp16
+    int full_fp16;
+    const int* qpos;        // [nV] permuted position of a free vertex, -1 if pinned
+    const int* qvert;       // [nVf] vertex id at permuted position qx
+    float4* hvec;           // [nVf] R_a^T g_a at permuted position qx
 };
 
 }  // namespace jgs2
@@ -140,6 +147,12 @@ struct jgs2_solver {
     uint32_t* d_incslot = nullptr;
     int* d_colperm = nullptr;
     float* d_Uring = nullptr;
+    void* d_Ufull = nullptr;               // exact variant: [nVf * 9 * nVf] float or _Float16
+    bool full_fp16 = false;
+    int* d_qpos = nullptr;                 // [nV]
+    int* d_qvert = nullptr;                // [nVf]
+    float4* d_hvec = nullptr;              // [nVf]
+    bool have_full = false;
     int* d_samp_e = nullptr;
     float* d_samp = nullptr;
     double* d_partial = nullptr;
@@ -223,6 +236,8 @@ void launch_plain(jgs2_solver* s, const SweepArgs& a);
 void launch_damper(jgs2_solver* s, const SweepArgs& a);
 void launch_reduce_into(jgs2_solver* s, const double* in, int n, double* out);
 void launch_rotations(jgs2_solver* s, const SweepArgs& a);  // every free row (a.list unused)
+void launch_hvec(jgs2_solver* s, const SweepArgs& a);
+void launch_exact(jgs2_solver* s, const SweepArgs& a);
 void launch_commit(jgs2_solver* s, const SweepArgs& a);
 void launch_linear(jgs2_solver* s, const SweepArgs& a);
 void launch_param_grad(jgs2_solver* s, const d4* u, const float4* y, double* thbar);
@@ -241,6 +256,7 @@ void launch_velocity(jgs2_solver* s, float h);
 void launch_energy(jgs2_solver* s, const SweepArgs& a, int nT);
 int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed);
 int alloc_tables(jgs2_solver* s, int S);
+int alloc_full_tables(jgs2_solver* s);
 void prof_collect(jgs2_solver* s);
 hipEvent_t pool_event(jgs2_solver* s);
 }  // namespace jgs2

@@ -456,6 +456,69 @@ __global__ __launch_bounds__(256) void k_ritz_resid(const double* __restrict__ H
 }
 
 // ---------------------------------------------------------------------------
+// 6. full rows of U-bar (the exact variant)
+// ---------------------------------------------------------------------------
+// For vertex j of the chunk (permuted position p = p0 + j, free index
+// f = perm[p]) and every permuted position qx:
+//   Ufull[(f * 9 + 3 r + c) * nVf + qx] = (W_qx B_j^-1)[r][c]   (FP32)
+// with W_qx the 3x3 block of the solved columns at rows 3 qx .. 3 qx + 2 and
+// B_j = W_p (Eq. u), the same product as the one-ring rows of k_cubature.
+// A block takes one batch (21 vertices) and UF_ROWS positions, with the
+// batch's W rows for those positions staged in LDS (rows padded by one
+// double against bank conflicts); consecutive threads write consecutive
+// positions of one plane.
+constexpr int UF_ROWS = 32;
+template <typename UT>
+__global__ __launch_bounds__(256) void k_ufull(const double* __restrict__ W, int n_pad, int p0, int n_vert, int nVf,
+                                               const int* __restrict__ perm, UT* __restrict__ Ufull) {
+    const int batch = blockIdx.y;
+    const int qx0 = blockIdx.x * UF_ROWS;
+    const double* Wb = W + (size_t)batch * n_pad * NB;
+    __shared__ double sW[3 * UF_ROWS][NB + 1];
+    __shared__ double sBinv[VPBATCH][9];
+    __shared__ int sF[VPBATCH];
+    const int nrow = 3 * min(UF_ROWS, nVf - qx0);
+    for (int i = threadIdx.x; i < 3 * UF_ROWS * NB; i += blockDim.x) {
+        const int rr = i / NB, cc = i % NB;
+        sW[rr][cc] = rr < nrow ? Wb[(size_t)(3 * qx0 + rr) * NB + cc] : 0.0;
+    }
+    if (threadIdx.x < VPBATCH) {
+        const int jj = threadIdx.x;
+        const int j = batch * VPBATCH + jj;
+        int fj = -1;
+        if (j < n_vert) {
+            const int p = p0 + j;
+            double B[9], C[9];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) B[3 * r + c] = Wb[(size_t)(3 * p + r) * NB + 3 * jj + c];
+            cof3(B, C);  // B^-1 = cof(B)^T / det B
+            const double det = B[0] * C[0] + B[1] * C[1] + B[2] * C[2];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) sBinv[jj][3 * r + c] = C[3 * c + r] / det;
+            fj = perm[p];
+        }
+        sF[jj] = fj;
+    }
+    __syncthreads();
+    const int t = threadIdx.x % UF_ROWS;
+    const int qx = qx0 + t;
+    if (qx >= nVf) return;
+    for (int jj = threadIdx.x / UF_ROWS; jj < VPBATCH; jj += blockDim.x / UF_ROWS) {
+        const int f = sF[jj];
+        if (f < 0) continue;
+        double Wr[9];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k) Wr[3 * r + k] = sW[3 * t + r][3 * jj + k];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                const double u = Wr[3 * r] * sBinv[jj][c] + Wr[3 * r + 1] * sBinv[jj][3 + c] +
+                                 Wr[3 * r + 2] * sBinv[jj][6 + c];
+                Ufull[((size_t)f * 9 + 3 * r + c) * nVf + qx] = (UT)u;
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 5. per-vertex correction tables and greedy NNLS cubature (one wave each)
 // ---------------------------------------------------------------------------
 struct CubArgs {
@@ -1280,6 +1343,18 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
     DevBuf<double> dW;
     DevBuf<int> dfirst;
     if ((r = dW.alloc(s, (size_t)chunk_batches * n_pad * NB)) || (r = dfirst.alloc(s, chunk_batches))) return r;
+    // exact variant: every row of U-bar, over the permuted positions of the free vertices
+    const bool want_full = s->p.variant == JGS2_EXACT;
+    if (want_full) {
+        std::vector<int> qpos(nV, -1), qvert(nVf);
+        for (int q = 0; q < nVf; ++q) {
+            qvert[q] = s->free_ids[perm[q]];
+            qpos[qvert[q]] = q;
+        }
+        if ((r = alloc_full_tables(s))) return r;
+        PCHK(hipMemcpyAsync(s->d_qpos, qpos.data(), nV * 4, hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(s->d_qvert, qvert.data(), nVf * 4, hipMemcpyHostToDevice, st));
+    }
     CubArgs ca;
     std::memset(&ca, 0, sizeof(ca));
     ca.nV = nV; ca.nVf = nVf; ca.nT = nT; ca.n_pad = n_pad; ca.nTp = nTp; ca.S = S; ca.n_cand = n_cand;
@@ -1299,6 +1374,12 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
         ca.p0 = p0;
         ca.n_vert = nvert;
         hipLaunchKernelGGL(k_cubature, dim3(nvert), dim3(64), 0, st, ca);
+        if (want_full && s->full_fp16)
+            hipLaunchKernelGGL(k_ufull<_Float16>, dim3((nVf + UF_ROWS - 1) / UF_ROWS, nbatch), dim3(256), 0, st, dW.p,
+                               n_pad, p0, nvert, nVf, dperm.p, (_Float16*)s->d_Ufull);
+        else if (want_full)
+            hipLaunchKernelGGL(k_ufull<float>, dim3((nVf + UF_ROWS - 1) / UF_ROWS, nbatch), dim3(256), 0, st, dW.p,
+                               n_pad, p0, nvert, nVf, dperm.p, (float*)s->d_Ufull);
         PCHK(hipGetLastError());
         PCHK(hipStreamSynchronize(st));
         stage("vertex chunk", t_start);
@@ -1308,6 +1389,7 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
     PCHK(hipStreamSynchronize(st));
     s->S = S;
     s->have_corr = true;
+    s->have_full = want_full;
     (void)nf; (void)K;
     return JGS2_OK;
 }

@@ -32,6 +32,7 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_inc_n); dfree(s->d_ring); dfree(s->d_ring_n); dfree(s->d_incslot); dfree(s->d_colperm);
     dfree(s->d_inc4); dfree(s->d_irec_c); dfree(s->d_incn_c); dfree(s->d_vid_c); dfree(s->d_fbody_c);
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
+    dfree(s->d_Ufull); dfree(s->d_qpos); dfree(s->d_qvert); dfree(s->d_hvec); s->have_full = false;
     dfree(s->d_ck_u); dfree(s->d_ck_v); dfree(s->d_seg); dfree(s->d_y); dfree(s->d_ynext); dfree(s->d_xbar);
     dfree(s->d_vbar); dfree(s->d_rhs); dfree(s->d_thbar);
     dfree(s->d_fbody); dfree(s->d_seg_idx); dfree(s->d_body_on); dfree(s->d_body_sweeps);
@@ -81,6 +82,7 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
         for (int k = 0; k < 4; ++k) a.planes[i][k] = (float)s->p.planes[i][k];
     a.d_hat = (float)s->p.d_hat; a.kappa = (float)s->p.kappa;
     a.fbody = s->d_fbody; a.body_on = s->d_body_on; a.one_body = s->n_bodies == 1;
+    a.Ufull = s->d_Ufull; a.full_fp16 = s->full_fp16; a.qpos = s->d_qpos; a.qvert = s->d_qvert; a.hvec = s->d_hvec;
     for (int i = 0; i < s->p.n_planes; ++i)
         for (int k = 0; k < 4; ++k) a.planes_d[i][k] = s->p.planes[i][k];
 }
@@ -125,6 +127,25 @@ void prof_collect(jgs2_solver* s) {
 
 namespace jgs2 {
 // Device correction tables for S samples per free vertex (zero-filled).
+// Full U-bar rows of the exact variant and their index tables (freed first).
+int alloc_full_tables(jgs2_solver* s) {
+    const size_t nf = s->nVf;
+    for (void** p : {(void**)&s->d_Ufull, (void**)&s->d_qpos, (void**)&s->d_qvert, (void**)&s->d_hvec}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    s->have_full = false;
+    int r;
+    s->full_fp16 = s->p.exact_fp16 != 0;
+    const size_t el = s->full_fp16 ? 2 : sizeof(float);
+    if ((r = hip_check(s, hipMalloc((void**)&s->d_Ufull, nf * 9 * nf * el), "hipMalloc full U-bar rows")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_qpos, (size_t)s->nV * sizeof(int)), "hipMalloc tables")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_qvert, nf * sizeof(int)), "hipMalloc tables")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_hvec, nf * sizeof(float4)), "hipMalloc tables")))
+        return r;
+    return JGS2_OK;
+}
+
 int alloc_tables(jgs2_solver* s, int S) {
     const size_t nf = s->nVf, K = s->K;
     const size_t Sd = S > 0 ? S : 1;
@@ -197,7 +218,8 @@ template <typename T> static int upload(jgs2_solver* s, T* d, const T* h, size_t
 static int validate_params(const jgs2_params* p, std::string& why) {
     if (!p) { why = "params is NULL"; return JGS2_E_INVALID; }
     if (!(p->dt > 0) || !std::isfinite(p->dt)) { why = "dt must be positive"; return JGS2_E_INVALID; }
-    if (p->variant != JGS2_PLAIN && p->variant != JGS2_CUBATURE && p->variant != JGS2_DAMPER) {
+    if (p->variant != JGS2_PLAIN && p->variant != JGS2_CUBATURE && p->variant != JGS2_DAMPER &&
+        p->variant != JGS2_EXACT) {
         why = "unknown variant";
         return JGS2_E_INVALID;
     }
@@ -345,7 +367,7 @@ int32_t jgs2_set_params(jgs2_solver* s, const jgs2_params* p) {
     s->ro_valid = false;
     drop_graphs(s);
     // the correction's rest Hessian carries M / h^2: it belongs to the old step
-    if (dt_changed) s->have_corr = false;
+    if (dt_changed) s->have_corr = s->have_full = false;
     if (dt_changed && s->have_material) {
         if ((r = upload_material_records(s)) != JGS2_OK) return r;
     }
@@ -550,7 +572,7 @@ int32_t jgs2_set_material(jgs2_solver* s, const double* E, const double* nu, con
     if (r != JGS2_OK) return r;
     if ((r = upload_incidence_records(s)) != JGS2_OK) return r;
     s->have_material = true;
-    s->have_corr = false;
+    s->have_corr = s->have_full = false;
     s->ro_valid = false;
     return JGS2_OK;
 }
@@ -799,6 +821,10 @@ static bool ready_to_step(jgs2_solver* s) {
     // the sweep kernels read the bodies' stop flags (a failed set_bodies leaves none)
     if (!s->have_bodies) { s->err = "no body tables (set_bodies failed)"; return false; }
     if (s->p.variant != JGS2_PLAIN && !s->have_corr) { s->err = "no correction (precompute or import)"; return false; }
+    if (s->p.variant == JGS2_EXACT && !s->have_full) {
+        s->err = "no full U-bar rows (precompute with the JGS2_EXACT variant)";
+        return false;
+    }
     return true;
 }
 
@@ -883,6 +909,35 @@ static int sweep_once(jgs2_solver* s) {
     SweepArgs a;
     build_sweep_args(s, a);
     const bool cub = s->p.variant == JGS2_CUBATURE;  // the two-phase R3 sweeps
+    if (s->p.variant == JGS2_EXACT) {
+        // gradients and rotations at the iterate, their rest-frame form in the
+        // rows' order, then every row's exact local solve (Jacobi), or the
+        // same for one colour at a time (GS, gradients refreshed per colour)
+        if (s->p.order == JGS2_JACOBI) {
+            if (!s->phase1_valid) launch_phase1(s, a, true, true);
+            launch_hvec(s, a);
+            launch_exact(s, a);
+            if (s->p.line_search) {
+                int r = line_search(s);
+                if (r != JGS2_OK) return r;
+            }
+            swap_u(s);
+        } else {
+            for (int c = 0; c < s->n_colors; ++c) {
+                SweepArgs all = a;
+                launch_phase1(s, all, true, true);
+                launch_hvec(s, all);
+                SweepArgs ac = a;
+                ac.list = s->d_colperm + s->col_off[c];
+                ac.n_list = s->col_off[c + 1] - s->col_off[c];
+                ac.in_place = 1;
+                launch_exact(s, ac);
+            }
+            s->phase1_valid = false;
+        }
+        s->sweeps_in_step++;
+        return jgs2::hip_check(s, hipGetLastError(), "sweep launch");
+    }
     if (s->p.variant == JGS2_DAMPER) {
         // rotations of the sweep's starting iterate x^k (Sec. 4.3), held for
         // every colour; each row's gradient and diagonal block are gathered

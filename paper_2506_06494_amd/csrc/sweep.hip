@@ -251,22 +251,47 @@ __device__ __forceinline__ void block_partial(double val, bool lane0, double* pa
 // polar rotation R_a; per-block partial sums of |g|^2 (FP64).
 // ---------------------------------------------------------------------------
 // One incident tet's share of g_v and of the volume-weighted F sum, added
-// with weight w (own corner e.x & 3 is vertex v).
-__device__ __forceinline__ void phase1_term(const SweepArgs& a, const int4 e, int v, float w, float* g, float* Fs) {
+// with weight w (own corner e.x & 3 is vertex v).  The gradient is evaluated
+// in FP64 (displacement gradient from the FP64 positions, stress and sum):
+// its terms (elastic, inertial, external) nearly cancel at a converged step,
+// so an FP32 evaluation would floor the relative residual of stiff bodies
+// near 1e-4.  The rotation's F sum stays FP32.
+__device__ __forceinline__ void phase1_term(const SweepArgs& a, const int4 e, int v, double w, double* g,
+                                            float* Fs) {
     const int c = e.x & 3;
     Tet T;
     load_tet_inc(a.tet, e, v, T);
-    float H[9], cH[9], P[9], gn[3];
-    Kin<float> K;
-    dispgrad(a.u, T, H);
+    const d4 u0 = a.u[T.id[0]], u1 = a.u[T.id[1]], u2 = a.u[T.id[2]], u3 = a.u[T.id[3]];
+    const double du[3][3] = {{u1.x - u0.x, u1.y - u0.y, u1.z - u0.z},
+                             {u2.x - u0.x, u2.y - u0.y, u2.z - u0.z},
+                             {u3.x - u0.x, u3.y - u0.y, u3.z - u0.z}};
+    double D[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) D[i] = (double)T.D[i];
+    double H[9], cH[9], P[9], gn[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) H[3 * i + j] = du[0][i] * D[j] + du[1][i] * D[3 + j] + du[2][i] * D[6 + j];
+    Kin<double> K;
     kinematics(H, K, cH);
-    snh_stress_H(H, K, cH, T.vmu, T.vlam, P);
-    gradN(T.D, c, gn);
+    snh_stress_H(H, K, cH, (double)T.vmu, (double)T.vlam, P);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) g[i] = fmaf(w, P[3 * i] * gn[0] + P[3 * i + 1] * gn[1] + P[3 * i + 2] * gn[2], g[i]);
-    const float wv = w * T.vol;
+    for (int j = 0; j < 3; ++j) {
+        const double r0 = D[j], r1 = D[3 + j], r2 = D[6 + j];
+        gn[j] = c == 0 ? -(r0 + r1 + r2) : (c == 1 ? r0 : (c == 2 ? r1 : r2));
+    }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Fs[i] = fmaf(wv, K.F[i], Fs[i]);
+    for (int i = 0; i < 3; ++i) g[i] = fma(w, P[3 * i] * gn[0] + P[3 * i + 1] * gn[1] + P[3 * i + 2] * gn[2], g[i]);
+    const float wv = (float)w * T.vol;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Fs[i] = fmaf(wv, (float)K.F[i], Fs[i]);
+}
+
+__device__ __forceinline__ double lane_sum_d(double v) {
+#pragma unroll
+    for (int o = LPV / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LPV);
+    return v;
 }
 
 // GATED (several bodies, inside a step's sweeps): rows of bodies that have
@@ -291,31 +316,34 @@ __global__ __launch_bounds__(BLOCK) void k_phase1(SweepArgs a, int want_R) {
     const int n = a.inc_n[f];
     const int4 e0 = GATED ? make_int4(0, 0, 0, 0) : a.inc4[(size_t)f * a.maxi + min(lane, a.maxi - 1)];
     const d4 uv = a.u[v], zv = a.zu[v];
-    float g[3] = {0.f, 0.f, 0.f}, Fs[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    double g[3] = {0.0, 0.0, 0.0};
+    float Fs[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int j0 = lane;
     if constexpr (!GATED) {
         const bool has = lane < n;
         const int4 e = make_int4(has ? e0.x : 0, has ? e0.y : 0, has ? e0.z : 0, has ? e0.w : 0);
-        phase1_term(a, e, v, has ? 1.0f : 0.0f, g, Fs);
+        phase1_term(a, e, v, has ? 1.0 : 0.0, g, Fs);
         j0 += LPV;
     }
     if (active)
-        for (int j = j0; j < n; j += LPV) phase1_term(a, a.inc4[(size_t)f * a.maxi + j], v, 1.0f, g, Fs);
+        for (int j = j0; j < n; j += LPV) phase1_term(a, a.inc4[(size_t)f * a.maxi + j], v, 1.0, g, Fs);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) g[i] = lane_sum(g[i]);
+    for (int i = 0; i < 3; ++i) g[i] = lane_sum_d(g[i]);
     if (want_R) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) Fs[i] = lane_sum(Fs[i]);
     }
     double gsq = 0.0;
     if (active && lane == 0) {
-        const float m = (float)zv.w;
-        g[0] += m * (float)(uv.x - zv.x);
-        g[1] += m * (float)(uv.y - zv.y);
-        g[2] += m * (float)(uv.z - zv.z);
-        barrier_terms(a, v, uv, g, nullptr);
-        a.g[v] = make_float4(g[0], g[1], g[2], 0.0f);
-        gsq = (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
+        const double m = zv.w;
+        g[0] += m * (uv.x - zv.x);
+        g[1] += m * (uv.y - zv.y);
+        g[2] += m * (uv.z - zv.z);
+        float gb[3] = {0.f, 0.f, 0.f};
+        barrier_terms(a, v, uv, gb, nullptr);
+        g[0] += gb[0]; g[1] += gb[1]; g[2] += gb[2];
+        a.g[v] = make_float4((float)g[0], (float)g[1], (float)g[2], 0.0f);
+        gsq = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
         if (want_R) {
             float mx = 0.0f;
 #pragma unroll
@@ -829,6 +857,176 @@ __global__ __launch_bounds__(BLK) void k_rot(SweepArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Exact co-rotated subspace (the literal form of Eq. local_newton with the
+// derivatives of Eq. relation and the co-rotated rows of Eq. tilde_phi):
+//   b_f = sum_a Phi_{f,a}^T g_a = R_f sum_a Ubar_{f,a}^T (R_a^T g_a)
+//   A_f = m_f / h^2 I + H^B_f + sum_{e ni f} sum_b H_e[c_f, b] Phi_{f,b}
+// with Phi_{f,b} = R_b Ubar_{f,b} R_f^T (the identity at b = f, zero at pinned
+// b), A_f symmetrised, x_f <- x_f - omega A_f^-1 b_f.
+// ---------------------------------------------------------------------------
+// Rest-frame gradients h_qx = R_a^T g_a in the order of the full rows.
+__global__ __launch_bounds__(256) void k_hvec(SweepArgs a) {
+    const int qx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (qx >= a.nVf) return;
+    const int v = a.qvert[qx];
+    const float4 g = a.g[v];
+    float R[9];
+    load_rot(a.R, v, R);
+    a.hvec[qx] = make_float4(R[0] * g.x + R[3] * g.y + R[6] * g.z, R[1] * g.x + R[4] * g.y + R[7] * g.z,
+                             R[2] * g.x + R[5] * g.y + R[8] * g.z, 0.0f);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One wave per row (4 rows per 256-thread block).  The wave first streams
+// the row's 9 planes of U-bar (non-temporal: every row is read once per
+// sweep; UT = float or _Float16) against the rest-frame gradients, with FP64
+// partial sums; then its lanes take the row's incident tets for the Hessian
+// term; lane 0 solves.
+template <typename UT>
+__global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int row = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int nidx = a.list ? a.n_list : a.nVf;
+    if (row >= nidx) return;  // the whole wave
+    const int f = a.list ? a.list[row] : row;
+    const int v = a.free_ids[f];
+    const d4 uv = a.u[v];
+    if (!body_on(a, f)) {
+        if (lane == 0 && !a.in_place) a.unext[v] = uv;  // a stopped body's Jacobi buffer carried over
+        return;
+    }
+    const size_t plane = (size_t)a.nVf;
+    const UT* U = static_cast<const UT*>(a.Ufull) + (size_t)f * 9 * plane;
+    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+    int qx = lane;
+    // four positions per lane in flight
+    for (; qx + 192 < a.nVf; qx += 256) {
+        float u[4][9];
+        float4 h[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            h[k] = a.hvec[qx + 64 * k];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) u[k][q] = (float)__builtin_nontemporal_load(U + q * plane + qx + 64 * k);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            y0 += (double)(u[k][0] * h[k].x + u[k][3] * h[k].y + u[k][6] * h[k].z);
+            y1 += (double)(u[k][1] * h[k].x + u[k][4] * h[k].y + u[k][7] * h[k].z);
+            y2 += (double)(u[k][2] * h[k].x + u[k][5] * h[k].y + u[k][8] * h[k].z);
+        }
+    }
+    for (; qx < a.nVf; qx += 64) {
+        const float4 h = a.hvec[qx];
+        float u[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) u[q] = (float)__builtin_nontemporal_load(U + q * plane + qx);
+        y0 += (double)(u[0] * h.x + u[3] * h.y + u[6] * h.z);
+        y1 += (double)(u[1] * h.x + u[4] * h.y + u[7] * h.z);
+        y2 += (double)(u[2] * h.x + u[5] * h.y + u[8] * h.z);
+    }
+    y0 = wave_sum_d(y0);
+    y1 = wave_sum_d(y1);
+    y2 = wave_sum_d(y2);
+    float Ri[9];
+    load_rot(a.R, v, Ri);
+    // Hessian term over the incident tets, one per lane
+    float A9[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int n = a.inc_n[f];
+    for (int j = lane; j < n; j += 64) {
+        const int4 e = a.inc4[(size_t)f * a.maxi + j];
+        const int c = e.x & 3;
+        Tet T;
+        load_tet_inc(a.tet, e, v, T);
+        float H[9], cH[9];
+        Kin<float> K;
+        dispgrad(a.u, T, H);
+        kinematics(H, K, cH);
+        float dF[3][9];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int q = 0; q < 9; ++q) dF[d][q] = 0.0f;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int vb = T.id[b];
+            float Phi[9];
+            if (vb == v) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) Phi[q] = (q % 4 == 0) ? 1.0f : 0.0f;
+            } else {
+                const int qb = a.qpos[vb];
+                if (qb < 0) {
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) Phi[q] = 0.0f;
+                } else {
+                    float Ub[9], Rb[9];
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) Ub[q] = (float)U[q * plane + qb];
+                    load_rot(a.R, vb, Rb);
+                    corotate(Ub, Ri, Rb, Phi);
+                }
+            }
+            float gnb[3];
+            gradN(T.D, b, gnb);
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int jj = 0; jj < 3; ++jj) dF[d][3 * i + jj] = fmaf(Phi[3 * i + d], gnb[jj], dF[d][3 * i + jj]);
+        }
+        float gnc[3];
+        gradN(T.D, c, gnc);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            float dP[9];
+            snh_dstress(K.F, K.C, 1.0f + K.Jm1, T.vmu, T.vlam, dF[d], dP);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                A9[3 * i + d] += dP[3 * i] * gnc[0] + dP[3 * i + 1] * gnc[1] + dP[3 * i + 2] * gnc[2];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) A9[q] = wave_sum_f(A9[q]);
+    if (lane == 0) {
+        const float yy[3] = {(float)y0, (float)y1, (float)y2};
+        float b[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) b[i] = Ri[3 * i] * yy[0] + Ri[3 * i + 1] * yy[1] + Ri[3 * i + 2] * yy[2];
+        const float m = (float)a.zu[v].w;
+        float A[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) A[3 * i + jj] = 0.5f * (A9[3 * i + jj] + A9[3 * jj + i]);
+        A[0] += m; A[4] += m; A[8] += m;
+        float gd[3] = {0.f, 0.f, 0.f}, Hb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        barrier_terms(a, v, uv, gd, Hb);
+        A[0] += Hb[0]; A[1] += Hb[1]; A[2] += Hb[2];
+        A[3] += Hb[1]; A[4] += Hb[3]; A[5] += Hb[4];
+        A[6] += Hb[2]; A[7] += Hb[4]; A[8] += Hb[5];
+        float dx[3];
+        local_solve(A, b, dx);
+        float st[3] = {a.omega * dx[0], a.omega * dx[1], a.omega * dx[2]};
+        clamp_step(a, v, uv, st);
+        d4* out = a.in_place ? const_cast<d4*>(a.u) : a.unext;
+        out[v] = make_d4(uv.x + st[0], uv.y + st[1], uv.z + st[2], 0.0);
+    }
+}
+
 // thetabar_t -= sum_c y_c . (V_t P(F_t) grad N_c) at the displacement u:
 // the derivative of the step's optimality condition with respect to
 // log E_t is the element's elastic force, since mu and lambda scale with E.
@@ -1212,6 +1410,18 @@ void launch_damper(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<2>(s, 
 // Rotation pass in a fixed shape (8 lanes per row, 64 rows per block): its
 // cost is the gather plus one polar decomposition per row, which this shape
 // runs 64 to a wave.
+void launch_hvec(jgs2_solver* s, const SweepArgs& a) {
+    launch(s, JGS2_K_HVEC, k_hvec, dim3((a.nVf + 255) / 256), dim3(256), a);
+}
+
+// One wave per row, four rows per block.
+void launch_exact(jgs2_solver* s, const SweepArgs& a) {
+    const int n = a.list ? a.n_list : a.nVf;
+    if (n == 0) return;
+    if (a.full_fp16) launch(s, JGS2_K_EXACT, k_exact<_Float16>, dim3((n + 3) / 4), dim3(256), a);
+    else launch(s, JGS2_K_EXACT, k_exact<float>, dim3((n + 3) / 4), dim3(256), a);
+}
+
 void launch_rotations(jgs2_solver* s, const SweepArgs& a) {
     constexpr int W = 8, BLK = 512, NV = BLK / W;
     const int nb = (a.nVf + NV - 1) / NV;
