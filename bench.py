@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--max-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="4x4x16 beam instead (quick check)")
-    ap.add_argument("--modes", default="jgs2_exact_jacobi,jgs2_exact_jacobi_fp16,jgs2_exact_gs,jgs2_damper_gs,"
+    ap.add_argument("--modes", default="jgs2_exact_jacobi,jgs2_exact_gs,jgs2_damper_gs,"
                                        "jgs2_damper_jacobi_w0.8,"
                                        "jgs2_jacobi,jgs2_gs,plain_jacobi,"
                                        "plain_jacobi_w0.8,plain_jacobi_w0.5,plain_jacobi_w0.3,plain_gs,"
@@ -47,6 +47,8 @@ def parse():
                     help="launch every sweep kernel eagerly instead of replaying captured sweep groups (same "
                          "kernels and arguments; used for traced runs)")
     ap.add_argument("--batched-beams", type=int, default=256)
+    ap.add_argument("--batched-steps", type=int, default=4, help="steps of the batched leg (30 in its full run)")
+    ap.add_argument("--contact-steps", type=int, default=120)
     ap.add_argument("--no-contact", action="store_true", help="skip the 10-sphere contact leg")
     ap.add_argument("--leg", choices=["contact"], help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -79,7 +81,7 @@ def main():
         calibrate_copy()
         return
     if args.leg == "contact":                  # child process of the default run
-        print(json.dumps(contact_leg()))
+        print(json.dumps(contact_leg(steps=args.contact_steps)))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU path.",
@@ -87,7 +89,7 @@ def main():
         sys.exit(2)
     # the contact leg runs first, in a child process started before this one
     # touches the GPU, so that a failure there cannot take the whole run down
-    con = None if args.no_contact or args.small else contact_leg_child()
+    con = None if args.no_contact or args.small else contact_leg_child(args.contact_steps)
     from paper_2506_06494_amd import inputs, jgs2
 
     stiff = [float(e) for e in args.stiffness.split(",")]
@@ -132,21 +134,35 @@ def main():
         sc = make(E)
         m = sc.mesh
         corr = None
+        exact_keep = {}      # one exact-variant handle per row precision, shared by its modes
         for name, cfg in modes:
             kw = dict(check_every=16)
             kw.update(cfg)
-            s = jgs2.Solver(dt=sc.dt, gravity=sc.gravity, rel_tol=1e-5, max_sweeps=args.max_sweeps,
-                            use_graph=0 if args.no_graph else 1, **kw)
-            s.upload_mesh(m.X, m.tets, m.pinned)
-            s.set_material(sc.E, sc.nu, sc.rho)
-            if cfg["variant"] == jgs2.EXACT:
-                # its own precompute: the full U-bar rows stay on the device
+            fp16 = kw.get("exact_fp16", 0)
+            if cfg["variant"] == jgs2.EXACT and fp16 in exact_keep:
+                s = exact_keep[fp16]           # the same U-bar rows; only the order and checks change
+                s.set_params(**{k: v for k, v in kw.items() if k != "variant"})
+            else:
+                s = jgs2.Solver(dt=sc.dt, gravity=sc.gravity, rel_tol=1e-5, max_sweeps=args.max_sweeps,
+                                use_graph=0 if args.no_graph else 1, **kw)
+                s.upload_mesh(m.X, m.tets, m.pinned)
+                s.set_material(sc.E, sc.nu, sc.rho)
+            if cfg["variant"] == jgs2.EXACT and fp16 not in exact_keep:
+                # its own precompute: the full U-bar rows stay on the device (the same run
+                # also trains the cubature tables, which the sampled modes then import)
+                key = f"{E:g} exact" + (" fp16" if fp16 else "")
                 print(f"[bench] E={E:g} {name}: GPU precompute with full rows ...", file=sys.stderr, flush=True)
                 t0 = time.perf_counter()
                 s.precompute(samples=4, n_cand=64, seed=0)
-                precompute_s[f"{E:g} exact"] = time.perf_counter() - t0
-                print(f"[bench] E={E:g} precompute (full rows) {precompute_s[f'{E:g} exact']:.2f} s", file=sys.stderr,
-                      flush=True)
+                precompute_s[key] = time.perf_counter() - t0
+                print(f"[bench] E={E:g} precompute (full rows) {precompute_s[key]:.2f} s", file=sys.stderr, flush=True)
+                exact_keep[fp16] = s
+                if corr is None:
+                    corr = s.export_correction(4)
+                    if corr0 is None:
+                        corr0 = corr
+            elif cfg["variant"] == jgs2.EXACT:
+                pass
             elif cfg["variant"] != jgs2.PLAIN:
                 if corr is None:
                     print(f"[bench] E={E:g} GPU precompute ...", file=sys.stderr, flush=True)
@@ -226,8 +242,11 @@ def main():
                              r_final_max=float(max(r["r_final"] for r in recs)))
             results.setdefault(name, {})[f"{E:g}"] = entry
             kernel_stats.setdefault(name, {})[f"{E:g}"] = kt
-            s.close()
+            if cfg["variant"] != jgs2.EXACT:
+                s.close()
             print(f"[bench] E={E:g} {name}: {json.dumps(entry)}", file=sys.stderr, flush=True)
+        for s in exact_keep.values():
+            s.close()
         print(f"[bench] E={E:g} done: " + ", ".join(
             f"{n}={results[n][f'{E:g}'].get('s_per_step', results[n][f'{E:g}']['status'])}" for n, _ in modes),
             file=sys.stderr, flush=True)
@@ -293,11 +312,11 @@ def main():
     jgs2_sweep = measure_cubature_sweep(sc0, corr0) if corr0 is not None else None
 
     adj = None if args.no_adjoint or args.small else adjoint_leg()
-    bat = None if args.no_batched or args.small else batched_leg(args.batched_beams)
+    bat = None if args.no_batched or args.small else batched_leg(args.batched_beams, steps=args.batched_steps)
 
     cpu = None
     if not args.no_cpu_baseline and value is not None:
-        cpu = cpu_baseline(sc0, results[head_mode][E0]["sweeps_per_step"], n_colors)
+        cpu = cpu_baseline(sc0, results[head_mode][E0]["sweeps_per_step"])
 
     line = {
         "metric": METRIC, "value": value, "unit": "s/step", "n_gpus": 1, "steps": args.steps,
@@ -341,13 +360,16 @@ def compare_table(results, names, stiff, head_mode):
     return out
 
 
-def batched_leg(n_beams=256, steps=2, max_sweeps=1000, check_every=8, omega=1.5):
+def batched_leg(n_beams=256, steps=4, loop_steps=2, max_sweeps=20000, check_every=8, omega=1.5):
     """Many-beam workload: n_beams beams with cross-section a, b in U{4..24},
     length in U{16..96} cells of 0.05 m, log-uniform E in [1e4, 1e7], nu in
     U[0.3, 0.48] (seed 0), pinned at x = 0, gravity, from rest; coloured GS
     (omega 1.5) with per-beam residuals and stop masks, sweep groups replayed
-    from captured graphs, launch shape from the autotuner.  Compared with the
-    same beams stepped one after another with their own solvers."""
+    from captured graphs, launch shape from the autotuner; `steps` steps, each
+    until every beam reaches 1e-5 (or the sweep cap).  Compared with the same
+    beams stepped one after another with their own solvers over the first
+    `loop_steps` steps (the batched run's first `loop_steps` steps are timed
+    separately for that comparison)."""
     from paper_2506_06494_amd import inputs, jgs2
     spec = inputs.batched_beams(n_beams, seed=0)
     meshes, E, nu = [], [], []
@@ -381,13 +403,22 @@ def batched_leg(n_beams=256, steps=2, max_sweeps=1000, check_every=8, omega=1.5)
             "bytes_per_launch": round(per_launch),
             "achieved": round(per_launch / (ms * 1e-3 / n) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / HBM_PEAK_GBS, 4)
-    sync()
-    t0 = time.perf_counter()
-    stats = [s.step(raise_on_error=False) for _ in range(steps)]
-    sync()
-    tb = (time.perf_counter() - t0) / steps
-    sw, rel = s.body_stats()
+    stats, t_steps, conv = [], [], []
+    for k in range(steps):
+        sync()
+        t0 = time.perf_counter()
+        st = s.step(raise_on_error=False)
+        sync()
+        t_steps.append(time.perf_counter() - t0)
+        stats.append(st)
+        sw, rel = s.body_stats()
+        conv.append(int(np.sum(rel <= 1e-5)))
+        print(f"[bench] batched step {k}: {t_steps[-1]:.3f} s, {st['sweeps']} sweeps, {conv[-1]}/{n_beams} beams "
+              f"converged, status {st['status']}", file=sys.stderr, flush=True)
+        if st["status"] < 0:
+            break
     s.close()
+    tb = float(np.mean(t_steps[:loop_steps]))
     # per-beam launch loop: the same beams, one solver each, same parameters and tuning
     solvers = []
     for m, (L, a, b, Eb, nub) in zip(meshes, spec):
@@ -399,28 +430,30 @@ def batched_leg(n_beams=256, steps=2, max_sweeps=1000, check_every=8, omega=1.5)
         solvers.append(q)
     sync()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for _ in range(loop_steps):
         for q in solvers:
             q.step(raise_on_error=False)
     sync()
-    tl = (time.perf_counter() - t0) / steps
+    tl = (time.perf_counter() - t0) / loop_steps
     for q in solvers:
         q.close()
     out = {"workload": f"{n_beams} beams (seed 0): {u.nV:,} vertices, {u.nT:,} tets, cross-section U{{4..24}}^2, "
                        f"length U{{16..96}}, E log-U[1e4,1e7], nu U[0.3,0.48], from rest, gravity",
-           "steps": steps, "max_sweeps": max_sweeps, "omega": omega, "tuned_shape": [lpv, blk],
-           "batched_s_per_step": tb, "per_beam_loop_s_per_step": tl, "speedup": tl / tb,
-           "beams_converged_last_step": int(np.sum(rel <= 1e-5)), "sweeps_last_step_max": int(sw.max()),
-           "sweeps_last_step_mean": float(sw.mean()), "status": [st["status"] for st in stats],
+           "steps": len(stats), "max_sweeps": max_sweeps, "omega": omega, "tuned_shape": [lpv, blk],
+           "batched_s_per_step": float(np.mean(t_steps)), "batched_s_per_step_first": tb,
+           "per_beam_loop_s_per_step_first": tl, "speedup_first_steps": tl / tb, "loop_steps": loop_steps,
+           "beams_converged_per_step": conv, "all_converged_every_step": all(c == n_beams for c in conv),
+           "sweeps_per_step": [st["sweeps"] for st in stats], "status": [st["status"] for st in stats],
            "roofline": roof}
     print(f"[bench] batched: {json.dumps(out)}", file=sys.stderr, flush=True)
     return out
 
 
-def contact_leg_child(timeout_s=900):
+def contact_leg_child(steps=120, timeout_s=900):
     import subprocess
     try:
-        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--leg", "contact"], capture_output=True,
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--leg", "contact", "--contact-steps",
+                            str(steps)], capture_output=True,
                            text=True, timeout=timeout_s)
     except subprocess.TimeoutExpired:
         return {"error": f"contact leg exceeded {timeout_s} s"}
@@ -432,23 +465,20 @@ def contact_leg_child(timeout_s=900):
     return json.loads(lines[-1])
 
 
-def contact_leg(steps=3, max_sweeps=3000, check_every=16):
-    """Contact workload: the 10 voxelised spheres of radius 0.3 m (0.01 m grid,
-    1,217,690 vertices, 6,786,240 tets; five with E 2e6, five with E 1e5,
-    nu 0.45, centres drawn with seed 0 in the 2 x 2 x 4 m box), each lowered
-    until its lowest vertex is 0.6 mm above the floor and moving down at
-    1 m/s, so the floor barrier (d_hat 1e-3 m, kappa 1e4) is active from the
-    first step; floor and four walls as planes, gravity -z, dt 1/120; plain
-    coloured GS with the per-vertex feasibility clamp, per-sphere residuals."""
+def contact_leg(steps=120, max_sweeps=400, check_every=16):
+    """Contact workload as configured: the 10 voxelised spheres of radius
+    0.3 m (0.01 m grid, 1,217,690 vertices, 6,786,240 tets; five with E 2e6,
+    five with E 1e5, nu 0.45) at rest at their seeded centres in the 2 x 2 x 4 m
+    box, dropped under gravity (-z) for 120 steps of 1/120 s; floor and four
+    walls as IPC plane barriers (d_hat 1e-3 m, kappa 1e4); plain coloured GS
+    with the per-vertex feasibility clamp and per-sphere residuals, at most
+    `max_sweeps` sweeps per step (a step that stops there is reported as not
+    converged)."""
     from paper_2506_06494_amd import inputs, jgs2
     sc = inputs.contact_scene(0)
     m = sc.mesh
     X = m.X.copy()
-    for b in range(int(m.body.max()) + 1):
-        idx = m.body == b
-        X[idx, 2] -= X[idx, 2].min() - 6e-4
     v0 = np.zeros_like(X)
-    v0[:, 2] = -1.0
     s = jgs2.Solver(dt=sc.dt, gravity=sc.gravity, planes=sc.planes, d_hat=sc.d_hat, kappa=sc.kappa, order=jgs2.GS,
                     omega=1.0, rel_tol=1e-5, max_sweeps=max_sweeps, check_every=check_every, use_graph=1)
     s.upload_mesh(X, m.tets, m.pinned)
@@ -470,67 +500,92 @@ def contact_leg(steps=3, max_sweeps=3000, check_every=16):
             "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / HBM_PEAK_GBS, 4)
     s.set_state(X, v0)
+    zmin, stats = [], []
     sync()
     t0 = time.perf_counter()
-    stats = [s.step(raise_on_error=False) for _ in range(steps)]
+    for k in range(steps):
+        st = s.step(raise_on_error=False)
+        stats.append(st)
+        if st["status"] < 0:
+            break
+        if k % 10 == 9 or k == steps - 1:
+            x, _ = s.get_state()
+            zmin.append(float(x[:, 2].min()))
+            print(f"[bench] contact step {k + 1}: {st['sweeps']} sweeps, r {st['r_final']:.2e}, status "
+                  f"{st['status']}, lowest vertex z {zmin[-1]:.5f} m", file=sys.stderr, flush=True)
     sync()
-    tc = (time.perf_counter() - t0) / steps
-    x, _ = s.get_state()
-    sw, rel = s.body_stats()
+    tc = (time.perf_counter() - t0) / len(stats)
     s.close()
-    out = {"workload": f"10 spheres r 0.3 m (0.01 m grid): {m.nV:,} vertices, {m.nT:,} tets, lowered to 0.6 mm above "
-                       "the floor at 1 m/s down, planes z=0, x=0,2, y=0,2, d_hat 1e-3, kappa 1e4",
-           "steps": steps, "s_per_step": tc, "status": [st["status"] for st in stats],
-           "sweeps_per_step": [st["sweeps"] for st in stats], "r_final": [st["r_final"] for st in stats],
-           "min_floor_distance_m": float(x[:, 2].min()), "colours": int(ncol), "tuned_shape": [lpv, blk],
+    sw = [st["sweeps"] for st in stats]
+    status = [st["status"] for st in stats]
+    out = {"workload": f"10 spheres r 0.3 m (0.01 m grid): {m.nV:,} vertices, {m.nT:,} tets, at rest at seeded centres "
+                       "in the 2 x 2 x 4 m box, dropped; planes z=0, x=0,2, y=0,2, d_hat 1e-3, kappa 1e4",
+           "steps": len(stats), "max_sweeps": max_sweeps, "s_per_step": tc,
+           "steps_converged": int(sum(1 for v in status if v == jgs2.OK)),
+           "steps_at_sweep_cap": int(sum(1 for v in status if v == jgs2.NOT_CONVERGED)),
+           "failed": [v for v in status if v < 0], "sweeps_per_step_mean": float(np.mean(sw)),
+           "sweeps_per_step": sw, "r_final_max": float(max(st["r_final"] for st in stats)),
+           "lowest_vertex_z_every_10_steps": zmin, "colours": int(ncol), "tuned_shape": [lpv, blk],
            "roofline": roof}
-    print(f"[bench] contact: {json.dumps(out)}", file=sys.stderr, flush=True)
+    print(f"[bench] contact: {json.dumps({k: v for k, v in out.items() if k != 'sweeps_per_step'})}",
+          file=sys.stderr, flush=True)
     return out
 
 
-def adjoint_leg(n_steps=30, ckpt_every=5, omega=1.7):
+def adjoint_leg(n_steps=30, ckpt_every=5):
     """Differentiation workload: 16x16x64 beam (18,785 vertices, 98,304
-    tets), per-tet log E = log 1e6 + U(-0.3, 0.3), u = 0, 30 steps of plain
-    coloured GS (step scale omega) to 1e-5, loss |tip centroid - target|^2;
-    forward rollout with checkpoints every 5 steps, then the adjoint
-    (recompute + linear sweeps to 1e-5 + stiffness gradient), both timed with
-    a synchronised wall clock."""
+    tets), per-tet log E = log 1e6 + U(-0.3, 0.3), u = 0, 30 steps to 1e-5,
+    loss |tip centroid - target|^2; forward rollout with checkpoints every 5
+    steps, then the adjoint (recompute + linear sweeps to 1e-5 + stiffness
+    gradient), both timed with a synchronised wall clock.  Run with the exact
+    co-rotated subspace in Jacobi order (forward steps and the adjoint's
+    linear sweeps), and with plain coloured GS at step scale 1.7 for
+    comparison."""
     from paper_2506_06494_amd import inputs, jgs2
     sc, logE, target = inputs.diff_beam(0)
     m = sc.mesh
-    s = jgs2.Solver(dt=sc.dt, gravity=sc.gravity, order=jgs2.GS, omega=omega, rel_tol=1e-5, adj_rel_tol=1e-5,
-                    check_every=16, use_graph=1)
-    s.upload_mesh(m.X, m.tets, m.pinned)
-    s.set_material(np.exp(logE), 0.45, 1000.0)
     tip = np.nonzero(m.X[:, 0] >= m.X[:, 0].max() - 1e-12)[0]
-    out = {}
-    for rep in range(2):                       # the first pass warms up
-        s.set_state(m.X, np.zeros_like(m.X))
-        sync()
-        t0 = time.perf_counter()
-        s.rollout(n_steps, ckpt_every)
-        sync()
-        tf = time.perf_counter() - t0
-        x, _ = s.get_state()
-        r = x[tip].mean(0) - target
-        xbar = np.zeros_like(x)
-        xbar[tip] = 2.0 * r / tip.size
-        sync()
-        t0 = time.perf_counter()
-        th, _, vb0, st = s.rollout_backward(xbar)
-        sync()
-        tb = time.perf_counter() - t0
-        out = {"workload": "beam 16x16x64 (18,785 vertices, 98,304 tets), log E = log 1e6 + U(-0.3,0.3), "
-                           f"30 steps, checkpoints every 5, plain coloured GS (omega {omega}) forward and adjoint "
-                           "to 1e-5",
-               "loss": float(r @ r), "forward_s_per_step": tf / n_steps, "adjoint_s_per_step": tb / n_steps,
-               "ratio": tb / tf, "adjoint_sweeps_per_step": st["adjoint_sweeps"] / n_steps,
-               "recompute_sweeps_per_step": st["forward_sweeps"] / n_steps,
-               "max_adjoint_rel_res": st["max_rel_res"], "thetabar_norm": float(np.linalg.norm(th)),
-               "ubar": vb0[~m.pinned.astype(bool)].sum(0).tolist()}
-        print(f"[bench] adjoint pass {rep}: {json.dumps(out)}", file=sys.stderr, flush=True)
-    s.close()
-    return out
+    legs = {}
+    for name, cfg in (("jgs2_exact_jacobi", dict(variant=jgs2.EXACT, order=jgs2.JACOBI, omega=1.0, check_every=1)),
+                      ("plain_gs_w1.7", dict(variant=jgs2.PLAIN, order=jgs2.GS, omega=1.7, check_every=16))):
+        s = jgs2.Solver(dt=sc.dt, gravity=sc.gravity, rel_tol=1e-5, adj_rel_tol=1e-5, use_graph=1, **cfg)
+        s.upload_mesh(m.X, m.tets, m.pinned)
+        s.set_material(np.exp(logE), 0.45, 1000.0)
+        if cfg["variant"] == jgs2.EXACT:
+            t0 = time.perf_counter()
+            s.precompute(samples=4, n_cand=64, seed=0)
+            pre = time.perf_counter() - t0
+        out = {}
+        for rep in range(2):                       # the first pass warms up
+            s.set_state(m.X, np.zeros_like(m.X))
+            sync()
+            t0 = time.perf_counter()
+            fst = s.rollout(n_steps, ckpt_every)
+            sync()
+            tf = time.perf_counter() - t0
+            x, _ = s.get_state()
+            r = x[tip].mean(0) - target
+            xbar = np.zeros_like(x)
+            xbar[tip] = 2.0 * r / tip.size
+            sync()
+            t0 = time.perf_counter()
+            th, _, vb0, st = s.rollout_backward(xbar)
+            sync()
+            tb = time.perf_counter() - t0
+            out = {"mode": name, "forward_status": jgs2.STATUS_NAMES.get(fst["status"], fst["status"]),
+                   "adjoint_status": jgs2.STATUS_NAMES.get(st["status"], st["status"]),
+                   "loss": float(r @ r), "forward_s_per_step": tf / n_steps, "adjoint_s_per_step": tb / n_steps,
+                   "ratio": tb / tf, "adjoint_sweeps_per_step": st["adjoint_sweeps"] / n_steps,
+                   "recompute_sweeps_per_step": st["forward_sweeps"] / n_steps,
+                   "max_adjoint_rel_res": st["max_rel_res"], "thetabar_norm": float(np.linalg.norm(th)),
+                   "ubar": st["ubar"].tolist()}
+            if cfg["variant"] == jgs2.EXACT:
+                out["precompute_s"] = pre
+            print(f"[bench] adjoint {name} pass {rep}: {json.dumps(out)}", file=sys.stderr, flush=True)
+        s.close()
+        legs[name] = out
+    return {"workload": "beam 16x16x64 (18,785 vertices, 98,304 tets), log E = log 1e6 + U(-0.3,0.3), 30 steps, "
+                        "checkpoints every 5, forward and adjoint to 1e-5", "modes": legs}
 
 
 def kernel_source_sha1():
@@ -632,58 +687,40 @@ def measure_cubature_sweep(sc, corr, sweeps=64):
     return out
 
 
-class _StandInTables:
-    """Correction tables of the oracle's shape with seeded stand-in values
-    (S random non-incident samples per free vertex, unit weights, scaled
-    identity basis rows): the cost of an oracle sweep depends on the table
-    shapes only, and building the oracle's own tables for this beam is far
-    beyond a bounded sample."""
-
-    def __init__(self, mdl, ring, S, seed):
-        rng = np.random.default_rng(seed)
-        self.verts = mdl.free_ids
-        n = self.verts.size
-        self.nbr = [ring[v][mdl.free[ring[v]]] for v in self.verts]
-        self.U_nbr = [np.broadcast_to(0.1 * np.eye(3), (a.size, 3, 3)).copy() for a in self.nbr]
-        self.samples = rng.integers(0, mdl.nT, size=(n, S))
-        for k, v in enumerate(self.verts):
-            for j in range(S):
-                while np.any(mdl.tets[self.samples[k, j]] == v):
-                    self.samples[k, j] = rng.integers(0, mdl.nT)
-        self.weights = np.ones((n, S))
-        self.U_samp = np.broadcast_to(0.1 * np.eye(3), (n, S, 4, 3, 3)).copy()
-        self.gcoef = np.zeros((n, S, 4))
-
-
-def cpu_baseline(sc, sweeps_per_step, n_colors, S=4, seed=0):
-    """The oracle's damper-reading coloured Gauss-Seidel (variant R2D, the
-    headline mode), timed on one host core on a bounded sample: whole colour
-    passes (gradients, rotations and element Hessians at the current iterate,
-    then the colour's local systems and solves, as the oracle does before
-    every colour), repeated for about 10 s, scaled by colours x sweeps per
-    step of the GPU run."""
+def cpu_baseline(sc, sweeps_per_step, n_rows=192, seed=0):
+    """The oracle's exact-subspace Jacobi sweep (variant RX, the headline
+    mode), timed on one host core on a bounded sample: the gradient, the
+    per-vertex rotations and the sparse Hessian of the whole mesh at the
+    iterate (once per sweep), then the local systems (H row block times the
+    co-rotated U-bar rows, reduced gradient over every free vertex) and
+    solves of `n_rows` rows, scaled to every free row and to the GPU run's
+    sweeps per step.  The U-bar rows are seeded stand-ins of the right shape:
+    the sweep's cost depends on their shape only, and the oracle's own rows
+    for this beam (three band solves per vertex, 2 x 49 GB in FP64) are
+    precompute, far beyond a bounded sample."""
     from threadpoolctl import threadpool_limits
-    from oracle import fem, mesh as omesh, sweep as osw
+    from oracle import fem, sweep as osw
     mdl = fem.model_from_scene(sc)
-    ring = omesh.one_ring(mdl.tets, mdl.nV)
-    col = omesh.greedy_coloring(ring, mdl.free)
-    tab = _StandInTables(mdl, ring, S, seed)
-    sw = osw.Sweeper(mdl, tab, osw.R2D)
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(mdl.free_ids, n_rows, replace=False))
+    U = 0.01 * rng.standard_normal((n_rows, mdl.nV, 3, 3))
     z = mdl.inertial_target(sc.x0, sc.v0)
     x = sc.x0.copy()
-    passes = 0
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        while passes < 8 and (passes == 0 or time.perf_counter() - t0 < 10.0):
-            verts = np.nonzero(col == passes % n_colors)[0]
-            A, b = sw.systems(x, z, verts)
-            osw.local_solve(A, b)
-            passes += 1
-        dt = (time.perf_counter() - t0) / passes
-    return {"value": round(dt * n_colors * sweeps_per_step, 3), "unit": "s/step", "cores": 1, "kind": "oracle",
-            "sample": f"{passes} oracle R2D colour passes on {sc.mesh.name} ({dt:.2f} s each, stand-in "
-                      f"correction tables of the same shape), x {n_colors} colours x {sweeps_per_step:.1f} GPU "
-                      f"sweeps/step (extrapolated)"}
+        g, R = osw.phase1(mdl, x, z)
+        H = mdl.hessian(x)
+        t_mesh = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        A, b = osw.literal_exact_systems(mdl, osw.corotated_rows(U, R, rows), g, H, rows)
+        osw.local_solve(A, b)
+        t_rows = time.perf_counter() - t0
+    per_sweep = t_mesh + t_rows / n_rows * mdl.free_ids.size
+    return {"value": round(per_sweep * sweeps_per_step, 3), "unit": "s/step", "cores": 1, "kind": "oracle",
+            "sample": f"oracle RX Jacobi sweep on {sc.mesh.name}: whole-mesh gradient, rotations and Hessian "
+                      f"({t_mesh:.2f} s) + {n_rows} sampled rows ({t_rows:.2f} s, stand-in U-bar rows of the same "
+                      f"shape), scaled to {mdl.free_ids.size} rows ({per_sweep:.1f} s per sweep) x "
+                      f"{sweeps_per_step:.1f} GPU sweeps/step (extrapolated)"}
 
 
 if __name__ == "__main__":

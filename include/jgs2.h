@@ -240,6 +240,16 @@ int32_t jgs2_get_poses(jgs2_solver* s, int32_t* n_poses, double* eigenvalues);
 /* State: positions x and velocities v (nV x 3) copied from / to the host. */
 int32_t jgs2_set_state(jgs2_solver* s, const double* x, const double* v);
 int32_t jgs2_get_state(jgs2_solver* s, double* x, double* v);
+/* The same for a state that lives in device memory (Sec. 3, Eq. variation:
+ * x-hat and its velocity): x and v are device pointers (allocations of the
+ * HIP runtime libjgs2 is linked against) to nV x 3 doubles, row-major, read
+ * or written on the handle's stream, which the calls wait for; nothing
+ * crosses PCIe but a 4-byte flag.  set_state_device returns JGS2_E_INVALID
+ * (and leaves no state) if a value is not finite; velocities of pinned
+ * vertices are stored as zero.  Results are bitwise those of the host
+ * calls. */
+int32_t jgs2_set_state_device(jgs2_solver* s, const double* x, const double* v);
+int32_t jgs2_get_state_device(jgs2_solver* s, double* x, double* v);
 
 /* One implicit-Euler step (Sec. 3): z = xhat + h vhat + h^2 g, x0 = xhat,
  * sweeps until |g|/|g(x0)| <= rel_tol or max_sweeps, then v = (x - xhat)/h.

@@ -83,6 +83,7 @@ struct SweepArgs {
     const float4* lrhs;     // [nV] right-hand side
     const float* mh2;       // [nV] m_a / h^2 (0 if pinned)
     int no_write;           // residual partials only, no update
+    float4* lres;           // [nV] optional: the linear residual H y - rhs per free vertex
     // bodies: a free vertex of a body whose residual reached rel_tol is skipped
     const int* fbody;       // [nVf] body of each free vertex
     const int* body_on;     // [n_bodies] 1 while the body iterates (nullptr: all; the
@@ -153,6 +154,9 @@ struct jgs2_solver {
     int* d_qvert = nullptr;                // [nVf]
     float4* d_hvec = nullptr;              // [nVf]
     bool have_full = false;
+    double* d_X64 = nullptr;               // device state I/O: FP64 rest positions [nV * 3]
+    uint8_t* d_pin8 = nullptr;             // [nV]
+    int* d_flag = nullptr;                 // [1]
     int* d_samp_e = nullptr;
     float* d_samp = nullptr;
     double* d_partial = nullptr;
@@ -238,6 +242,7 @@ void launch_reduce_into(jgs2_solver* s, const double* in, int n, double* out);
 void launch_rotations(jgs2_solver* s, const SweepArgs& a);  // every free row (a.list unused)
 void launch_hvec(jgs2_solver* s, const SweepArgs& a);
 void launch_exact(jgs2_solver* s, const SweepArgs& a);
+void launch_exact_linear(jgs2_solver* s, const SweepArgs& a);
 void launch_commit(jgs2_solver* s, const SweepArgs& a);
 void launch_linear(jgs2_solver* s, const SweepArgs& a);
 void launch_param_grad(jgs2_solver* s, const d4* u, const float4* y, double* thbar);

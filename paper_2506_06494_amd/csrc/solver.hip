@@ -33,6 +33,7 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_inc4); dfree(s->d_irec_c); dfree(s->d_incn_c); dfree(s->d_vid_c); dfree(s->d_fbody_c);
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
     dfree(s->d_Ufull); dfree(s->d_qpos); dfree(s->d_qvert); dfree(s->d_hvec); s->have_full = false;
+    dfree(s->d_X64); dfree(s->d_pin8); dfree(s->d_flag);
     dfree(s->d_ck_u); dfree(s->d_ck_v); dfree(s->d_seg); dfree(s->d_y); dfree(s->d_ynext); dfree(s->d_xbar);
     dfree(s->d_vbar); dfree(s->d_rhs); dfree(s->d_thbar);
     dfree(s->d_fbody); dfree(s->d_seg_idx); dfree(s->d_body_on); dfree(s->d_body_sweeps);
@@ -730,6 +731,98 @@ int32_t jgs2_set_state(jgs2_solver* s, const double* x, const double* v) {
     return JGS2_OK;
 }
 
+// Device-resident state: x, v are nV x 3 doubles in device memory.
+__global__ void k_state_in(int nV, const double* __restrict__ X64, const uint8_t* __restrict__ pinned,
+                           const double* __restrict__ x, const double* __restrict__ v, d4* __restrict__ uhat,
+                           d4* __restrict__ u, d4* __restrict__ unext, float4* __restrict__ vhat,
+                           int* __restrict__ bad) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nV) return;
+    double uu[3];
+    float vl[3];
+    bool ok = true;
+    for (int i = 0; i < 3; ++i) {
+        const double xi = x[3 * a + i], vi = v[3 * a + i];
+        ok = ok && isfinite(xi) && isfinite(vi);
+        uu[i] = xi - X64[3 * a + i];
+        vl[i] = pinned[a] ? 0.0f : (float)vi;
+    }
+    if (!ok) *bad = 1;
+    const d4 ud = make_d4(uu[0], uu[1], uu[2], 0.0);
+    uhat[a] = ud;
+    u[a] = ud;
+    unext[a] = ud;
+    vhat[a] = make_float4(vl[0], vl[1], vl[2], 0.0f);
+}
+
+__global__ void k_state_out(int nV, const double* __restrict__ X64, const d4* __restrict__ u,
+                            const float4* __restrict__ vhat, double* __restrict__ x, double* __restrict__ v) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nV) return;
+    const d4 ud = u[a];
+    const float4 vv = vhat[a];
+    if (x) {
+        x[3 * a] = X64[3 * a] + ud.x;
+        x[3 * a + 1] = X64[3 * a + 1] + ud.y;
+        x[3 * a + 2] = X64[3 * a + 2] + ud.z;
+    }
+    if (v) {
+        v[3 * a] = vv.x;
+        v[3 * a + 1] = vv.y;
+        v[3 * a + 2] = vv.z;
+    }
+}
+
+// FP64 rest positions and pinned flags on the device, made on first use.
+static int ensure_state_io(jgs2_solver* s) {
+    if (s->d_X64) return JGS2_OK;
+    const size_t nV = s->nV;
+    int r;
+    if ((r = dalloc(s, s->d_X64, 3 * nV)) || (r = dalloc(s, s->d_pin8, nV)) || (r = dalloc(s, s->d_flag, 1)))
+        return r;
+    std::vector<uint8_t> pin(nV);
+    for (size_t a = 0; a < nV; ++a) pin[a] = s->pinned[a] ? 1 : 0;
+    if ((r = upload(s, s->d_X64, s->X.data(), 3 * nV)) || (r = upload(s, s->d_pin8, pin.data(), nV))) return r;
+    return JGS2_OK;
+}
+
+int32_t jgs2_set_state_device(jgs2_solver* s, const double* x, const double* v) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_mesh) return s->fail(JGS2_E_NOT_READY, "no mesh");
+    if (!x || !v) return s->fail(JGS2_E_INVALID, "NULL state");
+    int r = ensure_state_io(s);
+    if (r != JGS2_OK) return r;
+    HIPCHK(hipMemsetAsync(s->d_flag, 0, sizeof(int), s->stream));
+    hipLaunchKernelGGL(k_state_in, dim3((s->nV + 255) / 256), dim3(256), 0, s->stream, s->nV,
+                       (const double*)s->d_X64, (const uint8_t*)s->d_pin8, x, v, s->d_uhat, s->d_u, s->d_unext,
+                       s->d_vhat, s->d_flag);
+    HIPCHK(hipGetLastError());
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, s->d_flag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (bad) {
+        s->have_state = false;
+        return s->fail(JGS2_E_INVALID, "non-finite state");
+    }
+    s->have_state = true;
+    s->in_step = false;
+    s->phase1_valid = false;
+    s->ro_valid = false;
+    return JGS2_OK;
+}
+
+int32_t jgs2_get_state_device(jgs2_solver* s, double* x, double* v) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_state) return s->fail(JGS2_E_NOT_READY, "no state");
+    int r = ensure_state_io(s);
+    if (r != JGS2_OK) return r;
+    hipLaunchKernelGGL(k_state_out, dim3((s->nV + 255) / 256), dim3(256), 0, s->stream, s->nV,
+                       (const double*)s->d_X64, (const d4*)s->d_u, (const float4*)s->d_vhat, x, v);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return JGS2_OK;
+}
+
 int32_t jgs2_get_state(jgs2_solver* s, double* x, double* v) {
     if (!s) return JGS2_E_INVALID;
     if (!s->have_state) return s->fail(JGS2_E_NOT_READY, "no state");
@@ -1372,11 +1465,41 @@ static int adjoint_solve(jgs2_solver* s, const d4* xstar, int64_t* sweeps, doubl
     }
     if ((r = linear_residual2(s, a, &r2)) != JGS2_OK) return r;
     *rel = std::sqrt(r2 / b2);
+    const bool exact = s->p.variant == JGS2_EXACT;
+    if (exact) launch_rotations(s, a);  // the co-rotated rows at x*
     int k = 0;
     while (*rel > s->p.adj_rel_tol && k < s->p.adj_max_sweeps) {
         const int n = std::min(s->p.check_every, s->p.adj_max_sweeps - k);
         for (int i = 0; i < n; ++i) {
-            if (s->p.order == JGS2_JACOBI) {
+            if (exact) {
+                // the exact subspace's local systems of H(x*) y = rhs: residual
+                // r = H y - rhs at every vertex, its rest-frame form, then the
+                // rows (all of them, or one colour at a time with r refreshed)
+                const int nc = s->p.order == JGS2_JACOBI ? 1 : s->n_colors;
+                for (int c = 0; c < nc; ++c) {
+                    SweepArgs ar = a;
+                    ar.list = nullptr;
+                    ar.n_list = 0;
+                    ar.no_write = 1;
+                    ar.ly = s->d_y;
+                    ar.lres = s->d_g;
+                    launch_linear(s, ar);
+                    SweepArgs ah = a;
+                    ah.g = s->d_g;
+                    launch_hvec(s, ah);
+                    SweepArgs ae = a;
+                    ae.ly = s->d_y;
+                    if (s->p.order == JGS2_JACOBI) {
+                        ae.lynext = s->d_ynext;
+                    } else {
+                        ae.in_place = 1;
+                        ae.list = s->d_colperm + s->col_off[c];
+                        ae.n_list = s->col_off[c + 1] - s->col_off[c];
+                    }
+                    launch_exact_linear(s, ae);
+                }
+                if (s->p.order == JGS2_JACOBI) std::swap(s->d_y, s->d_ynext);
+            } else if (s->p.order == JGS2_JACOBI) {
                 SweepArgs aj = a;
                 aj.ly = s->d_y;
                 aj.lynext = s->d_ynext;

@@ -752,6 +752,7 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
             barrier_terms(a, v, uv, g, A6);
         }
         gsq = (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
+        if (LIN && a.lres) a.lres[v] = make_float4(g[0], g[1], g[2], 0.0f);
         if (!a.no_write) {
             float A[9] = {A6[0], A6[1], A6[2], A6[1], A6[3], A6[4], A6[2], A6[4], A6[5]};
             float dx[3];
@@ -894,7 +895,10 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 // sweep; UT = float or _Float16) against the rest-frame gradients, with FP64
 // partial sums; then its lanes take the row's incident tets for the Hessian
 // term; lane 0 solves.
-template <typename UT>
+// LIN (adjoint): the same local system of H(x*) y = rhs, with the linear
+// residual r = H y - rhs in place of g (its rest-frame form in a.hvec), the
+// Hessian at a.u = x*, and the update applied to y.
+template <typename UT, bool LIN>
 __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
     const int lane = threadIdx.x & 63;
     const int row = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
@@ -903,7 +907,7 @@ __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
     const int f = a.list ? a.list[row] : row;
     const int v = a.free_ids[f];
     const d4 uv = a.u[v];
-    if (!body_on(a, f)) {
+    if (!LIN && !body_on(a, f)) {
         if (lane == 0 && !a.in_place) a.unext[v] = uv;  // a stopped body's Jacobi buffer carried over
         return;
     }
@@ -1006,7 +1010,7 @@ __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
         float b[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) b[i] = Ri[3 * i] * yy[0] + Ri[3 * i + 1] * yy[1] + Ri[3 * i + 2] * yy[2];
-        const float m = (float)a.zu[v].w;
+        const float m = LIN ? a.mh2[v] : (float)a.zu[v].w;
         float A[9];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -1021,9 +1025,15 @@ __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
         float dx[3];
         local_solve(A, b, dx);
         float st[3] = {a.omega * dx[0], a.omega * dx[1], a.omega * dx[2]};
-        clamp_step(a, v, uv, st);
-        d4* out = a.in_place ? const_cast<d4*>(a.u) : a.unext;
-        out[v] = make_d4(uv.x + st[0], uv.y + st[1], uv.z + st[2], 0.0);
+        if (LIN) {
+            const float4 yv = a.ly[v];
+            float4* out = a.in_place ? const_cast<float4*>(a.ly) : a.lynext;
+            out[v] = make_float4(yv.x + st[0], yv.y + st[1], yv.z + st[2], 0.0f);
+        } else {
+            clamp_step(a, v, uv, st);
+            d4* out = a.in_place ? const_cast<d4*>(a.u) : a.unext;
+            out[v] = make_d4(uv.x + st[0], uv.y + st[1], uv.z + st[2], 0.0);
+        }
     }
 }
 
@@ -1418,8 +1428,15 @@ void launch_hvec(jgs2_solver* s, const SweepArgs& a) {
 void launch_exact(jgs2_solver* s, const SweepArgs& a) {
     const int n = a.list ? a.n_list : a.nVf;
     if (n == 0) return;
-    if (a.full_fp16) launch(s, JGS2_K_EXACT, k_exact<_Float16>, dim3((n + 3) / 4), dim3(256), a);
-    else launch(s, JGS2_K_EXACT, k_exact<float>, dim3((n + 3) / 4), dim3(256), a);
+    if (a.full_fp16) launch(s, JGS2_K_EXACT, k_exact<_Float16, false>, dim3((n + 3) / 4), dim3(256), a);
+    else launch(s, JGS2_K_EXACT, k_exact<float, false>, dim3((n + 3) / 4), dim3(256), a);
+}
+
+void launch_exact_linear(jgs2_solver* s, const SweepArgs& a) {
+    const int n = a.list ? a.n_list : a.nVf;
+    if (n == 0) return;
+    if (a.full_fp16) launch(s, JGS2_K_EXACT, k_exact<_Float16, true>, dim3((n + 3) / 4), dim3(256), a);
+    else launch(s, JGS2_K_EXACT, k_exact<float, true>, dim3((n + 3) / 4), dim3(256), a);
 }
 
 void launch_rotations(jgs2_solver* s, const SweepArgs& a) {

@@ -241,6 +241,22 @@ def twist_velocity(mesh: Mesh, amplitude: float = 2.0) -> np.ndarray:
     return v
 
 
+def twisted_positions(mesh: Mesh, total_angle: float = 0.3) -> np.ndarray:
+    """Positions of the beam with each cross-section at distance s from the
+    pinned end turned by total_angle * s / L about the long axis (a prescribed
+    deformed configuration, no solve)."""
+    X = mesh.X
+    L = X[:, 0].max()
+    cy = 0.5 * (X[:, 1].min() + X[:, 1].max())
+    cz = 0.5 * (X[:, 2].min() + X[:, 2].max())
+    th = total_angle * X[:, 0] / L
+    c, s = np.cos(th), np.sin(th)
+    x = X.copy()
+    x[:, 1] = cy + c * (X[:, 1] - cy) - s * (X[:, 2] - cz)
+    x[:, 2] = cz + s * (X[:, 1] - cy) + c * (X[:, 2] - cz)
+    return x
+
+
 def tiny_beam(seed: int = 0, E: float = 1e6, nu: float = 0.4) -> Scene:
     """4x4 cross-section, 16 long, 0.05 m cells (425 vertices, 1536 tets),
     one step from rest with a 1e-6 m jitter on the free vertices."""

@@ -6,11 +6,13 @@ rho 1000, dt 1/120, initial twist 2 rad/s): the precompute on a sample of
 free vertices (training-pose eigenvalues, one-ring U-bar rows, cubature
 samples, weights, fit residuals), the positions of sampled vertices after
 two plain Jacobi sweeps (omega 0.8) of the first step, and (E 1e5) after four
-coloured GS sweeps with step scales 1.5 and 1.6 (the benchmark's fastest
-sweeps on this beam).
+coloured GS sweeps with step scales 1.5 and 1.6, and the positions of
+sampled vertices after one Jacobi sweep of the exact co-rotated subspace
+from a prescribed twisted configuration.
 
     python tests/golden/make_goldens.py            # several minutes on one core
     python tests/golden/make_goldens.py gs_w1.6    # one of the files
+    python tests/golden/make_goldens.py exact      # the exact-subspace sweep
 """
 import json
 import os
@@ -72,12 +74,38 @@ def golden_plain_gs(E, sweeps=4, omega=1.5):
             "rel_res": hist}
 
 
+def golden_exact_jacobi(E, n=96, angle=0.3):
+    """One Jacobi sweep of the exact co-rotated subspace (variant RX) at
+    sampled vertices, from the beam twisted by `angle` over its length and at
+    rest (x0 = x-hat = twisted, v = 0): each sampled vertex's step needs only
+    its own U-bar row (three solves with the rest Hessian), the gradient,
+    rotations and Hessian at x0."""
+    sc = inputs.single_beam(E)
+    mdl = fem.model_from_scene(sc)
+    x0 = inputs.twisted_positions(sc.mesh, angle)
+    v0 = np.zeros_like(x0)
+    z = mdl.inertial_target(x0, v0)
+    verts = sampled_vertices(mdl, n, 4)
+    solver = oc.RestSolver(oc.rest_hessian(mdl))
+    U = oc.ubar_rows(mdl, solver, verts)
+    g, R = osw.phase1(mdl, x0, z)
+    H = mdl.hessian(x0)
+    A, b = osw.literal_exact_systems(mdl, osw.corotated_rows(U, R, verts), g, H, verts)
+    dx = osw.local_solve(A, b)
+    return {"E": E, "angle": angle, "verts": verts.tolist(), "x": (x0[verts] + dx).tolist(), "dx": dx.tolist(),
+            "r0": float(np.linalg.norm(mdl.to_free(g)))}
+
+
 def main():
-    which = sys.argv[1:] or ["precompute", "jacobi", "gs"]
+    which = sys.argv[1:] or ["precompute", "jacobi", "gs", "exact"]
     for E in (1e5, 1e8):
         if "precompute" in which:
             path = os.path.join(HERE, f"beam16x16x128_E{E:g}_precompute.json")
             json.dump(golden_precompute(E), open(path, "w"))
+            print("wrote", path, flush=True)
+        if "exact" in which:
+            path = os.path.join(HERE, f"beam16x16x128_E{E:g}_exact_jacobi.json")
+            json.dump(golden_exact_jacobi(E), open(path, "w"))
             print("wrote", path, flush=True)
         if "jacobi" in which:
             path = os.path.join(HERE, f"beam16x16x128_E{E:g}_plain_jacobi.json")

@@ -52,3 +52,25 @@ def test_infeasible_start_is_rejected():
     with pytest.raises(jgs2.JGS2Error) as e:
         s.step()
     assert e.value.code == jgs2.E_INFEASIBLE
+
+
+def test_phase1_gradient_with_active_barrier_matches_oracle():
+    """Phase 1 (FP64 gradient) with the floor barrier active at many bottom
+    vertices (0.6 mm above the plane, d_hat 1 mm): the assembled gradient,
+    barrier terms included, against the oracle's."""
+    sc = inputs.sphere_on_floor(speed=1.0)
+    mdl = fem.model_from_scene(sc)
+    z = mdl.inertial_target(sc.x0, sc.v0)
+    go = mdl.gradient(sc.x0, z)
+    gb = mdl.barrier_gradient(sc.x0)
+    active = np.abs(gb).max(1) > 0
+    assert active.sum() >= 4
+    s = make_solver(sc, variant=jgs2.PLAIN, order=jgs2.GS)
+    s.set_state(sc.x0, sc.v0)
+    s.begin_step()
+    gg, _ = s.phase1()
+    s.close()
+    scale = np.abs(go).max()
+    assert np.abs(gg - go).max() <= 1e-5 * scale
+    # the barrier rows themselves, relative to their own size
+    assert np.abs(gg[active] - go[active]).max() <= 1e-4 * np.abs(go[active]).max()

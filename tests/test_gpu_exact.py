@@ -106,3 +106,75 @@ def test_exact_needs_its_tables(tiny):
     st = s.step(raise_on_error=False)
     assert st["status"] == jgs2.E_NOT_READY
     s.close()
+
+
+def test_exact_adjoint_matches_oracle_adjoint():
+    """The differentiable rollout with the exact subspace in the forward
+    steps and in the adjoint's linear sweeps (the same local systems of
+    H(x*) y = rhs, residual in place of the gradient): stiffness and initial
+    state cotangents against the FP64 oracle adjoint, with few sweeps per
+    adjoint solve."""
+    from oracle import adjoint as oa
+    m = inputs.beam_mesh(8, 3, 3, 0.05)
+    g = inputs.SplitMix64(11)
+    logE = np.log(1e5) + g.uniform_array(m.nT, -0.3, 0.3)
+    u = np.array([0.05, -0.1, 0.2])
+    n = 5
+    mdl = fem.Model(m.X, m.tets, m.pinned, np.exp(logE), 0.45, 1000.0, 1.0 / 120)
+    v0 = np.zeros_like(m.X)
+    v0[~m.pinned.astype(bool)] = u
+    xs, _ = oa.forward(mdl, mdl.X.copy(), oa.initial_velocity(mdl, u), n)
+    rng = np.random.default_rng(3)
+    xbar = rng.standard_normal(m.X.shape)
+    vbar = 0.01 * rng.standard_normal(m.X.shape)
+    th_o, xb_o, vb_o = oa.backward(mdl, xs, xbar, vbar)
+    s = jgs2.Solver(variant=jgs2.EXACT, order=jgs2.JACOBI, rel_tol=1e-6, adj_rel_tol=1e-6, check_every=1,
+                    max_sweeps=50, adj_max_sweeps=50)
+    s.upload_mesh(m.X, m.tets, m.pinned)
+    s.set_material(np.exp(logE), 0.45, 1000.0)
+    s.precompute(samples=4, n_cand=64, seed=0)
+    s.set_state(m.X, v0)
+    assert s.rollout(n, ckpt_every=2)["status"] == jgs2.OK
+    x, _ = s.get_state()
+    assert np.abs(x - xs[-1]).max() <= 1e-5 * bbox_diag(m.X)
+    th, xb0, vb0, st = s.rollout_backward(xbar, vbar)
+    s.close()
+    print(f"exact adjoint: {st['adjoint_sweeps']} adjoint sweeps over {st['steps']} steps, "
+          f"max rel res {st['max_rel_res']:.2e}", flush=True)
+    assert st["status"] == jgs2.OK and st["steps"] == n and st["max_rel_res"] <= 1e-6
+    assert st["adjoint_sweeps"] <= 6 * n
+    rel = np.linalg.norm(th - th_o) / np.linalg.norm(th_o)
+    cos = th @ th_o / (np.linalg.norm(th) * np.linalg.norm(th_o))
+    assert rel <= 1e-2 and cos >= 0.999, (rel, cos)
+    pin = m.pinned.astype(bool)
+    for a, b in ((xb0, xb_o), (vb0, vb_o)):
+        assert np.linalg.norm(a[~pin] - b[~pin]) <= 1e-2 * np.linalg.norm(b[~pin])
+
+
+def test_exact_sweep_with_indefinite_local_systems_matches_oracle(tiny, tiny_exact):
+    """A state where some exact local systems are indefinite (one interior
+    vertex pushed 0.1 m through its neighbours, inverting tets): the PD guard
+    of the local solve shifts them on both sides (the same pivot rule), and
+    one Jacobi sweep matches the oracle."""
+    sc, mdl, _ = tiny
+    z = mdl.inertial_target(sc.x0, sc.v0)
+    v = 156
+    x0 = sc.x0.copy()
+    x0[v, 1] += 0.1
+    sw = osw.Sweeper(mdl, tiny_exact, osw.RX)
+    A, _ = sw.systems(x0, z)
+    shifted = [k for k in range(A.shape[0])
+               if osw._ldl_pivots(A[k]).min() <= 1e-6 * abs(np.trace(A[k]))]
+    assert len(shifted) >= 1
+    xo = sw.jacobi(x0, z)
+    s = gpu_exact(sc, order=jgs2.JACOBI)
+    s.set_state(x0, sc.v0)
+    s.begin_step()
+    s.iterate(1)
+    xg, _ = s.get_state()
+    s.close()
+    # the step's inertial target is that of x-hat = x0 on both sides
+    moved = np.abs(xo - x0).max()
+    err = np.abs(xg - xo).max()
+    print(f"{len(shifted)} shifted systems; max |x_gpu - x_oracle| = {err:.3e} (moved {moved:.3e})", flush=True)
+    assert err <= 2e-3 * moved

@@ -110,3 +110,53 @@ def test_shared_velocity_cotangent_is_the_free_sum(tiny):
     assert st["status"] == jgs2.OK
     ref = vb0[~mdl.pinned].astype(np.float64).sum(0)
     np.testing.assert_allclose(st["ubar"], ref, rtol=1e-12, atol=1e-12 * np.abs(vb0).max())
+
+
+def test_device_state_io_is_bitwise_the_host_io(tiny):
+    """jgs2_set_state_device / jgs2_get_state_device with buffers allocated
+    through the HIP runtime the library links: a step started from a
+    device-resident state ends bitwise where the host-state step ends."""
+    sc, mdl, tab = tiny
+    hip = C.CDLL("libamdhip64.so.7")
+    hip.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+    hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    hip.hipFree.argtypes = [C.c_void_p]
+    nbytes = sc.x0.size * 8
+    bufs = []
+    for _ in range(4):
+        p = C.c_void_p()
+        assert hip.hipMalloc(C.byref(p), nbytes) == 0
+        bufs.append(p)
+    dx, dv, dx2, dv2 = bufs
+    H2D, D2H = 1, 2
+    try:
+        x0 = np.ascontiguousarray(sc.x0, dtype=np.float64)
+        v0 = np.ascontiguousarray(sc.v0 + 0.01, dtype=np.float64)
+        assert hip.hipMemcpy(dx, x0.ctypes.data, nbytes, H2D) == 0
+        assert hip.hipMemcpy(dv, v0.ctypes.data, nbytes, H2D) == 0
+        a = make_solver(sc, variant=jgs2.PLAIN, order=jgs2.GS)
+        a.set_state_device(dx.value, dv.value)
+        a.step()
+        a.get_state_device(dx2.value, dv2.value)
+        xa, va = np.empty_like(x0), np.empty_like(x0)
+        assert hip.hipMemcpy(xa.ctypes.data, dx2, nbytes, D2H) == 0
+        assert hip.hipMemcpy(va.ctypes.data, dv2, nbytes, D2H) == 0
+        b = make_solver(sc, variant=jgs2.PLAIN, order=jgs2.GS)
+        b.set_state(x0, v0)
+        b.step()
+        xb, vb = b.get_state()
+        np.testing.assert_array_equal(xa, xb)
+        np.testing.assert_array_equal(va, vb)
+        # a non-finite value is refused and leaves no state
+        bad = x0.copy()
+        bad[7, 1] = np.nan
+        assert hip.hipMemcpy(dx, bad.ctypes.data, nbytes, H2D) == 0
+        with pytest.raises(jgs2.JGS2Error):
+            a.set_state_device(dx.value, dv.value)
+        r, _ = raw_step(a)
+        assert r == jgs2.E_NOT_READY
+        a.close()
+        b.close()
+    finally:
+        for p in bufs:
+            hip.hipFree(p)
