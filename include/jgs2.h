@@ -263,7 +263,12 @@ int32_t jgs2_begin_step(jgs2_solver* s);
 int32_t jgs2_iterate(jgs2_solver* s, int32_t n_sweeps, double* rel_res);
 int32_t jgs2_end_step(jgs2_solver* s);
 
-/* |g| over free DOFs at the current iterate, and |g| / r0. */
+/* |g| over free DOFs at the current iterate, and |g| / r0, with g the
+ * gradient of the incremental potential E of Eq. variation (inertia of
+ * Sec. 3, elasticity, plane barriers of Eq. barrier), evaluated in FP64.
+ * The paper's own measure, the last sweep's |dx| (Sec. 8, Table 1), is in
+ * jgs2_step_stats.dx_norm.  JGS2_E_NOT_READY without mesh, material,
+ * state or (non-plain variants) correction. */
 int32_t jgs2_residual(jgs2_solver* s, double* abs_res, double* rel_res);
 /* Differentiable rollout.  The paper defines the forward step only; its
  * derivative is taken through the step's optimality condition
@@ -299,7 +304,11 @@ int32_t jgs2_rollout(jgs2_solver* s, int32_t n_steps, int32_t ckpt_every, jgs2_s
 int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* vbar, double* thetabar,
                               double* xbar0, double* vbar0, double* ubar, jgs2_adjoint_stats* stats);
 
-/* Incremental potential E at the current iterate (FP64 sum of FP32 terms). */
+/* Incremental potential E of Eq. variation at the current iterate: the
+ * inertia term (1/2h^2)|M^(1/2)(x - z)|^2 of Sec. 3, the stable Neo-Hookean
+ * energy and the log barriers of Eq. barrier (infinite for a vertex on or
+ * behind a plane); an FP64 sum of FP32 element terms.  JGS2_E_NOT_READY as
+ * for jgs2_residual. */
 int32_t jgs2_energy(jgs2_solver* s, double* e);
 /* Allocation-free variant of jgs2_energy, for callers that cannot allocate
  * device memory: code under HIP graph capture, tight serving loops, hosts
@@ -319,7 +328,10 @@ int32_t jgs2_energy_noalloc(jgs2_solver* s, double* e);
  * rotations R (nV x 3x3 row-major, identity at pinned vertices) at the
  * current iterate: the outputs of the first sweep phase. */
 int32_t jgs2_get_phase1(jgs2_solver* s, double* g, double* R);
-/* Greedy colour per vertex (-1 for pinned) and the colour count. */
+/* Greedy colour per vertex (-1 for pinned) and the colour count: the
+ * independent groups of the Gauss-Seidel order of Sec. 8.1 (each colour is
+ * the smallest one unused by the vertex's lower-id free neighbours), the
+ * order of the GS sweeps.  color has nV entries (may be NULL). */
 int32_t jgs2_get_coloring(jgs2_solver* s, int32_t* color, int32_t* n_colors);
 
 /* Per-kernel device timing with HIP events on the handle's stream.  While
