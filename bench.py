@@ -102,11 +102,9 @@ def main():
 
     modes = [
         # the exact co-rotated subspace (every row of U-bar, no cubature), Jacobi and coloured GS
-        # (a residual check after every sweep: a sweep streams every U-bar row, so one sweep
-        # past convergence costs more than the check)
+        # (a residual check after every sweep: a sweep streams the whole of H-bar^-1, so one
+        # sweep past convergence costs more than the check)
         ("jgs2_exact_jacobi", dict(variant=jgs2.EXACT, order=jgs2.JACOBI, omega=1.0, check_every=1)),
-        ("jgs2_exact_jacobi_fp16", dict(variant=jgs2.EXACT, order=jgs2.JACOBI, omega=1.0, check_every=1,
-                                        exact_fp16=1)),
         ("jgs2_exact_gs", dict(variant=jgs2.EXACT, order=jgs2.GS, omega=1.0, check_every=1)),
         # the damper reading of the correction in coloured GS, no step scale
         ("jgs2_damper_gs", dict(variant=jgs2.DAMPER, order=jgs2.GS, omega=1.0)),
@@ -134,29 +132,28 @@ def main():
         sc = make(E)
         m = sc.mesh
         corr = None
-        exact_keep = {}      # one exact-variant handle per row precision, shared by its modes
+        exact_keep = {}      # one exact-variant handle, shared by its modes
         for name, cfg in modes:
             kw = dict(check_every=16)
             kw.update(cfg)
-            fp16 = kw.get("exact_fp16", 0)
-            if cfg["variant"] == jgs2.EXACT and fp16 in exact_keep:
-                s = exact_keep[fp16]           # the same U-bar rows; only the order and checks change
+            if cfg["variant"] == jgs2.EXACT and exact_keep:
+                s = exact_keep["exact"]        # the same H-bar^-1 tiles; only the order and checks change
                 s.set_params(**{k: v for k, v in kw.items() if k != "variant"})
             else:
                 s = jgs2.Solver(dt=sc.dt, gravity=sc.gravity, rel_tol=1e-5, max_sweeps=args.max_sweeps,
                                 use_graph=0 if args.no_graph else 1, **kw)
                 s.upload_mesh(m.X, m.tets, m.pinned)
                 s.set_material(sc.E, sc.nu, sc.rho)
-            if cfg["variant"] == jgs2.EXACT and fp16 not in exact_keep:
-                # its own precompute: the full U-bar rows stay on the device (the same run
-                # also trains the cubature tables, which the sampled modes then import)
-                key = f"{E:g} exact" + (" fp16" if fp16 else "")
-                print(f"[bench] E={E:g} {name}: GPU precompute with full rows ...", file=sys.stderr, flush=True)
+            if cfg["variant"] == jgs2.EXACT and not exact_keep:
+                # its own precompute: H-bar^-1 stays on the device (the same run also
+                # trains the cubature tables, which the sampled modes then import)
+                key = f"{E:g} exact"
+                print(f"[bench] E={E:g} {name}: GPU precompute with H-bar^-1 tiles ...", file=sys.stderr, flush=True)
                 t0 = time.perf_counter()
                 s.precompute(samples=4, n_cand=64, seed=0)
                 precompute_s[key] = time.perf_counter() - t0
-                print(f"[bench] E={E:g} precompute (full rows) {precompute_s[key]:.2f} s", file=sys.stderr, flush=True)
-                exact_keep[fp16] = s
+                print(f"[bench] E={E:g} precompute (with tiles) {precompute_s[key]:.2f} s", file=sys.stderr, flush=True)
+                exact_keep["exact"] = s
                 if corr is None:
                     corr = s.export_correction(4)
                     if corr0 is None:
@@ -295,9 +292,11 @@ def main():
         elif dom == "rot":
             per_launch = sweep_bytes("rot", **cnt)
             kname = "k_rot"
+        elif dom == "symv":       # one launch per reduced gradient (per sweep, or per colour in GS)
+            per_launch = sweep_bytes("symv", **cnt)
+            kname = "k_symv"
         elif dom == "exact":      # Jacobi: one launch over every row; GS: one per colour
-            per_launch = sweep_bytes("exact", **cnt, el=2 if "fp16" in head_mode else 4) * (
-                1 if "jacobi" in head_mode else 1.0 / n_colors)
+            per_launch = sweep_bytes("exact", **cnt) * (1 if "jacobi" in head_mode else 1.0 / n_colors)
             kname = "k_exact"
         else:
             per_launch, kname = None, dom
@@ -619,7 +618,7 @@ def measured_traffic(kernel, workload_tag, shape=None):
     return None
 
 
-def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches=1, el=4):
+def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches=1):
     """Compulsory (algorithmic) bytes moved by one launch of a sweep kernel,
     counting every datum it must touch once: tet records 80 B (64 B without
     the id word), incidence entries 4 B or 16 B with corner ids (plus 4 B
@@ -635,8 +634,16 @@ def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches
         return 64.0 * n_inc + 64.0 * Vf + 32.0 * V
     if kind == "plain_gs_sweep":  # all colour launches of one sweep; positions read once per colour
         return 64.0 * n_inc + 64.0 * Vf + 32.0 * V * n_colors
-    if kind == "exact":       # every row's 9 planes of U-bar (el bytes each) + incident tets, positions, h
-        return 9.0 * el * Vf * Vf + 96.0 * n_inc + 16.0 * Vf + 64.0 * V
+    if kind == "symv":        # the stored tiles of H-bar^-1 (rows past Vf not read), 1 KB partials written:
+        q, g = 64, 8          # one per tile row and one per tile column of each 8 x 8 super-tile
+        nt = (Vf + q - 1) // q
+        ns = (nt + g - 1) // g
+        rows = sum(min(q, Vf - i * q) * (i + 1) for i in range(nt))
+        valid = [min(g, nt - g * k) for k in range(ns)]
+        parts = sum(valid[si] + valid[sj] for si in range(ns) for sj in range(si + 1))
+        return 36.0 * q * rows + 1024.0 * parts + 16.0 * Vf
+    if kind == "exact":       # incident tets, positions, y and B^-1 per row, rotations, result
+        return 96.0 * n_inc + (16.0 + 36.0 + 16.0) * Vf + 64.0 * V
     if kind == "rot":         # records and positions; row id and count read, rotation written
         return 64.0 * n_inc + 24.0 * Vf + 32.0 * V
     if kind == "damper_gs_sweep":  # plain terms + per sample 168 B record + 80 B tet; rotations per colour

@@ -62,8 +62,11 @@ extern "C" {
  *                 A_i = H_ii + sum_{a in N(i)} H_{i,a} Phi_{i,a} (the one
  *                 ring; symmetrised), b_i = sum_a Phi_{i,a}^T g_a over every
  *                 free vertex (no cubature).  At rest a Jacobi sweep is the
- *                 Newton step (Sec. 4.2).  Needs the full rows of U-bar from
- *                 jgs2_precompute (nVf^2 x 9 floats on the device).          */
+ *                 Newton step (Sec. 4.2).  Since U-bar_{i,a} =
+ *                 (H-bar^-1)_{a,i} B_i^-1 (Eq. u), jgs2_precompute keeps the
+ *                 symmetric H-bar^-1 once on the device (about nVf^2 x 18
+ *                 bytes in FP32) and b_i = R_i B_i^-1 (H-bar^-1 h)_i with
+ *                 h_a = R_a^T g_a.                                            */
 #define JGS2_PLAIN     0
 #define JGS2_CUBATURE  3
 #define JGS2_DAMPER    4
@@ -97,9 +100,6 @@ typedef struct jgs2_params {
     int32_t adj_max_sweeps;     /* sweep cap per adjoint solve */
     int32_t use_graph;          /* 1: replay each group of check_every sweeps and its
                                    residual check as one captured HIP graph */
-    int32_t exact_fp16;         /* JGS2_EXACT: 1 keeps the U-bar rows in FP16 (half the
-                                   bytes streamed per sweep), 0 in FP32; read by
-                                   jgs2_precompute */
 } jgs2_params;
 
 typedef struct jgs2_step_stats {
@@ -206,11 +206,11 @@ int32_t jgs2_set_material_log_e(jgs2_solver* s, const double* log_E, const doubl
  * eigenvectors), U-bar by Eq. u, greedy NNLS cubature with `samples` samples
  * per vertex drawn from `n_cand` candidates per round (counter-based
  * SplitMix64 keyed by `seed`).  Needed by JGS2_CUBATURE and JGS2_DAMPER.
- * When the handle's variant is JGS2_EXACT it also keeps every row of U-bar
- * (Eq. u) for every free vertex on the device, nVf^2 x 36 bytes in FP32 or
- * nVf^2 x 18 bytes with params.exact_fp16 (JGS2_E_OOM when that does not
- * fit).  U-bar is dimensionless (U-bar_{i,i} = I); the FP16 copy changes the
- * sweep's preconditioner, not its fixed point (b_i vanishes with g). */
+ * When the handle's variant is JGS2_EXACT it also keeps, for every free
+ * vertex, the columns of H-bar^-1 that define its U-bar rows (Eq. u): the
+ * lower triangle of 64 x 64-vertex tiles of H-bar^-1 in FP32 over the
+ * vertices' bandwidth-reducing order, about nVf^2 x 18 bytes
+ * (JGS2_E_OOM when that does not fit), and B_i^-1 per free vertex. */
 int32_t jgs2_precompute(jgs2_solver* s, int32_t samples, int32_t n_cand, uint64_t seed);
 
 /* Correction tables in free-vertex order (free vertices ascending by id).
@@ -353,9 +353,11 @@ int32_t jgs2_get_coloring(jgs2_solver* s, int32_t* color, int32_t* n_colors);
 #define JGS2_K_ADJVEC    10  /* adjoint: mass products, next right-hand side */
 #define JGS2_K_DAMPER    11  /* damper-corrected local solves, fused with the gather */
 #define JGS2_K_ROT       12  /* per-vertex rotations alone (the damper sweeps' start) */
-#define JGS2_K_EXACT     13  /* exact-subspace local solves (reduced gradient over all rows) */
-#define JGS2_K_HVEC      14  /* rest-frame gradients R_a^T g_a in the exact rows' order */
-#define JGS2_NKERNELS    15
+#define JGS2_K_EXACT     13  /* exact-subspace local solves (Hessian term, 3x3 solve) */
+#define JGS2_K_HVEC      14  /* rest-frame gradients R_a^T g_a in the tiles' position order */
+#define JGS2_K_SYMV      15  /* H-bar^-1 tiles against those gradients, both ways per tile */
+#define JGS2_K_YSUM      16  /* tile partials summed per position */
+#define JGS2_NKERNELS    17
 int32_t jgs2_set_profiling(jgs2_solver* s, int32_t on);
 int32_t jgs2_kernel_times(jgs2_solver* s, double* ms, int64_t* launches);
 

@@ -89,13 +89,19 @@ struct SweepArgs {
     const int* body_on;     // [n_bodies] 1 while the body iterates (nullptr: all; the
                             // plain forward sweep requires it)
     int one_body;           // every free vertex is in body 0 (its flag is read once per wave)
-    // exact variant: full U-bar rows [(f * 9 + comp) * nVf + qx] over the permuted
-    // positions qx of the free vertices, and the rest-frame gradients in that order
-    const void* Ufull;      // float, or _Float16 when full_fp16
-    int full_fp16;
+    // exact variant: the rest Hessian's inverse in the lower triangle of
+    // 64 x 64-vertex tiles over the permuted positions q of the free vertices
+    // (tile (I, J), I >= J, at I (I + 1) / 2 + J, laid out [q % 64][3 r + c][q' % 64]),
+    // B_q^-1 = ((H-bar^-1)_{q,q})^-1 per position, and per-sweep vectors
+    const float* Mt;        // [n_tiles * 64 * 9 * 64]
+    const float* Binv;      // [nVf * 9]
     const int* qpos;        // [nV] permuted position of a free vertex, -1 if pinned
-    const int* qvert;       // [nVf] vertex id at permuted position qx
-    float4* hvec;           // [nVf] R_a^T g_a at permuted position qx
+    const int* qvert;       // [nVf] vertex id at position q
+    const int* qfree;       // [nVf] free index at position q
+    float4* hvec;           // [nVf rounded up to 64] R_a^T g_a at position q, zero past nVf
+    float4* prow;           // [n_super * ntq * 64] row partials of H-bar^-1 h per super-tile column
+    float4* pcol;           // [n_super * ntq * 64] column partials per super-tile row
+    float4* yq;             // [nVf] (H-bar^-1 h)_q
 };
 
 }  // namespace jgs2
@@ -148,11 +154,14 @@ struct jgs2_solver {
     uint32_t* d_incslot = nullptr;
     int* d_colperm = nullptr;
     float* d_Uring = nullptr;
-    void* d_Ufull = nullptr;               // exact variant: [nVf * 9 * nVf] float or _Float16
-    bool full_fp16 = false;
+    float* d_Mt = nullptr;                 // exact variant: H-bar^-1 tiles (see SweepArgs)
+    float* d_Binv = nullptr;               // [nVf * 9]
     int* d_qpos = nullptr;                 // [nV]
     int* d_qvert = nullptr;                // [nVf]
+    int* d_qfree = nullptr;                // [nVf]
     float4* d_hvec = nullptr;              // [nVf]
+    float4* d_part = nullptr;              // [2 * n_super * ntq * 64]: row, then column partials
+    float4* d_yq = nullptr;                // [nVf]
     bool have_full = false;
     double* d_X64 = nullptr;               // device state I/O: FP64 rest positions [nV * 3]
     uint8_t* d_pin8 = nullptr;             // [nV]
@@ -240,7 +249,8 @@ void launch_plain(jgs2_solver* s, const SweepArgs& a);
 void launch_damper(jgs2_solver* s, const SweepArgs& a);
 void launch_reduce_into(jgs2_solver* s, const double* in, int n, double* out);
 void launch_rotations(jgs2_solver* s, const SweepArgs& a);  // every free row (a.list unused)
-void launch_hvec(jgs2_solver* s, const SweepArgs& a);
+// y = H-bar^-1 (R^T g) in position order, from a.g and a.R (three launches)
+void launch_reduced_gradient(jgs2_solver* s, const SweepArgs& a);
 void launch_exact(jgs2_solver* s, const SweepArgs& a);
 void launch_exact_linear(jgs2_solver* s, const SweepArgs& a);
 void launch_commit(jgs2_solver* s, const SweepArgs& a);
@@ -262,6 +272,14 @@ void launch_energy(jgs2_solver* s, const SweepArgs& a, int nT);
 int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed);
 int alloc_tables(jgs2_solver* s, int S);
 int alloc_full_tables(jgs2_solver* s);
+// tiles of the exact variant's H-bar^-1: side, tiles per super-tile side,
+// count over nVf positions
+constexpr int MT_Q = 64;
+constexpr int MT_SG = 8;
+inline size_t mt_tiles(int nVf) {
+    const size_t n = (size_t)(nVf + MT_Q - 1) / MT_Q;
+    return n * (n + 1) / 2;
+}
 void prof_collect(jgs2_solver* s);
 hipEvent_t pool_event(jgs2_solver* s);
 }  // namespace jgs2

@@ -456,36 +456,35 @@ __global__ __launch_bounds__(256) void k_ritz_resid(const double* __restrict__ H
 }
 
 // ---------------------------------------------------------------------------
-// 6. full rows of U-bar (the exact variant)
+// 6. the rest Hessian's inverse in symmetric tiles (the exact variant)
 // ---------------------------------------------------------------------------
-// For vertex j of the chunk (permuted position p = p0 + j, free index
-// f = perm[p]) and every permuted position qx:
-//   Ufull[(f * 9 + 3 r + c) * nVf + qx] = (W_qx B_j^-1)[r][c]   (FP32)
-// with W_qx the 3x3 block of the solved columns at rows 3 qx .. 3 qx + 2 and
-// B_j = W_p (Eq. u), the same product as the one-ring rows of k_cubature.
-// A block takes one batch (21 vertices) and UF_ROWS positions, with the
-// batch's W rows for those positions staged in LDS (rows padded by one
-// double against bank conflicts); consecutive threads write consecutive
-// positions of one plane.
-constexpr int UF_ROWS = 32;
-template <typename UT>
-__global__ __launch_bounds__(256) void k_ufull(const double* __restrict__ W, int n_pad, int p0, int n_vert, int nVf,
-                                               const int* __restrict__ perm, UT* __restrict__ Ufull) {
+// U-bar_{i,a} = (H-bar^-1)_{a,i} B_i^-1 with B_i = (H-bar^-1)_{i,i} (Eq. u), so
+// the exact variant keeps the symmetric H-bar^-1 once: its 3x3 blocks over
+// the permuted positions in 64 x 64-vertex tiles, only tiles (I, J) with
+// I >= J (at I (I + 1) / 2 + J; a diagonal tile holds both triangles), each
+// laid out [row position % 64][3 r + c][column position % 64], and B_p^-1 per
+// position p.  The solved columns of a batch (21 consecutive positions p)
+// are the blocks (H-bar^-1)_{q,p} for every row position q (W rows 3q..3q+2);
+// a block of threads takes 32 row positions of one batch, staged in LDS
+// (rows padded by one double against bank conflicts), and writes those on or
+// below the tile diagonal; consecutive threads write consecutive columns of
+// one tile row.
+constexpr int MT_ROWS = 32;
+__global__ __launch_bounds__(256) void k_mtiles(const double* __restrict__ W, int n_pad, int p0, int n_vert, int nVf,
+                                                float* __restrict__ Mt, float* __restrict__ Binv) {
     const int batch = blockIdx.y;
-    const int qx0 = blockIdx.x * UF_ROWS;
+    const int qx0 = blockIdx.x * MT_ROWS;
     const double* Wb = W + (size_t)batch * n_pad * NB;
-    __shared__ double sW[3 * UF_ROWS][NB + 1];
-    __shared__ double sBinv[VPBATCH][9];
-    __shared__ int sF[VPBATCH];
-    const int nrow = 3 * min(UF_ROWS, nVf - qx0);
-    for (int i = threadIdx.x; i < 3 * UF_ROWS * NB; i += blockDim.x) {
+    __shared__ double sW[3 * MT_ROWS][NB + 1];
+    const int nrow = 3 * min(MT_ROWS, nVf - qx0);
+    for (int i = threadIdx.x; i < 3 * MT_ROWS * NB; i += blockDim.x) {
         const int rr = i / NB, cc = i % NB;
         sW[rr][cc] = rr < nrow ? Wb[(size_t)(3 * qx0 + rr) * NB + cc] : 0.0;
     }
-    if (threadIdx.x < VPBATCH) {
+    // B_p^-1 of the batch's positions, once per batch
+    if (blockIdx.x == 0 && threadIdx.x < VPBATCH) {
         const int jj = threadIdx.x;
         const int j = batch * VPBATCH + jj;
-        int fj = -1;
         if (j < n_vert) {
             const int p = p0 + j;
             double B[9], C[9];
@@ -494,27 +493,23 @@ __global__ __launch_bounds__(256) void k_ufull(const double* __restrict__ W, int
             cof3(B, C);  // B^-1 = cof(B)^T / det B
             const double det = B[0] * C[0] + B[1] * C[1] + B[2] * C[2];
             for (int r = 0; r < 3; ++r)
-                for (int c = 0; c < 3; ++c) sBinv[jj][3 * r + c] = C[3 * c + r] / det;
-            fj = perm[p];
+                for (int c = 0; c < 3; ++c) Binv[(size_t)p * 9 + 3 * r + c] = (float)(C[3 * c + r] / det);
         }
-        sF[jj] = fj;
     }
     __syncthreads();
-    const int t = threadIdx.x % UF_ROWS;
-    const int qx = qx0 + t;
-    if (qx >= nVf) return;
-    for (int jj = threadIdx.x / UF_ROWS; jj < VPBATCH; jj += blockDim.x / UF_ROWS) {
-        const int f = sF[jj];
-        if (f < 0) continue;
-        double Wr[9];
+    const int jj = threadIdx.x % 32;  // column of the batch (VPBATCH of 32 used)
+    const int j = batch * VPBATCH + jj;
+    if (jj >= VPBATCH || j >= n_vert) return;
+    const int p = p0 + j;
+    const int J = p / MT_Q, jl = p % MT_Q;
+    for (int t = threadIdx.x / 32; t < MT_ROWS; t += blockDim.x / 32) {
+        const int qa = qx0 + t;
+        if (qa >= nVf) break;
+        const int I = qa / MT_Q;
+        if (I < J) continue;  // upper triangle: kept as the transpose, written by qa's batch
+        float* T = Mt + ((size_t)I * (I + 1) / 2 + J) * ((size_t)MT_Q * 9 * MT_Q) + (size_t)(qa % MT_Q) * 9 * MT_Q + jl;
         for (int r = 0; r < 3; ++r)
-            for (int k = 0; k < 3; ++k) Wr[3 * r + k] = sW[3 * t + r][3 * jj + k];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) {
-                const double u = Wr[3 * r] * sBinv[jj][c] + Wr[3 * r + 1] * sBinv[jj][3 + c] +
-                                 Wr[3 * r + 2] * sBinv[jj][6 + c];
-                Ufull[((size_t)f * 9 + 3 * r + c) * nVf + qx] = (UT)u;
-            }
+            for (int c = 0; c < 3; ++c) T[(3 * r + c) * MT_Q] = (float)sW[3 * t + r][3 * jj + c];
     }
 }
 
@@ -1343,7 +1338,7 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
     DevBuf<double> dW;
     DevBuf<int> dfirst;
     if ((r = dW.alloc(s, (size_t)chunk_batches * n_pad * NB)) || (r = dfirst.alloc(s, chunk_batches))) return r;
-    // exact variant: every row of U-bar, over the permuted positions of the free vertices
+    // exact variant: H-bar^-1 in tiles over the permuted positions of the free vertices
     const bool want_full = s->p.variant == JGS2_EXACT;
     if (want_full) {
         std::vector<int> qpos(nV, -1), qvert(nVf);
@@ -1354,6 +1349,7 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
         if ((r = alloc_full_tables(s))) return r;
         PCHK(hipMemcpyAsync(s->d_qpos, qpos.data(), nV * 4, hipMemcpyHostToDevice, st));
         PCHK(hipMemcpyAsync(s->d_qvert, qvert.data(), nVf * 4, hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(s->d_qfree, perm.data(), nVf * 4, hipMemcpyHostToDevice, st));
     }
     CubArgs ca;
     std::memset(&ca, 0, sizeof(ca));
@@ -1374,12 +1370,9 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
         ca.p0 = p0;
         ca.n_vert = nvert;
         hipLaunchKernelGGL(k_cubature, dim3(nvert), dim3(64), 0, st, ca);
-        if (want_full && s->full_fp16)
-            hipLaunchKernelGGL(k_ufull<_Float16>, dim3((nVf + UF_ROWS - 1) / UF_ROWS, nbatch), dim3(256), 0, st, dW.p,
-                               n_pad, p0, nvert, nVf, dperm.p, (_Float16*)s->d_Ufull);
-        else if (want_full)
-            hipLaunchKernelGGL(k_ufull<float>, dim3((nVf + UF_ROWS - 1) / UF_ROWS, nbatch), dim3(256), 0, st, dW.p,
-                               n_pad, p0, nvert, nVf, dperm.p, (float*)s->d_Ufull);
+        if (want_full)
+            hipLaunchKernelGGL(k_mtiles, dim3((nVf + MT_ROWS - 1) / MT_ROWS, nbatch), dim3(256), 0, st, dW.p, n_pad,
+                               p0, nvert, nVf, s->d_Mt, s->d_Binv);
         PCHK(hipGetLastError());
         PCHK(hipStreamSynchronize(st));
         stage("vertex chunk", t_start);

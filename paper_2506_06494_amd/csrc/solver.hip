@@ -32,7 +32,8 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_inc_n); dfree(s->d_ring); dfree(s->d_ring_n); dfree(s->d_incslot); dfree(s->d_colperm);
     dfree(s->d_inc4); dfree(s->d_irec_c); dfree(s->d_incn_c); dfree(s->d_vid_c); dfree(s->d_fbody_c);
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
-    dfree(s->d_Ufull); dfree(s->d_qpos); dfree(s->d_qvert); dfree(s->d_hvec); s->have_full = false;
+    dfree(s->d_Mt); dfree(s->d_Binv); dfree(s->d_qpos); dfree(s->d_qvert); dfree(s->d_qfree); dfree(s->d_hvec);
+    dfree(s->d_part); dfree(s->d_yq); s->have_full = false;
     dfree(s->d_X64); dfree(s->d_pin8); dfree(s->d_flag);
     dfree(s->d_ck_u); dfree(s->d_ck_v); dfree(s->d_seg); dfree(s->d_y); dfree(s->d_ynext); dfree(s->d_xbar);
     dfree(s->d_vbar); dfree(s->d_rhs); dfree(s->d_thbar);
@@ -83,7 +84,11 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
         for (int k = 0; k < 4; ++k) a.planes[i][k] = (float)s->p.planes[i][k];
     a.d_hat = (float)s->p.d_hat; a.kappa = (float)s->p.kappa;
     a.fbody = s->d_fbody; a.body_on = s->d_body_on; a.one_body = s->n_bodies == 1;
-    a.Ufull = s->d_Ufull; a.full_fp16 = s->full_fp16; a.qpos = s->d_qpos; a.qvert = s->d_qvert; a.hvec = s->d_hvec;
+    a.Mt = s->d_Mt; a.Binv = s->d_Binv; a.qpos = s->d_qpos; a.qvert = s->d_qvert; a.qfree = s->d_qfree;
+    a.hvec = s->d_hvec; a.yq = s->d_yq;
+    const size_t ntq_ = ((size_t)s->nVf + MT_Q - 1) / MT_Q;
+    a.prow = s->d_part;
+    a.pcol = s->d_part ? s->d_part + (ntq_ + MT_SG - 1) / MT_SG * ntq_ * MT_Q : nullptr;
     for (int i = 0; i < s->p.n_planes; ++i)
         for (int k = 0; k < 4; ++k) a.planes_d[i][k] = s->p.planes[i][k];
 }
@@ -128,21 +133,32 @@ void prof_collect(jgs2_solver* s) {
 
 namespace jgs2 {
 // Device correction tables for S samples per free vertex (zero-filled).
-// Full U-bar rows of the exact variant and their index tables (freed first).
+// The exact variant's H-bar^-1 tiles and h (zero-filled: the padding past
+// nVf, in the last tile row and column and at the end of h, must read as
+// zero), B^-1 per position, the position tables and the per-sweep vectors
+// (freed first).
 int alloc_full_tables(jgs2_solver* s) {
-    const size_t nf = s->nVf;
-    for (void** p : {(void**)&s->d_Ufull, (void**)&s->d_qpos, (void**)&s->d_qvert, (void**)&s->d_hvec}) {
+    const size_t nf = s->nVf, nt = mt_tiles(s->nVf);
+    const size_t nfp = (nf + MT_Q - 1) / MT_Q * MT_Q;  // h padded to whole tiles, zero past nVf
+    const size_t ntq = nfp / MT_Q, npart = (ntq + MT_SG - 1) / MT_SG * ntq * MT_Q;
+    for (void** p : {(void**)&s->d_Mt, (void**)&s->d_Binv, (void**)&s->d_qpos, (void**)&s->d_qvert,
+                     (void**)&s->d_qfree, (void**)&s->d_hvec, (void**)&s->d_part, (void**)&s->d_yq}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
     s->have_full = false;
     int r;
-    s->full_fp16 = s->p.exact_fp16 != 0;
-    const size_t el = s->full_fp16 ? 2 : sizeof(float);
-    if ((r = hip_check(s, hipMalloc((void**)&s->d_Ufull, nf * 9 * nf * el), "hipMalloc full U-bar rows")) ||
+    const size_t mt_bytes = nt * MT_Q * 9 * MT_Q * sizeof(float);
+    if ((r = hip_check(s, hipMalloc((void**)&s->d_Mt, mt_bytes), "hipMalloc H-bar^-1 tiles")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_Binv, nf * 9 * sizeof(float)), "hipMalloc tables")) ||
         (r = hip_check(s, hipMalloc((void**)&s->d_qpos, (size_t)s->nV * sizeof(int)), "hipMalloc tables")) ||
         (r = hip_check(s, hipMalloc((void**)&s->d_qvert, nf * sizeof(int)), "hipMalloc tables")) ||
-        (r = hip_check(s, hipMalloc((void**)&s->d_hvec, nf * sizeof(float4)), "hipMalloc tables")))
+        (r = hip_check(s, hipMalloc((void**)&s->d_qfree, nf * sizeof(int)), "hipMalloc tables")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_hvec, nfp * sizeof(float4)), "hipMalloc tables")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_part, 2 * npart * sizeof(float4)), "hipMalloc tables")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_yq, nf * sizeof(float4)), "hipMalloc tables")) ||
+        (r = hip_check(s, hipMemsetAsync(s->d_Mt, 0, mt_bytes, s->stream), "hipMemsetAsync tiles")) ||
+        (r = hip_check(s, hipMemsetAsync(s->d_hvec, 0, nfp * sizeof(float4), s->stream), "hipMemsetAsync h")))
         return r;
     return JGS2_OK;
 }
@@ -915,7 +931,7 @@ static bool ready_to_step(jgs2_solver* s) {
     if (!s->have_bodies) { s->err = "no body tables (set_bodies failed)"; return false; }
     if (s->p.variant != JGS2_PLAIN && !s->have_corr) { s->err = "no correction (precompute or import)"; return false; }
     if (s->p.variant == JGS2_EXACT && !s->have_full) {
-        s->err = "no full U-bar rows (precompute with the JGS2_EXACT variant)";
+        s->err = "no H-bar^-1 tiles (precompute with the JGS2_EXACT variant)";
         return false;
     }
     return true;
@@ -1008,7 +1024,7 @@ static int sweep_once(jgs2_solver* s) {
         // same for one colour at a time (GS, gradients refreshed per colour)
         if (s->p.order == JGS2_JACOBI) {
             if (!s->phase1_valid) launch_phase1(s, a, true, true);
-            launch_hvec(s, a);
+            launch_reduced_gradient(s, a);
             launch_exact(s, a);
             if (s->p.line_search) {
                 int r = line_search(s);
@@ -1019,7 +1035,7 @@ static int sweep_once(jgs2_solver* s) {
             for (int c = 0; c < s->n_colors; ++c) {
                 SweepArgs all = a;
                 launch_phase1(s, all, true, true);
-                launch_hvec(s, all);
+                launch_reduced_gradient(s, all);
                 SweepArgs ac = a;
                 ac.list = s->d_colperm + s->col_off[c];
                 ac.n_list = s->col_off[c + 1] - s->col_off[c];
@@ -1486,7 +1502,7 @@ static int adjoint_solve(jgs2_solver* s, const d4* xstar, int64_t* sweeps, doubl
                     launch_linear(s, ar);
                     SweepArgs ah = a;
                     ah.g = s->d_g;
-                    launch_hvec(s, ah);
+                    launch_reduced_gradient(s, ah);
                     SweepArgs ae = a;
                     ae.ly = s->d_y;
                     if (s->p.order == JGS2_JACOBI) {

@@ -861,12 +861,18 @@ __global__ __launch_bounds__(BLK) void k_rot(SweepArgs a) {
 // ---------------------------------------------------------------------------
 // Exact co-rotated subspace (the literal form of Eq. local_newton with the
 // derivatives of Eq. relation and the co-rotated rows of Eq. tilde_phi):
-//   b_f = sum_a Phi_{f,a}^T g_a = R_f sum_a Ubar_{f,a}^T (R_a^T g_a)
+//   b_f = sum_a Phi_{f,a}^T g_a = R_f B_f^-1 (H-bar^-1 h)_f,  h_a = R_a^T g_a
+// (U-bar_{f,a} = (H-bar^-1)_{a,f} B_f^-1 by Eq. u, and H-bar^-1 is symmetric),
 //   A_f = m_f / h^2 I + H^B_f + sum_{e ni f} sum_b H_e[c_f, b] Phi_{f,b}
-// with Phi_{f,b} = R_b Ubar_{f,b} R_f^T (the identity at b = f, zero at pinned
-// b), A_f symmetrised, x_f <- x_f - omega A_f^-1 b_f.
+// with Phi_{f,b} = R_b U-bar_{f,b} R_f^T (the identity at b = f, zero at pinned
+// b), A_f symmetrised, x_f <- x_f - omega A_f^-1 b_f.  H-bar^-1 is kept once,
+// as the lower triangle of 64 x 64-vertex tiles over the positions q.
 // ---------------------------------------------------------------------------
-// Rest-frame gradients h_qx = R_a^T g_a in the order of the full rows.
+constexpr size_t MT_TILE = (size_t)MT_Q * 9 * MT_Q;  // floats per tile
+
+__device__ __forceinline__ size_t tile_index(int I, int J) { return (size_t)I * (I + 1) / 2 + J; }
+
+// Rest-frame gradients h_q = R_a^T g_a in position order.
 __global__ __launch_bounds__(256) void k_hvec(SweepArgs a) {
     const int qx = blockIdx.x * blockDim.x + threadIdx.x;
     if (qx >= a.nVf) return;
@@ -890,62 +896,241 @@ __device__ __forceinline__ float wave_sum_f(float v) {
     return v;
 }
 
-// One wave per row (4 rows per 256-thread block).  The wave first streams
-// the row's 9 planes of U-bar (non-temporal: every row is read once per
-// sweep; UT = float or _Float16) against the rest-frame gradients, with FP64
-// partial sums; then its lanes take the row's incident tets for the Hessian
-// term; lane 0 solves.
+// y = H-bar^-1 h over super-tiles of MT_SG x MT_SG tiles: block (SI, SJ),
+// SI >= SJ, of MT_SG waves; wave w takes tile row I = MT_SG SI + w across the
+// stored tiles (I, J) of tile columns J = MT_SG SJ .. MT_SG SJ + MT_SG - 1,
+// J <= I.  Lane (s, c) = (lane / 16, lane % 16) reads columns 4c .. 4c + 3 of
+// rows il = 4k + s as 16-byte loads, two 4-row batches (18 loads) in flight;
+// the zero-filled padding past nVf (of the tiles and of h) reads as zero and
+// batches wholly past it are skipped.  Each tile is read once,
+// non-temporally, and applied both ways:
+//  * row parts (M h_J): summed over the row's 16 lanes by DPP and kept by
+//    lane (s, k) for row 4k + s, accumulated over the wave's tiles in column
+//    order, then stored once per wave as prow[SJ][I];
+//  * column parts of off-diagonal tiles (M^T h_I): summed per lane, then over
+//    the four 16-lane rows, into LDS; after the block's barrier wave j sums
+//    the column parts of tile column MT_SG SJ + j over the waves in order and
+//    stores pcol[SI][J].
+// Each super-tile thus writes 2 MT_SG partial vectors for MT_SG^2 tiles
+// (stores interleaved with the streamed reads cost HBM time in proportion to
+// their bytes), as non-temporal stores.  Every sum runs in a fixed order: no
+// atomics, the result is bitwise-deterministic.  Indices are wave-uniform and
+// kept in scalar registers.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(64 * MT_SG) void k_symv(SweepArgs a) {
+    __shared__ float sCol[MT_SG][MT_SG][3][MT_Q];  // [wave][tile column][component][column]
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int bt = blockIdx.x;
+    // bt = SI (SI + 1) / 2 + SJ, SJ <= SI
+    int SI = __builtin_amdgcn_readfirstlane((int)((sqrtf(8.0f * (float)bt + 1.0f) - 1.0f) * 0.5f));
+    while ((SI + 1) * (SI + 2) / 2 <= bt) ++SI;
+    while (SI * (SI + 1) / 2 > bt) --SI;
+    const int SJ = bt - SI * (SI + 1) / 2;
+    const int ntq = (a.nVf + MT_Q - 1) / MT_Q;
+    const int I = MT_SG * SI + w;
+    const int lane = threadIdx.x & 63, sr = lane >> 4, c = lane & 15;
+    float4 mine = make_float4(0.f, 0.f, 0.f, 0.f);  // row 4c + sr of tile row I
+    if (I < ntq) {
+        const int nrow = min(MT_Q, a.nVf - I * MT_Q);
+        const float4* hI = a.hvec + I * MT_Q + sr;
+#pragma unroll 1
+        for (int j = 0; j < MT_SG; ++j) {
+            const int J = MT_SG * SJ + j;
+            if (J > I) break;  // upper triangle
+            float hx[4], hy[4], hz[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float4 h = a.hvec[J * MT_Q + 4 * c + k];
+                hx[k] = h.x;
+                hy[k] = h.y;
+                hz[k] = h.z;
+            }
+            const f32x4* T4 = reinterpret_cast<const f32x4*>(a.Mt + ((size_t)I * (I + 1) / 2 + J) * MT_TILE);
+            float cs[4][3];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cs[k][0] = cs[k][1] = cs[k][2] = 0.f;
+#pragma unroll 1
+            for (int kk = 0; 4 * kk < nrow; kk += 2) {
+                f32x4 m[2][9];
+                float4 hi[2];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int il = 4 * (kk + b) + sr;
+#pragma unroll
+                    for (int q = 0; q < 9; ++q)
+                        m[b][q] = __builtin_nontemporal_load(T4 + ((size_t)il * 9 + q) * (MT_Q / 4) + c);
+                    hi[b] = hI[4 * (kk + b)];
+                }
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float m0 = m[b][0][k], m1 = m[b][1][k], m2 = m[b][2][k];
+                        const float m3 = m[b][3][k], m4 = m[b][4][k], m5 = m[b][5][k];
+                        const float m6 = m[b][6][k], m7 = m[b][7][k], m8 = m[b][8][k];
+                        r0 = fmaf(m0, hx[k], fmaf(m1, hy[k], fmaf(m2, hz[k], r0)));
+                        r1 = fmaf(m3, hx[k], fmaf(m4, hy[k], fmaf(m5, hz[k], r1)));
+                        r2 = fmaf(m6, hx[k], fmaf(m7, hy[k], fmaf(m8, hz[k], r2)));
+                        cs[k][0] = fmaf(m0, hi[b].x, fmaf(m3, hi[b].y, fmaf(m6, hi[b].z, cs[k][0])));
+                        cs[k][1] = fmaf(m1, hi[b].x, fmaf(m4, hi[b].y, fmaf(m7, hi[b].z, cs[k][1])));
+                        cs[k][2] = fmaf(m2, hi[b].x, fmaf(m5, hi[b].y, fmaf(m8, hi[b].z, cs[k][2])));
+                    }
+                    r0 = lane_sum_w<16>(r0);
+                    r1 = lane_sum_w<16>(r1);
+                    r2 = lane_sum_w<16>(r2);
+                    if (c == kk + b) {
+                        mine.x += r0;
+                        mine.y += r1;
+                        mine.z += r2;
+                    }
+                }
+            }
+            if (I != J) {
+                // column sums over the four 16-lane rows; lane (sr, c) keeps column 4c + sr
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        float v = cs[k][r];
+                        v += __shfl_xor(v, 16, 64);
+                        v += __shfl_xor(v, 32, 64);
+                        cs[k][r] = v;
+                    }
+                float c0 = cs[0][0], c1 = cs[0][1], c2 = cs[0][2];
+#pragma unroll
+                for (int k = 1; k < 4; ++k)
+                    if (sr == k) {
+                        c0 = cs[k][0];
+                        c1 = cs[k][1];
+                        c2 = cs[k][2];
+                    }
+                sCol[w][j][0][4 * c + sr] = c0;
+                sCol[w][j][1][4 * c + sr] = c1;
+                sCol[w][j][2][4 * c + sr] = c2;
+            }
+        }
+        const f32x4 mv = {mine.x, mine.y, mine.z, 0.0f};
+        __builtin_nontemporal_store(mv, reinterpret_cast<f32x4*>(a.prow) + ((size_t)SJ * ntq + I) * MT_Q + 4 * c + sr);
+    }
+    __syncthreads();
+    // column partials of tile column J = MT_SG SJ + w: the waves' parts in order
+    const int J = MT_SG * SJ + w;
+    if (J < ntq) {
+        float y0 = 0.f, y1 = 0.f, y2 = 0.f;
+#pragma unroll 1
+        for (int ww = 0; ww < MT_SG; ++ww) {
+            const int Iw = MT_SG * SI + ww;
+            if (Iw > J && Iw < ntq) {
+                y0 += sCol[ww][w][0][lane];
+                y1 += sCol[ww][w][1][lane];
+                y2 += sCol[ww][w][2][lane];
+            }
+        }
+        const f32x4 yv = {y0, y1, y2, 0.0f};
+        __builtin_nontemporal_store(yv, reinterpret_cast<f32x4*>(a.pcol) + ((size_t)SI * ntq + J) * MT_Q + lane);
+    }
+}
+
+// (H-bar^-1 h)_q for the 64 positions of tile row X (in super-tile row SX):
+// the row partials prow[SJ][X], SJ <= SX, then the column partials
+// pcol[SI][X], SI >= SX, wave w taking every fourth, FP64 sums, the four
+// waves combined in a fixed order.
+__global__ __launch_bounds__(256) void k_ysum(SweepArgs a) {
+    __shared__ double sy[4][MT_Q][3];
+    const int X = blockIdx.x;
+    const int ntq = (a.nVf + MT_Q - 1) / MT_Q;
+    const int ns = (ntq + MT_SG - 1) / MT_SG;
+    const int SX = X / MT_SG;
+    const int n = ns + 1;  // SX + 1 row partials, ns - SX column partials
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    auto at = [&](int k) -> const float4* {
+        return k <= SX ? a.prow + ((size_t)k * ntq + X) * MT_Q + lane
+                       : a.pcol + ((size_t)(SX + k - SX - 1) * ntq + X) * MT_Q + lane;
+    };
+    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+    int k = w;
+    for (; k + 28 < n; k += 32) {  // eight loads in flight
+        float4 p[8];
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) p[kb] = *at(k + 4 * kb);
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) {
+            y0 += p[kb].x;
+            y1 += p[kb].y;
+            y2 += p[kb].z;
+        }
+    }
+    for (; k < n; k += 4) {
+        const float4 p = *at(k);
+        y0 += p.x;
+        y1 += p.y;
+        y2 += p.z;
+    }
+    sy[w][lane][0] = y0;
+    sy[w][lane][1] = y1;
+    sy[w][lane][2] = y2;
+    __syncthreads();
+    const int q = X * MT_Q + threadIdx.x;
+    if (threadIdx.x < MT_Q && q < a.nVf) {
+        float y[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            y[r] = (float)(((sy[0][threadIdx.x][r] + sy[1][threadIdx.x][r]) + sy[2][threadIdx.x][r]) + sy[3][threadIdx.x][r]);
+        a.yq[q] = make_float4(y[0], y[1], y[2], 0.0f);
+    }
+}
+
+// (H-bar^-1)_{b,f} as a 3x3 block (row-major) from the tiles.
+__device__ __forceinline__ void mblock(const float* __restrict__ Mt, int qb, int qf, float* M) {
+    const int TB = qb / MT_Q, TF = qf / MT_Q;
+    if (TB >= TF) {
+        const float* T = Mt + tile_index(TB, TF) * MT_TILE + (size_t)(qb % MT_Q) * 9 * MT_Q + qf % MT_Q;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) M[q] = T[q * MT_Q];
+    } else {  // kept as (H-bar^-1)_{f,b}, its transpose
+        const float* T = Mt + tile_index(TF, TB) * MT_TILE + (size_t)(qf % MT_Q) * 9 * MT_Q + qb % MT_Q;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) M[3 * r + c] = T[(3 * c + r) * MT_Q];
+    }
+}
+
+// One wave per row (4 rows per 256-thread block), rows in position order
+// when every row is swept (neighbouring rows then share the tile lines of
+// their one-ring blocks) or from a.list (free indices).  The reduced
+// gradient comes from a.yq; the lanes take the row's incident tets for the
+// Hessian term; lane 0 solves.
 // LIN (adjoint): the same local system of H(x*) y = rhs, with the linear
-// residual r = H y - rhs in place of g (its rest-frame form in a.hvec), the
+// residual r = H y - rhs in place of g (its rest-frame form behind a.yq), the
 // Hessian at a.u = x*, and the update applied to y.
-template <typename UT, bool LIN>
+template <bool LIN>
 __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
     const int lane = threadIdx.x & 63;
     const int row = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     const int nidx = a.list ? a.n_list : a.nVf;
     if (row >= nidx) return;  // the whole wave
-    const int f = a.list ? a.list[row] : row;
-    const int v = a.free_ids[f];
+    int f, v, qf;
+    if (a.list) {
+        f = a.list[row];
+        v = a.free_ids[f];
+        qf = a.qpos[v];
+    } else {
+        qf = row;
+        f = a.qfree[qf];
+        v = a.qvert[qf];
+    }
     const d4 uv = a.u[v];
     if (!LIN && !body_on(a, f)) {
         if (lane == 0 && !a.in_place) a.unext[v] = uv;  // a stopped body's Jacobi buffer carried over
         return;
     }
-    const size_t plane = (size_t)a.nVf;
-    const UT* U = static_cast<const UT*>(a.Ufull) + (size_t)f * 9 * plane;
-    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
-    int qx = lane;
-    // four positions per lane in flight
-    for (; qx + 192 < a.nVf; qx += 256) {
-        float u[4][9];
-        float4 h[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            h[k] = a.hvec[qx + 64 * k];
-#pragma unroll
-            for (int q = 0; q < 9; ++q) u[k][q] = (float)__builtin_nontemporal_load(U + q * plane + qx + 64 * k);
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            y0 += (double)(u[k][0] * h[k].x + u[k][3] * h[k].y + u[k][6] * h[k].z);
-            y1 += (double)(u[k][1] * h[k].x + u[k][4] * h[k].y + u[k][7] * h[k].z);
-            y2 += (double)(u[k][2] * h[k].x + u[k][5] * h[k].y + u[k][8] * h[k].z);
-        }
-    }
-    for (; qx < a.nVf; qx += 64) {
-        const float4 h = a.hvec[qx];
-        float u[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) u[q] = (float)__builtin_nontemporal_load(U + q * plane + qx);
-        y0 += (double)(u[0] * h.x + u[3] * h.y + u[6] * h.z);
-        y1 += (double)(u[1] * h.x + u[4] * h.y + u[7] * h.z);
-        y2 += (double)(u[2] * h.x + u[5] * h.y + u[8] * h.z);
-    }
-    y0 = wave_sum_d(y0);
-    y1 = wave_sum_d(y1);
-    y2 = wave_sum_d(y2);
-    float Ri[9];
+    float Ri[9], Bi[9];
     load_rot(a.R, v, Ri);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Bi[q] = a.Binv[(size_t)qf * 9 + q];
     // Hessian term over the incident tets, one per lane
     float A9[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const int n = a.inc_n[f];
@@ -976,9 +1161,13 @@ __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
 #pragma unroll
                     for (int q = 0; q < 9; ++q) Phi[q] = 0.0f;
                 } else {
-                    float Ub[9], Rb[9];
+                    float M[9], Ub[9], Rb[9];
+                    mblock(a.Mt, qb, qf, M);
 #pragma unroll
-                    for (int q = 0; q < 9; ++q) Ub[q] = (float)U[q * plane + qb];
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int cc = 0; cc < 3; ++cc)
+                            Ub[3 * r + cc] = M[3 * r] * Bi[cc] + M[3 * r + 1] * Bi[3 + cc] + M[3 * r + 2] * Bi[6 + cc];
                     load_rot(a.R, vb, Rb);
                     corotate(Ub, Ri, Rb, Phi);
                 }
@@ -1006,10 +1195,14 @@ __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) A9[q] = wave_sum_f(A9[q]);
     if (lane == 0) {
-        const float yy[3] = {(float)y0, (float)y1, (float)y2};
-        float b[3];
+        // b = R_f B_f^-1 y
+        const float4 y4 = a.yq[qf];
+        const float yy[3] = {y4.x, y4.y, y4.z};
+        float by[3], b[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) b[i] = Ri[3 * i] * yy[0] + Ri[3 * i + 1] * yy[1] + Ri[3 * i + 2] * yy[2];
+        for (int i = 0; i < 3; ++i) by[i] = Bi[3 * i] * yy[0] + Bi[3 * i + 1] * yy[1] + Bi[3 * i + 2] * yy[2];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) b[i] = Ri[3 * i] * by[0] + Ri[3 * i + 1] * by[1] + Ri[3 * i + 2] * by[2];
         const float m = LIN ? a.mh2[v] : (float)a.zu[v].w;
         float A[9];
 #pragma unroll
@@ -1417,28 +1610,31 @@ void launch_linear(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<1>(s, 
 
 void launch_damper(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<2>(s, a); }
 
-// Rotation pass in a fixed shape (8 lanes per row, 64 rows per block): its
-// cost is the gather plus one polar decomposition per row, which this shape
-// runs 64 to a wave.
-void launch_hvec(jgs2_solver* s, const SweepArgs& a) {
+// h, the tile products and their per-position sums.
+void launch_reduced_gradient(jgs2_solver* s, const SweepArgs& a) {
+    if (a.nVf == 0) return;
     launch(s, JGS2_K_HVEC, k_hvec, dim3((a.nVf + 255) / 256), dim3(256), a);
+    const int ns = (a.nVf + MT_Q * MT_SG - 1) / (MT_Q * MT_SG);
+    launch(s, JGS2_K_SYMV, k_symv, dim3((unsigned)(ns * (ns + 1) / 2)), dim3(64 * MT_SG), a);
+    launch(s, JGS2_K_YSUM, k_ysum, dim3((a.nVf + MT_Q - 1) / MT_Q), dim3(256), a);
 }
 
 // One wave per row, four rows per block.
 void launch_exact(jgs2_solver* s, const SweepArgs& a) {
     const int n = a.list ? a.n_list : a.nVf;
     if (n == 0) return;
-    if (a.full_fp16) launch(s, JGS2_K_EXACT, k_exact<_Float16, false>, dim3((n + 3) / 4), dim3(256), a);
-    else launch(s, JGS2_K_EXACT, k_exact<float, false>, dim3((n + 3) / 4), dim3(256), a);
+    launch(s, JGS2_K_EXACT, k_exact<false>, dim3((n + 3) / 4), dim3(256), a);
 }
 
 void launch_exact_linear(jgs2_solver* s, const SweepArgs& a) {
     const int n = a.list ? a.n_list : a.nVf;
     if (n == 0) return;
-    if (a.full_fp16) launch(s, JGS2_K_EXACT, k_exact<_Float16, true>, dim3((n + 3) / 4), dim3(256), a);
-    else launch(s, JGS2_K_EXACT, k_exact<float, true>, dim3((n + 3) / 4), dim3(256), a);
+    launch(s, JGS2_K_EXACT, k_exact<true>, dim3((n + 3) / 4), dim3(256), a);
 }
 
+// Rotation pass in a fixed shape (8 lanes per row, 64 rows per block): its
+// cost is the gather plus one polar decomposition per row, which this shape
+// runs 64 to a wave.
 void launch_rotations(jgs2_solver* s, const SweepArgs& a) {
     constexpr int W = 8, BLK = 512, NV = BLK / W;
     const int nb = (a.nVf + NV - 1) / NV;

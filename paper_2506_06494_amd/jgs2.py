@@ -28,7 +28,7 @@ class Params(C.Structure):
                 ("omega", C.c_double), ("rel_tol", C.c_double), ("max_sweeps", C.c_int32),
                 ("check_every", C.c_int32), ("d_hat", C.c_double), ("kappa", C.c_double),
                 ("n_planes", C.c_int32), ("line_search", C.c_int32), ("planes", (C.c_double * 4) * MAX_PLANES),
-                ("adj_rel_tol", C.c_double), ("adj_max_sweeps", C.c_int32), ("use_graph", C.c_int32), ("exact_fp16", C.c_int32)]
+                ("adj_rel_tol", C.c_double), ("adj_max_sweeps", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -52,7 +52,7 @@ EXPORTS = ["jgs2_default_params", "jgs2_create", "jgs2_destroy", "jgs2_last_erro
            "jgs2_energy_noalloc", "jgs2_set_state_device", "jgs2_get_state_device"]
 
 KERNELS = ["phase1", "phase2", "plain", "commit", "reduce", "predict", "velocity", "energy", "linear", "paramgrad",
-           "adjvec", "damper", "rot", "exact", "hvec"]
+           "adjvec", "damper", "rot", "exact", "hvec", "symv", "ysum"]
 
 _lib = None
 
