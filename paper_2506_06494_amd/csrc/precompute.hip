@@ -1067,6 +1067,22 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
     std::vector<int> perm, iperm(nVf);
     rcm_order(s, perm);
     for (int p = 0; p < nVf; ++p) iperm[perm[p]] = p;
+    // exact variant: H-bar^-1 in tiles over the permuted positions of the free vertices,
+    // allocated before the precompute's temporaries (a 25 GB buffer placed among
+    // freed ones streams measurably slower)
+    const bool want_full = s->p.variant == JGS2_EXACT;
+    if (want_full) {
+        std::vector<int> qpos(nV, -1), qvert(nVf);
+        for (int q = 0; q < nVf; ++q) {
+            qvert[q] = s->free_ids[perm[q]];
+            qpos[qvert[q]] = q;
+        }
+        int r;
+        if ((r = alloc_full_tables(s))) return r;
+        PCHK(hipMemcpyAsync(s->d_qpos, qpos.data(), nV * 4, hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(s->d_qvert, qvert.data(), nVf * 4, hipMemcpyHostToDevice, st));
+        PCHK(hipMemcpyAsync(s->d_qfree, perm.data(), nVf * 4, hipMemcpyHostToDevice, st));
+    }
     const int n = 3 * nVf;
     const int nB = (n + NB - 1) / NB;
     const int n_pad = nB * NB;
@@ -1338,19 +1354,6 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
     DevBuf<double> dW;
     DevBuf<int> dfirst;
     if ((r = dW.alloc(s, (size_t)chunk_batches * n_pad * NB)) || (r = dfirst.alloc(s, chunk_batches))) return r;
-    // exact variant: H-bar^-1 in tiles over the permuted positions of the free vertices
-    const bool want_full = s->p.variant == JGS2_EXACT;
-    if (want_full) {
-        std::vector<int> qpos(nV, -1), qvert(nVf);
-        for (int q = 0; q < nVf; ++q) {
-            qvert[q] = s->free_ids[perm[q]];
-            qpos[qvert[q]] = q;
-        }
-        if ((r = alloc_full_tables(s))) return r;
-        PCHK(hipMemcpyAsync(s->d_qpos, qpos.data(), nV * 4, hipMemcpyHostToDevice, st));
-        PCHK(hipMemcpyAsync(s->d_qvert, qvert.data(), nVf * 4, hipMemcpyHostToDevice, st));
-        PCHK(hipMemcpyAsync(s->d_qfree, perm.data(), nVf * 4, hipMemcpyHostToDevice, st));
-    }
     CubArgs ca;
     std::memset(&ca, 0, sizeof(ca));
     ca.nV = nV; ca.nVf = nVf; ca.nT = nT; ca.n_pad = n_pad; ca.nTp = nTp; ca.S = S; ca.n_cand = n_cand;
