@@ -154,12 +154,16 @@ def cubature_system(model, ring, U, G, cid, i):
     outside = model.free & ~nbar
     # remote reduced gradient per pose (the plain definition)
     tau = np.einsum("vji,tvj->ti", U[outside], G[:, outside])          # (n_T, 3)
-    # per-cluster RMS normalisation
+    # per-cluster RMS normalisation, floored at 1e-3 of the largest cluster
+    # RMS at i (a cluster far below the others is near the round-off of the
+    # sums above and is not scaled up past 1e3 x)
     nT = tau.shape[0]
     ncl = int(cid.max()) + 1
     rms = np.array([np.sqrt(np.mean(np.sum(tau[cid == c] ** 2, axis=1))) for c in range(ncl)])
-    keep = rms > 1e-12 * rms.max() if rms.max() > 0 else np.zeros(ncl, dtype=bool)
-    scale = np.where(keep[cid], 1.0 / np.where(rms[cid] > 0, rms[cid], 1.0), 0.0)
+    if rms.max() > 0:
+        scale = 1.0 / np.maximum(rms[cid], 1e-3 * rms.max())
+    else:
+        scale = np.zeros(nT)
     b = (tau * scale[:, None]).ravel()
     coef = np.where(outside[tets], 1.0 / model.valence[tets], 0.0)     # (T,4)
     contains_i = np.any(tets == i, axis=1)
@@ -268,6 +272,7 @@ def precompute(model, verts=None, S=4, n_cand=64, seed=0, keep_full=True, solver
             samples[c0 + k], weights[c0 + k], fit[c0 + k] = train_vertex(
                 model, ring, U[k], G, cid, int(v), S=S, n_cand=n_cand, seed=seed)
     tab = Tables(model, verts, ring, U_full, samples, weights, fit, lam, cid)
+    tab.G = G  # training-pose gradients, for rebuilding a vertex's NNLS system
     if not keep_full:
         tab.U_full = None
     return tab

@@ -102,6 +102,7 @@ struct SweepArgs {
     float4* prow;           // [n_super * ntq * 64] row partials of H-bar^-1 h per super-tile column
     float4* pcol;           // [n_super * ntq * 64] column partials per super-tile row
     float4* yq;             // [nVf] (H-bar^-1 h)_q
+    const int* nactive;     // bodies still iterating (device count; nullptr: always run the product)
 };
 
 }  // namespace jgs2

@@ -531,6 +531,7 @@ struct CubArgs {
     const int* inc_n;
     const double* W;        // solved columns of this chunk
     const double* G;        // [nTp][n_pad] poses lambda_t v_t (permuted DOFs)
+    const double* GU;       // [nTp][n_pad] H-bar^-1 g^(t) (permuted DOFs)
     const double* lam;      // [nTp]
     const int* cid;         // [nTp]
     float* Uring;           // tables (device layout of the sweep)
@@ -677,12 +678,15 @@ __global__ __launch_bounds__(64) void k_cubature(CubArgs a) {
         ubar(sNbar[lane], U);
         for (int q = 0; q < 9; ++q) a.Uring[((size_t)f * 9 + q) * a.K + lane] = (float)U[q];
     }
-    // training targets: tau^(t) = B^-1 v_{t,i} - sum_{x in Nbar(i)} U-bar_{i,x}^T g_x^(t)
+    // training targets: the remote part of the reduced gradient,
+    //   tau^(t) = sum_{x not in Nbar(i)} U-bar_{i,x}^T g_x^(t)
+    //           = B^-1 (H-bar^-1 g^(t))_i - sum_{x in Nbar(i)} U-bar_{i,x}^T g_x^(t)
+    // (U-bar_{i,x}^T = B^-1 (H-bar^-1)_{i,x} by Eq. u, for any g)
     if (lane < nTp) {
         const int t = lane;
         double tau[3];
         double vi[3];
-        for (int r = 0; r < 3; ++r) vi[r] = a.G[(size_t)t * a.n_pad + 3 * p + r] / a.lam[t];
+        for (int r = 0; r < 3; ++r) vi[r] = a.GU[(size_t)t * a.n_pad + 3 * p + r];
         for (int r = 0; r < 3; ++r) tau[r] = sBinv[3 * r] * vi[0] + sBinv[3 * r + 1] * vi[1] + sBinv[3 * r + 2] * vi[2];
         for (int k = 0; k < nbar; ++k) {
             const int x = sNbar[k];
@@ -701,7 +705,10 @@ __global__ __launch_bounds__(64) void k_cubature(CubArgs a) {
         for (int r = 0; r < 3; ++r) sTau[3 * t + r] = tau[r];
     }
     __syncthreads();
-    // per-cluster RMS normalisation
+    // per-cluster RMS normalisation, each cluster divided by the larger of its
+    // RMS and 1e-3 of the largest cluster RMS at this vertex (a cluster whose
+    // remote gradient here is orders of magnitude below the others is near the
+    // round-off of the sums that form it; it is not scaled up past 1e3 x)
     if (lane == 0) {
         double rms[NTMAX];
         int ncl = 0;
@@ -717,7 +724,7 @@ __global__ __launch_bounds__(64) void k_cubature(CubArgs a) {
         }
         for (int t = 0; t < nTp; ++t) {
             const double r = rms[a.cid[t]];
-            sScale[t] = (mx > 0.0 && r > 1e-12 * mx) ? 1.0 / r : 0.0;
+            sScale[t] = mx > 0.0 ? 1.0 / fmax(r, 1e-3 * mx) : 0.0;
         }
     }
     __syncthreads();
@@ -1239,6 +1246,7 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
         if ((r = orth_into(dV.p, dQ.p))) return r;
     }
     bool converged = false;
+    double worst_prev = 1e300;
     for (int restart = 0; restart < 40 && !converged; ++restart) {
         for (int j = 0; j < MB; ++j) {
             double* Qj = dQ.p + (size_t)j * blk;
@@ -1295,7 +1303,12 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
         for (int k = 0; k < nwant; ++k) worst = std::max(worst, rn[k] / mu_top[k]);
         theta.resize(PMAX);
         for (int c = 0; c < PMAX; ++c) theta[c] = 1.0 / mu_top[c];
-        converged = worst < 1e-10;
+        // relative Ritz residual 1e-12: the poses then agree with an exact
+        // eigensolve to ~1e-12 / (the smallest relative gap between clusters),
+        // which the cubature columns inherit; a residual that has reached 1e-10
+        // and stopped falling (the band solves' round-off) is accepted
+        converged = worst < 1e-12 || (worst < 1e-10 && worst > 0.5 * worst_prev);
+        worst_prev = worst;
         stage(converged ? "eigen restart (converged)" : "eigen restart", t_start);
         if (!converged) {  // restart from the current Ritz block
             PCHK(hipMemcpyAsync(dV.p, dZ.p, blk * 8, hipMemcpyDeviceToDevice, st));
@@ -1314,9 +1327,11 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
     s->n_poses = nTp;
     s->pose_eigs.assign(theta.begin(), theta.begin() + std::min(nwant, (int)theta.size()));
     // G[t][dof] = lambda_t z_t (transpose of the first nTp columns of Z)
-    DevBuf<double> dG, dlam;
+    DevBuf<double> dG, dGU, dlam;
     DevBuf<int> dcid;
-    if ((r = dG.alloc(s, (size_t)nTp * n_pad)) || (r = dlam.alloc(s, nTp)) || (r = dcid.alloc(s, nTp))) return r;
+    if ((r = dG.alloc(s, (size_t)nTp * n_pad)) || (r = dGU.alloc(s, (size_t)nTp * n_pad)) ||
+        (r = dlam.alloc(s, nTp)) || (r = dcid.alloc(s, nTp)))
+        return r;
     {
         std::vector<double> Z((size_t)n_pad * PMAX), G((size_t)nTp * n_pad);
         PCHK(hipMemcpyAsync(Z.data(), dX.p, Z.size() * 8, hipMemcpyDeviceToHost, st));
@@ -1324,6 +1339,18 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
         for (int t = 0; t < nTp; ++t)
             for (int i = 0; i < n_pad; ++i) G[(size_t)t * n_pad + i] = theta[t] * Z[(size_t)i * PMAX + t];
         PCHK(hipMemcpyAsync(dG.p, G.data(), G.size() * 8, hipMemcpyHostToDevice, st));
+        // H-bar^-1 g^(t) by one band solve of the pose block ([row][PMAX], unused columns zero)
+        std::vector<double> Y((size_t)n_pad * PMAX, 0.0);
+        for (int i = 0; i < n_pad; ++i)
+            for (int t = 0; t < nTp; ++t) Y[(size_t)i * PMAX + t] = G[(size_t)t * n_pad + i];
+        PCHK(hipMemcpyAsync(dHZ.p, Y.data(), Y.size() * 8, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_band_solve_cols, dim3(NB / BS_CW), dim3(256), 0, st, dL.p, dLinv.p, nB, w, n_pad, dHZ.p);
+        PCHK(hipGetLastError());
+        PCHK(hipMemcpyAsync(Y.data(), dHZ.p, Y.size() * 8, hipMemcpyDeviceToHost, st));
+        PCHK(hipStreamSynchronize(st));
+        for (int t = 0; t < nTp; ++t)
+            for (int i = 0; i < n_pad; ++i) G[(size_t)t * n_pad + i] = Y[(size_t)i * PMAX + t];
+        PCHK(hipMemcpyAsync(dGU.p, G.data(), G.size() * 8, hipMemcpyHostToDevice, st));
         PCHK(hipMemcpyAsync(dlam.p, theta.data(), nTp * 8, hipMemcpyHostToDevice, st));
         PCHK(hipMemcpyAsync(dcid.p, cid.data(), nTp * 4, hipMemcpyHostToDevice, st));
     }
@@ -1360,7 +1387,7 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
     ca.K = s->K; ca.maxi = s->maxi; ca.E_free = nfree_el; ca.seed = seed;
     ca.tets = dtets.p; ca.free_ids = s->d_free; ca.free_index = dfidx.p; ca.perm = dperm.p; ca.iperm = diperm.p;
     ca.valence = dval.p; ca.ring = s->d_ring; ca.ring_n = s->d_ring_n; ca.inc = s->d_inc; ca.inc_n = s->d_inc_n;
-    ca.W = dW.p; ca.G = dG.p; ca.lam = dlam.p; ca.cid = dcid.p;
+    ca.W = dW.p; ca.G = dG.p; ca.GU = dGU.p; ca.lam = dlam.p; ca.cid = dcid.p;
     ca.Uring = s->d_Uring; ca.samp_e = s->d_samp_e; ca.samp = s->d_samp; ca.fit = dfit.p;
     for (int p0 = 0; p0 < nVf; p0 += chunk_batches * VPBATCH) {
         const int nvert = std::min(chunk_batches * VPBATCH, nVf - p0);

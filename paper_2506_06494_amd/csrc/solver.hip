@@ -85,7 +85,7 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
     a.d_hat = (float)s->p.d_hat; a.kappa = (float)s->p.kappa;
     a.fbody = s->d_fbody; a.body_on = s->d_body_on; a.one_body = s->n_bodies == 1;
     a.Mt = s->d_Mt; a.Binv = s->d_Binv; a.qpos = s->d_qpos; a.qvert = s->d_qvert; a.qfree = s->d_qfree;
-    a.hvec = s->d_hvec; a.yq = s->d_yq;
+    a.hvec = s->d_hvec; a.yq = s->d_yq; a.nactive = s->d_nactive;
     const size_t ntq_ = ((size_t)s->nVf + MT_Q - 1) / MT_Q;
     a.prow = s->d_part;
     a.pcol = s->d_part ? s->d_part + (ntq_ + MT_SG - 1) / MT_SG * ntq_ * MT_Q : nullptr;
@@ -1468,6 +1468,7 @@ static int adjoint_solve(jgs2_solver* s, const d4* xstar, int64_t* sweeps, doubl
     build_sweep_args(s, a);
     a.u = xstar;
     a.lrhs = s->d_rhs;
+    a.nactive = nullptr;  // the forward step's stop flags do not apply to the adjoint solve
     a.mh2 = s->d_mh2;
     double b2 = 0.0, r2 = 0.0;
     launch_norm2(s, s->d_rhs);

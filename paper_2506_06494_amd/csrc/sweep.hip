@@ -884,18 +884,6 @@ __global__ __launch_bounds__(256) void k_hvec(SweepArgs a) {
                              R[2] * g.x + R[5] * g.y + R[8] * g.z, 0.0f);
 }
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-__device__ __forceinline__ float wave_sum_f(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 // y = H-bar^-1 h over super-tiles of MT_SG x MT_SG tiles: block (SI, SJ),
 // SI >= SJ, of MT_SG waves; wave w takes tile row I = MT_SG SI + w across the
 // stored tiles (I, J) of tile columns J = MT_SG SJ .. MT_SG SJ + MT_SG - 1,
@@ -920,6 +908,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(64 * MT_SG) void k_symv(SweepArgs a) {
     __shared__ float sCol[MT_SG][MT_SG][3][MT_Q];  // [wave][tile column][component][column]
+    // a sweep issued after every body stopped (the host reads residuals one
+    // group late) changes nothing: skip its stream (uniform over the block)
+    if (a.nactive && *a.nactive == 0) return;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int bt = blockIdx.x;
     // bt = SI (SI + 1) / 2 + SJ, SJ <= SI
@@ -1082,36 +1073,23 @@ __global__ __launch_bounds__(256) void k_ysum(SweepArgs a) {
     }
 }
 
-// (H-bar^-1)_{b,f} as a 3x3 block (row-major) from the tiles.
-__device__ __forceinline__ void mblock(const float* __restrict__ Mt, int qb, int qf, float* M) {
-    const int TB = qb / MT_Q, TF = qf / MT_Q;
-    if (TB >= TF) {
-        const float* T = Mt + tile_index(TB, TF) * MT_TILE + (size_t)(qb % MT_Q) * 9 * MT_Q + qf % MT_Q;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) M[q] = T[q * MT_Q];
-    } else {  // kept as (H-bar^-1)_{f,b}, its transpose
-        const float* T = Mt + tile_index(TF, TB) * MT_TILE + (size_t)(qf % MT_Q) * 9 * MT_Q + qb % MT_Q;
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) M[3 * r + c] = T[(3 * c + r) * MT_Q];
-    }
-}
-
-// One wave per row (4 rows per 256-thread block), rows in position order
-// when every row is swept (neighbouring rows then share the tile lines of
-// their one-ring blocks) or from a.list (free indices).  The reduced
-// gradient comes from a.yq; the lanes take the row's incident tets for the
-// Hessian term; lane 0 solves.
+// Sixteen lanes per row (16 rows per 256-thread block), rows in position
+// order when every row is swept (neighbouring rows then share tet and
+// position lines) or from a.list (free indices).  The reduced gradient comes
+// from a.yq; the row's lanes take its incident tets for the Hessian term,
+// with Phi_{f,b} = R_b U-bar_{f,b} R_f^T from the row's one-ring U-bar rows
+// (contiguous per row, addressed by the incidence's slot word), summed over
+// the 16 lanes by DPP; the row's first lane solves.
 // LIN (adjoint): the same local system of H(x*) y = rhs, with the linear
 // residual r = H y - rhs in place of g (its rest-frame form behind a.yq), the
 // Hessian at a.u = x*, and the update applied to y.
+constexpr int EX_LANES = 16;
 template <bool LIN>
 __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int row = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & (EX_LANES - 1);
+    const int row = xcd_remap(blockIdx.x, gridDim.x) * (256 / EX_LANES) + (threadIdx.x / EX_LANES);
     const int nidx = a.list ? a.n_list : a.nVf;
-    if (row >= nidx) return;  // the whole wave
+    if (row >= nidx) return;  // the row's 16 lanes
     int f, v, qf;
     if (a.list) {
         f = a.list[row];
@@ -1127,15 +1105,14 @@ __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
         if (lane == 0 && !a.in_place) a.unext[v] = uv;  // a stopped body's Jacobi buffer carried over
         return;
     }
-    float Ri[9], Bi[9];
+    float Ri[9];
     load_rot(a.R, v, Ri);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) Bi[q] = a.Binv[(size_t)qf * 9 + q];
     // Hessian term over the incident tets, one per lane
     float A9[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const int n = a.inc_n[f];
-    for (int j = lane; j < n; j += 64) {
+    for (int j = lane; j < n; j += EX_LANES) {
         const int4 e = a.inc4[(size_t)f * a.maxi + j];
+        const uint32_t sl = a.incslot[(size_t)f * a.maxi + j];
         const int c = e.x & 3;
         Tet T;
         load_tet_inc(a.tet, e, v, T);
@@ -1150,27 +1127,20 @@ __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
             for (int q = 0; q < 9; ++q) dF[d][q] = 0.0f;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int vb = T.id[b];
+            const uint32_t sb = (sl >> (8 * b)) & 0xFFu;
             float Phi[9];
-            if (vb == v) {
+            if (sb == SLOT_SELF) {
 #pragma unroll
                 for (int q = 0; q < 9; ++q) Phi[q] = (q % 4 == 0) ? 1.0f : 0.0f;
+            } else if (sb == SLOT_NONE) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) Phi[q] = 0.0f;
             } else {
-                const int qb = a.qpos[vb];
-                if (qb < 0) {
+                float Ub[9], Rb[9];
 #pragma unroll
-                    for (int q = 0; q < 9; ++q) Phi[q] = 0.0f;
-                } else {
-                    float M[9], Ub[9], Rb[9];
-                    mblock(a.Mt, qb, qf, M);
-#pragma unroll
-                    for (int r = 0; r < 3; ++r)
-#pragma unroll
-                        for (int cc = 0; cc < 3; ++cc)
-                            Ub[3 * r + cc] = M[3 * r] * Bi[cc] + M[3 * r + 1] * Bi[3 + cc] + M[3 * r + 2] * Bi[6 + cc];
-                    load_rot(a.R, vb, Rb);
-                    corotate(Ub, Ri, Rb, Phi);
-                }
+                for (int q = 0; q < 9; ++q) Ub[q] = a.Uring[((size_t)f * 9 + q) * a.K + sb];
+                load_rot(a.R, T.id[b], Rb);
+                corotate(Ub, Ri, Rb, Phi);
             }
             float gnb[3];
             gradN(T.D, b, gnb);
@@ -1193,9 +1163,12 @@ __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
         }
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) A9[q] = wave_sum_f(A9[q]);
+    for (int q = 0; q < 9; ++q) A9[q] = lane_sum_w<EX_LANES>(A9[q]);
     if (lane == 0) {
         // b = R_f B_f^-1 y
+        float Bi[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Bi[q] = a.Binv[(size_t)qf * 9 + q];
         const float4 y4 = a.yq[qf];
         const float yy[3] = {y4.x, y4.y, y4.z};
         float by[3], b[3];
@@ -1619,17 +1592,19 @@ void launch_reduced_gradient(jgs2_solver* s, const SweepArgs& a) {
     launch(s, JGS2_K_YSUM, k_ysum, dim3((a.nVf + MT_Q - 1) / MT_Q), dim3(256), a);
 }
 
-// One wave per row, four rows per block.
+// Sixteen lanes per row, 16 rows per block.
 void launch_exact(jgs2_solver* s, const SweepArgs& a) {
     const int n = a.list ? a.n_list : a.nVf;
     if (n == 0) return;
-    launch(s, JGS2_K_EXACT, k_exact<false>, dim3((n + 3) / 4), dim3(256), a);
+    constexpr int R = 256 / EX_LANES;
+    launch(s, JGS2_K_EXACT, k_exact<false>, dim3((n + R - 1) / R), dim3(256), a);
 }
 
 void launch_exact_linear(jgs2_solver* s, const SweepArgs& a) {
     const int n = a.list ? a.n_list : a.nVf;
     if (n == 0) return;
-    launch(s, JGS2_K_EXACT, k_exact<true>, dim3((n + 3) / 4), dim3(256), a);
+    constexpr int R = 256 / EX_LANES;
+    launch(s, JGS2_K_EXACT, k_exact<true>, dim3((n + R - 1) / R), dim3(256), a);
 }
 
 // Rotation pass in a fixed shape (8 lanes per row, 64 rows per block): its

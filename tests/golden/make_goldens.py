@@ -40,13 +40,20 @@ def golden_precompute(E):
     sc = inputs.single_beam(E)
     mdl = fem.model_from_scene(sc)
     verts = sampled_vertices(mdl, N_SAMPLED, 1)
-    tab = oc.precompute(mdl, verts=verts, S=4, n_cand=64, seed=SEED, keep_full=False)
+    tab = oc.precompute(mdl, verts=verts, S=4, n_cand=64, seed=SEED, keep_full=True)
     out = {"E": E, "lam": tab.lam.tolist(), "cid": tab.cid.tolist(), "verts": verts.tolist(), "rows": []}
     for k, v in enumerate(verts):
+        # the vertex's NNLS system of Eq. cubature_weight restricted to its chosen
+        # samples (normalised columns and right-hand side), and its conditioning
+        b, column, _ = oc.cubature_system(mdl, tab.ring, tab.U_full[k], tab.G, tab.cid, int(v))
+        chosen = [int(x) for x in tab.samples[k] if x >= 0]
+        A = np.stack([column(x) for x in chosen], axis=1)
+        sv = np.linalg.svd(A, compute_uv=False)
         out["rows"].append({"v": int(v), "ring": tab.nbr[k].tolist(),
                             "U_ring": np.asarray(tab.U_nbr[k]).reshape(-1, 9).tolist(),
                             "samples": tab.samples[k].tolist(), "weights": tab.weights[k].tolist(),
-                            "U_samp": tab.U_samp[k].reshape(4, 4, 9).tolist(), "fit": float(tab.fit_res[k])})
+                            "U_samp": tab.U_samp[k].reshape(4, 4, 9).tolist(), "fit": float(tab.fit_res[k]),
+                            "A": A.tolist(), "b": b.tolist(), "cond": float(sv[0] / sv[-1])})
     return out
 
 

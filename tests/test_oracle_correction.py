@@ -3,6 +3,7 @@ greedy NNLS cubature) against the paper's identities and brute force."""
 import itertools
 
 import numpy as np
+import pytest
 import scipy.linalg as sla
 
 from oracle import correction as oc, rng as orng
@@ -62,8 +63,9 @@ def test_training_poses_are_eigenpairs_and_gap_cut(tiny):
 
 
 def test_training_target_closed_form(tiny):
-    """tau_i = B^-1 v_i - sum_{a in Nbar(i)} U-bar_{i,a}^T g_a, using
-    U-bar_i^T H-bar = B^-1 S_i (from Eq. u)."""
+    """tau_i = B^-1 (H-bar^-1 g)_i - sum_{a in Nbar(i)} U-bar_{i,a}^T g_a for
+    any g, since U-bar_{i,a}^T = B^-1 (H-bar^-1)_{i,a} (Eq. u); for an exact
+    eigenvector (g = lambda v) the first term is B^-1 v_i."""
     sc, mdl, tab = tiny
     H = oc.rest_hessian(mdl)
     sv = oc.RestSolver(H)
@@ -79,6 +81,15 @@ def test_training_target_closed_form(tiny):
     V = G[:, i, :] / lam[:, None]
     inner = np.einsum("vji,tvj->ti", U[nbar & mdl.free], G[:, nbar & mdl.free])
     np.testing.assert_allclose(tau_def, V @ Binv.T - inner, atol=1e-9 * np.abs(tau_def).max())
+    # arbitrary gradients (not eigenvectors): only the H-bar^-1 g form holds
+    rng = np.random.default_rng(5)
+    Gr = np.zeros_like(G)
+    Gr[:, mdl.free_ids] = rng.standard_normal((G.shape[0], mdl.free_ids.size, 3))
+    tau_r = np.einsum("vji,tvj->ti", U[out], Gr[:, out])
+    HiG = np.stack([mdl.from_free(sv.solve(mdl.to_free(Gr[t])))[i] for t in range(G.shape[0])])
+    inner_r = np.einsum("vji,tvj->ti", U[nbar & mdl.free], Gr[:, nbar & mdl.free])
+    np.testing.assert_allclose(tau_r, HiG @ Binv.T - inner_r, atol=1e-9 * np.abs(tau_r).max())
+    assert np.abs(tau_r - (Gr[:, i, :] @ Binv.T - inner_r)).max() > 1e-3 * np.abs(tau_r).max()
 
 
 def _nnls_brute(A, b):
@@ -132,3 +143,40 @@ def test_candidate_stream_is_splitmix64():
         out.append(orng._fin(s))
     assert out == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
     assert orng.step(0) == 0xE220A8397B1DCDAF
+
+
+def test_cluster_normalisation_caps_small_clusters(tiny):
+    """Reading of Eq. cubature_weight's normalisation: each pose cluster's
+    rows of the remote reduced gradient (and of every column) are divided by
+    the larger of the cluster's RMS at the vertex and 1e-3 of the largest
+    cluster RMS.  Every cluster of the tiny beam's vertex is within that range
+    (unit RMS).  A cluster scaled by 1e-2 keeps unit RMS and the system is
+    unchanged; one scaled by 1e-7 is not scaled back up: its rows keep their
+    direction at an RMS far below one, and the other rows are unchanged."""
+    sc, mdl, tab = tiny
+    H = oc.rest_hessian(mdl)
+    sv = oc.RestSolver(H)
+    lam, G, cid = oc.training_poses(mdl, H, sv)
+    k = 123
+    i = int(tab.verts[k])
+    U = tab.U_full[k]
+    b0, col0, elig = oc.cubature_system(mdl, tab.ring, U, G, cid, i)
+    s = int(np.nonzero(elig)[0][0])
+    rows = np.repeat(cid == 0, 3)
+    rms = lambda v: np.sqrt(np.mean(v.reshape(-1, 3).__pow__(2).sum(1)))
+    ncl = int(cid.max()) + 1
+    assert all(rms(b0[np.repeat(cid == c, 3)]) == pytest.approx(1.0) for c in range(ncl))
+    for scale in (1e-2, 1e-7):
+        Gs = G.copy()
+        Gs[cid == 0] *= scale
+        b, col, _ = oc.cubature_system(mdl, tab.ring, U, Gs, cid, i)
+        np.testing.assert_allclose(b[~rows], b0[~rows], rtol=1e-12)
+        np.testing.assert_allclose(col(s)[~rows], col0(s)[~rows], rtol=1e-12, atol=1e-300)
+        if scale == 1e-2:
+            np.testing.assert_allclose(b, b0, rtol=1e-9, atol=1e-12)
+        else:
+            ratio = b[rows] / b0[rows]
+            assert np.ptp(ratio) <= 1e-9 * np.abs(ratio).max()   # same direction, one factor
+            assert 0.0 < rms(b[rows]) < 1e-2
+            np.testing.assert_allclose(col(s)[rows], col0(s)[rows] * ratio[0], rtol=1e-9,
+                                       atol=1e-12 * np.abs(col0(s)).max())
