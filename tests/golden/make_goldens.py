@@ -4,7 +4,8 @@ Calls only the FP64 oracle (``oracle/``) on the seeded single-beam workload
 (16x16 cross-section, 128 long, 0.05 m cells; nu 0.45, E 1e5 and 1e8 Pa,
 rho 1000, dt 1/120, initial twist 2 rad/s): the precompute on a sample of
 free vertices (training-pose eigenvalues, one-ring U-bar rows, cubature
-samples, weights, fit residuals), the positions of sampled vertices after
+samples, weights, fit residuals, each vertex's NNLS system, and one R3
+Jacobi sweep of those vertices from a twisted state), the positions of sampled vertices after
 two plain Jacobi sweeps (omega 0.8) of the first step, and (E 1e5) after four
 coloured GS sweeps with step scales 1.5 and 1.6, and the positions of
 sampled vertices after one Jacobi sweep of the exact co-rotated subspace
@@ -24,7 +25,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
-from oracle import correction as oc, fem, sweep as osw  # noqa: E402
+from oracle import correction as oc, fem, mesh as omesh, sweep as osw  # noqa: E402
 from paper_2506_06494_amd import inputs  # noqa: E402
 
 N_SAMPLED = 24
@@ -42,6 +43,21 @@ def golden_precompute(E):
     verts = sampled_vertices(mdl, N_SAMPLED, 1)
     tab = oc.precompute(mdl, verts=verts, S=4, n_cand=64, seed=SEED, keep_full=True)
     out = {"E": E, "lam": tab.lam.tolist(), "cid": tab.cid.tolist(), "verts": verts.tolist(), "rows": []}
+    # one R3 Jacobi sweep (omega 1) at the sampled vertices with their own tables,
+    # from the beam twisted by 0.3 rad over its length, at rest (x0 = x-hat, v = 0);
+    # the local systems and the size of their sampled-element terms go beside it
+    angle = 0.3
+    x0 = inputs.twisted_positions(sc.mesh, angle)
+    z = mdl.inertial_target(x0, np.zeros_like(x0))
+    g, R = osw.phase1(mdl, x0, z)
+    He = mdl.element_hessians(x0)
+    ell = osw._Ell(mdl, tab, omesh.incidence(mdl.tets, mdl.nV))
+    A, b = osw.r3_systems(mdl, tab, ell, x0, g, R, He, None)
+    dx = osw.local_solve(A, b)
+    wabs = np.abs(tab.weights).sum(axis=1) * np.abs(He).max()
+    out["r3"] = {"angle": angle, "x": (x0[verts] + dx).tolist(), "dx": dx.tolist(), "A": A.tolist(),
+                 "cond": [float(np.linalg.cond(a)) for a in A],
+                 "sample_scale": [float(x) for x in wabs]}
     for k, v in enumerate(verts):
         # the vertex's NNLS system of Eq. cubature_weight restricted to its chosen
         # samples (normalised columns and right-hand side), and its conditioning
