@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--max-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="4x4x16 beam instead (quick check)")
-    ap.add_argument("--modes", default="jgs2_exact_jacobi,jgs2_exact_gs,jgs2_damper_gs,"
+    ap.add_argument("--modes", default="jgs2_exact_jacobi,jgs2_exact_jacobi_keep_all,jgs2_exact_gs,jgs2_damper_gs,"
                                        "jgs2_damper_jacobi_w0.8,"
                                        "jgs2_jacobi,jgs2_gs,plain_jacobi,"
                                        "plain_jacobi_w0.8,plain_jacobi_w0.5,plain_jacobi_w0.3,plain_gs,"
@@ -104,8 +104,13 @@ def main():
         # the exact co-rotated subspace (every row of U-bar, no cubature), Jacobi and coloured GS
         # (a residual check after every sweep: a sweep streams the whole of H-bar^-1, so one
         # sweep past convergence costs more than the check)
-        ("jgs2_exact_jacobi", dict(variant=jgs2.EXACT, order=jgs2.JACOBI, omega=1.0, check_every=1)),
-        ("jgs2_exact_gs", dict(variant=jgs2.EXACT, order=jgs2.GS, omega=1.0, check_every=1)),
+        # (tiles of H-bar^-1 whose entries are all at most 1e-10 of its largest are skipped,
+        # the library default; the _keep_all mode streams every tile)
+        ("jgs2_exact_jacobi", dict(variant=jgs2.EXACT, order=jgs2.JACOBI, omega=1.0, check_every=1,
+                                   exact_drop=1e-10)),
+        ("jgs2_exact_jacobi_keep_all", dict(variant=jgs2.EXACT, order=jgs2.JACOBI, omega=1.0, check_every=1,
+                                            exact_drop=0.0)),
+        ("jgs2_exact_gs", dict(variant=jgs2.EXACT, order=jgs2.GS, omega=1.0, check_every=1, exact_drop=1e-10)),
         # the damper reading of the correction in coloured GS, no step scale
         ("jgs2_damper_gs", dict(variant=jgs2.DAMPER, order=jgs2.GS, omega=1.0)),
         ("jgs2_damper_jacobi_w0.8", dict(variant=jgs2.DAMPER, order=jgs2.JACOBI, omega=0.8)),
@@ -225,6 +230,8 @@ def main():
             status = (jgs2.STATUS_NAMES[failed["status"]] if failed else
                       "NOT_CONVERGED" if (stalled or not ok) else "OK")
             entry = dict(status=status, converged_all=bool(ok), steps=len(recs))
+            if cfg["variant"] == jgs2.EXACT:
+                entry["exact_tiles"] = s.exact_tiles()
             if tuned:
                 entry["launch_shape"] = list(tuned)
             if failed:
@@ -293,7 +300,8 @@ def main():
             per_launch = sweep_bytes("rot", **cnt)
             kname = "k_rot"
         elif dom == "symv":       # one launch per reduced gradient (per sweep, or per colour in GS)
-            per_launch = sweep_bytes("symv", **cnt)
+            per_launch = sweep_bytes("symv", **cnt,
+                                     live_bytes=results[head_mode][E0]["exact_tiles"]["live_bytes"])
             kname = "k_symv"
         elif dom == "exact":      # Jacobi: one launch over every row; GS: one per colour
             per_launch = sweep_bytes("exact", **cnt) * (1 if "jacobi" in head_mode else 1.0 / n_colors)
@@ -618,7 +626,7 @@ def measured_traffic(kernel, workload_tag, shape=None):
     return None
 
 
-def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches=1):
+def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches=1, live_bytes=None):
     """Compulsory (algorithmic) bytes moved by one launch of a sweep kernel,
     counting every datum it must touch once: tet records 80 B (64 B without
     the id word), incidence entries 4 B or 16 B with corner ids (plus 4 B
@@ -634,14 +642,15 @@ def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches
         return 64.0 * n_inc + 64.0 * Vf + 32.0 * V
     if kind == "plain_gs_sweep":  # all colour launches of one sweep; positions read once per colour
         return 64.0 * n_inc + 64.0 * Vf + 32.0 * V * n_colors
-    if kind == "symv":        # the stored tiles of H-bar^-1 (rows past Vf not read), 1 KB partials written:
-        q, g = 64, 8          # one per tile row and one per tile column of each 8 x 8 super-tile
-        nt = (Vf + q - 1) // q
+    if kind == "symv":        # the live tiles of H-bar^-1 (every stored tile unless live_bytes is given;
+        q, g = 64, 8          # rows past Vf not read), 1 KB partials written: one per tile row and one
+        nt = (Vf + q - 1) // q  # per tile column of each 8 x 8 super-tile
         ns = (nt + g - 1) // g
         rows = sum(min(q, Vf - i * q) * (i + 1) for i in range(nt))
         valid = [min(g, nt - g * k) for k in range(ns)]
         parts = sum(valid[si] + valid[sj] for si in range(ns) for sj in range(si + 1))
-        return 36.0 * q * rows + 1024.0 * parts + 16.0 * Vf
+        tiles = 36.0 * q * rows if live_bytes is None else live_bytes
+        return tiles + 1024.0 * parts + 16.0 * Vf
     if kind == "exact":       # incident tets, positions, y and B^-1 per row, rotations, result
         return 96.0 * n_inc + (16.0 + 36.0 + 16.0) * Vf + 64.0 * V
     if kind == "rot":         # records and positions; row id and count read, rotation written

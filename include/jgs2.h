@@ -100,6 +100,11 @@ typedef struct jgs2_params {
     int32_t adj_max_sweeps;     /* sweep cap per adjoint solve */
     int32_t use_graph;          /* 1: replay each group of check_every sweeps and its
                                    residual check as one captured HIP graph */
+    double  exact_drop;         /* JGS2_EXACT: tiles of H-bar^-1 whose largest entry is at
+                                   most exact_drop x the largest entry of H-bar^-1 are
+                                   skipped by the sweep (0 keeps every tile; default
+                                   1e-10, at the FP32 resolution of the product); may
+                                   change between steps without a new precompute */
 } jgs2_params;
 
 typedef struct jgs2_step_stats {
@@ -212,6 +217,13 @@ int32_t jgs2_set_material_log_e(jgs2_solver* s, const double* log_E, const doubl
  * vertices' bandwidth-reducing order, about nVf^2 x 18 bytes
  * (JGS2_E_OOM when that does not fit), and B_i^-1 per free vertex. */
 int32_t jgs2_precompute(jgs2_solver* s, int32_t samples, int32_t n_cand, uint64_t seed);
+
+/* The exact variant's H-bar^-1 tiles after jgs2_precompute: the number of
+ * stored tiles (the lower triangle of 64 x 64-vertex tiles), the number a
+ * sweep streams under params.exact_drop, and the bytes those live tiles hold
+ * (rows past the last free vertex excluded).  Any pointer may be NULL.
+ * JGS2_E_NOT_READY without the tiles. */
+int32_t jgs2_exact_tiles(jgs2_solver* s, int64_t* n_tiles, int64_t* n_live, double* live_bytes);
 
 /* Correction tables in free-vertex order (free vertices ascending by id).
  * For free vertex f with one-ring list ring(f) = its free neighbours in

@@ -102,6 +102,7 @@ struct SweepArgs {
     float4* prow;           // [n_super * ntq * 64] row partials of H-bar^-1 h per super-tile column
     float4* pcol;           // [n_super * ntq * 64] column partials per super-tile row
     float4* yq;             // [nVf] (H-bar^-1 h)_q
+    const uint8_t* tlive;   // [n_tiles] 1: the tile is streamed (nullptr: all)
     const int* nactive;     // bodies still iterating (device count; nullptr: always run the product)
 };
 
@@ -163,6 +164,10 @@ struct jgs2_solver {
     float4* d_hvec = nullptr;              // [nVf]
     float4* d_part = nullptr;              // [2 * n_super * ntq * 64]: row, then column partials
     float4* d_yq = nullptr;                // [nVf]
+    uint8_t* d_tlive = nullptr;            // [n_tiles] live-tile flags under p.exact_drop
+    std::vector<float> tile_max;           // largest |entry| per tile, from the precompute
+    int64_t n_live = 0;
+    double live_bytes = 0.0;
     bool have_full = false;
     double* d_X64 = nullptr;               // device state I/O: FP64 rest positions [nV * 3]
     uint8_t* d_pin8 = nullptr;             // [nV]
@@ -273,6 +278,8 @@ void launch_energy(jgs2_solver* s, const SweepArgs& a, int nT);
 int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed);
 int alloc_tables(jgs2_solver* s, int S);
 int alloc_full_tables(jgs2_solver* s);
+// live-tile flags from tile_max and p.exact_drop (host, then one upload)
+int update_tile_mask(jgs2_solver* s);
 // tiles of the exact variant's H-bar^-1: side, tiles per super-tile side,
 // count over nVf positions
 constexpr int MT_Q = 64;

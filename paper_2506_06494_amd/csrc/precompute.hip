@@ -513,6 +513,22 @@ __global__ __launch_bounds__(256) void k_mtiles(const double* __restrict__ W, in
     }
 }
 
+// Largest |entry| of each stored tile (one block per tile), for the sweep's
+// live-tile flags.
+__global__ __launch_bounds__(256) void k_tile_absmax(const float* __restrict__ Mt, float* __restrict__ tmax) {
+    __shared__ float sm[256];
+    const float* T = Mt + (size_t)blockIdx.x * MT_Q * 9 * MT_Q;
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < MT_Q * 9 * MT_Q; i += 256) m = fmaxf(m, fabsf(T[i]));
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tmax[blockIdx.x] = sm[0];
+}
+
 // ---------------------------------------------------------------------------
 // 5. per-vertex correction tables and greedy NNLS cubature (one wave each)
 // ---------------------------------------------------------------------------
@@ -1410,6 +1426,17 @@ int precompute_device(jgs2_solver* s, int S, int n_cand, uint64_t seed) {
     s->fit.resize(nVf);
     PCHK(hipMemcpyAsync(s->fit.data(), dfit.p, nVf * 8, hipMemcpyDeviceToHost, st));
     PCHK(hipStreamSynchronize(st));
+    if (want_full) {
+        const size_t nt = mt_tiles(nVf);
+        DevBuf<float> dtmax;
+        if ((r = dtmax.alloc(s, nt))) return r;
+        hipLaunchKernelGGL(k_tile_absmax, dim3((unsigned)nt), dim3(256), 0, st, s->d_Mt, dtmax.p);
+        PCHK(hipGetLastError());
+        s->tile_max.resize(nt);
+        PCHK(hipMemcpyAsync(s->tile_max.data(), dtmax.p, nt * sizeof(float), hipMemcpyDeviceToHost, st));
+        PCHK(hipStreamSynchronize(st));
+        if ((r = update_tile_mask(s))) return r;
+    }
     s->S = S;
     s->have_corr = true;
     s->have_full = want_full;

@@ -33,7 +33,7 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_inc4); dfree(s->d_irec_c); dfree(s->d_incn_c); dfree(s->d_vid_c); dfree(s->d_fbody_c);
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
     dfree(s->d_Mt); dfree(s->d_Binv); dfree(s->d_qpos); dfree(s->d_qvert); dfree(s->d_qfree); dfree(s->d_hvec);
-    dfree(s->d_part); dfree(s->d_yq); s->have_full = false;
+    dfree(s->d_part); dfree(s->d_yq); dfree(s->d_tlive); s->have_full = false;
     dfree(s->d_X64); dfree(s->d_pin8); dfree(s->d_flag);
     dfree(s->d_ck_u); dfree(s->d_ck_v); dfree(s->d_seg); dfree(s->d_y); dfree(s->d_ynext); dfree(s->d_xbar);
     dfree(s->d_vbar); dfree(s->d_rhs); dfree(s->d_thbar);
@@ -85,7 +85,7 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
     a.d_hat = (float)s->p.d_hat; a.kappa = (float)s->p.kappa;
     a.fbody = s->d_fbody; a.body_on = s->d_body_on; a.one_body = s->n_bodies == 1;
     a.Mt = s->d_Mt; a.Binv = s->d_Binv; a.qpos = s->d_qpos; a.qvert = s->d_qvert; a.qfree = s->d_qfree;
-    a.hvec = s->d_hvec; a.yq = s->d_yq; a.nactive = s->d_nactive;
+    a.hvec = s->d_hvec; a.yq = s->d_yq; a.nactive = s->d_nactive; a.tlive = s->d_tlive;
     const size_t ntq_ = ((size_t)s->nVf + MT_Q - 1) / MT_Q;
     a.prow = s->d_part;
     a.pcol = s->d_part ? s->d_part + (ntq_ + MT_SG - 1) / MT_SG * ntq_ * MT_Q : nullptr;
@@ -142,7 +142,8 @@ int alloc_full_tables(jgs2_solver* s) {
     const size_t nfp = (nf + MT_Q - 1) / MT_Q * MT_Q;  // h padded to whole tiles, zero past nVf
     const size_t ntq = nfp / MT_Q, npart = (ntq + MT_SG - 1) / MT_SG * ntq * MT_Q;
     for (void** p : {(void**)&s->d_Mt, (void**)&s->d_Binv, (void**)&s->d_qpos, (void**)&s->d_qvert,
-                     (void**)&s->d_qfree, (void**)&s->d_hvec, (void**)&s->d_part, (void**)&s->d_yq}) {
+                     (void**)&s->d_qfree, (void**)&s->d_hvec, (void**)&s->d_part, (void**)&s->d_yq,
+                     (void**)&s->d_tlive}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -157,10 +158,38 @@ int alloc_full_tables(jgs2_solver* s) {
         (r = hip_check(s, hipMalloc((void**)&s->d_hvec, nfp * sizeof(float4)), "hipMalloc tables")) ||
         (r = hip_check(s, hipMalloc((void**)&s->d_part, 2 * npart * sizeof(float4)), "hipMalloc tables")) ||
         (r = hip_check(s, hipMalloc((void**)&s->d_yq, nf * sizeof(float4)), "hipMalloc tables")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_tlive, nt), "hipMalloc tables")) ||
         (r = hip_check(s, hipMemsetAsync(s->d_Mt, 0, mt_bytes, s->stream), "hipMemsetAsync tiles")) ||
         (r = hip_check(s, hipMemsetAsync(s->d_hvec, 0, nfp * sizeof(float4), s->stream), "hipMemsetAsync h")))
         return r;
     return JGS2_OK;
+}
+
+// A tile is live unless its largest |entry| is at most p.exact_drop times the
+// largest entry of H-bar^-1; its bytes are those of its rows below nVf.
+int update_tile_mask(jgs2_solver* s) {
+    const size_t nt = s->tile_max.size();
+    if (nt == 0 || !s->d_tlive) return JGS2_OK;
+    float gmax = 0.0f;
+    for (float m : s->tile_max) gmax = std::max(gmax, m);
+    const double cut = s->p.exact_drop * (double)gmax;
+    std::vector<uint8_t> live(nt);
+    s->n_live = 0;
+    s->live_bytes = 0.0;
+    const int ntq = (s->nVf + MT_Q - 1) / MT_Q;
+    for (int I = 0; I < ntq; ++I) {
+        const int rows = std::min(MT_Q, s->nVf - I * MT_Q);
+        for (int J = 0; J <= I; ++J) {
+            const size_t t = (size_t)I * (I + 1) / 2 + J;
+            live[t] = (double)s->tile_max[t] > cut ? 1 : 0;
+            if (live[t]) {
+                ++s->n_live;
+                s->live_bytes += (double)rows * 9 * MT_Q * sizeof(float);
+            }
+        }
+    }
+    drop_graphs(s);
+    return hip_check(s, hipMemcpy(s->d_tlive, live.data(), nt, hipMemcpyHostToDevice), "upload tile flags");
 }
 
 int alloc_tables(jgs2_solver* s, int S) {
@@ -247,6 +276,7 @@ static int validate_params(const jgs2_params* p, std::string& why) {
     if (p->n_planes > 0 && !(p->d_hat > 0 && p->kappa >= 0)) { why = "bad barrier parameters"; return JGS2_E_INVALID; }
     if (p->line_search && p->order != JGS2_JACOBI) { why = "the energy line search supports the Jacobi order"; return JGS2_E_INVALID; }
     if (!(p->adj_rel_tol > 0) || p->adj_max_sweeps < 0) { why = "bad adjoint solve limits"; return JGS2_E_INVALID; }
+    if (!(p->exact_drop >= 0.0 && p->exact_drop <= 1e-3)) { why = "exact_drop must be in [0, 1e-3]"; return JGS2_E_INVALID; }
     for (int i = 0; i < 3; ++i)
         if (!std::isfinite(p->gravity[i])) { why = "gravity must be finite"; return JGS2_E_INVALID; }
     return JGS2_OK;
@@ -332,6 +362,7 @@ void jgs2_default_params(jgs2_params* p) {
     p->kappa = 1e4;
     p->adj_rel_tol = 1e-5;
     p->adj_max_sweeps = 20000;
+    p->exact_drop = 1e-10;
 }
 
 int32_t jgs2_create(const jgs2_params* p, jgs2_solver** out) {
@@ -378,9 +409,13 @@ int32_t jgs2_set_params(jgs2_solver* s, const jgs2_params* p) {
     if (s->in_step && (p->dt != s->p.dt || std::memcmp(p->gravity, s->p.gravity, sizeof(p->gravity)) != 0))
         return s->fail(JGS2_E_INVALID, "dt and gravity cannot change inside a step");
     const bool dt_changed = p->dt != s->p.dt;
+    const bool drop_changed = p->exact_drop != s->p.exact_drop;
     if (p->line_search && s->n_bodies > 1)
         return s->fail(JGS2_E_INVALID, "the energy line search needs a single body");
     s->p = *p;
+    if (drop_changed && s->have_full && !dt_changed) {
+        if ((r = jgs2::update_tile_mask(s)) != JGS2_OK) return r;
+    }
     s->ro_valid = false;
     drop_graphs(s);
     // the correction's rest Hessian carries M / h^2: it belongs to the old step
@@ -388,6 +423,15 @@ int32_t jgs2_set_params(jgs2_solver* s, const jgs2_params* p) {
     if (dt_changed && s->have_material) {
         if ((r = upload_material_records(s)) != JGS2_OK) return r;
     }
+    return JGS2_OK;
+}
+
+int32_t jgs2_exact_tiles(jgs2_solver* s, int64_t* n_tiles, int64_t* n_live, double* live_bytes) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_full) return s->fail(JGS2_E_NOT_READY, "no H-bar^-1 tiles (precompute with the JGS2_EXACT variant)");
+    if (n_tiles) *n_tiles = (int64_t)s->tile_max.size();
+    if (n_live) *n_live = s->n_live;
+    if (live_bytes) *live_bytes = s->live_bytes;
     return JGS2_OK;
 }
 

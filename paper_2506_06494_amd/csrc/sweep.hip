@@ -929,6 +929,8 @@ __global__ __launch_bounds__(64 * MT_SG) void k_symv(SweepArgs a) {
         for (int j = 0; j < MT_SG; ++j) {
             const int J = MT_SG * SJ + j;
             if (J > I) break;  // upper triangle
+            const size_t tt = (size_t)I * (I + 1) / 2 + J;
+            if (a.tlive && !a.tlive[tt]) continue;  // below the drop threshold: not streamed
             float hx[4], hy[4], hz[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -937,7 +939,7 @@ __global__ __launch_bounds__(64 * MT_SG) void k_symv(SweepArgs a) {
                 hy[k] = h.y;
                 hz[k] = h.z;
             }
-            const f32x4* T4 = reinterpret_cast<const f32x4*>(a.Mt + ((size_t)I * (I + 1) / 2 + J) * MT_TILE);
+            const f32x4* T4 = reinterpret_cast<const f32x4*>(a.Mt + tt * MT_TILE);
             float cs[4][3];
 #pragma unroll
             for (int k = 0; k < 4; ++k) cs[k][0] = cs[k][1] = cs[k][2] = 0.f;
@@ -1013,7 +1015,7 @@ __global__ __launch_bounds__(64 * MT_SG) void k_symv(SweepArgs a) {
 #pragma unroll 1
         for (int ww = 0; ww < MT_SG; ++ww) {
             const int Iw = MT_SG * SI + ww;
-            if (Iw > J && Iw < ntq) {
+            if (Iw > J && Iw < ntq && (!a.tlive || a.tlive[(size_t)Iw * (Iw + 1) / 2 + J])) {
                 y0 += sCol[ww][w][0][lane];
                 y1 += sCol[ww][w][1][lane];
                 y2 += sCol[ww][w][2][lane];

@@ -28,7 +28,8 @@ class Params(C.Structure):
                 ("omega", C.c_double), ("rel_tol", C.c_double), ("max_sweeps", C.c_int32),
                 ("check_every", C.c_int32), ("d_hat", C.c_double), ("kappa", C.c_double),
                 ("n_planes", C.c_int32), ("line_search", C.c_int32), ("planes", (C.c_double * 4) * MAX_PLANES),
-                ("adj_rel_tol", C.c_double), ("adj_max_sweeps", C.c_int32), ("use_graph", C.c_int32)]
+                ("adj_rel_tol", C.c_double), ("adj_max_sweeps", C.c_int32), ("use_graph", C.c_int32),
+                ("exact_drop", C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -49,7 +50,7 @@ EXPORTS = ["jgs2_default_params", "jgs2_create", "jgs2_destroy", "jgs2_last_erro
            "jgs2_residual", "jgs2_energy", "jgs2_get_phase1", "jgs2_get_coloring", "jgs2_set_profiling",
            "jgs2_kernel_times", "jgs2_rollout", "jgs2_rollout_backward", "jgs2_set_bodies", "jgs2_get_body_stats",
            "jgs2_set_tuning", "jgs2_get_tuning", "jgs2_autotune", "jgs2_set_streaming", "jgs2_set_material_log_e",
-           "jgs2_energy_noalloc", "jgs2_set_state_device", "jgs2_get_state_device"]
+           "jgs2_energy_noalloc", "jgs2_set_state_device", "jgs2_get_state_device", "jgs2_exact_tiles"]
 
 KERNELS = ["phase1", "phase2", "plain", "commit", "reduce", "predict", "velocity", "energy", "linear", "paramgrad",
            "adjvec", "damper", "rot", "exact", "hvec", "symv", "ysum"]
@@ -82,6 +83,7 @@ def load(path: str = LIB_PATH):
         "jgs2_export_correction": (C.c_int32, [C.c_void_p, C.c_int32, d, i32, d, d, d]),
         "jgs2_get_ring_sizes": (C.c_int32, [C.c_void_p, i32, i32]),
         "jgs2_get_poses": (C.c_int32, [C.c_void_p, i32, d]),
+        "jgs2_exact_tiles": (C.c_int32, [C.c_void_p, P(C.c_int64), P(C.c_int64), d]),
         "jgs2_set_state": (C.c_int32, [C.c_void_p, d, d]),
         "jgs2_get_state": (C.c_int32, [C.c_void_p, d, d]),
         "jgs2_set_state_device": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -361,6 +363,13 @@ class Solver:
         return th, xb0, vb0, dict(status=r, steps=st.steps, adjoint_sweeps=st.adjoint_sweeps,
                                   forward_sweeps=st.forward_sweeps, max_rel_res=st.max_rel_res,
                                   seconds=st.seconds, ubar=ub)
+
+    def exact_tiles(self):
+        """Stored H-bar^-1 tiles of the exact variant, those the sweep streams
+        under exact_drop, and their bytes."""
+        nt, nl, b = C.c_int64(), C.c_int64(), C.c_double()
+        self._chk(self.lib.jgs2_exact_tiles(self.h, C.byref(nt), C.byref(nl), C.byref(b)))
+        return dict(n_tiles=nt.value, n_live=nl.value, live_bytes=b.value)
 
     def set_state_device(self, d_x, d_v):
         """d_x, d_v: device addresses (ints) of nV x 3 doubles."""

@@ -156,21 +156,31 @@ def test_full_size_exact_sweep_matches_golden(E):
     """One Jacobi sweep of the exact co-rotated subspace on the 16x16x128
     beam twisted by 0.3 rad over its length (rotations up to 0.3 rad), at 96
     sampled vertices, against the oracle's step of those vertices (their own
-    U-bar rows by FP64 band solves); the GPU computes every row on its own."""
+    U-bar rows by FP64 band solves); the GPU computes every row on its own,
+    with the default tile drop (tiles whose entries are all at most 1e-10 of
+    H-bar^-1's largest are skipped) and with every tile streamed."""
     g = load(E, "exact_jacobi")
     sc = inputs.single_beam(E)
     x0 = inputs.twisted_positions(sc.mesh, g["angle"])
     s = make_solver(sc, variant=jgs2.EXACT, order=jgs2.JACOBI)
     s.precompute(samples=4, n_cand=64, seed=0)
-    s.set_state(x0, np.zeros_like(x0))
-    s.begin_step()
-    s.iterate(1)
-    x, _ = s.get_state()
-    s.close()
     verts = np.array(g["verts"])
     dx_o = np.array(g["dx"])
-    dx_g = x[verts] - x0[verts]
-    err = np.abs(dx_g - dx_o).max()
-    print(f"E {E:g}: max |dx_gpu - dx_oracle| = {err:.3e} of max |dx| {np.abs(dx_o).max():.3e}", flush=True)
-    assert err <= 1e-5 * bbox_diag(sc.mesh.X)
-    assert err <= 2e-3 * np.abs(dx_o).max()
+    out = {}
+    for drop in (1e-10, 0.0):
+        s.set_params(exact_drop=drop)
+        tiles = s.exact_tiles()
+        s.set_state(x0, np.zeros_like(x0))
+        s.begin_step()
+        s.iterate(1)
+        x, _ = s.get_state()
+        s.end_step()
+        out[drop] = x[verts] - x0[verts]
+        err = np.abs(out[drop] - dx_o).max()
+        print(f"E {E:g} drop {drop:g}: {tiles['n_live']} of {tiles['n_tiles']} tiles streamed; "
+              f"max |dx_gpu - dx_oracle| = {err:.3e} of max |dx| {np.abs(dx_o).max():.3e}", flush=True)
+        assert err <= 1e-5 * bbox_diag(sc.mesh.X)
+        assert err <= 2e-3 * np.abs(dx_o).max()
+    s.close()
+    # the skipped tiles change the step by no more than the FP32 product's own error
+    assert np.abs(out[1e-10] - out[0.0]).max() <= 1e-5 * np.abs(dx_o).max()

@@ -29,6 +29,7 @@ int main(void) {
     F(jgs2_params, omega); F(jgs2_params, rel_tol); F(jgs2_params, max_sweeps); F(jgs2_params, check_every);
     F(jgs2_params, d_hat); F(jgs2_params, kappa); F(jgs2_params, n_planes); F(jgs2_params, line_search);
     F(jgs2_params, planes); F(jgs2_params, adj_rel_tol); F(jgs2_params, adj_max_sweeps); F(jgs2_params, use_graph);
+    F(jgs2_params, exact_drop);
     printf("jgs2_step_stats size %zu\\n", sizeof(jgs2_step_stats));
     F(jgs2_step_stats, sweeps); F(jgs2_step_stats, status); F(jgs2_step_stats, r0); F(jgs2_step_stats, r_final);
     F(jgs2_step_stats, seconds); F(jgs2_step_stats, ls_halvings); F(jgs2_step_stats, dx_norm);
