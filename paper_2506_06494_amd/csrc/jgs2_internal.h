@@ -103,6 +103,8 @@ struct SweepArgs {
     float4* pcol;           // [n_super * ntq * 64] column partials per super-tile row
     float4* yq;             // [nVf] (H-bar^-1 h)_q
     const uint8_t* tlive;   // [n_tiles] 1: the tile is streamed (nullptr: all)
+    const int* slist;       // [n_slive] super-tiles holding a live tile (nullptr: all)
+    int n_slive;
     const int* nactive;     // bodies still iterating (device count; nullptr: always run the product)
 };
 
@@ -165,6 +167,8 @@ struct jgs2_solver {
     float4* d_part = nullptr;              // [2 * n_super * ntq * 64]: row, then column partials
     float4* d_yq = nullptr;                // [nVf]
     uint8_t* d_tlive = nullptr;            // [n_tiles] live-tile flags under p.exact_drop
+    int* d_slist = nullptr;                // [n_super] live super-tiles, ascending
+    int n_slive = -1;                      // -1: every super-tile
     std::vector<float> tile_max;           // largest |entry| per tile, from the precompute
     int64_t n_live = 0;
     double live_bytes = 0.0;

@@ -33,7 +33,8 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_inc4); dfree(s->d_irec_c); dfree(s->d_incn_c); dfree(s->d_vid_c); dfree(s->d_fbody_c);
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
     dfree(s->d_Mt); dfree(s->d_Binv); dfree(s->d_qpos); dfree(s->d_qvert); dfree(s->d_qfree); dfree(s->d_hvec);
-    dfree(s->d_part); dfree(s->d_yq); dfree(s->d_tlive); s->have_full = false;
+    dfree(s->d_part); dfree(s->d_yq); dfree(s->d_tlive); dfree(s->d_slist); s->n_slive = -1;
+    s->have_full = false;
     dfree(s->d_X64); dfree(s->d_pin8); dfree(s->d_flag);
     dfree(s->d_ck_u); dfree(s->d_ck_v); dfree(s->d_seg); dfree(s->d_y); dfree(s->d_ynext); dfree(s->d_xbar);
     dfree(s->d_vbar); dfree(s->d_rhs); dfree(s->d_thbar);
@@ -86,6 +87,8 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
     a.fbody = s->d_fbody; a.body_on = s->d_body_on; a.one_body = s->n_bodies == 1;
     a.Mt = s->d_Mt; a.Binv = s->d_Binv; a.qpos = s->d_qpos; a.qvert = s->d_qvert; a.qfree = s->d_qfree;
     a.hvec = s->d_hvec; a.yq = s->d_yq; a.nactive = s->d_nactive; a.tlive = s->d_tlive;
+    a.slist = s->n_slive >= 0 ? s->d_slist : nullptr;
+    a.n_slive = s->n_slive;
     const size_t ntq_ = ((size_t)s->nVf + MT_Q - 1) / MT_Q;
     a.prow = s->d_part;
     a.pcol = s->d_part ? s->d_part + (ntq_ + MT_SG - 1) / MT_SG * ntq_ * MT_Q : nullptr;
@@ -143,11 +146,12 @@ int alloc_full_tables(jgs2_solver* s) {
     const size_t ntq = nfp / MT_Q, npart = (ntq + MT_SG - 1) / MT_SG * ntq * MT_Q;
     for (void** p : {(void**)&s->d_Mt, (void**)&s->d_Binv, (void**)&s->d_qpos, (void**)&s->d_qvert,
                      (void**)&s->d_qfree, (void**)&s->d_hvec, (void**)&s->d_part, (void**)&s->d_yq,
-                     (void**)&s->d_tlive}) {
+                     (void**)&s->d_tlive, (void**)&s->d_slist}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
     s->have_full = false;
+    s->n_slive = -1;
     int r;
     const size_t mt_bytes = nt * MT_Q * 9 * MT_Q * sizeof(float);
     if ((r = hip_check(s, hipMalloc((void**)&s->d_Mt, mt_bytes), "hipMalloc H-bar^-1 tiles")) ||
@@ -159,6 +163,8 @@ int alloc_full_tables(jgs2_solver* s) {
         (r = hip_check(s, hipMalloc((void**)&s->d_part, 2 * npart * sizeof(float4)), "hipMalloc tables")) ||
         (r = hip_check(s, hipMalloc((void**)&s->d_yq, nf * sizeof(float4)), "hipMalloc tables")) ||
         (r = hip_check(s, hipMalloc((void**)&s->d_tlive, nt), "hipMalloc tables")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_slist, (ntq + MT_SG - 1) / MT_SG * ((ntq + MT_SG - 1) / MT_SG + 1) / 2 *
+                                                             sizeof(int)), "hipMalloc tables")) ||
         (r = hip_check(s, hipMemsetAsync(s->d_Mt, 0, mt_bytes, s->stream), "hipMemsetAsync tiles")) ||
         (r = hip_check(s, hipMemsetAsync(s->d_hvec, 0, nfp * sizeof(float4), s->stream), "hipMemsetAsync h")))
         return r;
@@ -188,8 +194,28 @@ int update_tile_mask(jgs2_solver* s) {
             }
         }
     }
+    // super-tiles with at least one live tile, in launch order; the partials of
+    // the others are never written, so they are cleared here once
+    const int ns = (ntq + MT_SG - 1) / MT_SG;
+    std::vector<int> slist;
+    for (int SI = 0; SI < ns; ++SI)
+        for (int SJ = 0; SJ <= SI; ++SJ) {
+            bool any = false;
+            for (int I = MT_SG * SI; I < std::min(ntq, MT_SG * SI + MT_SG) && !any; ++I)
+                for (int J = MT_SG * SJ; J <= std::min(I, MT_SG * SJ + MT_SG - 1) && !any; ++J)
+                    any = live[(size_t)I * (I + 1) / 2 + J] != 0;
+            if (any) slist.push_back(SI * (SI + 1) / 2 + SJ);
+        }
     drop_graphs(s);
-    return hip_check(s, hipMemcpy(s->d_tlive, live.data(), nt, hipMemcpyHostToDevice), "upload tile flags");
+    int r;
+    const size_t npart = (size_t)ns * ntq * MT_Q;
+    if ((r = hip_check(s, hipMemcpy(s->d_tlive, live.data(), nt, hipMemcpyHostToDevice), "upload tile flags")) ||
+        (r = hip_check(s, hipMemcpy(s->d_slist, slist.data(), slist.size() * sizeof(int), hipMemcpyHostToDevice),
+                       "upload super-tile list")) ||
+        (r = hip_check(s, hipMemset(s->d_part, 0, 2 * npart * sizeof(float4)), "clear partials")))
+        return r;
+    s->n_slive = (int)slist.size();
+    return JGS2_OK;
 }
 
 int alloc_tables(jgs2_solver* s, int S) {

@@ -912,7 +912,7 @@ __global__ __launch_bounds__(64 * MT_SG) void k_symv(SweepArgs a) {
     // group late) changes nothing: skip its stream (uniform over the block)
     if (a.nactive && *a.nactive == 0) return;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int bt = blockIdx.x;
+    const int bt = a.slist ? a.slist[blockIdx.x] : (int)blockIdx.x;
     // bt = SI (SI + 1) / 2 + SJ, SJ <= SI
     int SI = __builtin_amdgcn_readfirstlane((int)((sqrtf(8.0f * (float)bt + 1.0f) - 1.0f) * 0.5f));
     while ((SI + 1) * (SI + 2) / 2 <= bt) ++SI;
@@ -1590,7 +1590,8 @@ void launch_reduced_gradient(jgs2_solver* s, const SweepArgs& a) {
     if (a.nVf == 0) return;
     launch(s, JGS2_K_HVEC, k_hvec, dim3((a.nVf + 255) / 256), dim3(256), a);
     const int ns = (a.nVf + MT_Q * MT_SG - 1) / (MT_Q * MT_SG);
-    launch(s, JGS2_K_SYMV, k_symv, dim3((unsigned)(ns * (ns + 1) / 2)), dim3(64 * MT_SG), a);
+    const int nb = a.slist ? a.n_slive : ns * (ns + 1) / 2;
+    if (nb > 0) launch(s, JGS2_K_SYMV, k_symv, dim3((unsigned)nb), dim3(64 * MT_SG), a);
     launch(s, JGS2_K_YSUM, k_ysum, dim3((a.nVf + MT_Q - 1) / MT_Q), dim3(256), a);
 }
 
