@@ -300,8 +300,8 @@ def main():
             per_launch = sweep_bytes("rot", **cnt)
             kname = "k_rot"
         elif dom == "symv":       # one launch per reduced gradient (per sweep, or per colour in GS)
-            per_launch = sweep_bytes("symv", **cnt,
-                                     live_bytes=results[head_mode][E0]["exact_tiles"]["live_bytes"])
+            et = results[head_mode][E0]["exact_tiles"]
+            per_launch = sweep_bytes("symv", **cnt, live_bytes=et["live_bytes"], part_bytes=et["part_bytes"])
             kname = "k_symv"
         elif dom == "exact":      # Jacobi: one launch over every row; GS: one per colour
             per_launch = sweep_bytes("exact", **cnt) * (1 if "jacobi" in head_mode else 1.0 / n_colors)
@@ -626,7 +626,8 @@ def measured_traffic(kernel, workload_tag, shape=None):
     return None
 
 
-def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches=1, live_bytes=None):
+def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches=1, live_bytes=None,
+                part_bytes=None):
     """Compulsory (algorithmic) bytes moved by one launch of a sweep kernel,
     counting every datum it must touch once: tet records 80 B (64 B without
     the id word), incidence entries 4 B or 16 B with corner ids (plus 4 B
@@ -644,13 +645,13 @@ def sweep_bytes(kind, T, n_inc, Vf, V, ring_entries=0, S=4, n_colors=1, launches
         return 64.0 * n_inc + 64.0 * Vf + 32.0 * V * n_colors
     if kind == "symv":        # the live tiles of H-bar^-1 (every stored tile unless live_bytes is given;
         q, g = 64, 8          # rows past Vf not read), 1 KB partials written: one per tile row and one
-        nt = (Vf + q - 1) // q  # per tile column of each 8 x 8 super-tile
+        nt = (Vf + q - 1) // q  # per tile column of each 8 x 8 super-tile (launched ones: part_bytes)
         ns = (nt + g - 1) // g
         rows = sum(min(q, Vf - i * q) * (i + 1) for i in range(nt))
         valid = [min(g, nt - g * k) for k in range(ns)]
         parts = sum(valid[si] + valid[sj] for si in range(ns) for sj in range(si + 1))
         tiles = 36.0 * q * rows if live_bytes is None else live_bytes
-        return tiles + 1024.0 * parts + 16.0 * Vf
+        return tiles + (1024.0 * parts if part_bytes is None else part_bytes) + 16.0 * Vf
     if kind == "exact":       # incident tets, positions, y and B^-1 per row, rotations, result
         return 96.0 * n_inc + (16.0 + 36.0 + 16.0) * Vf + 64.0 * V
     if kind == "rot":         # records and positions; row id and count read, rotation written

@@ -172,6 +172,7 @@ struct jgs2_solver {
     std::vector<float> tile_max;           // largest |entry| per tile, from the precompute
     int64_t n_live = 0;
     double live_bytes = 0.0;
+    double part_bytes = 0.0;
     bool have_full = false;
     double* d_X64 = nullptr;               // device state I/O: FP64 rest positions [nV * 3]
     uint8_t* d_pin8 = nullptr;             // [nV]

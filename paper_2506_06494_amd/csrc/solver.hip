@@ -206,6 +206,14 @@ int update_tile_mask(jgs2_solver* s) {
                     any = live[(size_t)I * (I + 1) / 2 + J] != 0;
             if (any) slist.push_back(SI * (SI + 1) / 2 + SJ);
         }
+    s->part_bytes = 0.0;
+    for (int b : slist) {
+        int SI = 0;
+        while ((SI + 1) * (SI + 2) / 2 <= b) ++SI;
+        const int SJ = b - SI * (SI + 1) / 2;
+        const int rows = std::min(MT_SG, ntq - MT_SG * SI), cols = std::min(MT_SG, ntq - MT_SG * SJ);
+        s->part_bytes += (double)(rows + cols) * MT_Q * sizeof(float4);
+    }
     drop_graphs(s);
     int r;
     const size_t npart = (size_t)ns * ntq * MT_Q;
@@ -452,12 +460,14 @@ int32_t jgs2_set_params(jgs2_solver* s, const jgs2_params* p) {
     return JGS2_OK;
 }
 
-int32_t jgs2_exact_tiles(jgs2_solver* s, int64_t* n_tiles, int64_t* n_live, double* live_bytes) {
+int32_t jgs2_exact_tiles(jgs2_solver* s, int64_t* n_tiles, int64_t* n_live, double* live_bytes,
+                         double* part_bytes) {
     if (!s) return JGS2_E_INVALID;
     if (!s->have_full) return s->fail(JGS2_E_NOT_READY, "no H-bar^-1 tiles (precompute with the JGS2_EXACT variant)");
     if (n_tiles) *n_tiles = (int64_t)s->tile_max.size();
     if (n_live) *n_live = s->n_live;
     if (live_bytes) *live_bytes = s->live_bytes;
+    if (part_bytes) *part_bytes = s->part_bytes;
     return JGS2_OK;
 }
 

@@ -83,7 +83,7 @@ def load(path: str = LIB_PATH):
         "jgs2_export_correction": (C.c_int32, [C.c_void_p, C.c_int32, d, i32, d, d, d]),
         "jgs2_get_ring_sizes": (C.c_int32, [C.c_void_p, i32, i32]),
         "jgs2_get_poses": (C.c_int32, [C.c_void_p, i32, d]),
-        "jgs2_exact_tiles": (C.c_int32, [C.c_void_p, P(C.c_int64), P(C.c_int64), d]),
+        "jgs2_exact_tiles": (C.c_int32, [C.c_void_p, P(C.c_int64), P(C.c_int64), d, d]),
         "jgs2_set_state": (C.c_int32, [C.c_void_p, d, d]),
         "jgs2_get_state": (C.c_int32, [C.c_void_p, d, d]),
         "jgs2_set_state_device": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -366,10 +366,10 @@ class Solver:
 
     def exact_tiles(self):
         """Stored H-bar^-1 tiles of the exact variant, those the sweep streams
-        under exact_drop, and their bytes."""
-        nt, nl, b = C.c_int64(), C.c_int64(), C.c_double()
-        self._chk(self.lib.jgs2_exact_tiles(self.h, C.byref(nt), C.byref(nl), C.byref(b)))
-        return dict(n_tiles=nt.value, n_live=nl.value, live_bytes=b.value)
+        under exact_drop, their bytes and the partial-sum bytes a sweep writes."""
+        nt, nl, b, pb = C.c_int64(), C.c_int64(), C.c_double(), C.c_double()
+        self._chk(self.lib.jgs2_exact_tiles(self.h, C.byref(nt), C.byref(nl), C.byref(b), C.byref(pb)))
+        return dict(n_tiles=nt.value, n_live=nl.value, live_bytes=b.value, part_bytes=pb.value)
 
     def set_state_device(self, d_x, d_v):
         """d_x, d_v: device addresses (ints) of nV x 3 doubles."""
