@@ -43,6 +43,8 @@ def parse():
                     help="launch shape (lanes per vertex x block) of the single-beam plain modes; 16x64 is what "
                          "the autotuner picks on the 16x16x128 beam on MI355X")
     ap.add_argument("--tune", action="store_true", help="run the autotuner instead of using --shape")
+    ap.add_argument("--jsonl", default=None,
+                    help="append one JSON record per timed step of every mode to this file")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every sweep kernel eagerly instead of replaying captured sweep groups (same "
                          "kernels and arguments; used for traced runs)")
@@ -226,6 +228,13 @@ def main():
                     s.set_profiling(False)
             else:
                 wall = 0.0
+            if args.jsonl:
+                with open(args.jsonl, "a") as fj:
+                    for k, r in enumerate(recs):
+                        fj.write(json.dumps(dict(mode=name, E=E, step=k, sweeps=int(r["sweeps"]),
+                                                 status=jgs2.STATUS_NAMES.get(r["status"], str(r["status"])),
+                                                 r0=r["r0"], r_final=r["r_final"], dx_norm=r.get("dx_norm"),
+                                                 device_s=r["seconds"])) + "\n")
             ok = failed is None and stalled is None and all(r["status"] == jgs2.OK for r in recs)
             status = (jgs2.STATUS_NAMES[failed["status"]] if failed else
                       "NOT_CONVERGED" if (stalled or not ok) else "OK")

@@ -34,7 +34,7 @@ def build(verbose=False):
     if failed:
         raise RuntimeError("hipcc failed")
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-lrocprofiler-sdk-roctx", "-o", tmp]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

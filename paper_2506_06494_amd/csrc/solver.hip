@@ -6,12 +6,23 @@
 #include <mutex>
 #include <numeric>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "jgs2_internal.h"
 #include "jgs2_math.h"
 
 using jgs2::KMAX;
 using jgs2::SMAX;
 using jgs2::SREC;
+
+// roctx range over a host call (visible with rocprofv3 --marker-trace; a
+// no-op without a tool attached)
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 namespace jgs2 {
 
@@ -789,6 +800,7 @@ int32_t jgs2_export_correction(jgs2_solver* s, int32_t S, double* U_ring, int32_
 }
 
 int32_t jgs2_precompute(jgs2_solver* s, int32_t samples, int32_t n_cand, uint64_t seed) {
+    TraceRange trace_range("jgs2_precompute");
     if (!s) return JGS2_E_INVALID;
     if (!s->have_mesh || !s->have_material) return s->fail(JGS2_E_NOT_READY, "no mesh or material");
     if (samples < 1 || samples > SMAX || n_cand < 1 || n_cand > 64)
@@ -1080,6 +1092,7 @@ static int energy_of(jgs2_solver* s, d4* state, double* e) {
 // Global backtracking on the incremental potential (FP64 sum of FP32
 // terms): halve the Jacobi move while E(x + t dx) > E(x), at most 8 times.
 static int line_search(jgs2_solver* s) {
+    TraceRange trace_range("jgs2_line_search");
     double e0 = 0, e1 = 0;
     int r;
     if ((r = energy_of(s, s->d_u, &e0)) || (r = energy_of(s, s->d_unext, &e1))) return r;
@@ -1190,6 +1203,7 @@ static int sweep_once(jgs2_solver* s) {
 // k sweeps followed by the residual launches (with the per-body stop
 // decision); replayed from a captured graph when use_graph is set.
 static int sweep_group(jgs2_solver* s, int k) {
+    TraceRange trace_range("jgs2_sweep_group");
     const bool graphable = s->p.use_graph && !s->prof && !s->p.line_search;
     if (!graphable) {
         for (int i = 0; i < k; ++i) {
@@ -1314,6 +1328,7 @@ static int finish_readback(jgs2_solver* s, int slot, double* rel) {
 }
 
 int32_t jgs2_step(jgs2_solver* s, jgs2_step_stats* st) {
+    TraceRange trace_range("jgs2_step");
     if (!s) return JGS2_E_INVALID;
     jgs2_step_stats loc;
     std::memset(&loc, 0, sizeof(loc));
@@ -1628,6 +1643,7 @@ static int adjoint_solve(jgs2_solver* s, const d4* xstar, int64_t* sweeps, doubl
 extern "C" {
 
 int32_t jgs2_rollout(jgs2_solver* s, int32_t n_steps, int32_t ckpt_every, jgs2_step_stats* last) {
+    TraceRange trace_range("jgs2_rollout");
     if (!s) return JGS2_E_INVALID;
     if (n_steps < 1 || ckpt_every < 1) return s->fail(JGS2_E_INVALID, "n_steps and ckpt_every must be >= 1");
     if (!ready_to_step(s)) return JGS2_E_NOT_READY;
@@ -1668,6 +1684,7 @@ int32_t jgs2_rollout(jgs2_solver* s, int32_t n_steps, int32_t ckpt_every, jgs2_s
 
 int32_t jgs2_rollout_backward(jgs2_solver* s, const double* xbar, const double* vbar, double* thetabar,
                               double* xbar0, double* vbar0, double* ubar, jgs2_adjoint_stats* stats) {
+    TraceRange trace_range("jgs2_rollout_backward");
     if (!s) return JGS2_E_INVALID;
     if (!s->ro_valid) return s->fail(JGS2_E_NOT_READY, "no rollout to differentiate");
     if (!xbar) return s->fail(JGS2_E_INVALID, "NULL xbar");
