@@ -128,6 +128,8 @@ def main():
         # over-relaxation; on the 16x16x128 beam 1.6 needs the fewest sweeps of 1.5..1.9)
         ("plain_gs_w1.5", dict(variant=jgs2.PLAIN, order=jgs2.GS, omega=1.5)),
         ("plain_gs_w1.6", dict(variant=jgs2.PLAIN, order=jgs2.GS, omega=1.6)),
+        # the same with each sweep group as one persistent cooperative launch (not a default mode)
+        ("plain_gs_w1.6_persistent", dict(variant=jgs2.PLAIN, order=jgs2.GS, omega=1.6, persistent=1)),
     ]
     wanted = args.modes.split(",")
     modes = [m for m in modes if m[0] in wanted]
@@ -143,6 +145,7 @@ def main():
         for name, cfg in modes:
             kw = dict(check_every=16)
             kw.update(cfg)
+            persistent = kw.pop("persistent", 0)
             if cfg["variant"] == jgs2.EXACT and exact_keep:
                 s = exact_keep["exact"]        # the same H-bar^-1 tiles; only the order and checks change
                 s.set_params(**{k: v for k, v in kw.items() if k != "variant"})
@@ -180,6 +183,8 @@ def main():
                 else:
                     s.import_correction(4, corr["U_ring"].reshape(-1, 9), corr["samples"], corr["weights"],
                                         corr["U_samp"])
+            if persistent:
+                s.set_persistent(True)
             s.set_state(sc.x0, sc.v0)
             tuned = None
             if cfg["variant"] == jgs2.PLAIN:
@@ -431,8 +436,23 @@ def batched_leg(n_beams=256, steps=4, loop_steps=2, max_sweeps=20000, check_ever
         conv.append(int(np.sum(rel <= 1e-5)))
         print(f"[bench] batched step {k}: {t_steps[-1]:.3f} s, {st['sweeps']} sweeps, {conv[-1]}/{n_beams} beams "
               f"converged, status {st['status']}", file=sys.stderr, flush=True)
+        if k == loop_steps - 1:
+            x_graph = s.get_state()[0]
         if st["status"] < 0:
             break
+    # the same first steps with each sweep group as one persistent cooperative launch
+    s.set_state(u.X, np.zeros_like(u.X))
+    s.set_persistent(True)
+    t_pers = []
+    for k in range(loop_steps):
+        sync()
+        t0 = time.perf_counter()
+        s.step(raise_on_error=False)
+        sync()
+        t_pers.append(time.perf_counter() - t0)
+    pers_bitwise = bool(np.array_equal(s.get_state()[0], x_graph))
+    print(f"[bench] batched persistent: {np.mean(t_pers):.3f} s/step over the first {loop_steps} steps, "
+          f"bitwise equal to the graph replay: {pers_bitwise}", file=sys.stderr, flush=True)
     s.close()
     tb = float(np.mean(t_steps[:loop_steps]))
     # per-beam launch loop: the same beams, one solver each, same parameters and tuning
@@ -458,6 +478,7 @@ def batched_leg(n_beams=256, steps=4, loop_steps=2, max_sweeps=20000, check_ever
            "steps": len(stats), "max_sweeps": max_sweeps, "omega": omega, "tuned_shape": [lpv, blk],
            "batched_s_per_step": float(np.mean(t_steps)), "batched_s_per_step_first": tb,
            "per_beam_loop_s_per_step_first": tl, "speedup_first_steps": tl / tb, "loop_steps": loop_steps,
+           "persistent_s_per_step_first": float(np.mean(t_pers)), "persistent_bitwise_equal": pers_bitwise,
            "beams_converged_per_step": conv, "all_converged_every_step": all(c == n_beams for c in conv),
            "sweeps_per_step": [st["sweeps"] for st in stats], "status": [st["status"] for st in stats],
            "roofline": roof}

@@ -189,6 +189,16 @@ int32_t jgs2_get_tuning(jgs2_solver* s, int32_t* lanes_per_vertex, int32_t* bloc
  * cache.  Results are bitwise the same in every mode.  Errors: JGS2_E_INVALID
  * for any other mode. */
 int32_t jgs2_set_streaming(jgs2_solver* s, int32_t mode);
+/* on = 1: a group of check_every coloured Gauss-Seidel sweeps of the plain
+ * variant runs as one persistent cooperative launch over every colour and
+ * sweep, its blocks (no more than the device keeps resident at once) taking
+ * the row blocks of each colour in turn with a grid-wide barrier between
+ * colours; 0 (default): one launch per colour (replayed from a captured graph
+ * with use_graph).  Results are bitwise the same.  Other variants and
+ * orders, the energy line search and profiling use the per-colour launches.
+ * Errors: JGS2_E_INVALID for another value; the launch itself reports
+ * JGS2_E_HIP if the runtime refuses it. */
+int32_t jgs2_set_persistent(jgs2_solver* s, int32_t on);
 /* Times `sweeps` sweeps of the first step from the current state in every
  * launch shape (HIP events), keeps the fastest and reports it; the state is
  * left unchanged.  ms (16 entries, may be NULL) receives each shape's time in

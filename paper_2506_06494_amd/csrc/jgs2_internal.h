@@ -223,6 +223,9 @@ struct jgs2_solver {
     // launch shape of the plain / linear sweep kernels
     int tune_lpv = 32, tune_block = 256;
     int stream_mode = -1;  // incidence records: -1 auto (> 128 MiB), 0 cached, 1 streamed
+    bool persistent = false;               // plain GS groups as one cooperative launch
+    int* d_coloff = nullptr;               // [n_colors + 1] colour offsets of the colour-ordered rows
+    int n_cus = 0;                         // compute units of the device
     // captured sweep groups (k sweeps + residual check) per Jacobi parity
     hipStream_t own_stream = nullptr;
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
@@ -266,6 +269,9 @@ void launch_exact(jgs2_solver* s, const SweepArgs& a);
 void launch_exact_linear(jgs2_solver* s, const SweepArgs& a);
 void launch_commit(jgs2_solver* s, const SweepArgs& a);
 void launch_linear(jgs2_solver* s, const SweepArgs& a);
+// k coloured GS sweeps of the plain variant in one cooperative launch (the
+// iterate kept in uprev before the last one); returns the launch's status
+int launch_plain_persistent(jgs2_solver* s, const SweepArgs& a, int k);
 void launch_param_grad(jgs2_solver* s, const d4* u, const float4* y, double* thbar);
 void launch_adj_vec(jgs2_solver* s, const float4* y, float4* xbar, float4* vbar, float4* rhs);
 void launch_norm2(jgs2_solver* s, const float4* w);

@@ -40,7 +40,7 @@ template <typename T> static void dfree(T*& p) {
 void free_device(jgs2_solver* s) {
     dfree(s->d_tet); dfree(s->d_X); dfree(s->d_u); dfree(s->d_unext); dfree(s->d_uhat); dfree(s->d_vhat);
     dfree(s->d_zu); dfree(s->d_mh2); dfree(s->d_g); dfree(s->d_R); dfree(s->d_free); dfree(s->d_inc);
-    dfree(s->d_inc_n); dfree(s->d_ring); dfree(s->d_ring_n); dfree(s->d_incslot); dfree(s->d_colperm);
+    dfree(s->d_inc_n); dfree(s->d_ring); dfree(s->d_ring_n); dfree(s->d_incslot); dfree(s->d_colperm); dfree(s->d_coloff);
     dfree(s->d_inc4); dfree(s->d_irec_c); dfree(s->d_incn_c); dfree(s->d_vid_c); dfree(s->d_fbody_c);
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
     dfree(s->d_Mt); dfree(s->d_Binv); dfree(s->d_qpos); dfree(s->d_qvert); dfree(s->d_qfree); dfree(s->d_hvec);
@@ -626,7 +626,8 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
         (r = dalloc(s, s->d_incslot, nf * s->maxi)) || (r = dalloc(s, s->d_inc_n, nf)) ||
         (r = dalloc(s, s->d_ring, nf * s->K)) || (r = dalloc(s, s->d_ring_n, nf)) ||
         (r = dalloc(s, s->d_colperm, nf)) || (r = dalloc(s, s->d_tet, (size_t)nT * TET_F4)) ||
-        (r = dalloc(s, s->d_inc4, nf * s->maxi)) || (r = dalloc(s, s->d_uprev, V4)))
+        (r = dalloc(s, s->d_inc4, nf * s->maxi)) || (r = dalloc(s, s->d_uprev, V4)) ||
+        (r = dalloc(s, s->d_coloff, (size_t)s->n_colors + 1)))
         return r;
     s->n_partial = std::max<int>((s->nVf + 1) / 2, (std::max(nT, s->nVf) + 255) / 256) + 1;
     if ((r = dalloc(s, s->d_partial, (size_t)s->n_partial)) || (r = dalloc(s, s->d_red, 4))) return r;
@@ -637,7 +638,8 @@ int32_t jgs2_upload_mesh(jgs2_solver* s, int32_t nV, const double* X, int32_t nT
         (r = upload(s, s->d_free, s->free_ids.data(), nf)) || (r = upload(s, s->d_inc, s->inc.data(), nf * s->maxi)) ||
         (r = upload(s, s->d_incslot, s->incslot.data(), nf * s->maxi)) || (r = upload(s, s->d_inc_n, s->inc_n.data(), nf)) ||
         (r = upload(s, s->d_ring, s->ring.data(), nf * s->K)) || (r = upload(s, s->d_ring_n, s->ring_n.data(), nf)) ||
-        (r = upload(s, s->d_colperm, s->col_perm.data(), nf)) || (r = upload(s, s->d_inc4, s->inc4.data(), nf * s->maxi)))
+        (r = upload(s, s->d_colperm, s->col_perm.data(), nf)) || (r = upload(s, s->d_inc4, s->inc4.data(), nf * s->maxi)) ||
+        (r = upload(s, s->d_coloff, s->col_off.data(), (size_t)s->n_colors + 1)))
         return r;
     {
         std::vector<int> incnc(nf), vidc(nf);
@@ -1204,6 +1206,18 @@ static int sweep_once(jgs2_solver* s) {
 // decision); replayed from a captured graph when use_graph is set.
 static int sweep_group(jgs2_solver* s, int k) {
     TraceRange trace_range("jgs2_sweep_group");
+    if (s->persistent && s->p.variant == JGS2_PLAIN && s->p.order == JGS2_GS && !s->p.line_search && !s->prof) {
+        // the whole group as one cooperative launch, then the residual check
+        SweepArgs a;
+        build_sweep_args(s, a);
+        a.in_place = 1;
+        int r = launch_plain_persistent(s, a, k);
+        if (r != JGS2_OK) return r;
+        residual_launches(s, k);
+        s->sweeps_in_step += k;
+        s->phase1_valid = false;
+        return jgs2::hip_check(s, hipGetLastError(), "sweep launch");
+    }
     const bool graphable = s->p.use_graph && !s->prof && !s->p.line_search;
     if (!graphable) {
         for (int i = 0; i < k; ++i) {
@@ -1908,6 +1922,19 @@ int32_t jgs2_set_tuning(jgs2_solver* s, int32_t lanes_per_vertex, int32_t block)
     if (!valid_shape(lanes_per_vertex, block)) return s->fail(JGS2_E_INVALID, "unsupported launch shape");
     s->tune_lpv = lanes_per_vertex;
     s->tune_block = block;
+    drop_graphs(s);
+    return JGS2_OK;
+}
+
+int32_t jgs2_set_persistent(jgs2_solver* s, int32_t on) {
+    if (!s) return JGS2_E_INVALID;
+    if (on != 0 && on != 1) return s->fail(JGS2_E_INVALID, "persistent must be 0 or 1");
+    if (on && s->n_cus == 0) {
+        int r = hip_check(s, hipDeviceGetAttribute(&s->n_cus, hipDeviceAttributeMultiprocessorCount, s->device),
+                          "compute unit count");
+        if (r != JGS2_OK) return r;
+    }
+    s->persistent = on != 0;
     drop_graphs(s);
     return JGS2_OK;
 }

@@ -15,6 +15,8 @@
 // rotation as a unit quaternion.
 #include <hip/hip_ext.h>
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "jgs2_internal.h"
 #include "jgs2_math.h"
 
@@ -653,18 +655,17 @@ __device__ __forceinline__ void damper_sample_quad(const SweepArgs& a, int e, in
 // R_a Ubar_{i,a} R_i^T over the row's cubature samples, b_i = g_i; each
 // sample goes to one quad of the row's lanes (W / 4 samples per round),
 // rotations are those of the last rotation (or phase-1) pass.
+// Rows blk * NV .. blk * NV + NV - 1 of the range [cbase, cbase + nidx) (rows
+// in colour order: a colour is a contiguous range, a Jacobi sweep the whole
+// range, so no list is read before the rows).
 template <bool LIN, int W, int BLK, bool SPEC, bool NT, bool DAMP = false>
-__device__ __forceinline__ void plain_body(const SweepArgs& a) {
+__device__ __forceinline__ void plain_body(const SweepArgs& a, int blk, int cbase, int nidx) {
     constexpr int NV = BLK / W;
     const int lane = threadIdx.x % W;
     const int vloc = threadIdx.x / W;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    // rows in colour order: a colour is the contiguous range [cbase, cbase + n),
-    // a Jacobi sweep the whole range, so no list is read before the rows
     const int idx = blk * NV + vloc;
-    const int nidx = a.list ? a.n_list : a.nVf;
     const bool in_range = idx < nidx;
-    const int q = in_range ? a.cbase + idx : 0;
+    const int q = in_range ? cbase + idx : 0;
     // Everything that needs only the row index is fetched up front and
     // without branches (q is a valid row even out of range; rows are padded
     // to maxi entries): the row's count, this lane's first incidence record
@@ -771,12 +772,50 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a) {
     if (a.no_write) block_partial_t<NV, W>(gsq, active && lane == 0, a.partial);  // uniform branch
 }
 
+#define PLAIN_ROWS(a) xcd_remap(blockIdx.x, gridDim.x), (a).cbase, (a).list ? (a).n_list : (a).nVf
 template <int W, int BLK, bool SPEC, bool NT>
-__global__ __launch_bounds__(BLK) void k_plain(SweepArgs a) { plain_body<false, W, BLK, SPEC, NT>(a); }
+__global__ __launch_bounds__(BLK) void k_plain(SweepArgs a) { plain_body<false, W, BLK, SPEC, NT>(a, PLAIN_ROWS(a)); }
 template <int W, int BLK, bool SPEC, bool NT>
-__global__ __launch_bounds__(BLK) void k_damper(SweepArgs a) { plain_body<false, W, BLK, SPEC, NT, true>(a); }
+__global__ __launch_bounds__(BLK) void k_damper(SweepArgs a) {
+    plain_body<false, W, BLK, SPEC, NT, true>(a, PLAIN_ROWS(a));
+}
 template <int W, int BLK, bool NT>
-__global__ __launch_bounds__(BLK) void k_linear(SweepArgs a) { plain_body<true, W, BLK, true, NT>(a); }
+__global__ __launch_bounds__(BLK) void k_linear(SweepArgs a) { plain_body<true, W, BLK, true, NT>(a, PLAIN_ROWS(a)); }
+#undef PLAIN_ROWS
+
+// A whole group of k coloured Gauss-Seidel sweeps (plain variant, forward) in
+// one cooperative launch: every block walks the row blocks of colour c
+// (block b takes b, b + gridDim, ...), then the grid waits at a barrier
+// before colour c + 1; before the group's last sweep the grid keeps the
+// iterate for the |dx| check.  The launch holds no more blocks than the
+// device keeps resident at once (the runtime refuses a larger cooperative
+// launch), and every block reaches every barrier: the loops are uniform and
+// plain_body has no early exit.  The same rows see the same arithmetic as in
+// one launch per colour, so the result is bitwise that of those launches.
+template <int W, int BLK, bool SPEC, bool NT>
+__global__ __launch_bounds__(BLK) void k_plain_persistent(SweepArgs a, int k, const int* __restrict__ col_off,
+                                                           int n_colors, d4* __restrict__ uprev) {
+    constexpr int NV = BLK / W;
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    // blocks are dealt to the 8 XCDs in turn (block i on XCD i % 8): each XCD's
+    // blocks take a contiguous eighth of a colour's row blocks, as xcd_remap
+    // gives a one-launch-per-colour grid (the grid is a multiple of 8)
+    const int xcd = blockIdx.x & 7, rank = blockIdx.x >> 3, per = gridDim.x >> 3;
+    for (int it = 0; it < k; ++it) {
+        if (it == k - 1) {
+            for (int i = blockIdx.x * BLK + threadIdx.x; i < a.nV; i += gridDim.x * BLK) uprev[i] = a.u[i];
+            grid.sync();
+        }
+        for (int c = 0; c < n_colors; ++c) {
+            const int c0 = col_off[c], n = col_off[c + 1] - c0;
+            const int nb = (n + NV - 1) / NV;
+            const int q = nb >> 3, r = nb & 7;
+            const int lo = xcd * q + min(xcd, r), hi = lo + q + (xcd < r ? 1 : 0);
+            for (int b = lo + rank; b < hi; b += per) plain_body<false, W, BLK, SPEC, NT>(a, b, c0, n);
+            grid.sync();
+        }
+    }
+}
 
 // Per-vertex rotations alone (Sec. 4.3): R_a is the polar rotation of the
 // volume-weighted mean deformation gradient of a's incident tets, the same
@@ -1580,6 +1619,42 @@ static void launch_plain_any(jgs2_solver* s, const SweepArgs& a) {
 }
 
 void launch_plain(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<0>(s, a); }
+
+// Grid: the resident block count (occupancy x compute units), or fewer when
+// the largest colour has fewer row blocks.  The block is 256 threads whatever
+// the tuned block size (rows are independent: the result does not depend on
+// it), the lanes per vertex are the tuned ones (they fix the summation order).
+template <int W>
+static int launch_persistent_w(jgs2_solver* s, const SweepArgs& a, int k) {
+    constexpr int BLK = 256, NV = BLK / W;
+    void (*kern)(SweepArgs, int, const int*, int, d4*) =
+        a.one_body ? (a.nt_records ? k_plain_persistent<W, BLK, true, true> : k_plain_persistent<W, BLK, true, false>)
+                   : (a.nt_records ? k_plain_persistent<W, BLK, false, true> : k_plain_persistent<W, BLK, false, false>);
+    int per_cu = 0;
+    int r = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, BLK, 0),
+                      "persistent occupancy");
+    if (r != JGS2_OK) return r;
+    int most = 0;
+    for (int c = 0; c < s->n_colors; ++c) most = std::max(most, s->col_off[c + 1] - s->col_off[c]);
+    // a multiple of 8 (one share per XCD), at least 8
+    const int grid = std::max(8, std::min(per_cu * s->n_cus, (most + NV - 1) / NV) / 8 * 8);
+    SweepArgs aa = a;
+    int kk = k, nc = s->n_colors;
+    const int* co = s->d_coloff;
+    d4* up = s->d_uprev;
+    void* args[] = {(void*)&aa, (void*)&kk, (void*)&co, (void*)&nc, (void*)&up};
+    return hip_check(s, hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(BLK), args, 0, s->stream),
+                     "persistent cooperative launch");
+}
+
+int launch_plain_persistent(jgs2_solver* s, const SweepArgs& a, int k) {
+    switch (s->tune_lpv) {
+        case 4: return launch_persistent_w<4>(s, a, k);
+        case 8: return launch_persistent_w<8>(s, a, k);
+        case 16: return launch_persistent_w<16>(s, a, k);
+        default: return launch_persistent_w<32>(s, a, k);
+    }
+}
 
 void launch_linear(jgs2_solver* s, const SweepArgs& a) { launch_plain_any<1>(s, a); }
 

@@ -50,7 +50,7 @@ EXPORTS = ["jgs2_default_params", "jgs2_create", "jgs2_destroy", "jgs2_last_erro
            "jgs2_residual", "jgs2_energy", "jgs2_get_phase1", "jgs2_get_coloring", "jgs2_set_profiling",
            "jgs2_kernel_times", "jgs2_rollout", "jgs2_rollout_backward", "jgs2_set_bodies", "jgs2_get_body_stats",
            "jgs2_set_tuning", "jgs2_get_tuning", "jgs2_autotune", "jgs2_set_streaming", "jgs2_set_material_log_e",
-           "jgs2_energy_noalloc", "jgs2_set_state_device", "jgs2_get_state_device", "jgs2_exact_tiles"]
+           "jgs2_energy_noalloc", "jgs2_set_state_device", "jgs2_get_state_device", "jgs2_exact_tiles", "jgs2_set_persistent"]
 
 KERNELS = ["phase1", "phase2", "plain", "commit", "reduce", "predict", "velocity", "energy", "linear", "paramgrad",
            "adjvec", "damper", "rot", "exact", "hvec", "symv", "ysum"]
@@ -84,6 +84,7 @@ def load(path: str = LIB_PATH):
         "jgs2_get_ring_sizes": (C.c_int32, [C.c_void_p, i32, i32]),
         "jgs2_get_poses": (C.c_int32, [C.c_void_p, i32, d]),
         "jgs2_exact_tiles": (C.c_int32, [C.c_void_p, P(C.c_int64), P(C.c_int64), d, d]),
+        "jgs2_set_persistent": (C.c_int32, [C.c_void_p, C.c_int32]),
         "jgs2_set_state": (C.c_int32, [C.c_void_p, d, d]),
         "jgs2_get_state": (C.c_int32, [C.c_void_p, d, d]),
         "jgs2_set_state_device": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -363,6 +364,10 @@ class Solver:
         return th, xb0, vb0, dict(status=r, steps=st.steps, adjoint_sweeps=st.adjoint_sweeps,
                                   forward_sweeps=st.forward_sweeps, max_rel_res=st.max_rel_res,
                                   seconds=st.seconds, ubar=ub)
+
+    def set_persistent(self, on=True):
+        """Coloured GS groups of the plain variant as one cooperative launch."""
+        self._chk(self.lib.jgs2_set_persistent(self.h, int(on)))
 
     def exact_tiles(self):
         """Stored H-bar^-1 tiles of the exact variant, those the sweep streams

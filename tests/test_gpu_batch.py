@@ -155,3 +155,32 @@ def test_streamed_records_are_bitwise_cached(bodies):
         assert np.array_equal(x, x0) and np.array_equal(v, v0) and sw == sw0
     with pytest.raises(jgs2.JGS2Error):
         s.set_streaming(2)
+
+
+@pytest.mark.parametrize("bodies,lpv", [(False, 16), (True, 8), (True, 32)])
+def test_persistent_gs_is_bitwise_the_per_colour_launches(bodies, lpv):
+    """Coloured GS groups as one cooperative launch (grid barriers between
+    colours) give bit for bit the per-colour launches (captured graphs), for
+    one body and for batched bodies that stop at different sweep counts, in
+    several lane counts per vertex; the sweeps per body agree too."""
+    parts = beam_parts()
+    out = []
+    for persistent in (False, True):
+        if bodies:
+            s, _ = batched(parts, order=jgs2.GS, omega=1.5, use_graph=1)
+        else:
+            m, E, nu, v0 = parts[0]
+            s = solver_for(m, E, nu, order=jgs2.GS, omega=1.5, use_graph=1)
+            s.set_state(m.X, v0)
+        s.set_tuning(lpv, 256)
+        s.set_persistent(persistent)
+        stats = [s.step() for _ in range(2)]
+        sweeps = s.body_stats()[0] if bodies else None
+        out.append((s.get_state(), [st["sweeps"] for st in stats], sweeps))
+    (x0, v0), sw0, b0 = out[0]
+    (x1, v1), sw1, b1 = out[1]
+    assert np.array_equal(x1, x0) and np.array_equal(v1, v0) and sw1 == sw0
+    if bodies:
+        assert np.array_equal(b1, b0)
+    with pytest.raises(jgs2.JGS2Error):
+        s.set_persistent(2)
