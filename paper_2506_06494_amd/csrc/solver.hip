@@ -1226,6 +1226,9 @@ static int sweep_group(jgs2_solver* s, int k) {
             if (r != JGS2_OK) return r;
         }
         residual_launches(s, k);
+        // the check's phase 1 left g (and, for the corrected variants, R) at
+        // the iterate the next sweep starts from
+        s->phase1_valid = s->p.variant != JGS2_PLAIN;
         return jgs2::hip_check(s, hipGetLastError(), "sweep launch");
     }
     // a Jacobi group of odd length leaves u and unext swapped: graphs are
