@@ -198,3 +198,50 @@ def test_exact_sweep_with_indefinite_local_systems_matches_oracle(tiny, tiny_exa
                   f"|dx_gpu - dx_oracle| {np.linalg.norm(dg - do):.3e}", flush=True)
         assert np.all(np.isfinite(dg)) and np.linalg.norm(dg - do) <= tol, (v, kappa, dg, do)
     print(f"{len(shifted)} shifted systems; worst error / tolerance {worst:.3f}", flush=True)
+
+
+def test_exact_batched_bodies_match_the_single_solves():
+    """Three beams of different size and stiffness uploaded as one mesh with
+    their own bodies, exact Jacobi, two steps: the rest Hessian is block
+    diagonal, so every tile coupling two bodies is exactly zero and is not
+    streamed even with exact_drop 0; each body's steps match the body solved
+    alone to FP32 summation order (the tiles group the sums differently) and
+    take the same sweeps within one."""
+    specs = [(16, 4, 4, 1e5, 0.45), (12, 3, 5, 1e6, 0.40), (10, 4, 3, 1e8, 0.45)]
+    meshes, Es, nus, v0s = [], [], [], []
+    for (L, a, b, E, nu) in specs:
+        m = inputs.beam_mesh(L, a, b, 0.05)
+        meshes.append(m)
+        Es.append(np.full(m.nT, E))
+        nus.append(np.full(m.nT, nu))
+        v0s.append(inputs.twist_velocity(m, 2.0))
+    u = inputs.concat_meshes(meshes)
+    kw = dict(variant=jgs2.EXACT, order=jgs2.JACOBI, rel_tol=1e-5, check_every=1, max_sweeps=40, exact_drop=0.0)
+    s = jgs2.Solver(**kw)
+    s.upload_mesh(u.X, u.tets, u.pinned)
+    s.set_material(np.concatenate(Es), np.concatenate(nus), 1000.0)
+    s.set_bodies(u.body)
+    s.precompute(samples=4, n_cand=64, seed=0)
+    tiles = s.exact_tiles()
+    assert tiles["n_live"] < tiles["n_tiles"], tiles
+    s.set_state(u.X, np.concatenate(v0s))
+    for _ in range(2):
+        s.step()
+    xb, _ = s.get_state()
+    sweeps_b, _ = s.body_stats()
+    off = np.concatenate([[0], np.cumsum([m.nV for m in meshes])])
+    for k, m in enumerate(meshes):
+        s1 = jgs2.Solver(**kw)
+        s1.upload_mesh(m.X, m.tets, m.pinned)
+        s1.set_material(Es[k], nus[k], 1000.0)
+        s1.precompute(samples=4, n_cand=64, seed=0)
+        s1.set_state(m.X, v0s[k])
+        for _ in range(2):
+            st1 = s1.step()
+        x1, _ = s1.get_state()
+        err = np.abs(xb[off[k]:off[k + 1]] - x1).max()
+        print(f"body {k}: {sweeps_b[k]} / {st1['sweeps']} sweeps (batched / alone), max |dx| {err:.3e}", flush=True)
+        assert err <= 1e-6 * bbox_diag(m.X)
+        assert abs(int(sweeps_b[k]) - int(st1["sweeps"])) <= 1
+        s1.close()
+    s.close()
