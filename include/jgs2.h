@@ -227,6 +227,18 @@ int32_t jgs2_set_material_log_e(jgs2_solver* s, const double* log_E, const doubl
  * vertices' bandwidth-reducing order, about nVf^2 x 18 bytes
  * (JGS2_E_OOM when that does not fit), and B_i^-1 per free vertex. */
 int32_t jgs2_precompute(jgs2_solver* s, int32_t samples, int32_t n_cand, uint64_t seed);
+/* The same with a cache file at `path` (NULL: plain jgs2_precompute).  If the
+ * file holds this library build's precompute for the same mesh, pinning,
+ * material, dt, variant (exact or not), samples, n_cand and seed (a 64-bit
+ * hash of all of them and sizes are checked), the tables are loaded from it
+ * and *loaded = 1 (may be NULL); otherwise the precompute runs and the file
+ * is written (through a temporary file renamed at the end), *loaded = 0.
+ * For the exact variant the file holds every stored H-bar^-1 tile (about
+ * nVf^2 x 18 bytes).  JGS2_E_INVALID if the file cannot be written (the
+ * tables are still computed) or a matching file is truncated (the handle is
+ * then left without tables). */
+int32_t jgs2_precompute_cached(jgs2_solver* s, int32_t samples, int32_t n_cand, uint64_t seed, const char* path,
+                               int32_t* loaded);
 
 /* The exact variant's H-bar^-1 tiles after jgs2_precompute: the number of
  * stored tiles (the lower triangle of 64 x 64-vertex tiles), the number a

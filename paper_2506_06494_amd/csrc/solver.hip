@@ -2,7 +2,9 @@
 // time-step driver and the C ABI declared in include/jgs2.h.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <mutex>
 #include <numeric>
 
@@ -705,6 +707,182 @@ int32_t jgs2_get_ring_sizes(jgs2_solver* s, int32_t* nVf, int32_t* sizes) {
     if (nVf) *nVf = s->nVf;
     if (sizes) std::copy(s->ring_n.begin(), s->ring_n.end(), sizes);
     return JGS2_OK;
+}
+
+// ---- precompute cache file ----
+// Layout: a header (format tag, a 64-bit FNV-1a key over everything the
+// precompute depends on, sizes), then the pose eigenvalues, the NNLS fits,
+// the one-ring U-bar rows, the sample ids and records, and for the exact
+// variant B^-1, the position tables, the tile maxima and every stored tile.
+// The key includes this library build's date and time, so a rebuilt library
+// never reads an older build's file.
+namespace {
+struct CacheHeader {
+    char tag[8];
+    uint64_t key;
+    int32_t nV, nT, nVf, K, S, exact, n_poses, n_eigs;
+    int64_t n_tiles;
+};
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+uint64_t cache_key(const jgs2_solver* s, int S, int n_cand, uint64_t seed) {
+    static const char build[] = __DATE__ " " __TIME__;
+    uint64_t h = 1469598103934665603ull;
+    h = fnv1a(h, build, sizeof(build));
+    h = fnv1a(h, s->X.data(), s->X.size() * sizeof(double));
+    h = fnv1a(h, s->tets.data(), s->tets.size() * sizeof(int));
+    h = fnv1a(h, s->pinned.data(), s->pinned.size());
+    h = fnv1a(h, s->E.data(), s->E.size() * sizeof(double));
+    h = fnv1a(h, s->nu.data(), s->nu.size() * sizeof(double));
+    h = fnv1a(h, s->rho.data(), s->rho.size() * sizeof(double));
+    const int exact = s->p.variant == JGS2_EXACT;
+    h = fnv1a(h, &s->p.dt, sizeof(double));
+    h = fnv1a(h, &S, sizeof(S));
+    h = fnv1a(h, &n_cand, sizeof(n_cand));
+    h = fnv1a(h, &seed, sizeof(seed));
+    return fnv1a(h, &exact, sizeof(exact));
+}
+
+constexpr size_t CACHE_CHUNK = (size_t)64 << 20;  // staging bytes per copy
+
+bool put(FILE* f, const void* p, size_t n) { return n == 0 || std::fwrite(p, 1, n, f) == n; }
+bool get(FILE* f, void* p, size_t n) { return n == 0 || std::fread(p, 1, n, f) == n; }
+
+// Device buffer <-> file through one host staging buffer, chunk by chunk.
+bool put_dev(FILE* f, const void* d, size_t n, std::vector<char>& stage) {
+    for (size_t o = 0; o < n; o += CACHE_CHUNK) {
+        const size_t m = std::min(CACHE_CHUNK, n - o);
+        if (hipMemcpy(stage.data(), static_cast<const char*>(d) + o, m, hipMemcpyDeviceToHost) != hipSuccess ||
+            !put(f, stage.data(), m))
+            return false;
+    }
+    return true;
+}
+
+bool get_dev(FILE* f, void* d, size_t n, std::vector<char>& stage) {
+    for (size_t o = 0; o < n; o += CACHE_CHUNK) {
+        const size_t m = std::min(CACHE_CHUNK, n - o);
+        if (!get(f, stage.data(), m) ||
+            hipMemcpy(static_cast<char*>(d) + o, stage.data(), m, hipMemcpyHostToDevice) != hipSuccess)
+            return false;
+    }
+    return true;
+}
+
+size_t tile_floats(const jgs2_solver* s) { return jgs2::mt_tiles(s->nVf) * jgs2::MT_Q * 9 * jgs2::MT_Q; }
+
+int write_cache(jgs2_solver* s, const char* path, int n_cand, uint64_t seed) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return s->fail(JGS2_E_INVALID, "cannot write the precompute cache");
+    (void)hipStreamSynchronize(s->stream);
+    const size_t nf = s->nVf, S = s->S, K = s->K;
+    CacheHeader hd;
+    std::memset(&hd, 0, sizeof(hd));
+    std::memcpy(hd.tag, "JGS2PC01", 8);
+    hd.key = cache_key(s, s->S, n_cand, seed);
+    hd.nV = s->nV; hd.nT = s->nT; hd.nVf = s->nVf; hd.K = s->K; hd.S = s->S;
+    hd.exact = s->have_full; hd.n_poses = s->n_poses; hd.n_eigs = (int32_t)s->pose_eigs.size();
+    hd.n_tiles = s->have_full ? (int64_t)s->tile_max.size() : 0;
+    std::vector<char> stage(CACHE_CHUNK);
+    bool ok = put(f, &hd, sizeof(hd)) && put(f, s->pose_eigs.data(), s->pose_eigs.size() * sizeof(double)) &&
+              put(f, s->fit.data(), nf * sizeof(double)) &&
+              put_dev(f, s->d_Uring, nf * 9 * K * sizeof(float), stage) &&
+              put_dev(f, s->d_samp_e, nf * S * sizeof(int), stage) &&
+              put_dev(f, s->d_samp, nf * jgs2::SREC * S * sizeof(float), stage);
+    if (ok && s->have_full)
+        ok = put_dev(f, s->d_Binv, nf * 9 * sizeof(float), stage) &&
+             put_dev(f, s->d_qpos, (size_t)s->nV * sizeof(int), stage) &&
+             put_dev(f, s->d_qvert, nf * sizeof(int), stage) && put_dev(f, s->d_qfree, nf * sizeof(int), stage) &&
+             put(f, s->tile_max.data(), s->tile_max.size() * sizeof(float)) &&
+             put_dev(f, s->d_Mt, tile_floats(s) * sizeof(float), stage);
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        (void)std::remove(tmp.c_str());
+        return s->fail(JGS2_E_INVALID, "cannot write the precompute cache");
+    }
+    return JGS2_OK;
+}
+
+// 1: loaded; 0: no file or not this precompute's (nothing changed); < 0: a
+// read error after the handle's tables were replaced (they are invalid).
+int read_cache(jgs2_solver* s, const char* path, int S, int n_cand, uint64_t seed) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return 0;
+    CacheHeader hd;
+    const bool exact = s->p.variant == JGS2_EXACT;
+    if (!get(f, &hd, sizeof(hd)) || std::memcmp(hd.tag, "JGS2PC01", 8) != 0 ||
+        hd.key != cache_key(s, S, n_cand, seed) || hd.nV != s->nV || hd.nT != s->nT || hd.nVf != s->nVf ||
+        hd.K != s->K || hd.S != S || hd.exact != (exact ? 1 : 0) || hd.n_eigs < 0 ||
+        (exact && hd.n_tiles != (int64_t)jgs2::mt_tiles(s->nVf))) {
+        std::fclose(f);
+        return 0;
+    }
+    s->have_corr = s->have_full = false;
+    const size_t nf = s->nVf, K = s->K;
+    int r;
+    if ((r = jgs2::alloc_tables(s, S)) != JGS2_OK || (exact && (r = jgs2::alloc_full_tables(s)) != JGS2_OK)) {
+        std::fclose(f);
+        return r;
+    }
+    (void)hipStreamSynchronize(s->stream);
+    std::vector<char> stage(CACHE_CHUNK);
+    s->pose_eigs.assign(hd.n_eigs, 0.0);
+    s->fit.assign(nf, 0.0);
+    bool ok = get(f, s->pose_eigs.data(), s->pose_eigs.size() * sizeof(double)) &&
+              get(f, s->fit.data(), nf * sizeof(double)) &&
+              get_dev(f, s->d_Uring, nf * 9 * K * sizeof(float), stage) &&
+              get_dev(f, s->d_samp_e, nf * S * sizeof(int), stage) &&
+              get_dev(f, s->d_samp, nf * jgs2::SREC * S * sizeof(float), stage);
+    if (ok && exact) {
+        s->tile_max.assign(hd.n_tiles, 0.0f);
+        ok = get_dev(f, s->d_Binv, nf * 9 * sizeof(float), stage) &&
+             get_dev(f, s->d_qpos, (size_t)s->nV * sizeof(int), stage) &&
+             get_dev(f, s->d_qvert, nf * sizeof(int), stage) && get_dev(f, s->d_qfree, nf * sizeof(int), stage) &&
+             get(f, s->tile_max.data(), s->tile_max.size() * sizeof(float)) &&
+             get_dev(f, s->d_Mt, tile_floats(s) * sizeof(float), stage);
+    }
+    std::fclose(f);
+    if (!ok) return s->fail(JGS2_E_INVALID, "the precompute cache is truncated or unreadable");
+    s->S = S;
+    s->n_poses = hd.n_poses;
+    s->have_corr = true;
+    if (exact) {
+        s->have_full = true;
+        if ((r = jgs2::update_tile_mask(s)) != JGS2_OK) {
+            s->have_full = false;
+            return r;
+        }
+    }
+    return 1;
+}
+}  // namespace
+
+int32_t jgs2_precompute_cached(jgs2_solver* s, int32_t samples, int32_t n_cand, uint64_t seed, const char* path,
+                               int32_t* loaded) {
+    if (!s) return JGS2_E_INVALID;
+    if (loaded) *loaded = 0;
+    if (!path) return jgs2_precompute(s, samples, n_cand, seed);
+    if (!s->have_mesh || !s->have_material) return s->fail(JGS2_E_NOT_READY, "no mesh or material");
+    if (samples < 1 || samples > SMAX || n_cand < 1 || n_cand > 64)
+        return s->fail(JGS2_E_INVALID, "samples in [1,8] and candidates in [1,64] required");
+    TraceRange trace_range("jgs2_precompute_cached");
+    int r = read_cache(s, path, samples, n_cand, seed);
+    if (r < 0) return r;
+    if (r == 1) {
+        if (loaded) *loaded = 1;
+        return JGS2_OK;
+    }
+    if ((r = jgs2_precompute(s, samples, n_cand, seed)) != JGS2_OK) return r;
+    return write_cache(s, path, n_cand, seed);
 }
 
 int32_t jgs2_get_poses(jgs2_solver* s, int32_t* n_poses, double* eigenvalues) {

@@ -50,7 +50,7 @@ EXPORTS = ["jgs2_default_params", "jgs2_create", "jgs2_destroy", "jgs2_last_erro
            "jgs2_residual", "jgs2_energy", "jgs2_get_phase1", "jgs2_get_coloring", "jgs2_set_profiling",
            "jgs2_kernel_times", "jgs2_rollout", "jgs2_rollout_backward", "jgs2_set_bodies", "jgs2_get_body_stats",
            "jgs2_set_tuning", "jgs2_get_tuning", "jgs2_autotune", "jgs2_set_streaming", "jgs2_set_material_log_e",
-           "jgs2_energy_noalloc", "jgs2_set_state_device", "jgs2_get_state_device", "jgs2_exact_tiles", "jgs2_set_persistent"]
+           "jgs2_energy_noalloc", "jgs2_set_state_device", "jgs2_get_state_device", "jgs2_exact_tiles", "jgs2_set_persistent", "jgs2_precompute_cached"]
 
 KERNELS = ["phase1", "phase2", "plain", "commit", "reduce", "predict", "velocity", "energy", "linear", "paramgrad",
            "adjvec", "damper", "rot", "exact", "hvec", "symv", "ysum"]
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
         "jgs2_get_poses": (C.c_int32, [C.c_void_p, i32, d]),
         "jgs2_exact_tiles": (C.c_int32, [C.c_void_p, P(C.c_int64), P(C.c_int64), d, d]),
         "jgs2_set_persistent": (C.c_int32, [C.c_void_p, C.c_int32]),
+        "jgs2_precompute_cached": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_char_p,
+                                               P(C.c_int32)]),
         "jgs2_set_state": (C.c_int32, [C.c_void_p, d, d]),
         "jgs2_get_state": (C.c_int32, [C.c_void_p, d, d]),
         "jgs2_set_state_device": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -234,8 +236,17 @@ class Solver:
                for a in (log_E, nu, rho)]
         self._chk(self.lib.jgs2_set_material_log_e(self.h, *[_dptr(a) for a in arr]))
 
-    def precompute(self, samples=4, n_cand=64, seed=0):
-        self._chk(self.lib.jgs2_precompute(self.h, samples, n_cand, C.c_uint64(seed)))
+    def precompute(self, samples=4, n_cand=64, seed=0, cache=None):
+        """GPU precompute; with `cache` (a file path) load it from there when
+        the file matches these inputs, else compute and write it.  Returns
+        True when loaded from the cache."""
+        if cache is None:
+            self._chk(self.lib.jgs2_precompute(self.h, samples, n_cand, C.c_uint64(seed)))
+            return False
+        loaded = C.c_int32()
+        self._chk(self.lib.jgs2_precompute_cached(self.h, samples, n_cand, C.c_uint64(seed),
+                                                  os.fsencode(cache), C.byref(loaded)))
+        return bool(loaded.value)
 
     def ring_sizes(self):
         n = C.c_int32()

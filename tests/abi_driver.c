@@ -1,7 +1,8 @@
 /* Drives the C ABI of libjgs2 end to end on a small generated beam, checking
  * every status: mesh, material, the exact variant's precompute and steps,
  * energy (also without allocation), residual, device-state round trip, the
- * coloured plain sweeps, a rollout and its adjoint, and the documented error
+ * coloured plain sweeps, a rollout and its adjoint, the precompute cache file
+ * (when a directory is given as the first argument), and the documented error
  * paths.  Built against a host-sanitised library (AddressSanitizer and
  * UndefinedBehaviorSanitizer on the host code) by
  * `python -m paper_2506_06494_amd.build --sanitize`; exits 0 when every call
@@ -70,7 +71,7 @@ static void beam(int nx, int ny, int nz, double h, double** X, int* nV, int32_t*
                 }
 }
 
-int main(void) {
+int main(int argc, char** argv) {
     jgs2_solver* s = NULL;
     double* X;
     int32_t* tets;
@@ -109,6 +110,24 @@ int main(void) {
     int64_t n_tiles = 0, n_live = 0;
     double live_bytes = 0, part_bytes = 0;
     EXPECT(jgs2_exact_tiles(s, &n_tiles, &n_live, &live_bytes, &part_bytes), JGS2_OK);
+
+    /* precompute cache: the first call computes and writes, the second loads */
+    int32_t loaded = -1;
+    if (argc > 1) {
+        char path[1024];
+        snprintf(path, sizeof path, "%s/abi_driver_precompute.bin", argv[1]);
+        EXPECT(jgs2_precompute_cached(s, 4, 64, 0, path, &loaded), JGS2_OK);
+        if (loaded != 0) {
+            fprintf(stderr, "FAIL first cached precompute loaded=%d\n", loaded);
+            ++failures;
+        }
+        EXPECT(jgs2_precompute_cached(s, 4, 64, 0, path, &loaded), JGS2_OK);
+        if (loaded != 1) {
+            fprintf(stderr, "FAIL second cached precompute loaded=%d\n", loaded);
+            ++failures;
+        }
+        EXPECT(jgs2_precompute_cached(s, 0, 64, 0, path, &loaded), JGS2_E_INVALID);
+    }
 
     /* exact variant: three steps */
     jgs2_step_stats st;

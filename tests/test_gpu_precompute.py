@@ -87,3 +87,38 @@ def test_precomputed_sweep_matches_imported_oracle_tables(tiny):
     v = tab.verts[same]
     d = np.abs(out[0][v] - out[1][v]).max()
     assert d <= 1e-3 * np.abs(out[1][v] - x[v]).max() + 1e-9
+
+
+@pytest.mark.parametrize("variant", [jgs2.CUBATURE, jgs2.EXACT])
+def test_precompute_cache_round_trip(tiny, tmp_path, variant):
+    """jgs2_precompute_cached: the first call computes and writes the file,
+    a second handle with the same inputs loads it and then steps bit for bit
+    like the first; other inputs (stiffness, seed) do not load it."""
+    sc, mdl, _ = tiny
+    path = str(tmp_path / "pre.bin")
+    runs = []
+    for k in range(2):
+        s = make_solver(sc, variant=variant, order=jgs2.JACOBI, check_every=1)
+        loaded = s.precompute(samples=4, n_cand=64, seed=0, cache=path)
+        assert loaded == (k == 1)
+        ex = s.export_correction(4)
+        s.set_state(sc.x0, sc.v0)
+        st = [s.step(raise_on_error=False) for _ in range(2)]
+        runs.append((s.get_state()[0], ex, [r["sweeps"] for r in st], s.poses()))
+        if variant == jgs2.EXACT:
+            runs[-1] += (s.exact_tiles(),)
+        s.close()
+    (x0, e0, sw0, p0, *t0), (x1, e1, sw1, p1, *t1) = runs
+    assert np.array_equal(x0, x1) and sw0 == sw1 and np.array_equal(p0, p1)
+    for key in ("U_ring", "samples", "weights", "U_samp"):
+        assert np.array_equal(e0[key], e1[key]), key
+    assert t0 == t1
+    # a different seed or stiffness is a different precompute: computed, not loaded
+    s = make_solver(sc, variant=variant)
+    assert not s.precompute(samples=4, n_cand=64, seed=1, cache=path)
+    s.close()
+    s = jgs2.Solver(dt=sc.dt, gravity=sc.gravity, variant=variant)
+    s.upload_mesh(sc.mesh.X, sc.mesh.tets, sc.mesh.pinned)
+    s.set_material(2.0 * np.asarray(sc.E), sc.nu, sc.rho)
+    assert not s.precompute(samples=4, n_cand=64, seed=0, cache=path)
+    s.close()

@@ -13,14 +13,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 DRIVER = os.path.join(ROOT, "paper_2506_06494_amd", "abi_driver_san")
 
 
-def test_abi_driver_under_host_sanitizers():
+def test_abi_driver_under_host_sanitizers(tmp_path):
     if not os.path.exists(DRIVER):
         pytest.skip("sanitised build not present")
     env = dict(os.environ)
     # the HIP runtime keeps process-lifetime allocations: leak reports off
     env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=0:halt_on_error=1"
     env["UBSAN_OPTIONS"] = "print_stacktrace=1:halt_on_error=1"
-    r = subprocess.run([DRIVER], env=env, capture_output=True, text=True, timeout=300)
+    r = subprocess.run([DRIVER, str(tmp_path)], env=env, capture_output=True, text=True, timeout=300)
     print(r.stdout)
     print(r.stderr[-4000:])
     assert r.returncode == 0
