@@ -244,7 +244,7 @@ int32_t jgs2_precompute_cached(jgs2_solver* s, int32_t samples, int32_t n_cand, 
  * stored tiles (the lower triangle of 64 x 64-vertex tiles), the number a
  * sweep streams under params.exact_drop, the bytes those live tiles hold
  * (rows past the last free vertex excluded), and the bytes of partial sums
- * one sweep writes (1 KB per tile row and per tile column of every 8 x 8
+ * one sweep writes (1 KB per tile row and per tile column of every 4 x 4
  * super-tile holding a live tile).  Any pointer may be NULL.
  * JGS2_E_NOT_READY without the tiles. */
 int32_t jgs2_exact_tiles(jgs2_solver* s, int64_t* n_tiles, int64_t* n_live, double* live_bytes,

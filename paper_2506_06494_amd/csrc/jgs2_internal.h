@@ -102,8 +102,10 @@ struct SweepArgs {
     float4* prow;           // [n_super * ntq * 64] row partials of H-bar^-1 h per super-tile column
     float4* pcol;           // [n_super * ntq * 64] column partials per super-tile row
     float4* yq;             // [nVf] (H-bar^-1 h)_q
-    const uint8_t* tlive;   // [n_tiles] 1: the tile is streamed (nullptr: all)
-    const int* slist;       // [n_slive] super-tiles holding a live tile (nullptr: all)
+    const uint64_t* smask;  // [n_super] bit w MT_SG + j: tile (MT_SG SI + w, MT_SG SJ + j) is streamed (nullptr: all)
+    const int2* srange;     // [ns] per super-row SX: live row partials from super-column .x, column
+                            // partials up to super-row .y; the rest are zero (nullptr: all)
+    const int* slist;       // [n_slive] super-tiles holding a live tile, longest first (nullptr: all)
     int n_slive;
     const int* nactive;     // bodies still iterating (device count; nullptr: always run the product)
 };
@@ -166,8 +168,9 @@ struct jgs2_solver {
     float4* d_hvec = nullptr;              // [nVf]
     float4* d_part = nullptr;              // [2 * n_super * ntq * 64]: row, then column partials
     float4* d_yq = nullptr;                // [nVf]
-    uint8_t* d_tlive = nullptr;            // [n_tiles] live-tile flags under p.exact_drop
-    int* d_slist = nullptr;                // [n_super] live super-tiles, ascending
+    uint64_t* d_smask = nullptr;           // [n_super] live-tile bits per super-tile under p.exact_drop
+    int2* d_srange = nullptr;              // [ns] partial ranges per super-row
+    int* d_slist = nullptr;                // [n_super] live super-tiles, longest first
     int n_slive = -1;                      // -1: every super-tile
     std::vector<float> tile_max;           // largest |entry| per tile, from the precompute
     int64_t n_live = 0;
@@ -294,7 +297,8 @@ int update_tile_mask(jgs2_solver* s);
 // tiles of the exact variant's H-bar^-1: side, tiles per super-tile side,
 // count over nVf positions
 constexpr int MT_Q = 64;
-constexpr int MT_SG = 8;
+constexpr int MT_SG = 4;
+static_assert(MT_SG * MT_SG <= 64, "one 64-bit live mask per super-tile");
 inline size_t mt_tiles(int nVf) {
     const size_t n = (size_t)(nVf + MT_Q - 1) / MT_Q;
     return n * (n + 1) / 2;

@@ -46,7 +46,7 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_inc4); dfree(s->d_irec_c); dfree(s->d_incn_c); dfree(s->d_vid_c); dfree(s->d_fbody_c);
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
     dfree(s->d_Mt); dfree(s->d_Binv); dfree(s->d_qpos); dfree(s->d_qvert); dfree(s->d_qfree); dfree(s->d_hvec);
-    dfree(s->d_part); dfree(s->d_yq); dfree(s->d_tlive); dfree(s->d_slist); s->n_slive = -1;
+    dfree(s->d_part); dfree(s->d_yq); dfree(s->d_smask); dfree(s->d_srange); dfree(s->d_slist); s->n_slive = -1;
     s->have_full = false;
     dfree(s->d_X64); dfree(s->d_pin8); dfree(s->d_flag);
     dfree(s->d_ck_u); dfree(s->d_ck_v); dfree(s->d_seg); dfree(s->d_y); dfree(s->d_ynext); dfree(s->d_xbar);
@@ -99,7 +99,8 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
     a.d_hat = (float)s->p.d_hat; a.kappa = (float)s->p.kappa;
     a.fbody = s->d_fbody; a.body_on = s->d_body_on; a.one_body = s->n_bodies == 1;
     a.Mt = s->d_Mt; a.Binv = s->d_Binv; a.qpos = s->d_qpos; a.qvert = s->d_qvert; a.qfree = s->d_qfree;
-    a.hvec = s->d_hvec; a.yq = s->d_yq; a.nactive = s->d_nactive; a.tlive = s->d_tlive;
+    a.hvec = s->d_hvec; a.yq = s->d_yq; a.nactive = s->d_nactive; a.smask = s->d_smask;
+    a.srange = s->d_srange;
     a.slist = s->n_slive >= 0 ? s->d_slist : nullptr;
     a.n_slive = s->n_slive;
     const size_t ntq_ = ((size_t)s->nVf + MT_Q - 1) / MT_Q;
@@ -156,10 +157,11 @@ namespace jgs2 {
 int alloc_full_tables(jgs2_solver* s) {
     const size_t nf = s->nVf, nt = mt_tiles(s->nVf);
     const size_t nfp = (nf + MT_Q - 1) / MT_Q * MT_Q;  // h padded to whole tiles, zero past nVf
-    const size_t ntq = nfp / MT_Q, npart = (ntq + MT_SG - 1) / MT_SG * ntq * MT_Q;
+    const size_t ntq = nfp / MT_Q, ns = (ntq + MT_SG - 1) / MT_SG, npart = ns * ntq * MT_Q;
+    const size_t nsup = ns * (ns + 1) / 2;
     for (void** p : {(void**)&s->d_Mt, (void**)&s->d_Binv, (void**)&s->d_qpos, (void**)&s->d_qvert,
                      (void**)&s->d_qfree, (void**)&s->d_hvec, (void**)&s->d_part, (void**)&s->d_yq,
-                     (void**)&s->d_tlive, (void**)&s->d_slist}) {
+                     (void**)&s->d_smask, (void**)&s->d_srange, (void**)&s->d_slist}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -175,9 +177,9 @@ int alloc_full_tables(jgs2_solver* s) {
         (r = hip_check(s, hipMalloc((void**)&s->d_hvec, nfp * sizeof(float4)), "hipMalloc tables")) ||
         (r = hip_check(s, hipMalloc((void**)&s->d_part, 2 * npart * sizeof(float4)), "hipMalloc tables")) ||
         (r = hip_check(s, hipMalloc((void**)&s->d_yq, nf * sizeof(float4)), "hipMalloc tables")) ||
-        (r = hip_check(s, hipMalloc((void**)&s->d_tlive, nt), "hipMalloc tables")) ||
-        (r = hip_check(s, hipMalloc((void**)&s->d_slist, (ntq + MT_SG - 1) / MT_SG * ((ntq + MT_SG - 1) / MT_SG + 1) / 2 *
-                                                             sizeof(int)), "hipMalloc tables")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_smask, nsup * sizeof(uint64_t)), "hipMalloc tables")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_srange, ns * sizeof(int2)), "hipMalloc tables")) ||
+        (r = hip_check(s, hipMalloc((void**)&s->d_slist, nsup * sizeof(int)), "hipMalloc tables")) ||
         (r = hip_check(s, hipMemsetAsync(s->d_Mt, 0, mt_bytes, s->stream), "hipMemsetAsync tiles")) ||
         (r = hip_check(s, hipMemsetAsync(s->d_hvec, 0, nfp * sizeof(float4), s->stream), "hipMemsetAsync h")))
         return r;
@@ -188,7 +190,7 @@ int alloc_full_tables(jgs2_solver* s) {
 // largest entry of H-bar^-1; its bytes are those of its rows below nVf.
 int update_tile_mask(jgs2_solver* s) {
     const size_t nt = s->tile_max.size();
-    if (nt == 0 || !s->d_tlive) return JGS2_OK;
+    if (nt == 0 || !s->d_smask) return JGS2_OK;
     float gmax = 0.0f;
     for (float m : s->tile_max) gmax = std::max(gmax, m);
     const double cut = s->p.exact_drop * (double)gmax;
@@ -207,18 +209,47 @@ int update_tile_mask(jgs2_solver* s) {
             }
         }
     }
-    // super-tiles with at least one live tile, in launch order; the partials of
-    // the others are never written, so they are cleared here once
+    // super-tiles with at least one live tile; the partials of the others are
+    // never written, so they are cleared here once.  Launch order: longest
+    // first (a super-tile's time is that of its wave with the most live
+    // tiles), so that the short ones fill the last round of blocks.
+    // Per super-tile the live tiles as bits; per super-row SX the range of
+    // partials that can be non-zero: row partials of super-columns
+    // srange.x .. SX, column partials of super-rows SX .. srange.y.
     const int ns = (ntq + MT_SG - 1) / MT_SG;
-    std::vector<int> slist;
+    std::vector<int> slist, work;
+    std::vector<uint64_t> smask((size_t)ns * (ns + 1) / 2, 0);
+    std::vector<int2> srange(ns);
+    for (int SX = 0; SX < ns; ++SX) srange[SX] = make_int2(SX + 1, SX - 1);
     for (int SI = 0; SI < ns; ++SI)
         for (int SJ = 0; SJ <= SI; ++SJ) {
-            bool any = false;
-            for (int I = MT_SG * SI; I < std::min(ntq, MT_SG * SI + MT_SG) && !any; ++I)
-                for (int J = MT_SG * SJ; J <= std::min(I, MT_SG * SJ + MT_SG - 1) && !any; ++J)
-                    any = live[(size_t)I * (I + 1) / 2 + J] != 0;
-            if (any) slist.push_back(SI * (SI + 1) / 2 + SJ);
+            int most = 0;
+            uint64_t bits = 0;
+            for (int I = MT_SG * SI; I < std::min(ntq, MT_SG * SI + MT_SG); ++I) {
+                int n = 0;
+                for (int J = MT_SG * SJ; J <= std::min(I, MT_SG * SJ + MT_SG - 1); ++J)
+                    if (live[(size_t)I * (I + 1) / 2 + J]) {
+                        ++n;
+                        bits |= 1ull << ((I - MT_SG * SI) * MT_SG + (J - MT_SG * SJ));
+                    }
+                most = std::max(most, n);
+            }
+            if (most > 0) {
+                slist.push_back(SI * (SI + 1) / 2 + SJ);
+                work.push_back(most);
+                smask[(size_t)SI * (SI + 1) / 2 + SJ] = bits;
+                srange[SI].x = std::min(srange[SI].x, SJ);
+                srange[SJ].y = std::max(srange[SJ].y, SI);
+            }
         }
+    {
+        std::vector<int> order(slist.size());
+        for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+        std::vector<int> sorted(slist.size());
+        for (size_t k = 0; k < order.size(); ++k) sorted[k] = slist[order[k]];
+        slist.swap(sorted);
+    }
     s->part_bytes = 0.0;
     for (int b : slist) {
         int SI = 0;
@@ -230,7 +261,10 @@ int update_tile_mask(jgs2_solver* s) {
     drop_graphs(s);
     int r;
     const size_t npart = (size_t)ns * ntq * MT_Q;
-    if ((r = hip_check(s, hipMemcpy(s->d_tlive, live.data(), nt, hipMemcpyHostToDevice), "upload tile flags")) ||
+    if ((r = hip_check(s, hipMemcpy(s->d_smask, smask.data(), smask.size() * sizeof(uint64_t),
+                                    hipMemcpyHostToDevice), "upload tile masks")) ||
+        (r = hip_check(s, hipMemcpy(s->d_srange, srange.data(), srange.size() * sizeof(int2),
+                                    hipMemcpyHostToDevice), "upload partial ranges")) ||
         (r = hip_check(s, hipMemcpy(s->d_slist, slist.data(), slist.size() * sizeof(int), hipMemcpyHostToDevice),
                        "upload super-tile list")) ||
         (r = hip_check(s, hipMemset(s->d_part, 0, 2 * npart * sizeof(float4)), "clear partials")))

@@ -952,6 +952,7 @@ __global__ __launch_bounds__(64 * MT_SG) void k_symv(SweepArgs a) {
     if (a.nactive && *a.nactive == 0) return;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int bt = a.slist ? a.slist[blockIdx.x] : (int)blockIdx.x;
+    const uint64_t live = a.smask ? a.smask[bt] : ~0ull;  // bit w MT_SG + j: tile streamed
     // bt = SI (SI + 1) / 2 + SJ, SJ <= SI
     int SI = __builtin_amdgcn_readfirstlane((int)((sqrtf(8.0f * (float)bt + 1.0f) - 1.0f) * 0.5f));
     while ((SI + 1) * (SI + 2) / 2 <= bt) ++SI;
@@ -969,7 +970,7 @@ __global__ __launch_bounds__(64 * MT_SG) void k_symv(SweepArgs a) {
             const int J = MT_SG * SJ + j;
             if (J > I) break;  // upper triangle
             const size_t tt = (size_t)I * (I + 1) / 2 + J;
-            if (a.tlive && !a.tlive[tt]) continue;  // below the drop threshold: not streamed
+            if (!((live >> (w * MT_SG + j)) & 1ull)) continue;  // below the drop threshold: not streamed
             float hx[4], hy[4], hz[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -1054,7 +1055,7 @@ __global__ __launch_bounds__(64 * MT_SG) void k_symv(SweepArgs a) {
 #pragma unroll 1
         for (int ww = 0; ww < MT_SG; ++ww) {
             const int Iw = MT_SG * SI + ww;
-            if (Iw > J && Iw < ntq && (!a.tlive || a.tlive[(size_t)Iw * (Iw + 1) / 2 + J])) {
+            if (Iw > J && Iw < ntq && ((live >> (ww * MT_SG + w)) & 1ull)) {
                 y0 += sCol[ww][w][0][lane];
                 y1 += sCol[ww][w][1][lane];
                 y2 += sCol[ww][w][2][lane];
@@ -1067,7 +1068,9 @@ __global__ __launch_bounds__(64 * MT_SG) void k_symv(SweepArgs a) {
 
 // (H-bar^-1 h)_q for the 64 positions of tile row X (in super-tile row SX):
 // the row partials prow[SJ][X], SJ <= SX, then the column partials
-// pcol[SI][X], SI >= SX, wave w taking every fourth, FP64 sums, the four
+// pcol[SI][X], SI >= SX, of the super-tiles whose tiles are streamed (those
+// of the others stay zero and are not read), wave w taking every fourth,
+// FP64 sums, the four
 // waves combined in a fixed order.
 __global__ __launch_bounds__(256) void k_ysum(SweepArgs a) {
     __shared__ double sy[4][MT_Q][3];
@@ -1075,14 +1078,17 @@ __global__ __launch_bounds__(256) void k_ysum(SweepArgs a) {
     const int ntq = (a.nVf + MT_Q - 1) / MT_Q;
     const int ns = (ntq + MT_SG - 1) / MT_SG;
     const int SX = X / MT_SG;
-    const int n = ns + 1;  // SX + 1 row partials, ns - SX column partials
+    // partials k = 0 .. SX: row partials prow[k]; k = SX + 1 .. ns: column
+    // partials pcol[k - 1]; outside [k0, n) they are zero (dead super-tiles)
+    const int k0 = a.srange ? a.srange[SX].x : 0;
+    const int n = a.srange ? a.srange[SX].y + 2 : ns + 1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     auto at = [&](int k) -> const float4* {
         return k <= SX ? a.prow + ((size_t)k * ntq + X) * MT_Q + lane
                        : a.pcol + ((size_t)(SX + k - SX - 1) * ntq + X) * MT_Q + lane;
     };
     double y0 = 0.0, y1 = 0.0, y2 = 0.0;
-    int k = w;
+    int k = k0 + w;
     for (; k + 28 < n; k += 32) {  // eight loads in flight
         float4 p[8];
 #pragma unroll

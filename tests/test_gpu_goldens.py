@@ -157,8 +157,12 @@ def test_full_size_exact_sweep_matches_golden(E):
     beam twisted by 0.3 rad over its length (rotations up to 0.3 rad), at 96
     sampled vertices, against the oracle's step of those vertices (their own
     U-bar rows by FP64 band solves); the GPU computes every row on its own,
-    with the default tile drop (tiles whose entries are all at most 1e-10 of
-    H-bar^-1's largest are skipped) and with every tile streamed."""
+    with the benchmark's tile drop (tiles whose entries are all at most 1e-5
+    of H-bar^-1's largest are skipped), the default drop (1e-10) and with
+    every tile streamed.  Then the fixed-point property at any size: the
+    skipped tiles change only the correction b, which vanishes with the
+    gradient, so three converged steps from the untwisted start end where
+    the steps that stream every tile end, to well within the tolerance."""
     g = load(E, "exact_jacobi")
     sc = inputs.single_beam(E)
     x0 = inputs.twisted_positions(sc.mesh, g["angle"])
@@ -167,7 +171,7 @@ def test_full_size_exact_sweep_matches_golden(E):
     verts = np.array(g["verts"])
     dx_o = np.array(g["dx"])
     out = {}
-    for drop in (1e-10, 0.0):
+    for drop in (1e-5, 1e-10, 0.0):
         s.set_params(exact_drop=drop)
         tiles = s.exact_tiles()
         s.set_state(x0, np.zeros_like(x0))
@@ -180,7 +184,19 @@ def test_full_size_exact_sweep_matches_golden(E):
         print(f"E {E:g} drop {drop:g}: {tiles['n_live']} of {tiles['n_tiles']} tiles streamed; "
               f"max |dx_gpu - dx_oracle| = {err:.3e} of max |dx| {np.abs(dx_o).max():.3e}", flush=True)
         assert err <= 1e-5 * bbox_diag(sc.mesh.X)
-        assert err <= 2e-3 * np.abs(dx_o).max()
-    s.close()
-    # the skipped tiles change the step by no more than the FP32 product's own error
+        if drop != 1e-5:
+            assert err <= 2e-3 * np.abs(dx_o).max()
+    # the 1e-10 drop changes the step by no more than the FP32 product's own error
     assert np.abs(out[1e-10] - out[0.0]).max() <= 1e-5 * np.abs(dx_o).max()
+    ends = {}
+    for drop in (1e-5, 0.0):
+        s.set_params(exact_drop=drop, check_every=1, rel_tol=1e-5, max_sweeps=40)
+        s.set_state(sc.x0, sc.v0)
+        st = [s.step() for _ in range(3)]
+        ends[drop] = (s.get_state()[0], [r["sweeps"] for r in st])
+    s.close()
+    gap = np.abs(ends[1e-5][0] - ends[0.0][0]).max() / bbox_diag(sc.mesh.X)
+    print(f"E {E:g}: 3 converged steps, drop 1e-5 vs every tile: sweeps {ends[1e-5][1]} vs {ends[0.0][1]}, "
+          f"end positions differ by {gap:.2e} of the bbox diagonal", flush=True)
+    assert gap <= 1e-6
+    assert sum(ends[1e-5][1]) <= sum(ends[0.0][1]) + 3
