@@ -293,7 +293,8 @@ def main():
     if kt:
         dom = max(kt, key=lambda k: kt[k][0])
         ms, n = kt[dom]
-        shape = results[head_mode][E0].get("launch_shape") or [32, 256]
+        # lanes per vertex x block of the tunable sweep kernels; None for the others
+        shape = results[head_mode][E0].get("launch_shape") if dom in ("plain", "damper") else None
         tag = ("beam16x16x128" if not args.small else "beam4x4x16") + "_" + head_mode
         if dom == "phase1":       # every launch gathers every free vertex
             per_launch = sweep_bytes("phase1", cnt["T"], cnt["n_inc"], cnt["Vf"], cnt["V"])
