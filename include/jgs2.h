@@ -42,6 +42,7 @@ extern "C" {
 #define JGS2_E_DIVERGED   -5  /* residual grew past 1e8 x its start value */
 #define JGS2_E_INFEASIBLE -6  /* a vertex is on or behind a contact plane */
 #define JGS2_E_NONFINITE  -7  /* NaN/Inf appeared in the residual */
+#define JGS2_E_BOUNDS     -8  /* bounds-checked build: an index check in a sweep kernel failed */
 
 /* Local system of a vertex sub-problem (Sec. 8.1: one sub-problem per vertex,
  * N_i = 3).
@@ -397,6 +398,22 @@ int32_t jgs2_get_coloring(jgs2_solver* s, int32_t* color, int32_t* n_colors);
 #define JGS2_NKERNELS    17
 int32_t jgs2_set_profiling(jgs2_solver* s, int32_t on);
 int32_t jgs2_kernel_times(jgs2_solver* s, double* ms, int64_t* launches);
+
+/* Debugging aid, not part of the method.  The library built with
+ * JGS2_BOUNDS_CHECK (libjgs2_bounds.so, `python -m paper_2506_06494_amd.build
+ * --bounds`) checks, inside the sweep kernels (gradient gather, exact-variant
+ * tile product, sums and local solves, plain, linear and damper sweeps), every
+ * index read from a table before it is used: list entries, vertex, tet and
+ * position ids, one-ring slots, super-tile ids and partial ranges.  A failed
+ * check keeps the access inside its buffer (index 0 is used instead) and
+ * records the first failure: the kernel source line, the index and its
+ * extent; jgs2_step then fails with JGS2_E_BOUNDS and names them.
+ * jgs2_bounds_report copies that record (line 0: no failure; any pointer may
+ * be NULL) and clears it when clear != 0.  jgs2_bounds_selftest records a
+ * failure (index 1 of extent 0) from a kernel that touches no buffer, to test
+ * the reporting path.  In other builds both return JGS2_E_INVALID. */
+int32_t jgs2_bounds_report(jgs2_solver* s, int32_t* line, int64_t* index, int64_t* extent, int32_t clear);
+int32_t jgs2_bounds_selftest(jgs2_solver* s);
 
 #ifdef __cplusplus
 }

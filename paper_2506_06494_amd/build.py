@@ -13,13 +13,21 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Wno-unused-result"]
 
 
-def build(verbose=False):
+BOUNDS_LIB = os.path.join(HERE, "libjgs2_bounds.so")
+
+
+def build(verbose=False, bounds=False):
+    """libjgs2.so, or with bounds=True libjgs2_bounds.so: the same sources
+    with JGS2_BOUNDS_CHECK (index checks in the sweep kernels)."""
+    lib = BOUNDS_LIB if bounds else LIB
+    extra = ["-DJGS2_BOUNDS_CHECK"] if bounds else []
+    suffix = ".bounds.o" if bounds else ".o"
     objs = []
     procs = []
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     for src in SOURCES:
-        obj = os.path.join(HERE, "_build", src.replace(".hip", ".o"))
-        cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(HERE, "_build", src.replace(".hip", suffix))
+        cmd = ["hipcc", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -33,11 +41,11 @@ def build(verbose=False):
             failed = True
     if failed:
         raise RuntimeError("hipcc failed")
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-lrocprofiler-sdk-roctx", "-o", tmp]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 # Host-side sanitisers only (device code is built as usual): each -fsanitize
@@ -79,5 +87,7 @@ def build_sanitized(verbose=False):
 if __name__ == "__main__":
     if "--sanitize" in sys.argv:
         print(build_sanitized(verbose=True))
+    elif "--bounds" in sys.argv:
+        print(build(verbose=True, bounds=True))
     else:
         print(build(verbose=True))

@@ -42,6 +42,9 @@ constexpr int IREC_F4 = 4;
 
 struct SweepArgs {
     int nV, nVf, maxi, K, S;
+    int nT;
+    unsigned long long* bounds;  // bounds-checked build: first failed index check (line, index,
+                                 // extent); nullptr otherwise
     const int* free_ids;    // [nVf]
     const int* list;        // optional subset of free indices (colour), or nullptr
     int n_list;
@@ -220,6 +223,7 @@ struct jgs2_solver {
     // d_r2 point into it
     double* d_rb = nullptr;
     int* d_nactive = nullptr;              // [1]
+    unsigned long long* d_bounds = nullptr;  // bounds-checked build: [4] first failed index check
     double *d_r2 = nullptr, *d_r0sq = nullptr;  // [n_bodies]
     std::vector<double> r2_host, r0sq_host;
     int n_active = 0;
@@ -268,6 +272,8 @@ void launch_reduce_into(jgs2_solver* s, const double* in, int n, double* out);
 void launch_rotations(jgs2_solver* s, const SweepArgs& a);  // every free row (a.list unused)
 // y = H-bar^-1 (R^T g) in position order, from a.g and a.R (three launches)
 void launch_reduced_gradient(jgs2_solver* s, const SweepArgs& a);
+// bounds-checked build: one record of a failed check, written without any access
+void launch_bounds_selftest(jgs2_solver* s);
 void launch_exact(jgs2_solver* s, const SweepArgs& a);
 void launch_exact_linear(jgs2_solver* s, const SweepArgs& a);
 void launch_commit(jgs2_solver* s, const SweepArgs& a);

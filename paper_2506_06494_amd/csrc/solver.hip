@@ -82,6 +82,7 @@ void drop_graphs(jgs2_solver* s) {
 void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
     std::memset(&a, 0, sizeof(a));
     a.nV = s->nV; a.nVf = s->nVf; a.maxi = s->maxi; a.K = s->K; a.S = s->have_corr ? s->S : 0;
+    a.nT = s->nT; a.bounds = s->d_bounds;
     a.free_ids = s->d_free; a.list = nullptr; a.n_list = 0;
     a.tet = s->d_tet; a.inc = s->d_inc; a.inc4 = s->d_inc4; a.incslot = s->d_incslot; a.inc_n = s->d_inc_n;
     // records beyond half of the 256 MB last-level cache are streamed
@@ -462,6 +463,13 @@ int32_t jgs2_create(const jgs2_params* p, jgs2_solver** out) {
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) { delete s; return JGS2_E_HIP; }
     if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess) { delete s; return JGS2_E_HIP; }
     if (setup_scratch(s) != JGS2_OK) { delete s; return JGS2_E_HIP; }
+#ifdef JGS2_BOUNDS_CHECK
+    if (hipMalloc((void**)&s->d_bounds, 4 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(s->d_bounds, 0, 4 * sizeof(unsigned long long)) != hipSuccess) {
+        jgs2_destroy(s);
+        return JGS2_E_HIP;
+    }
+#endif
     *out = s;
     return JGS2_OK;
 }
@@ -477,7 +485,33 @@ void jgs2_destroy(jgs2_solver* s) {
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
+    if (s->d_bounds) (void)hipFree(s->d_bounds);
     delete s;
+}
+
+int32_t jgs2_bounds_report(jgs2_solver* s, int32_t* line, int64_t* index, int64_t* extent, int32_t clear) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->d_bounds) return s->fail(JGS2_E_INVALID, "not a bounds-checked build");
+    unsigned long long rec[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(rec, s->d_bounds, sizeof(rec), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (line) *line = (int32_t)rec[0];
+    if (index) *index = (int64_t)rec[1];
+    if (extent) *extent = (int64_t)rec[2];
+    if (clear) {
+        HIPCHK(hipMemsetAsync(s->d_bounds, 0, sizeof(rec), s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    return JGS2_OK;
+}
+
+int32_t jgs2_bounds_selftest(jgs2_solver* s) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->d_bounds) return s->fail(JGS2_E_INVALID, "not a bounds-checked build");
+    jgs2::launch_bounds_selftest(s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return JGS2_OK;
 }
 
 const char* jgs2_last_error(const jgs2_solver* s) { return s ? s->err.c_str() : "null handle"; }
@@ -1638,6 +1672,18 @@ int32_t jgs2_step(jgs2_solver* s, jgs2_step_stats* st) {
     loc.sweeps = most; loc.status = status; loc.r0 = s->r0; loc.r_final = rel; loc.seconds = ms * 1e-3;
     loc.ls_halvings = s->ls_halvings;
     loc.dx_norm = s->dx_norm;
+    if (s->d_bounds) {  // bounds-checked build: a failed index check fails the step
+        int32_t line = 0;
+        int64_t idx = 0, ext = 0;
+        if ((r = jgs2_bounds_report(s, &line, &idx, &ext, 0)) != JGS2_OK) return r;
+        if (line != 0) {
+            loc.status = JGS2_E_BOUNDS;
+            if (st) *st = loc;
+            return s->fail(JGS2_E_BOUNDS, "index check failed in sweep.hip line " + std::to_string(line) +
+                                              ": index " + std::to_string(idx) + " of extent " +
+                                              std::to_string(ext));
+        }
+    }
     if (st) *st = loc;
     if (status != JGS2_OK) s->err = "max_sweeps reached above rel_tol";
     return status;

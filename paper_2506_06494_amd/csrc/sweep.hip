@@ -22,6 +22,50 @@
 
 namespace jgs2 {
 
+// ---------------------------------------------------------------------------
+// Index checks of the bounds-checked build (compiled with JGS2_BOUNDS_CHECK).
+// An index read from a table (a list entry, a vertex or tet id, a position,
+// a one-ring slot, a super-tile id or a partial range) is checked against
+// its buffer's extent before use.  The first failure's source line, value
+// and extent go to the handle's record; the index is replaced by 0 so that
+// the access stays inside the buffer.  In other builds ix() is the index.
+// ---------------------------------------------------------------------------
+#ifdef JGS2_BOUNDS_CHECK
+__device__ __noinline__ void bounds_fail(unsigned long long* rec, long long i, long long n, int site) {
+    if (atomicCAS(rec, 0ull, (unsigned long long)site) == 0ull) {
+        rec[1] = (unsigned long long)i;
+        rec[2] = (unsigned long long)n;
+    }
+}
+#endif
+
+__device__ __forceinline__ int ix(const SweepArgs& a, long long i, long long n, int site) {
+#ifdef JGS2_BOUNDS_CHECK
+    if ((unsigned long long)i >= (unsigned long long)n) {
+        if (a.bounds) bounds_fail(a.bounds, i, n, site);
+        return 0;
+    }
+#else
+    (void)a; (void)n; (void)site;
+#endif
+    return (int)i;
+}
+#define IX(a, i, n) ix((a), (i), (n), __LINE__)
+
+// An incidence entry (tet << 2 | corner, three corner vertex ids), checked.
+__device__ __forceinline__ int4 ix_inc(const SweepArgs& a, int4 e, int site) {
+#ifdef JGS2_BOUNDS_CHECK
+    e.x = (ix(a, e.x >> 2, a.nT, site) << 2) | (e.x & 3);
+    e.y = ix(a, e.y, a.nV, site);
+    e.z = ix(a, e.z, a.nV, site);
+    e.w = ix(a, e.w, a.nV, site);
+#else
+    (void)a; (void)site;
+#endif
+    return e;
+}
+#define IX_INC(a, e) ix_inc((a), (e), __LINE__)
+
 // Launches a kernel; while profiling, the dispatch itself stamps a start and
 // an end event (hipExtLaunchKernelGGL), so the recorded duration is the
 // kernel's own execution time.
@@ -262,7 +306,7 @@ __device__ __forceinline__ void phase1_term(const SweepArgs& a, const int4 e, in
                                             float* Fs) {
     const int c = e.x & 3;
     Tet T;
-    load_tet_inc(a.tet, e, v, T);
+    load_tet_inc(a.tet, IX_INC(a, e), v, T);
     const d4 u0 = a.u[T.id[0]], u1 = a.u[T.id[1]], u2 = a.u[T.id[2]], u3 = a.u[T.id[3]];
     const double du[3][3] = {{u1.x - u0.x, u1.y - u0.y, u1.z - u0.z},
                              {u2.x - u0.x, u2.y - u0.y, u2.z - u0.z},
@@ -308,13 +352,13 @@ __global__ __launch_bounds__(BLOCK) void k_phase1(SweepArgs a, int want_R) {
     const int idx = blk * VPB + vloc;
     const int nidx = a.list ? a.n_list : a.nVf;
     const bool in_range = idx < nidx;
-    const int f = in_range ? (a.list ? a.list[idx] : idx) : 0;
+    const int f = in_range ? (a.list ? IX(a, a.list[idx], a.nVf) : idx) : 0;
     const bool active = GATED ? (in_range && a.body_on[a.fbody[f]] != 0) : in_range;
     // Row-level loads first and without branches (f is a valid row even out
     // of range; rows are padded to maxi entries); every lane then gathers its
     // first incident tet before n is tested (padding reads tet 0 and vertex 0
     // and adds with weight 0), so a lane waits on row -> corners -> positions.
-    const int v = a.free_ids[f];
+    const int v = IX(a, a.free_ids[f], a.nV);
     const int n = a.inc_n[f];
     const int4 e0 = GATED ? make_int4(0, 0, 0, 0) : a.inc4[(size_t)f * a.maxi + min(lane, a.maxi - 1)];
     const d4 uv = a.u[v], zv = a.zu[v];
@@ -545,6 +589,17 @@ __device__ __forceinline__ void load_irec(const float4* __restrict__ r, int stri
     T.mi = 0.0f;
 }
 
+// The corner ids of an incidence record, checked (bounds-checked build).
+__device__ __forceinline__ void ix_ids(const SweepArgs& a, Tet& T, int site) {
+#ifdef JGS2_BOUNDS_CHECK
+#pragma unroll
+    for (int k = 0; k < 4; ++k) T.id[k] = ix(a, T.id[k], a.nV, site);
+#else
+    (void)a; (void)T; (void)site;
+#endif
+}
+#define IX_IDS(a, T) ix_ids((a), (T), __LINE__)
+
 template <bool LIN>
 __device__ __forceinline__ void plain_tet_term(const SweepArgs& a, const Tet& T, int c, float w, float* g, float* A6) {
     float H[9], cH[9], gn[3], t[3];
@@ -674,13 +729,19 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a, int blk, int cbas
     // row, and the first record's corner positions are gathered by every lane
     // before the flag or n is tested (zero records name vertex 0 and add with
     // weight 0), so a lane waits on two levels: records -> positions.
-    const int vself = a.vid_c[q];
+    const int vself = IX(a, a.vid_c[q], a.nV);
     const int n = a.incn_c[q];
     const float4* row = a.irec_c + (size_t)q * IREC_F4 * a.maxi;
     Tet T0, T1;
     int c0 = 0, c1 = 0;
-    if constexpr (SPEC) load_irec<NT>(row + min(lane, a.maxi - 1), a.maxi, vself, T0, c0);
-    if constexpr (SPEC && W < 32) load_irec<NT>(row + min(lane + W, a.maxi - 1), a.maxi, vself, T1, c1);
+    if constexpr (SPEC) {
+        load_irec<NT>(row + min(lane, a.maxi - 1), a.maxi, vself, T0, c0);
+        IX_IDS(a, T0);
+    }
+    if constexpr (SPEC && W < 32) {
+        load_irec<NT>(row + min(lane + W, a.maxi - 1), a.maxi, vself, T1, c1);
+        IX_IDS(a, T1);
+    }
     const d4 uv = a.u[vself];
     d4 zv = make_d4(0.0, 0.0, 0.0, 0.0);
     float4 yv = make_float4(0.f, 0.f, 0.f, 0.f), rv = yv;
@@ -709,6 +770,7 @@ __device__ __forceinline__ void plain_body(const SweepArgs& a, int blk, int cbas
             Tet T;
             int c;
             load_irec<NT>(row + j, a.maxi, vself, T, c);
+            IX_IDS(a, T);
             plain_tet_term<LIN>(a, T, c, 1.0f, g, A6);
         }
     if constexpr (DAMP && !LIN) {
@@ -837,7 +899,7 @@ __global__ __launch_bounds__(BLK) void k_rot(SweepArgs a) {
     const int idx = blk * NV + vloc;
     const bool in_range = idx < a.nVf;
     const int q = in_range ? idx : 0;
-    const int vself = a.vid_c[q];
+    const int vself = IX(a, a.vid_c[q], a.nV);
     const int n = a.incn_c[q];
     const float4* row = a.irec_c + (size_t)q * IREC_F4 * a.maxi;
     // the first record of every lane is gathered before n or the body flag
@@ -845,6 +907,7 @@ __global__ __launch_bounds__(BLK) void k_rot(SweepArgs a) {
     Tet T0;
     int c0 = 0;
     load_irec<NT>(row + min(lane, a.maxi - 1), a.maxi, vself, T0, c0);
+    IX_IDS(a, T0);
     const int flag = SPEC ? a.body_on[0] : a.body_on[a.fbody_c[q]];
     const bool active = in_range & (flag != 0);
     // sums of V_e (F_e - I) and of V_e over the incident tets
@@ -862,6 +925,7 @@ __global__ __launch_bounds__(BLK) void k_rot(SweepArgs a) {
             Tet T;
             int c;
             load_irec<NT>(row + j, a.maxi, vself, T, c);
+            IX_IDS(a, T);
             float H[9];
             dispgrad(a.u, T, H);
 #pragma unroll
@@ -915,7 +979,7 @@ __device__ __forceinline__ size_t tile_index(int I, int J) { return (size_t)I * 
 __global__ __launch_bounds__(256) void k_hvec(SweepArgs a) {
     const int qx = blockIdx.x * blockDim.x + threadIdx.x;
     if (qx >= a.nVf) return;
-    const int v = a.qvert[qx];
+    const int v = IX(a, a.qvert[qx], a.nV);
     const float4 g = a.g[v];
     float R[9];
     load_rot(a.R, v, R);
@@ -951,7 +1015,8 @@ __global__ __launch_bounds__(64 * MT_SG) void k_symv(SweepArgs a) {
     // group late) changes nothing: skip its stream (uniform over the block)
     if (a.nactive && *a.nactive == 0) return;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int bt = a.slist ? a.slist[blockIdx.x] : (int)blockIdx.x;
+    const int nsq = ((a.nVf + MT_Q - 1) / MT_Q + MT_SG - 1) / MT_SG;  // super-rows
+    const int bt = a.slist ? IX(a, a.slist[blockIdx.x], (long long)nsq * (nsq + 1) / 2) : (int)blockIdx.x;
     const uint64_t live = a.smask ? a.smask[bt] : ~0ull;  // bit w MT_SG + j: tile streamed
     // bt = SI (SI + 1) / 2 + SJ, SJ <= SI
     int SI = __builtin_amdgcn_readfirstlane((int)((sqrtf(8.0f * (float)bt + 1.0f) - 1.0f) * 0.5f));
@@ -1080,8 +1145,8 @@ __global__ __launch_bounds__(256) void k_ysum(SweepArgs a) {
     const int SX = X / MT_SG;
     // partials k = 0 .. SX: row partials prow[k]; k = SX + 1 .. ns: column
     // partials pcol[k - 1]; outside [k0, n) they are zero (dead super-tiles)
-    const int k0 = a.srange ? a.srange[SX].x : 0;
-    const int n = a.srange ? a.srange[SX].y + 2 : ns + 1;
+    const int k0 = a.srange ? IX(a, a.srange[SX].x, SX + 2) : 0;
+    const int n = a.srange ? IX(a, a.srange[SX].y + 1, ns + 1) + 1 : ns + 1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     auto at = [&](int k) -> const float4* {
         return k <= SX ? a.prow + ((size_t)k * ntq + X) * MT_Q + lane
@@ -1139,13 +1204,13 @@ __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
     if (row >= nidx) return;  // the row's 16 lanes
     int f, v, qf;
     if (a.list) {
-        f = a.list[row];
-        v = a.free_ids[f];
-        qf = a.qpos[v];
+        f = IX(a, a.list[row], a.nVf);
+        v = IX(a, a.free_ids[f], a.nV);
+        qf = IX(a, a.qpos[v], a.nVf);
     } else {
         qf = row;
-        f = a.qfree[qf];
-        v = a.qvert[qf];
+        f = IX(a, a.qfree[qf], a.nVf);
+        v = IX(a, a.qvert[qf], a.nV);
     }
     const d4 uv = a.u[v];
     if (!LIN && !body_on(a, f)) {
@@ -1158,7 +1223,7 @@ __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
     float A9[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const int n = a.inc_n[f];
     for (int j = lane; j < n; j += EX_LANES) {
-        const int4 e = a.inc4[(size_t)f * a.maxi + j];
+        const int4 e = IX_INC(a, a.inc4[(size_t)f * a.maxi + j]);
         const uint32_t sl = a.incslot[(size_t)f * a.maxi + j];
         const int c = e.x & 3;
         Tet T;
@@ -1184,8 +1249,9 @@ __global__ __launch_bounds__(256) void k_exact(SweepArgs a) {
                 for (int q = 0; q < 9; ++q) Phi[q] = 0.0f;
             } else {
                 float Ub[9], Rb[9];
+                const int sk = IX(a, sb, a.K);
 #pragma unroll
-                for (int q = 0; q < 9; ++q) Ub[q] = a.Uring[((size_t)f * 9 + q) * a.K + sb];
+                for (int q = 0; q < 9; ++q) Ub[q] = a.Uring[((size_t)f * 9 + q) * a.K + sk];
                 load_rot(a.R, T.id[b], Rb);
                 corotate(Ub, Ri, Rb, Phi);
             }
@@ -1674,6 +1740,21 @@ void launch_reduced_gradient(jgs2_solver* s, const SweepArgs& a) {
     const int nb = a.slist ? a.n_slive : ns * (ns + 1) / 2;
     if (nb > 0) launch(s, JGS2_K_SYMV, k_symv, dim3((unsigned)nb), dim3(64 * MT_SG), a);
     launch(s, JGS2_K_YSUM, k_ysum, dim3((a.nVf + MT_Q - 1) / MT_Q), dim3(256), a);
+}
+
+#ifdef JGS2_BOUNDS_CHECK
+// Records a failed check (index 1 of extent 0) from one lane, touching no buffer.
+__global__ void k_bounds_selftest(unsigned long long* rec) {
+    if (threadIdx.x == 0) bounds_fail(rec, 1, 0, __LINE__);
+}
+#endif
+
+void launch_bounds_selftest(jgs2_solver* s) {
+#ifdef JGS2_BOUNDS_CHECK
+    hipLaunchKernelGGL(k_bounds_selftest, dim3(1), dim3(64), 0, s->stream, s->d_bounds);
+#else
+    (void)s;
+#endif
 }
 
 // Sixteen lanes per row, 16 rows per block.

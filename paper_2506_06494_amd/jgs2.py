@@ -12,15 +12,17 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libjgs2.so")
+BOUNDS_LIB_PATH = os.path.join(HERE, "libjgs2_bounds.so")  # index-checked sweep kernels
 
 OK, E_INVALID, E_OOM, E_HIP, E_NOT_READY, E_DIVERGED, E_INFEASIBLE, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
+E_BOUNDS = -8
 NOT_CONVERGED = 1
 PLAIN, CUBATURE, DAMPER, EXACT = 0, 3, 4, 5
 JACOBI, GS = 0, 1
 MAX_PLANES = 8
 
 STATUS_NAMES = {1: "NOT_CONVERGED", 0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -4: "NOT_READY", -5: "DIVERGED",
-                -6: "INFEASIBLE", -7: "NONFINITE"}
+                -6: "INFEASIBLE", -7: "NONFINITE", -8: "BOUNDS"}
 
 
 class Params(C.Structure):
@@ -50,7 +52,8 @@ EXPORTS = ["jgs2_default_params", "jgs2_create", "jgs2_destroy", "jgs2_last_erro
            "jgs2_residual", "jgs2_energy", "jgs2_get_phase1", "jgs2_get_coloring", "jgs2_set_profiling",
            "jgs2_kernel_times", "jgs2_rollout", "jgs2_rollout_backward", "jgs2_set_bodies", "jgs2_get_body_stats",
            "jgs2_set_tuning", "jgs2_get_tuning", "jgs2_autotune", "jgs2_set_streaming", "jgs2_set_material_log_e",
-           "jgs2_energy_noalloc", "jgs2_set_state_device", "jgs2_get_state_device", "jgs2_exact_tiles", "jgs2_set_persistent", "jgs2_precompute_cached"]
+           "jgs2_energy_noalloc", "jgs2_set_state_device", "jgs2_get_state_device", "jgs2_exact_tiles", "jgs2_set_persistent", "jgs2_precompute_cached",
+           "jgs2_bounds_report", "jgs2_bounds_selftest"]
 
 KERNELS = ["phase1", "phase2", "plain", "commit", "reduce", "predict", "velocity", "energy", "linear", "paramgrad",
            "adjvec", "damper", "rot", "exact", "hvec", "symv", "ysum"]
@@ -85,6 +88,8 @@ def load(path: str = LIB_PATH):
         "jgs2_get_poses": (C.c_int32, [C.c_void_p, i32, d]),
         "jgs2_exact_tiles": (C.c_int32, [C.c_void_p, P(C.c_int64), P(C.c_int64), d, d]),
         "jgs2_set_persistent": (C.c_int32, [C.c_void_p, C.c_int32]),
+        "jgs2_bounds_report": (C.c_int32, [C.c_void_p, P(C.c_int32), P(C.c_int64), P(C.c_int64), C.c_int32]),
+        "jgs2_bounds_selftest": (C.c_int32, [C.c_void_p]),
         "jgs2_precompute_cached": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_char_p,
                                                P(C.c_int32)]),
         "jgs2_set_state": (C.c_int32, [C.c_void_p, d, d]),
@@ -375,6 +380,16 @@ class Solver:
         return th, xb0, vb0, dict(status=r, steps=st.steps, adjoint_sweeps=st.adjoint_sweeps,
                                   forward_sweeps=st.forward_sweeps, max_rel_res=st.max_rel_res,
                                   seconds=st.seconds, ubar=ub)
+
+    def bounds_report(self, clear=False):
+        """Bounds-checked build only: the first failed index check as
+        (kernel source line, index, extent); line 0 when none failed."""
+        line, idx, ext = C.c_int32(), C.c_int64(), C.c_int64()
+        self._chk(self.lib.jgs2_bounds_report(self.h, C.byref(line), C.byref(idx), C.byref(ext), int(clear)))
+        return line.value, idx.value, ext.value
+
+    def bounds_selftest(self):
+        self._chk(self.lib.jgs2_bounds_selftest(self.h))
 
     def set_persistent(self, on=True):
         """Coloured GS groups of the plain variant as one cooperative launch."""
