@@ -32,7 +32,8 @@ def parse():
     ap.add_argument("--max-sweeps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="4x4x16 beam instead (quick check)")
-    ap.add_argument("--modes", default="jgs2_exact_jacobi,jgs2_exact_jacobi_drop1e-10,jgs2_exact_jacobi_keep_all,jgs2_exact_gs,jgs2_damper_gs,"
+    ap.add_argument("--modes", default="jgs2_exact_jacobi,jgs2_exact_jacobi_drop1e-10,jgs2_exact_jacobi_keep_all,jgs2_exact_gs,"
+                                       "jgs2_exact_jacobi_fp16,jgs2_damper_gs,"
                                        "jgs2_damper_jacobi_w0.8,"
                                        "jgs2_jacobi,jgs2_gs,plain_jacobi,"
                                        "plain_jacobi_w0.8,plain_jacobi_w0.5,plain_jacobi_w0.3,plain_gs,"
@@ -116,6 +117,10 @@ def main():
         ("jgs2_exact_jacobi_keep_all", dict(variant=jgs2.EXACT, order=jgs2.JACOBI, omega=1.0, check_every=1,
                                             exact_drop=0.0)),
         ("jgs2_exact_gs", dict(variant=jgs2.EXACT, order=jgs2.GS, omega=1.0, check_every=1, exact_drop=1e-5)),
+        # the headline mode with the tiles stored in FP16, scaled per tile (half the streamed bytes;
+        # the conversion is one-way, so it runs after the other exact modes of the handle)
+        ("jgs2_exact_jacobi_fp16", dict(variant=jgs2.EXACT, order=jgs2.JACOBI, omega=1.0, check_every=1,
+                                        exact_drop=1e-5, tile_fp16=1)),
         # the damper reading of the correction in coloured GS, no step scale
         ("jgs2_damper_gs", dict(variant=jgs2.DAMPER, order=jgs2.GS, omega=1.0)),
         ("jgs2_damper_jacobi_w0.8", dict(variant=jgs2.DAMPER, order=jgs2.JACOBI, omega=0.8)),
@@ -149,6 +154,7 @@ def main():
             kw = dict(check_every=16)
             kw.update(cfg)
             persistent = kw.pop("persistent", 0)
+            tile_fp16 = kw.pop("tile_fp16", 0)
             if cfg["variant"] == jgs2.EXACT and exact_keep:
                 s = exact_keep["exact"]        # the same H-bar^-1 tiles; only the order and checks change
                 s.set_params(**{k: v for k, v in kw.items() if k != "variant"})
@@ -188,6 +194,8 @@ def main():
                                         corr["U_samp"])
             if persistent:
                 s.set_persistent(True)
+            if tile_fp16:
+                s.exact_tiles_fp16()
             s.set_state(sc.x0, sc.v0)
             tuned = None
             if cfg["variant"] == jgs2.PLAIN:

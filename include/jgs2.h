@@ -251,6 +251,19 @@ int32_t jgs2_precompute_cached(jgs2_solver* s, int32_t samples, int32_t n_cand, 
 int32_t jgs2_exact_tiles(jgs2_solver* s, int64_t* n_tiles, int64_t* n_live, double* live_bytes,
                          double* part_bytes);
 
+/* Converts the exact variant's stored H-bar^-1 tiles (Eq. u: U-bar_{i,a} =
+ * (H-bar^-1)_{a,i} B_i^-1) to FP16, halving the bytes each sweep streams:
+ * every entry is stored divided by its tile's scale (the tile's largest
+ * |entry| / 2^15, so that entry maps to 2^15), rounded to nearest; the sweep
+ * multiplies in FP32 and sums per position in FP64 as before.  The tiles
+ * only form the correction b, whose fixed point (zero gradient) and FP64
+ * residual test are unchanged; a step converges to the same tolerance.  The
+ * FP32 tiles are freed; a later jgs2_precompute (or a loaded cache) brings
+ * FP32 tiles back.  A second call does nothing.  JGS2_E_NOT_READY without
+ * tiles, JGS2_E_INVALID inside a step, JGS2_E_OOM if the FP16 copy does not
+ * fit beside the FP32 tiles. */
+int32_t jgs2_exact_tiles_fp16(jgs2_solver* s);
+
 /* Correction tables in free-vertex order (free vertices ascending by id).
  * For free vertex f with one-ring list ring(f) = its free neighbours in
  * ascending id order (length given by jgs2_get_ring_sizes):

@@ -97,6 +97,8 @@ struct SweepArgs {
     // (tile (I, J), I >= J, at I (I + 1) / 2 + J, laid out [q % 64][3 r + c][q' % 64]),
     // B_q^-1 = ((H-bar^-1)_{q,q})^-1 per position, and per-sweep vectors
     const float* Mt;        // [n_tiles * 64 * 9 * 64]
+    const _Float16* Mh;     // the same tiles in FP16, entry / tscale[tile] (after jgs2_exact_tiles_fp16)
+    const float* tscale;    // [n_tiles] FP16 tile scale
     const float* Binv;      // [nVf * 9]
     const int* qpos;        // [nV] permuted position of a free vertex, -1 if pinned
     const int* qvert;       // [nVf] vertex id at position q
@@ -164,6 +166,9 @@ struct jgs2_solver {
     int* d_colperm = nullptr;
     float* d_Uring = nullptr;
     float* d_Mt = nullptr;                 // exact variant: H-bar^-1 tiles (see SweepArgs)
+    _Float16* d_Mh = nullptr;              // the tiles in FP16 once converted (d_Mt then freed)
+    float* d_tscale = nullptr;             // [n_tiles] their scales
+    bool tiles_fp16 = false;
     float* d_Binv = nullptr;               // [nVf * 9]
     int* d_qpos = nullptr;                 // [nV]
     int* d_qvert = nullptr;                // [nVf]
@@ -274,6 +279,8 @@ void launch_rotations(jgs2_solver* s, const SweepArgs& a);  // every free row (a
 void launch_reduced_gradient(jgs2_solver* s, const SweepArgs& a);
 // bounds-checked build: one record of a failed check, written without any access
 void launch_bounds_selftest(jgs2_solver* s);
+// FP32 tiles -> FP16 tiles scaled per tile (entry x inv[tile])
+void launch_tiles_to_fp16(jgs2_solver* s, const float* Mt, _Float16* Mh, const float* inv, size_t n_tiles);
 void launch_exact(jgs2_solver* s, const SweepArgs& a);
 void launch_exact_linear(jgs2_solver* s, const SweepArgs& a);
 void launch_commit(jgs2_solver* s, const SweepArgs& a);

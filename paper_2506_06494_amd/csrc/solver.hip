@@ -45,7 +45,7 @@ void free_device(jgs2_solver* s) {
     dfree(s->d_inc_n); dfree(s->d_ring); dfree(s->d_ring_n); dfree(s->d_incslot); dfree(s->d_colperm); dfree(s->d_coloff);
     dfree(s->d_inc4); dfree(s->d_irec_c); dfree(s->d_incn_c); dfree(s->d_vid_c); dfree(s->d_fbody_c);
     dfree(s->d_Uring); dfree(s->d_samp_e); dfree(s->d_samp); dfree(s->d_partial); dfree(s->d_red);
-    dfree(s->d_Mt); dfree(s->d_Binv); dfree(s->d_qpos); dfree(s->d_qvert); dfree(s->d_qfree); dfree(s->d_hvec);
+    dfree(s->d_Mt); dfree(s->d_Mh); dfree(s->d_tscale); s->tiles_fp16 = false; dfree(s->d_Binv); dfree(s->d_qpos); dfree(s->d_qvert); dfree(s->d_qfree); dfree(s->d_hvec);
     dfree(s->d_part); dfree(s->d_yq); dfree(s->d_smask); dfree(s->d_srange); dfree(s->d_slist); s->n_slive = -1;
     s->have_full = false;
     dfree(s->d_X64); dfree(s->d_pin8); dfree(s->d_flag);
@@ -99,7 +99,7 @@ void build_sweep_args(jgs2_solver* s, SweepArgs& a) {
         for (int k = 0; k < 4; ++k) a.planes[i][k] = (float)s->p.planes[i][k];
     a.d_hat = (float)s->p.d_hat; a.kappa = (float)s->p.kappa;
     a.fbody = s->d_fbody; a.body_on = s->d_body_on; a.one_body = s->n_bodies == 1;
-    a.Mt = s->d_Mt; a.Binv = s->d_Binv; a.qpos = s->d_qpos; a.qvert = s->d_qvert; a.qfree = s->d_qfree;
+    a.Mt = s->d_Mt; a.Mh = s->d_Mh; a.tscale = s->d_tscale; a.Binv = s->d_Binv; a.qpos = s->d_qpos; a.qvert = s->d_qvert; a.qfree = s->d_qfree;
     a.hvec = s->d_hvec; a.yq = s->d_yq; a.nactive = s->d_nactive; a.smask = s->d_smask;
     a.srange = s->d_srange;
     a.slist = s->n_slive >= 0 ? s->d_slist : nullptr;
@@ -160,13 +160,15 @@ int alloc_full_tables(jgs2_solver* s) {
     const size_t nfp = (nf + MT_Q - 1) / MT_Q * MT_Q;  // h padded to whole tiles, zero past nVf
     const size_t ntq = nfp / MT_Q, ns = (ntq + MT_SG - 1) / MT_SG, npart = ns * ntq * MT_Q;
     const size_t nsup = ns * (ns + 1) / 2;
-    for (void** p : {(void**)&s->d_Mt, (void**)&s->d_Binv, (void**)&s->d_qpos, (void**)&s->d_qvert,
+    for (void** p : {(void**)&s->d_Mt, (void**)&s->d_Mh, (void**)&s->d_tscale, (void**)&s->d_Binv,
+                     (void**)&s->d_qpos, (void**)&s->d_qvert,
                      (void**)&s->d_qfree, (void**)&s->d_hvec, (void**)&s->d_part, (void**)&s->d_yq,
                      (void**)&s->d_smask, (void**)&s->d_srange, (void**)&s->d_slist}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
     s->have_full = false;
+    s->tiles_fp16 = false;
     s->n_slive = -1;
     int r;
     const size_t mt_bytes = nt * MT_Q * 9 * MT_Q * sizeof(float);
@@ -206,7 +208,7 @@ int update_tile_mask(jgs2_solver* s) {
             live[t] = (double)s->tile_max[t] > cut ? 1 : 0;
             if (live[t]) {
                 ++s->n_live;
-                s->live_bytes += (double)rows * 9 * MT_Q * sizeof(float);
+                s->live_bytes += (double)rows * 9 * MT_Q * (s->tiles_fp16 ? sizeof(_Float16) : sizeof(float));
             }
         }
     }
@@ -552,6 +554,44 @@ int32_t jgs2_exact_tiles(jgs2_solver* s, int64_t* n_tiles, int64_t* n_live, doub
     return JGS2_OK;
 }
 
+int32_t jgs2_exact_tiles_fp16(jgs2_solver* s) {
+    if (!s) return JGS2_E_INVALID;
+    if (!s->have_full) return s->fail(JGS2_E_NOT_READY, "no H-bar^-1 tiles (precompute with the JGS2_EXACT variant)");
+    if (s->in_step) return s->fail(JGS2_E_INVALID, "inside a step");
+    if (s->tiles_fp16) return JGS2_OK;
+    TraceRange trace_range("jgs2_exact_tiles_fp16");
+    const size_t nt = s->tile_max.size(), n = nt * jgs2::MT_Q * 9 * jgs2::MT_Q;
+    // the largest |entry| of a tile maps to 2^15 (below the FP16 maximum 65504)
+    std::vector<float> scale(nt), inv(nt);
+    for (size_t t = 0; t < nt; ++t) {
+        const float m = s->tile_max[t];
+        scale[t] = m > 0.0f ? m / 32768.0f : 1.0f;
+        inv[t] = m > 0.0f ? 32768.0f / m : 1.0f;
+    }
+    float* dinv = nullptr;
+    int r;
+    if ((r = jgs2::hip_check(s, hipMalloc((void**)&s->d_Mh, n * sizeof(_Float16)), "hipMalloc FP16 tiles")) ||
+        (r = jgs2::hip_check(s, hipMalloc((void**)&s->d_tscale, nt * sizeof(float)), "hipMalloc tile scales")) ||
+        (r = jgs2::hip_check(s, hipMalloc((void**)&dinv, nt * sizeof(float)), "hipMalloc tile scales"))) {
+        if (dinv) (void)hipFree(dinv);
+        if (s->d_Mh) (void)hipFree(s->d_Mh);
+        if (s->d_tscale) (void)hipFree(s->d_tscale);
+        s->d_Mh = nullptr;
+        s->d_tscale = nullptr;
+        return r;
+    }
+    HIPCHK(hipMemcpyAsync(s->d_tscale, scale.data(), nt * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(dinv, inv.data(), nt * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    jgs2::launch_tiles_to_fp16(s, s->d_Mt, s->d_Mh, dinv, nt);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->stream));
+    (void)hipFree(dinv);
+    (void)hipFree(s->d_Mt);
+    s->d_Mt = nullptr;
+    s->tiles_fp16 = true;
+    return jgs2::update_tile_mask(s);  // bytes per live tile halve; captured graphs are dropped
+}
+
 int32_t jgs2_set_stream(jgs2_solver* s, void* stream) {
     if (!s) return JGS2_E_INVALID;
     s->stream = (hipStream_t)stream;
@@ -848,6 +888,7 @@ bool get_dev(FILE* f, void* d, size_t n, std::vector<char>& stage) {
 size_t tile_floats(const jgs2_solver* s) { return jgs2::mt_tiles(s->nVf) * jgs2::MT_Q * 9 * jgs2::MT_Q; }
 
 int write_cache(jgs2_solver* s, const char* path, int n_cand, uint64_t seed) {
+    if (s->tiles_fp16) return s->fail(JGS2_E_INVALID, "the cache holds FP32 tiles: write it before converting");
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "wb");
     if (!f) return s->fail(JGS2_E_INVALID, "cannot write the precompute cache");

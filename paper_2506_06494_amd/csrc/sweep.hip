@@ -1008,7 +1008,12 @@ __global__ __launch_bounds__(256) void k_hvec(SweepArgs a) {
 // atomics, the result is bitwise-deterministic.  Indices are wave-uniform and
 // kept in scalar registers.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
+// HALF: the tiles in FP16, each entry stored divided by its tile's scale;
+// 8-byte loads, four 4-row batches in flight, products in FP32 from the
+// converted entries, the tile's row and column parts multiplied by the scale.
+template <bool HALF>
 __global__ __launch_bounds__(64 * MT_SG) void k_symv(SweepArgs a) {
     __shared__ float sCol[MT_SG][MT_SG][3][MT_Q];  // [wave][tile column][component][column]
     // a sweep issued after every body stopped (the host reads residuals one
@@ -1044,44 +1049,92 @@ __global__ __launch_bounds__(64 * MT_SG) void k_symv(SweepArgs a) {
                 hy[k] = h.y;
                 hz[k] = h.z;
             }
-            const f32x4* T4 = reinterpret_cast<const f32x4*>(a.Mt + tt * MT_TILE);
             float cs[4][3];
 #pragma unroll
             for (int k = 0; k < 4; ++k) cs[k][0] = cs[k][1] = cs[k][2] = 0.f;
+            if constexpr (HALF) {
+                const f16x4* T4 = reinterpret_cast<const f16x4*>(a.Mh + tt * MT_TILE);
+                const float sc = a.tscale[tt];
 #pragma unroll 1
-            for (int kk = 0; 4 * kk < nrow; kk += 2) {
-                f32x4 m[2][9];
-                float4 hi[2];
+                for (int kk = 0; 4 * kk < nrow; kk += 4) {
+                    f16x4 m[4][9];
+                    float4 hi[4];
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const int il = 4 * (kk + b) + sr;
+                    for (int b = 0; b < 4; ++b) {
+                        const int il = 4 * (kk + b) + sr;
 #pragma unroll
-                    for (int q = 0; q < 9; ++q)
-                        m[b][q] = __builtin_nontemporal_load(T4 + ((size_t)il * 9 + q) * (MT_Q / 4) + c);
-                    hi[b] = hI[4 * (kk + b)];
+                        for (int q = 0; q < 9; ++q)
+                            m[b][q] = __builtin_nontemporal_load(T4 + ((size_t)il * 9 + q) * (MT_Q / 4) + c);
+                        hi[b] = hI[4 * (kk + b)];
+                    }
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const float m0 = (float)m[b][0][k], m1 = (float)m[b][1][k], m2 = (float)m[b][2][k];
+                            const float m3 = (float)m[b][3][k], m4 = (float)m[b][4][k], m5 = (float)m[b][5][k];
+                            const float m6 = (float)m[b][6][k], m7 = (float)m[b][7][k], m8 = (float)m[b][8][k];
+                            r0 = fmaf(m0, hx[k], fmaf(m1, hy[k], fmaf(m2, hz[k], r0)));
+                            r1 = fmaf(m3, hx[k], fmaf(m4, hy[k], fmaf(m5, hz[k], r1)));
+                            r2 = fmaf(m6, hx[k], fmaf(m7, hy[k], fmaf(m8, hz[k], r2)));
+                            cs[k][0] = fmaf(m0, hi[b].x, fmaf(m3, hi[b].y, fmaf(m6, hi[b].z, cs[k][0])));
+                            cs[k][1] = fmaf(m1, hi[b].x, fmaf(m4, hi[b].y, fmaf(m7, hi[b].z, cs[k][1])));
+                            cs[k][2] = fmaf(m2, hi[b].x, fmaf(m5, hi[b].y, fmaf(m8, hi[b].z, cs[k][2])));
+                        }
+                        r0 = lane_sum_w<16>(r0);
+                        r1 = lane_sum_w<16>(r1);
+                        r2 = lane_sum_w<16>(r2);
+                        if (c == kk + b) {
+                            mine.x += sc * r0;
+                            mine.y += sc * r1;
+                            mine.z += sc * r2;
+                        }
+                    }
                 }
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+                for (int k = 0; k < 4; ++k) {
+                    cs[k][0] *= sc;
+                    cs[k][1] *= sc;
+                    cs[k][2] *= sc;
+                }
+            } else {
+                const f32x4* T4 = reinterpret_cast<const f32x4*>(a.Mt + tt * MT_TILE);
+#pragma unroll 1
+                for (int kk = 0; 4 * kk < nrow; kk += 2) {
+                    f32x4 m[2][9];
+                    float4 hi[2];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const float m0 = m[b][0][k], m1 = m[b][1][k], m2 = m[b][2][k];
-                        const float m3 = m[b][3][k], m4 = m[b][4][k], m5 = m[b][5][k];
-                        const float m6 = m[b][6][k], m7 = m[b][7][k], m8 = m[b][8][k];
-                        r0 = fmaf(m0, hx[k], fmaf(m1, hy[k], fmaf(m2, hz[k], r0)));
-                        r1 = fmaf(m3, hx[k], fmaf(m4, hy[k], fmaf(m5, hz[k], r1)));
-                        r2 = fmaf(m6, hx[k], fmaf(m7, hy[k], fmaf(m8, hz[k], r2)));
-                        cs[k][0] = fmaf(m0, hi[b].x, fmaf(m3, hi[b].y, fmaf(m6, hi[b].z, cs[k][0])));
-                        cs[k][1] = fmaf(m1, hi[b].x, fmaf(m4, hi[b].y, fmaf(m7, hi[b].z, cs[k][1])));
-                        cs[k][2] = fmaf(m2, hi[b].x, fmaf(m5, hi[b].y, fmaf(m8, hi[b].z, cs[k][2])));
+                    for (int b = 0; b < 2; ++b) {
+                        const int il = 4 * (kk + b) + sr;
+#pragma unroll
+                        for (int q = 0; q < 9; ++q)
+                            m[b][q] = __builtin_nontemporal_load(T4 + ((size_t)il * 9 + q) * (MT_Q / 4) + c);
+                        hi[b] = hI[4 * (kk + b)];
                     }
-                    r0 = lane_sum_w<16>(r0);
-                    r1 = lane_sum_w<16>(r1);
-                    r2 = lane_sum_w<16>(r2);
-                    if (c == kk + b) {
-                        mine.x += r0;
-                        mine.y += r1;
-                        mine.z += r2;
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const float m0 = m[b][0][k], m1 = m[b][1][k], m2 = m[b][2][k];
+                            const float m3 = m[b][3][k], m4 = m[b][4][k], m5 = m[b][5][k];
+                            const float m6 = m[b][6][k], m7 = m[b][7][k], m8 = m[b][8][k];
+                            r0 = fmaf(m0, hx[k], fmaf(m1, hy[k], fmaf(m2, hz[k], r0)));
+                            r1 = fmaf(m3, hx[k], fmaf(m4, hy[k], fmaf(m5, hz[k], r1)));
+                            r2 = fmaf(m6, hx[k], fmaf(m7, hy[k], fmaf(m8, hz[k], r2)));
+                            cs[k][0] = fmaf(m0, hi[b].x, fmaf(m3, hi[b].y, fmaf(m6, hi[b].z, cs[k][0])));
+                            cs[k][1] = fmaf(m1, hi[b].x, fmaf(m4, hi[b].y, fmaf(m7, hi[b].z, cs[k][1])));
+                            cs[k][2] = fmaf(m2, hi[b].x, fmaf(m5, hi[b].y, fmaf(m8, hi[b].z, cs[k][2])));
+                        }
+                        r0 = lane_sum_w<16>(r0);
+                        r1 = lane_sum_w<16>(r1);
+                        r2 = lane_sum_w<16>(r2);
+                        if (c == kk + b) {
+                            mine.x += r0;
+                            mine.y += r1;
+                            mine.z += r2;
+                        }
                     }
                 }
             }
@@ -1738,7 +1791,12 @@ void launch_reduced_gradient(jgs2_solver* s, const SweepArgs& a) {
     launch(s, JGS2_K_HVEC, k_hvec, dim3((a.nVf + 255) / 256), dim3(256), a);
     const int ns = (a.nVf + MT_Q * MT_SG - 1) / (MT_Q * MT_SG);
     const int nb = a.slist ? a.n_slive : ns * (ns + 1) / 2;
-    if (nb > 0) launch(s, JGS2_K_SYMV, k_symv, dim3((unsigned)nb), dim3(64 * MT_SG), a);
+    if (nb > 0) {
+        if (s->tiles_fp16)
+            launch(s, JGS2_K_SYMV, k_symv<true>, dim3((unsigned)nb), dim3(64 * MT_SG), a);
+        else
+            launch(s, JGS2_K_SYMV, k_symv<false>, dim3((unsigned)nb), dim3(64 * MT_SG), a);
+    }
     launch(s, JGS2_K_YSUM, k_ysum, dim3((a.nVf + MT_Q - 1) / MT_Q), dim3(256), a);
 }
 
@@ -1755,6 +1813,25 @@ void launch_bounds_selftest(jgs2_solver* s) {
 #else
     (void)s;
 #endif
+}
+
+// FP32 tiles to FP16, one block per tile: entry x inv[tile], rounded to nearest.
+__global__ __launch_bounds__(256) void k_tiles_to_fp16(const float* __restrict__ Mt, _Float16* __restrict__ Mh,
+                                                       const float* __restrict__ inv) {
+    const size_t t = blockIdx.x;
+    const float sc = inv[t];
+    const float4* src = reinterpret_cast<const float4*>(Mt + t * MT_TILE);
+    f16x4* dst = reinterpret_cast<f16x4*>(Mh + t * MT_TILE);
+    for (int i = threadIdx.x; i < (int)(MT_TILE / 4); i += 256) {
+        const float4 v = src[i];
+        const f16x4 h = {(_Float16)(v.x * sc), (_Float16)(v.y * sc), (_Float16)(v.z * sc), (_Float16)(v.w * sc)};
+        dst[i] = h;
+    }
+}
+
+void launch_tiles_to_fp16(jgs2_solver* s, const float* Mt, _Float16* Mh, const float* inv, size_t n_tiles) {
+    if (n_tiles == 0) return;
+    hipLaunchKernelGGL(k_tiles_to_fp16, dim3((unsigned)n_tiles), dim3(256), 0, s->stream, Mt, Mh, inv);
 }
 
 // Sixteen lanes per row, 16 rows per block.

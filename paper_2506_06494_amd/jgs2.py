@@ -53,7 +53,7 @@ EXPORTS = ["jgs2_default_params", "jgs2_create", "jgs2_destroy", "jgs2_last_erro
            "jgs2_kernel_times", "jgs2_rollout", "jgs2_rollout_backward", "jgs2_set_bodies", "jgs2_get_body_stats",
            "jgs2_set_tuning", "jgs2_get_tuning", "jgs2_autotune", "jgs2_set_streaming", "jgs2_set_material_log_e",
            "jgs2_energy_noalloc", "jgs2_set_state_device", "jgs2_get_state_device", "jgs2_exact_tiles", "jgs2_set_persistent", "jgs2_precompute_cached",
-           "jgs2_bounds_report", "jgs2_bounds_selftest"]
+           "jgs2_bounds_report", "jgs2_bounds_selftest", "jgs2_exact_tiles_fp16"]
 
 KERNELS = ["phase1", "phase2", "plain", "commit", "reduce", "predict", "velocity", "energy", "linear", "paramgrad",
            "adjvec", "damper", "rot", "exact", "hvec", "symv", "ysum"]
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
         "jgs2_set_persistent": (C.c_int32, [C.c_void_p, C.c_int32]),
         "jgs2_bounds_report": (C.c_int32, [C.c_void_p, P(C.c_int32), P(C.c_int64), P(C.c_int64), C.c_int32]),
         "jgs2_bounds_selftest": (C.c_int32, [C.c_void_p]),
+        "jgs2_exact_tiles_fp16": (C.c_int32, [C.c_void_p]),
         "jgs2_precompute_cached": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_char_p,
                                                P(C.c_int32)]),
         "jgs2_set_state": (C.c_int32, [C.c_void_p, d, d]),
@@ -401,6 +402,10 @@ class Solver:
         nt, nl, b, pb = C.c_int64(), C.c_int64(), C.c_double(), C.c_double()
         self._chk(self.lib.jgs2_exact_tiles(self.h, C.byref(nt), C.byref(nl), C.byref(b), C.byref(pb)))
         return dict(n_tiles=nt.value, n_live=nl.value, live_bytes=b.value, part_bytes=pb.value)
+
+    def exact_tiles_fp16(self):
+        """H-bar^-1 tiles stored in FP16 (scaled per tile) from here on."""
+        self._chk(self.lib.jgs2_exact_tiles_fp16(self.h))
 
     def set_state_device(self, d_x, d_v):
         """d_x, d_v: device addresses (ints) of nV x 3 doubles."""

@@ -2,7 +2,7 @@
 with JGS2_BOUNDS_CHECK) on small generated beams and prints one JSON line:
 the first failed index check after each phase (line 0: none), the tile
 counts of the exact variant, and the self-test's record.  Phases: exact
-Jacobi and GS with dead tiles, the exact adjoint, plain Jacobi and GS, the
+Jacobi and GS with dead tiles, exact Jacobi with FP16 tiles, the exact adjoint, plain Jacobi and GS, the
 damper sweeps, batched bodies, a plain rollout and its adjoint.  Run by
 tests/test_zy_bounds.py in a process of its own (the binding loads one
 library per process)."""
@@ -43,6 +43,9 @@ def main():
     record("exact_jacobi", s, [s.step(raise_on_error=False) for _ in range(2)])
     s.set_params(order=jgs2.GS)
     record("exact_gs", s, [s.step(raise_on_error=False) for _ in range(1)])
+    s.exact_tiles_fp16()
+    s.set_params(order=jgs2.JACOBI)
+    record("exact_jacobi_fp16", s, [s.step(raise_on_error=False) for _ in range(2)])
     s.set_params(order=jgs2.JACOBI, exact_drop=0.0)
     s.set_state(sc.x0, sc.v0)
     s.rollout(2, ckpt_every=1)

@@ -96,6 +96,41 @@ def test_exact_twisting_beam_steps_match_oracle(E):
     s.close()
 
 
+@pytest.mark.parametrize("E", [1e5])
+def test_exact_fp16_tiles_steps_match_oracle(E):
+    """The same three converged steps with H-bar^-1's tiles stored in FP16
+    (each tile scaled by its largest entry), on the soft beam: the tiles only
+    form the correction, so the steps converge to the oracle's positions in
+    as few sweeps; the conversion halves the streamed bytes, a second call
+    changes nothing and a new precompute brings FP32 tiles back.  (At
+    E = 1e8 FP16 entries are too coarse for the stiff rest Hessian's
+    inverse: the steps stall near r = 1e-2.)"""
+    sc = inputs.beam_scene(32, 4, 4, E=E, nu=0.45, steps=3)
+    mdl = fem.model_from_scene(sc)
+    s = gpu_exact(sc, order=jgs2.JACOBI, rel_tol=1e-5, max_sweeps=40, check_every=1)
+    t32 = s.exact_tiles()
+    s.exact_tiles_fp16()
+    s.exact_tiles_fp16()
+    t16 = s.exact_tiles()
+    assert t16["n_live"] == t32["n_live"] and t16["live_bytes"] == t32["live_bytes"] / 2
+    sw = osw.Sweeper(mdl, exact_tables(mdl), osw.RX)
+    s.set_state(sc.x0, sc.v0)
+    x, v = sc.x0.copy(), sc.v0.copy()
+    diag = bbox_diag(mdl.X)
+    for k in range(3):
+        st = s.step()
+        xg, _ = s.get_state()
+        x, v, hist = osw.run_step(sw, x, v, tol=1e-5, max_sweeps=12)
+        err = np.abs(xg - x).max()
+        print(f"E {E:g} FP16 step {k}: GPU {st['sweeps']} sweeps r {st['r_final']:.2e}; oracle {len(hist) - 1} "
+              f"sweeps; max |dx| {err:.3e}", flush=True)
+        assert st["status"] == jgs2.OK and st["sweeps"] <= 8
+        assert err <= 1e-5 * diag
+    s.precompute(samples=4, n_cand=64, seed=0)
+    assert s.exact_tiles()["live_bytes"] == t32["live_bytes"]
+    s.close()
+
+
 def test_exact_needs_its_tables(tiny):
     sc, mdl, tab = tiny
     s = make_solver(sc, variant=jgs2.EXACT)

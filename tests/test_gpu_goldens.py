@@ -189,14 +189,29 @@ def test_full_size_exact_sweep_matches_golden(E):
     # the 1e-10 drop changes the step by no more than the FP32 product's own error
     assert np.abs(out[1e-10] - out[0.0]).max() <= 1e-5 * np.abs(dx_o).max()
     ends = {}
-    for drop in (1e-5, 0.0):
-        s.set_params(exact_drop=drop, check_every=1, rel_tol=1e-5, max_sweeps=40)
+    for drop in (1e-5, 0.0, "fp16") if E < 1e6 else (1e-5, 0.0):  # FP16 tiles: soft bodies only
+        if drop == "fp16":
+            # the tiles in FP16 (scaled per tile), at the benchmark's drop: one sweep
+            # against the oracle, then the converged steps
+            s.exact_tiles_fp16()
+            s.set_params(exact_drop=1e-5, check_every=1, rel_tol=1e-5, max_sweeps=40)
+            s.set_state(x0, np.zeros_like(x0))
+            s.begin_step()
+            s.iterate(1)
+            x, _ = s.get_state()
+            s.end_step()
+            err = np.abs(x[verts] - x0[verts] - dx_o).max()
+            print(f"E {E:g} FP16 tiles, drop 1e-5: max |dx_gpu - dx_oracle| = {err:.3e}", flush=True)
+            assert err <= 1e-5 * bbox_diag(sc.mesh.X)
+        else:
+            s.set_params(exact_drop=drop, check_every=1, rel_tol=1e-5, max_sweeps=40)
         s.set_state(sc.x0, sc.v0)
         st = [s.step() for _ in range(3)]
         ends[drop] = (s.get_state()[0], [r["sweeps"] for r in st])
     s.close()
-    gap = np.abs(ends[1e-5][0] - ends[0.0][0]).max() / bbox_diag(sc.mesh.X)
-    print(f"E {E:g}: 3 converged steps, drop 1e-5 vs every tile: sweeps {ends[1e-5][1]} vs {ends[0.0][1]}, "
-          f"end positions differ by {gap:.2e} of the bbox diagonal", flush=True)
-    assert gap <= 1e-6
-    assert sum(ends[1e-5][1]) <= sum(ends[0.0][1]) + 3
+    for key in [k for k in ends if k != 0.0]:
+        gap = np.abs(ends[key][0] - ends[0.0][0]).max() / bbox_diag(sc.mesh.X)
+        print(f"E {E:g}: 3 converged steps, {key} vs every tile in FP32: sweeps {ends[key][1]} vs {ends[0.0][1]}, "
+              f"end positions differ by {gap:.2e} of the bbox diagonal", flush=True)
+        assert gap <= 1e-6
+        assert sum(ends[key][1]) <= sum(ends[0.0][1]) + 3
