@@ -51,6 +51,8 @@ def parse():
                          "kernels and arguments; used for traced runs)")
     ap.add_argument("--batched-beams", type=int, default=256)
     ap.add_argument("--batched-steps", type=int, default=4, help="steps of the batched leg (30 in its full run)")
+    ap.add_argument("--batched-roofline-only", action="store_true",
+                    help="batched leg: stop after the sweep kernel's roofline group (for profiling runs)")
     ap.add_argument("--contact-steps", type=int, default=120)
     ap.add_argument("--no-contact", action="store_true", help="skip the 10-sphere contact leg")
     ap.add_argument("--leg", choices=["contact"], help=argparse.SUPPRESS)
@@ -345,7 +347,8 @@ def main():
     jgs2_sweep = measure_cubature_sweep(sc0, corr0) if corr0 is not None else None
 
     adj = None if args.no_adjoint or args.small else adjoint_leg()
-    bat = None if args.no_batched or args.small else batched_leg(args.batched_beams, steps=args.batched_steps)
+    bat = None if args.no_batched or args.small else batched_leg(args.batched_beams, steps=args.batched_steps,
+                                                                 roofline_only=args.batched_roofline_only)
 
     cpu = None
     if not args.no_cpu_baseline and value is not None:
@@ -393,7 +396,7 @@ def compare_table(results, names, stiff, head_mode):
     return out
 
 
-def batched_leg(n_beams=256, steps=4, loop_steps=2, max_sweeps=20000, check_every=8, omega=1.5):
+def batched_leg(n_beams=256, steps=4, loop_steps=2, max_sweeps=20000, check_every=8, omega=1.5, roofline_only=False):
     """Many-beam workload: n_beams beams with cross-section a, b in U{4..24},
     length in U{16..96} cells of 0.05 m, log-uniform E in [1e4, 1e7], nu in
     U[0.3, 0.48] (seed 0), pinned at x = 0, gravity, from rest; coloured GS
@@ -402,7 +405,9 @@ def batched_leg(n_beams=256, steps=4, loop_steps=2, max_sweeps=20000, check_ever
     until every beam reaches 1e-5 (or the sweep cap).  Compared with the same
     beams stepped one after another with their own solvers over the first
     `loop_steps` steps (the batched run's first `loop_steps` steps are timed
-    separately for that comparison)."""
+    separately for that comparison).  roofline_only: return after the
+    roofline group (one sweep group of eager, event-timed launches after the
+    autotuner; no graph is captured)."""
     from paper_2506_06494_amd import inputs, jgs2
     spec = inputs.batched_beams(n_beams, seed=0)
     meshes, E, nu = [], [], []
@@ -436,6 +441,12 @@ def batched_leg(n_beams=256, steps=4, loop_steps=2, max_sweeps=20000, check_ever
             "bytes_per_launch": round(per_launch),
             "achieved": round(per_launch / (ms * 1e-3 / n) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / HBM_PEAK_GBS, 4)
+    traffic = measured_traffic("k_plain", f"batch{n_beams}_gs_w{omega:g}")
+    roof["traffic"] = None if traffic is None else round(traffic)
+    print(f"[bench] batched roofline group: {json.dumps(roof)}", file=sys.stderr, flush=True)
+    if roofline_only:
+        s.close()
+        return {"tuned_shape": [lpv, blk], "roofline": roof}
     stats, t_steps, conv = [], [], []
     for k in range(steps):
         sync()
