@@ -533,7 +533,9 @@ def contact_leg(steps=120, max_sweeps=400, check_every=16):
     walls as IPC plane barriers (d_hat 1e-3 m, kappa 1e4); plain coloured GS
     with the per-vertex feasibility clamp and per-sphere residuals, at most
     `max_sweeps` sweeps per step (a step that stops there is reported as not
-    converged)."""
+    converged).  steps = 0: only the sweep kernel's roofline group (eager,
+    event-timed launches after the autotuner; no graph is captured), for
+    profiling runs."""
     from paper_2506_06494_amd import inputs, jgs2
     sc = inputs.contact_scene(0)
     m = sc.mesh
@@ -559,6 +561,11 @@ def contact_leg(steps=120, max_sweeps=400, check_every=16):
             "bytes_per_launch": round(per_launch), "achieved": round(per_launch / (ms * 1e-3 / n) / 1e9, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / HBM_PEAK_GBS, 4)
+    traffic = measured_traffic("k_plain", "contact10_gs")
+    roof["traffic"] = None if traffic is None else round(traffic)
+    if steps == 0:
+        s.close()
+        return {"colours": int(ncol), "tuned_shape": [lpv, blk], "roofline": roof}
     s.set_state(X, v0)
     zmin, stats = [], []
     sync()
