@@ -580,12 +580,23 @@ int32_t jgs2_exact_tiles_fp16(jgs2_solver* s) {
         s->d_tscale = nullptr;
         return r;
     }
-    HIPCHK(hipMemcpyAsync(s->d_tscale, scale.data(), nt * sizeof(float), hipMemcpyHostToDevice, s->stream));
-    HIPCHK(hipMemcpyAsync(dinv, inv.data(), nt * sizeof(float), hipMemcpyHostToDevice, s->stream));
-    jgs2::launch_tiles_to_fp16(s, s->d_Mt, s->d_Mh, dinv, nt);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s->stream));
+    if ((r = jgs2::hip_check(s, hipMemcpyAsync(s->d_tscale, scale.data(), nt * sizeof(float), hipMemcpyHostToDevice,
+                                               s->stream), "upload tile scales")) == JGS2_OK &&
+        (r = jgs2::hip_check(s, hipMemcpyAsync(dinv, inv.data(), nt * sizeof(float), hipMemcpyHostToDevice, s->stream),
+                             "upload tile scales")) == JGS2_OK) {
+        jgs2::launch_tiles_to_fp16(s, s->d_Mt, s->d_Mh, dinv, nt);
+        if ((r = jgs2::hip_check(s, hipGetLastError(), "FP16 tile conversion")) == JGS2_OK)
+            r = jgs2::hip_check(s, hipStreamSynchronize(s->stream), "FP16 tile conversion");
+    }
+    (void)hipStreamSynchronize(s->stream);  // the host arrays above are read by queued copies
     (void)hipFree(dinv);
+    if (r != JGS2_OK) {  // the FP32 tiles stay in use
+        (void)hipFree(s->d_Mh);
+        (void)hipFree(s->d_tscale);
+        s->d_Mh = nullptr;
+        s->d_tscale = nullptr;
+        return r;
+    }
     (void)hipFree(s->d_Mt);
     s->d_Mt = nullptr;
     s->tiles_fp16 = true;
