@@ -22,6 +22,19 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_index_checked_library_exports_the_same_symbols():
+    """libjgs2_bounds.so (the same sources with JGS2_BOUNDS_CHECK) is a drop-in
+    twin of libjgs2.so: it loads without a GPU and exports every declared
+    symbol.  Skipped when it has not been built."""
+    import ctypes
+    import pytest
+    if not os.path.exists(jgs2.BOUNDS_LIB_PATH):
+        pytest.skip("libjgs2_bounds.so is not built")
+    lib = ctypes.CDLL(jgs2.BOUNDS_LIB_PATH)
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
 def test_default_params():
     p = jgs2.default_params()
     assert abs(p.dt - 1 / 120) < 1e-15 and p.gravity[1] == -9.8 and p.check_every == 8
