@@ -235,9 +235,9 @@ int32_t jgs2_precompute(jgs2_solver* s, int32_t samples, int32_t n_cand, uint64_
  * and *loaded = 1 (may be NULL); otherwise the precompute runs and the file
  * is written (through a temporary file renamed at the end), *loaded = 0.
  * For the exact variant the file holds every stored H-bar^-1 tile (about
- * nVf^2 x 18 bytes).  JGS2_E_INVALID if the file cannot be written (the
- * tables are still computed) or a matching file is truncated (the handle is
- * then left without tables). */
+ * nVf^2 x 18 bytes).  A matching file that is cut short is recomputed and
+ * rewritten.  JGS2_E_INVALID if the file cannot be written (the tables are
+ * still computed). */
 int32_t jgs2_precompute_cached(jgs2_solver* s, int32_t samples, int32_t n_cand, uint64_t seed, const char* path,
                                int32_t* loaded);
 

@@ -932,8 +932,8 @@ int write_cache(jgs2_solver* s, const char* path, int n_cand, uint64_t seed) {
     return JGS2_OK;
 }
 
-// 1: loaded; 0: no file or not this precompute's (nothing changed); < 0: a
-// read error after the handle's tables were replaced (they are invalid).
+// 1: loaded; 0: no file, not this precompute's, or cut short (the tables
+// are then recomputed); < 0: an allocation failure.
 int read_cache(jgs2_solver* s, const char* path, int S, int n_cand, uint64_t seed) {
     FILE* f = std::fopen(path, "rb");
     if (!f) return 0;
@@ -971,7 +971,7 @@ int read_cache(jgs2_solver* s, const char* path, int S, int n_cand, uint64_t see
              get_dev(f, s->d_Mt, tile_floats(s) * sizeof(float), stage);
     }
     std::fclose(f);
-    if (!ok) return s->fail(JGS2_E_INVALID, "the precompute cache is truncated or unreadable");
+    if (!ok) return 0;  // a matching header over a short or unreadable body: recompute and rewrite
     s->S = S;
     s->n_poses = hd.n_poses;
     s->have_corr = true;

@@ -1,5 +1,7 @@
 """GPU precompute (banded FP64 Cholesky, subspace-iteration poses, Eq. u,
 greedy NNLS cubature) against the oracle's precompute."""
+import os
+
 import numpy as np
 import pytest
 
@@ -113,6 +115,16 @@ def test_precompute_cache_round_trip(tiny, tmp_path, variant):
     for key in ("U_ring", "samples", "weights", "U_samp"):
         assert np.array_equal(e0[key], e1[key]), key
     assert t0 == t1
+    # a file cut short is recomputed and rewritten, then loads again
+    size = os.path.getsize(path)
+    with open(path, "r+b") as f:
+        f.truncate(size // 2)
+    for k in range(2):
+        s = make_solver(sc, variant=variant)
+        assert s.precompute(samples=4, n_cand=64, seed=0, cache=path) == (k == 1)
+        assert np.array_equal(s.export_correction(4)["U_ring"], e0["U_ring"])
+        s.close()
+    assert os.path.getsize(path) == size
     # a different seed or stiffness is a different precompute: computed, not loaded
     s = make_solver(sc, variant=variant)
     assert not s.precompute(samples=4, n_cand=64, seed=1, cache=path)
