@@ -1,5 +1,6 @@
 /* Drives the C ABI of libjgs2 end to end on a small generated beam, checking
- * every status: mesh, material, the exact variant's precompute and steps,
+ * every status: mesh, material, the exact variant's precompute and steps (also
+ * with FP16 tiles),
  * energy (also without allocation), residual, device-state round trip, the
  * coloured plain sweeps, a rollout and its adjoint, the precompute cache file
  * (when a directory is given as the first argument), and the documented error
@@ -129,9 +130,22 @@ int main(int argc, char** argv) {
         EXPECT(jgs2_precompute_cached(s, 0, 64, 0, path, &loaded), JGS2_E_INVALID);
     }
 
-    /* exact variant: three steps */
+    /* exact variant: three steps, then two more with the tiles in FP16 (a second
+     * conversion does nothing); the production library has no bounds record */
     jgs2_step_stats st;
     for (int k = 0; k < 3; ++k) EXPECT(jgs2_step(s, &st), JGS2_OK);
+    EXPECT(jgs2_exact_tiles_fp16(s), JGS2_OK);
+    EXPECT(jgs2_exact_tiles_fp16(s), JGS2_OK);
+    double half_bytes = 0;
+    EXPECT(jgs2_exact_tiles(s, NULL, NULL, &half_bytes, NULL), JGS2_OK);
+    if (half_bytes * 2.0 != live_bytes) {
+        fprintf(stderr, "FAIL FP16 live bytes %.0f, FP32 %.0f\n", half_bytes, live_bytes);
+        ++failures;
+    }
+    for (int k = 0; k < 2; ++k) EXPECT(jgs2_step(s, &st), JGS2_OK);
+    int32_t line = -1;
+    EXPECT(jgs2_bounds_report(s, &line, NULL, NULL, 0), JGS2_E_INVALID);
+    EXPECT(jgs2_bounds_selftest(s), JGS2_E_INVALID);
     double e0 = 0, e1 = 0, ra = 0, rr = 0;
     EXPECT(jgs2_energy(s, &e0), JGS2_OK);
     EXPECT(jgs2_energy_noalloc(s, &e1), JGS2_OK);
